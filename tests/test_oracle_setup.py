@@ -1,0 +1,280 @@
+"""Pins of the oracle's setup steps against brute force, closed forms and identities.
+
+Each test fixes a step of the CPU oracle to something other than itself, so
+that a dropped term, a wrong sign or index, or a transposed operand fails.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from oracle import coarsen, colouring, discretize, galerkin, hierarchy, knn, transfer
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+# ---------------------------------------------------------------- kNN (Sec. 2)
+def _knn_brute(q, d, k):
+    D2 = knn.sq_dist(q[:, None, :], d[None, :, :])
+    out = []
+    for i in range(len(q)):
+        order = np.lexsort((np.arange(len(d)), D2[i]))
+        out.append(order[:k])
+    return np.array(out)
+
+
+def test_knn_matches_bruteforce_random():
+    rng = np.random.default_rng(0)
+    x = synth.jittered_fibonacci_sphere(700, rng, 0.3)
+    idx, _ = knn.knn(x, x, 25)
+    assert np.array_equal(idx, _knn_brute(x, x, 25))
+
+
+def test_knn_ties_broken_by_index():
+    # integer lattice: many exactly equal distances
+    g = np.arange(7, dtype=np.float64)
+    X, Y = np.meshgrid(g, g)
+    pts = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], axis=1)
+    perm = np.random.default_rng(1).permutation(len(pts))
+    pts = pts[perm]
+    idx, _ = knn.knn(pts, pts, 13)
+    assert np.array_equal(idx, _knn_brute(pts, pts, 13))
+    assert np.all(idx[:, 0] == np.arange(len(pts)))
+
+
+def test_knn_coarse_queries():
+    rng = np.random.default_rng(2)
+    x = synth.jittered_fibonacci_sphere(600, rng, 0.3)
+    y = x[rng.choice(600, 150, replace=False)]
+    idx, _ = knn.knn(x, y, 3)
+    assert np.array_equal(idx, _knn_brute(x, y, 3))
+
+
+def test_duplicate_points_rejected():
+    x = synth.fibonacci_sphere(200)
+    x[17] = x[90]
+    with pytest.raises(knn.DuplicatePointsError):
+        knn.stencils(x, 10)
+
+
+# ------------------------------------------------------- weights (Sec. 2.2-2.3)
+def _flat_cross():
+    h = 0.1
+    return np.array([[0, 0], [h, 0], [-h, 0], [0, h], [0, -h], [h, h]], dtype=np.float64), h
+
+
+def test_rbffd_reduces_to_five_point_laplacian():
+    # n = L = 6 with degree 2: the polynomial constraints fix the weights, which
+    # are the quadratic-interpolation weights: the textbook 5-point stencil.
+    xh, h = _flat_cross()
+    c = discretize.rbffd_weights(xh[None], phs_order=1, deg=2)[0]
+    ref = np.array([-4, 1, 1, 1, 1, 0]) / h ** 2
+    assert np.allclose(c, ref, rtol=0, atol=1e-9 / h ** 2)
+
+
+def test_gfd_reduces_to_five_point_laplacian():
+    xh, h = _flat_cross()
+    sten = np.zeros((1, 6), dtype=np.int64)
+    c = discretize.gfd_weights(xh[None], sten, deg=2, alpha=4.0)[0]
+    ref = np.array([-4, 1, 1, 1, 1, 0]) / h ** 2
+    assert np.allclose(c, ref, rtol=0, atol=1e-9 / h ** 2)
+
+
+@pytest.mark.parametrize("disc,phs,deg,n", [("rbffd", 1, 2, 30), ("rbffd", 2, 3, 50), ("rbffd", 1, 3, 50),
+                                            ("gfd", 0, 2, 25)])
+def test_polynomial_reproduction_and_row_sums(disc, phs, deg, n):
+    """sum_j c_ij p(xh_j) = Lap p(0) for every monomial of degree <= l (eqs. rbf_fd_lap, wls_fd_lap)."""
+    wl = synth.star_workload(3000, n_probe=20000)
+    sten = knn.stencils(wl.xyz, n)
+    xh = discretize.project_stencils(wl.xyz, wl.normals, sten)
+    params = dict(disc=disc, phs_order=phs, poly_degree=deg, gfd_alpha=4.0)
+    c = discretize.lbo_weights(wl.xyz, wl.normals, sten, params)
+    s = np.sqrt((xh ** 2).sum(axis=2)).max(axis=1)
+    for a, b in discretize.monomial_exponents(deg):
+        # unscaled monomials in tangent coordinates; Lap(x^a y^b)(0) = 2 for x^2, y^2
+        val = (c * xh[..., 0] ** a * xh[..., 1] ** b).sum(axis=1)
+        exact = 2.0 if (a, b) in ((2, 0), (0, 2)) else 0.0
+        scale = np.abs(c).sum(axis=1) * s ** (a + b)
+        assert np.max(np.abs(val - exact) / scale) < 1e-10, (a, b)
+    assert np.max(np.abs(c.sum(axis=1)) / np.abs(c).sum(axis=1)) < 1e-12
+
+
+def _y54(x):
+    return x[:, 2] * (x[:, 0] ** 4 - 6 * x[:, 0] ** 2 * x[:, 1] ** 2 + x[:, 1] ** 4)
+
+
+def _lbo_error(n, disc, phs, deg, k):
+    x = synth.fibonacci_sphere(n)
+    sten = knn.stencils(x, k)
+    c = discretize.lbo_weights(x, x, sten, dict(disc=disc, phs_order=phs, poly_degree=deg, gfd_alpha=4.0))
+    u = _y54(x)
+    lap = (c * u[sten]).sum(axis=1)
+    return np.max(np.abs(lap - (-30.0) * u)) / np.max(np.abs(30.0 * u))
+
+
+@pytest.mark.parametrize("disc,phs,deg,k,order", [("rbffd", 1, 2, 30, 1.0), ("rbffd", 2, 3, 50, 1.8),
+                                                   ("gfd", 0, 2, 25, 1.0)])
+def test_lbo_spherical_harmonic_convergence(disc, phs, deg, k, order):
+    """D_h Y_5^4 -> -30 Y_5^4 on the unit sphere, error falling with N (eigenvalue from golden)."""
+    (lval, eig), = _golden("sphere_y54.txt")
+    assert int(eig) == -int(lval) * (int(lval) + 1)
+    e1 = _lbo_error(4096, disc, phs, deg, k)
+    e2 = _lbo_error(16384, disc, phs, deg, k)
+    rate = math.log(e1 / e2) / math.log(2.0)    # h halves when N quadruples
+    assert e2 < 0.05 and rate > order, (e1, e2, rate)
+
+
+# ------------------------------------------------------------- WSE (Sec. 4.1)
+@pytest.mark.parametrize("n,seed", [(400, 0), (1200, 1)])
+def test_wse_heap_matches_bruteforce(n, seed):
+    x = synth.jittered_fibonacci_sphere(n, np.random.default_rng(seed), 0.4)
+    a = coarsen.wse(x)
+    b = coarsen.wse_bruteforce(x)
+    assert np.array_equal(a, b)
+    assert len(a) == n // 4 and np.all(np.diff(a) > 0)
+
+
+def test_wse_improves_separation_over_random_subset():
+    x = synth.jittered_fibonacci_sphere(4000, np.random.default_rng(3), 0.4)
+    keep = coarsen.wse(x)
+    rnd = np.random.default_rng(4).choice(len(x), len(keep), replace=False)
+
+    def sep(pts):
+        _, d2 = knn.knn(pts, pts, 2)
+        return np.sqrt(d2[:, 1].min())
+    assert sep(x[keep]) > 2.0 * sep(x[rnd])
+    # quasi-uniform: min separation close to the mean spacing of a 1000-point cloud
+    assert sep(x[keep]) > 0.5 * math.sqrt(4 * math.pi / len(keep))
+
+
+@pytest.mark.parametrize("n1", [4096, 10000, 160000, 1 << 20, 500000, 300, 999, 1000, 1001, 64000, 64001])
+def test_level_count_formula(n1):
+    """p = floor(log(N_1/N_min)/log 4) + 1 and N_min <= N_p < 4 N_min (Alg. 2)."""
+    sizes = coarsen.level_sizes(n1, 250)
+    p_formula = math.floor(math.log(n1 / 250) / math.log(4) + 1e-12) + 1
+    assert len(sizes) == p_formula
+    assert 250 <= sizes[-1] < 1000
+    for j, s in enumerate(sizes):
+        assert s == n1 // 4 ** j
+
+
+def test_level_sizes_coarse_max_rule():
+    assert coarsen.level_sizes(4096, 0, 200) == [4096, 1024, 256, 64]
+
+
+def test_table1_defaults():
+    g = {k: int(v) for k, v in _golden("table1_parameters.txt")}
+    d = hierarchy.DEFAULTS
+    assert d["n_min"] == g["n_min"] and d["interp_size"] == g["interp_size"]
+    assert d["coarsen_factor"] == g["coarsen_factor"]
+    for l in (3, 5, 7):
+        assert (l + 1) * (l + 2) == g[f"stencil_l{l}"]
+
+
+# ---------------------------------------------------- interpolation (Sec. 3)
+def test_interpolation_reproduces_constants_and_injects():
+    x = synth.jittered_fibonacci_sphere(2000, np.random.default_rng(5), 0.3)
+    keep = coarsen.wse(x)
+    P, idx, inj = transfer.interpolation(x, x[keep], 3)
+    assert np.max(np.abs(P @ np.ones(P.shape[1]) - 1.0)) < 1e-14
+    # nested: every survivor row is exactly the unit row of itself
+    assert np.all(inj[keep])
+    Pd = P[keep].toarray()
+    assert np.array_equal(Pd, np.eye(len(keep)))
+    nnz = np.diff(P.indptr)
+    assert set(np.unique(nnz[~inj])) <= {3}
+
+
+def test_interpolation_weights_equal_interpolant_evaluation():
+    """d = weights from eq. rbf_fd_interp; evaluating the interpolant built from data
+    (the transposed system) at x_i must give sum_j d_ij u_j for any data u."""
+    rng = np.random.default_rng(6)
+    x = synth.jittered_fibonacci_sphere(800, rng, 0.3)
+    keep = coarsen.wse(x)
+    y = x[keep]
+    P, idx, inj = transfer.interpolation(x, y, 3)
+    u = rng.standard_normal(len(y))
+    Pu = P @ u
+    for i in np.nonzero(~inj)[0][:50]:
+        yy = y[idx[i]]
+        A = np.linalg.norm(yy[:, None, :] - yy[None, :, :], axis=2)
+        M = np.block([[A, np.ones((3, 1))], [np.ones((1, 3)), np.zeros((1, 1))]])
+        coef = np.linalg.solve(M, np.concatenate([u[idx[i]], [0.0]]))
+        s = np.linalg.norm(x[i] - yy, axis=1) @ coef[:3] + coef[3]
+        assert abs(s - Pu[i]) < 1e-12 * (1 + abs(s))
+
+
+# ----------------------------------------------------- Galerkin (Sec. 4.2, 4.4)
+def test_galerkin_dense_and_constant_identity():
+    wl = synth.torus_workload(3000)
+    H = hierarchy.build(wl.xyz, wl.normals, wl.params)
+    for j in range(len(H.levels) - 1):
+        lv, nx = H.levels[j], H.levels[j + 1]
+        dense = lv.P.toarray().T @ lv.L.toarray() @ lv.P.toarray()
+        assert np.max(np.abs(nx.L.toarray() - dense)) < 1e-12 * np.abs(dense).max()
+        # Poisson: L 1 = 0 (zero row sums) and P 1 = 1 give L_H 1 = 0
+        one = np.ones(nx.N)
+        assert np.max(np.abs(nx.L @ one)) < 1e-10 * abs(nx.L).max()
+        # border b_H = P^T b_h, and sum(b_H) = N_h because rows of P sum to 1
+        assert np.allclose(nx.b, lv.P.T @ lv.b)
+        assert abs(nx.b.sum() - lv.b.sum()) < 1e-9 * lv.b.sum()
+        # structural pattern contains the numeric pattern
+        assert (abs(nx.L) > 0).astype(int).multiply(1 - nx.pat.toarray()).sum() == 0
+
+
+# ----------------------------------------------------- colouring / hashing
+def test_splitmix64_published_values():
+    rows = _golden("splitmix64.txt")
+    args = np.array([int(a, 16) for a, _ in rows], dtype=np.uint64)
+    vals = [int(v, 16) for _, v in rows]
+    assert [int(v) for v in colouring.splitmix64(args)] == vals
+
+
+def _jp_sequential(G):
+    """Jones-Plassmann written as plain loops (for tiny graphs)."""
+    N = G.shape[0]
+    prio = colouring.priorities(G)
+    adj = [G.indices[G.indptr[i]:G.indptr[i + 1]].tolist() for i in range(N)]
+    colour = [-1] * N
+    while -1 in colour:
+        sel = [v for v in range(N) if colour[v] < 0 and all(colour[u] >= 0 or prio[u] < prio[v] for u in adj[v])]
+        new = {}
+        for v in sel:
+            used = {colour[u] for u in adj[v] if colour[u] >= 0}
+            c = 0
+            while c in used:
+                c += 1
+            new[v] = c
+        for v, c in new.items():
+            colour[v] = c
+    return np.array(colour)
+
+
+def test_colouring_matches_plain_loops_and_is_valid():
+    wl = synth.sphere_workload(1500)
+    wl.params["n_coarse_max"] = 100
+    H = hierarchy.build(wl.xyz, wl.normals, wl.params)
+    for lv in H.levels[:-1]:
+        assert colouring.is_valid_colouring(lv.pat, lv.colour)
+        G = colouring.symmetric_graph(lv.pat)
+        assert np.array_equal(lv.colour, _jp_sequential(G))
+
+
+def test_priorities_largest_degree_first():
+    G = sp.csr_matrix(np.array([[0, 1, 1, 1], [1, 0, 0, 0], [1, 0, 0, 1], [1, 0, 1, 0]]))
+    p = colouring.priorities(G)
+    assert p[0] == 3  # degree 3 beats everyone
+    c = colouring.jp_colouring(G)
+    assert c[0] == 0 and len(set(c[[0, 2, 3]])) == 3

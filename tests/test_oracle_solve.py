@@ -1,0 +1,269 @@
+"""Pins of the oracle's smoother, V-cycle, Krylov methods and precision emulation."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import synth
+from oracle import hierarchy, krylov, precision, vcycle
+
+
+@pytest.fixture(scope="module")
+def sphere_h():
+    wl = synth.sphere_workload(1500)
+    wl.params["n_coarse_max"] = 100
+    return wl, hierarchy.build(wl.xyz, wl.normals, wl.params)
+
+
+@pytest.fixture(scope="module")
+def torus_h():
+    wl = synth.torus_workload(2500)
+    wl.params["n_min"] = 150
+    return wl, hierarchy.build(wl.xyz, wl.normals, wl.params)
+
+
+def _perm(lv):
+    return np.argsort(lv.colour, kind="stable")
+
+
+# ------------------------------------------------------ Gauss-Seidel (Sec. 4.3)
+def test_multicolour_gs_is_sequential_gs_in_colour_order(sphere_h):
+    _, H = sphere_h
+    ops = vcycle.Fp64Ops(H)
+    lv = H.levels[0]
+    rng = np.random.default_rng(0)
+    f = rng.standard_normal(lv.N)
+    u0 = rng.standard_normal(lv.N)
+    u = vcycle.gs_sweep(ops, 0, u0.copy(), f)
+    # plain row-by-row loop, newest values used immediately
+    Ld = lv.L.toarray()
+    v = u0.copy()
+    for i in _perm(lv):
+        v[i] += (f[i] - Ld[i] @ v) / Ld[i, i]
+    assert np.max(np.abs(u - v)) <= 1e-13 * np.max(np.abs(v))
+
+
+def test_gs_is_triangular_splitting(sphere_h):
+    """u <- u + B^{-1}(f - L u), B the lower triangle of L in the update order (eq. smoother)."""
+    _, H = sphere_h
+    ops = vcycle.Fp64Ops(H)
+    lv = H.levels[1]
+    rng = np.random.default_rng(1)
+    f = rng.standard_normal(lv.N)
+    u0 = rng.standard_normal(lv.N)
+    u = vcycle.gs_sweep(ops, 1, u0.copy(), f)
+    p = _perm(lv)
+    Lp = lv.L.toarray()[np.ix_(p, p)]
+    B = np.tril(Lp)
+    ref = u0[p] + sla.solve_triangular(B, f[p] - Lp @ u0[p], lower=True)
+    assert np.allclose(u[p], ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    # backward sweep = upper triangle in the same order
+    ub = vcycle.gs_sweep(ops, 1, u0.copy(), f, reverse=True)
+    refb = u0[p] + sla.solve_triangular(np.triu(Lp), f[p] - Lp @ u0[p], lower=False)
+    assert np.allclose(ub[p], refb, rtol=0, atol=1e-12 * np.abs(refb).max())
+
+
+def test_bordered_gs_holds_multiplier(torus_h):
+    """u <- u + B^{-1}(f - L u - b lambda) (Sec. 4.4, inexact Uzawa with zero Schur complement)."""
+    _, H = torus_h
+    ops = vcycle.Fp64Ops(H)
+    lv = H.levels[1]
+    rng = np.random.default_rng(2)
+    f = rng.standard_normal(lv.N)
+    u0 = rng.standard_normal(lv.N)
+    lam = 0.37
+    u = vcycle.gs_sweep(ops, 1, u0.copy(), f, lam)
+    p = _perm(lv)
+    Lp = lv.L.toarray()[np.ix_(p, p)]
+    ref = u0[p] + sla.solve_triangular(np.tril(Lp), f[p] - Lp @ u0[p] - lv.b[p] * lam, lower=True)
+    assert np.allclose(u[p], ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
+# ------------------------------------------------------------ V-cycle (Alg. 3)
+def _dense_two_level(L, P, B, nu1, nu2):
+    """Dense V(nu1,nu2) two-level operator M (zero initial guess) from its definition."""
+    n = L.shape[0]
+    I = np.eye(n)
+    S = I - np.linalg.solve(B, L)                   # error propagation of one smoothing step
+    LH = P.T @ L @ P
+    C = I - P @ np.linalg.solve(LH, P.T @ L)        # coarse-grid correction
+    E = np.linalg.matrix_power(S, nu2) @ C @ np.linalg.matrix_power(S, nu1)
+    return (I - E) @ np.linalg.inv(L)
+
+
+@pytest.mark.parametrize("nu1,nu2", [(0, 0), (1, 0), (1, 1), (2, 1)])
+def test_two_level_cycle_matches_dense_definition(nu1, nu2):
+    wl = synth.sphere_workload(600)
+    wl.params["n_coarse_max"] = 160
+    H = hierarchy.build(wl.xyz, wl.normals, wl.params)
+    assert len(H.levels) == 2
+    lv = H.levels[0]
+    ops = vcycle.Fp64Ops(H)
+    p = _perm(lv)
+    L = lv.L.toarray()
+    Lp = L[np.ix_(p, p)]
+    Bp = np.tril(Lp)
+    B = np.zeros_like(L)
+    B[np.ix_(p, p)] = Bp
+    Md = _dense_two_level(L, lv.P.toarray(), B, nu1, nu2)
+    r = np.random.default_rng(3).standard_normal(lv.N)
+    z = vcycle.vcycle(ops, r, None, nu1, nu2)
+    assert np.max(np.abs(z - Md @ r)) <= 1e-10 * np.max(np.abs(Md @ r))
+
+
+def test_bordered_two_level_matches_dense_definition():
+    """Two-level bordered cycle against the dense formula with the operators of eq. gco_saddle_point."""
+    wl = synth.torus_workload(1200)
+    wl.params["n_min"] = 300
+    H = hierarchy.build(wl.xyz, wl.normals, wl.params)
+    assert len(H.levels) == 2
+    lv, cl = H.levels
+    ops = vcycle.Fp64Ops(H)
+    n, nc = lv.N, cl.N
+    L = lv.L.toarray()
+    b = lv.b
+    Lt = np.block([[L, b[:, None]], [b[None, :], np.zeros((1, 1))]])
+    Pt = np.zeros((n + 1, nc + 1))
+    Pt[:n, :nc] = lv.P.toarray()
+    Pt[n, nc] = 1.0
+    p = _perm(lv)
+    B = np.zeros((n + 1, n + 1))
+    B[np.ix_(p, p)] = np.tril(L[np.ix_(p, p)])
+    B[n, n] = 1.0
+    # smoother on the bordered system: only u is updated, lambda held fixed
+    I = np.eye(n + 1)
+    Sm = np.eye(n + 1)
+    Sm[:n, :] = I[:n, :] - np.linalg.solve(B, Lt)[:n, :]
+    LH = Pt.T @ Lt @ Pt
+    C = I - Pt @ np.linalg.solve(LH, Pt.T @ Lt)
+    E = Sm @ C @ Sm
+    Md = (I - E) @ np.linalg.inv(Lt)
+    rng = np.random.default_rng(4)
+    rt = np.concatenate([rng.standard_normal(n), [0.3]])
+    z, lam = vcycle.vcycle(ops, rt[:n], rt[n], 1, 1)
+    ref = Md @ rt
+    assert np.max(np.abs(np.concatenate([z, [lam]]) - ref)) <= 1e-9 * np.max(np.abs(ref))
+    # coarse operator of the bordered system is the Galerkin product (eq. gco_saddle_point)
+    assert np.allclose(LH[:nc, :nc], cl.L.toarray(), atol=1e-12 * abs(LH).max())
+    assert np.allclose(LH[:nc, nc], cl.b) and np.allclose(LH[nc, :nc], cl.b)
+
+
+def test_vcycle_is_linear(sphere_h, torus_h):
+    for wl, H in (sphere_h, torus_h):
+        ops = vcycle.Fp64Ops(H)
+        M = vcycle.make_preconditioner(ops, H.problem)
+        n = H.levels[0].N + (1 if H.problem == "poisson" else 0)
+        rng = np.random.default_rng(5)
+        a, b = rng.standard_normal(n), rng.standard_normal(n)
+        lhs = M(2.0 * a - 3.0 * b)
+        rhs = 2.0 * M(a) - 3.0 * M(b)
+        assert np.max(np.abs(lhs - rhs)) <= 1e-12 * np.max(np.abs(rhs))
+
+
+# ----------------------------------------------------- Krylov (Sec. 4.6, 5)
+@pytest.mark.parametrize("method", ["fgmres", "bicgstab"])
+def test_solve_matches_dense_direct(sphere_h, torus_h, method):
+    for wl, H in (sphere_h, torus_h):
+        A = vcycle.make_operator(H)
+        M = vcycle.make_preconditioner(vcycle.Fp64Ops(H), H.problem)
+        L = H.levels[0].L.toarray()
+        if H.problem == "poisson":
+            n = L.shape[0]
+            Ad = np.block([[L, np.ones((n, 1))], [np.ones((1, n)), np.zeros((1, 1))]])
+            f = np.concatenate([wl.f, [0.0]])
+        else:
+            Ad, f = L, wl.f
+        ref = np.linalg.solve(Ad, f)
+        solver = krylov.fgmres if method == "fgmres" else krylov.bicgstab
+        x, info = solver(A, M, f, tol=1e-12, maxit=300)
+        assert info.converged and info.rel_res_true <= 1e-12
+        assert np.linalg.norm(x - ref) <= 1e-9 * np.linalg.norm(ref)
+        if H.problem == "poisson":
+            assert abs(x[:-1].sum()) <= 1e-9 * np.abs(x[:-1]).sum()   # mean-zero constraint
+
+
+def test_krylov_trivial_preconditioners():
+    rng = np.random.default_rng(6)
+    n = 60
+    Ad = np.eye(n) * 4 + rng.standard_normal((n, n)) * 0.3
+    f = rng.standard_normal(n)
+    A = lambda v: Ad @ v
+    Minv = np.linalg.inv(Ad)
+    x, info = krylov.fgmres(A, lambda v: Minv @ v, f, tol=1e-12)
+    assert info.iters == 1
+    x, info = krylov.fgmres(A, lambda v: v, f, tol=1e-12, restart=10, maxit=400)
+    assert info.converged and np.allclose(x, np.linalg.solve(Ad, f), atol=1e-10)
+    x, info = krylov.bicgstab(A, lambda v: v, f, tol=1e-12, maxit=400)
+    assert info.converged and np.allclose(x, np.linalg.solve(Ad, f), atol=1e-10)
+
+
+def test_screened_sphere_solution_approaches_continuous(sphere_h):
+    """-Delta u + u = Y_5^4 on the unit sphere has u = Y_5^4 / 31 (Delta Y_5^4 = -30 Y_5^4)."""
+    wl, H = sphere_h
+    x = wl.xyz
+    y = x[:, 2] * (x[:, 0] ** 4 - 6 * x[:, 0] ** 2 * x[:, 1] ** 2 + x[:, 1] ** 4)
+    A = vcycle.make_operator(H)
+    M = vcycle.make_preconditioner(vcycle.Fp64Ops(H), H.problem)
+    u, info = krylov.fgmres(A, M, y, tol=1e-12)
+    err = np.max(np.abs(u - y / 31.0)) / np.max(np.abs(y / 31.0))
+    assert err < 0.05
+
+
+# -------------------------------------------------- reduced-precision emulation
+def _fp16_rne_exact(x: float) -> float:
+    """Round a double to the nearest binary16 value, ties to even, by exact rational arithmetic."""
+    if x == 0.0:
+        return 0.0
+    s = -1 if x < 0 else 1
+    a = Fraction(abs(x))
+    e = 15
+    while e > -14 and a < Fraction(2) ** e:
+        e -= 1
+    q = Fraction(2) ** (e - 10)              # spacing of binary16 values in [2^e, 2^(e+1)) (subnormal: e=-14)
+    k = a / q
+    fl = k.numerator // k.denominator
+    rem = k - fl
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and fl % 2 == 1):
+        fl += 1
+    return s * float(fl * q)
+
+
+def test_fp16_quantisation_is_single_rne_from_fp64():
+    rng = np.random.default_rng(7)
+    v = np.concatenate([rng.uniform(-1, 1, 3000), rng.uniform(-1e-4, 1e-4, 500),
+                        rng.uniform(-1e-7, 1e-7, 200)])
+    # values just off binary16 halfway points (double rounding through fp32 would fail)
+    a = np.float16(0.7)
+    b = np.nextafter(a, np.float16(1.0))
+    mid = (float(a) + float(b)) / 2
+    v = np.concatenate([v, [mid + 2 ** -40, mid - 2 ** -40, mid]])
+    q = v.astype(np.float16).astype(np.float64)
+    ref = np.array([_fp16_rne_exact(float(t)) for t in v])
+    assert np.array_equal(q, ref)
+
+
+def test_fp16_row_scale_definition():
+    L = sp.csr_matrix(np.array([[4.0, -1.0, 0.5], [0.0, -3.0, 1e-3], [2.0, 0.0, 2.0]]))
+    h, s = precision.fp16_row_scale(L)
+    assert s.dtype == np.float32 and np.allclose(s, [4.0, 3.0, 2.0])
+    rows = np.repeat(np.arange(3), np.diff(L.indptr))
+    assert np.max(np.abs(h.astype(np.float64) * s[rows] - L.data) / s[rows]) <= 2 ** -11
+
+
+def test_reduced_precision_vcycle_close_to_fp64(torus_h):
+    wl, H = torus_h
+    f = np.concatenate([wl.f, [0.0]])
+    z64 = vcycle.make_preconditioner(precision.ops_for(H, "fp64"), H.problem)(f)
+    for prec, tol in (("fp32", 1e-5), ("fp16", 5e-3)):
+        z = vcycle.make_preconditioner(precision.ops_for(H, prec), H.problem)(f)
+        assert np.linalg.norm(z - z64) / np.linalg.norm(z64) < tol, prec
+    A = vcycle.make_operator(H)
+    it = {}
+    for prec in ("fp64", "fp32", "fp16"):
+        M = vcycle.make_preconditioner(precision.ops_for(H, prec), H.problem)
+        x, info = krylov.fgmres(A, M, f, tol=1e-10)
+        assert info.converged and info.rel_res_true <= 1e-10
+        it[prec] = info.iters
+    assert abs(it["fp32"] - it["fp64"]) <= 1 and abs(it["fp16"] - it["fp64"]) <= 1
