@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""MGM-GMRES solve benchmark on one MI355X.
+
+Workload (the paper's headline use of MGM: a right preconditioner for GMRES,
+Sec. 4.6/5): torus R=1, r=1/3 with N=160,000 Poisson-disk points, RBF-FD
+PHS r^5 + degree-3 polynomials on 50-point stencils, the surface Poisson
+problem solved as the bordered system (Sec. 4.4), zero-mean trigonometric
+right-hand side, FGMRES(40) to relative residual 1e-10 with one MGM V(1,1)
+cycle per iteration. Inputs are seeded and synthetic (no dataset).
+
+A step is one complete solve from x0 = 0 (right-hand side resident in HBM,
+setup excluded as in the paper). The FP64 V-cycle and the reduced-precision
+V-cycles (FP32; FP16 values with FP32 row scales) are timed in turn; `value`
+is the solve time with the FP32 V-cycle (FP64 Krylov), the FP64 solve time
+and the ratio are reported beside it.
+
+roofline: the dominant kernel (the multicolour Gauss-Seidel colour phase,
+the most frequently launched and longest-running kernel of the V-cycle) is
+timed live with HIP events on its launch stream through mgm_time_kernel;
+achieved = algorithmic bytes per launch / mean launch time.
+
+cpu_baseline: the CPU oracle's FGMRES solve (same algorithm, FP64, NumPy/SciPy,
+single thread) on a bounded sample of the same workload family (N=40,000
+torus points, same discretisation and solver), scaled linearly in N to
+N=160,000 (iteration counts are N-independent for MGM, Tables 2-3).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n_sample: int, n_full: int):
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle import hierarchy, krylov, vcycle
+
+    wl = synth.torus_workload(n_sample)
+    H = hierarchy.build(wl.xyz, wl.normals, wl.params)
+    A = vcycle.make_operator(H)
+    M = vcycle.make_preconditioner(vcycle.Fp64Ops(H), H.problem)
+    f = np.concatenate([wl.f, [0.0]])
+    ts = []
+    with threadpool_limits(limits=1):
+        for _ in range(3):
+            t0 = time.perf_counter()
+            _, info = krylov.fgmres(A, M, f, tol=1e-10, restart=40, maxit=400)
+            ts.append(time.perf_counter() - t0)
+    t = float(np.median(ts))
+    return {"value": round(t * 1e3 * n_full / n_sample, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+            "sample": f"oracle FP64 FGMRES(40) solve to 1e-10 on the torus workload at N={n_sample} "
+                      f"({info.iters} iterations, median {t:.3f} s of 3 solves, setup excluded), scaled "
+                      f"x{n_full / n_sample:g} to N={n_full}; SciPy sparse kernels, BLAS limited to 1 thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=160_000)
+    ap.add_argument("--precisions", default="fp64,fp32,fp16")
+    ap.add_argument("--cpu-sample", type=int, default=40_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the MGM solve is not sharded across GPUs in this build "
+              "(see DESIGN.md for how it would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2204_06154_amd import mgm
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t0 = time.perf_counter()
+    wl = synth.torus_workload(args.n)
+    log(f"inputs N={args.n} generated in {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    m = mgm.Mgm(wl.xyz, wl.normals, wl.params, device=0)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    sizes = [int(s) for s in m.export("level_sizes")]
+    ncol = [int(c) for c in m.export("ncolours")]
+    log(f"setup {setup_s:.1f} s, levels {sizes}, colours {ncol}")
+    f = torch.tensor(np.concatenate([wl.f, [0.0]]), device="cuda")
+    u = torch.zeros_like(f)
+
+    results = {}
+    for prec in args.precisions.split(","):
+        m.set_precision(prec)
+        for _ in range(args.warmup):
+            u.zero_()
+            m.solve(f, u, krylov="fgmres", restart=40, maxit=400, rtol=1e-10)
+        torch.cuda.synchronize()
+        times = []
+        info = None
+        for _ in range(args.steps):
+            u.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = m.solve(f, u, krylov="fgmres", restart=40, maxit=400, rtol=1e-10)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        vc_ms, vc_bytes = m.time_kernel("vcycle", 0, reps=20)
+        results[prec] = dict(ms=1e3 * float(np.mean(times)), ms_min=1e3 * float(np.min(times)), iters=info["iters"],
+                             rel_res_true=info["rel_res_true"], vcycle_ms=vc_ms, vcycle_bytes=vc_bytes)
+        log(f"{prec}: {results[prec]['ms']:.2f} ms/solve, {info['iters']} iters, "
+            f"res {info['rel_res_true']:.2e}, V-cycle {vc_ms * 1e3:.0f} us")
+
+    main_prec = "fp32" if "fp32" in results else list(results)[0]
+    m.set_precision(main_prec)
+    gs_ms, gs_bytes = m.time_kernel("gs", 0, reps=10)
+    m.set_precision("fp64")
+    sp_ms, sp_bytes = m.time_kernel("spmv", 0, reps=50)
+    gs_gbs = gs_bytes / (gs_ms * 1e-3) / 1e9
+    sp_gbs = sp_bytes / (sp_ms * 1e-3) / 1e9
+    log(f"GS colour phase ({main_prec}, fine level): {gs_ms * 1e3:.2f} us, {gs_bytes / 1e6:.2f} MB -> {gs_gbs:.0f} GB/s")
+    log(f"SpMV (fp64, fine level): {sp_ms * 1e3:.2f} us, {sp_bytes / 1e6:.1f} MB -> {sp_gbs:.0f} GB/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        cpu = cpu_baseline(args.cpu_sample, args.n)
+        log(f"cpu baseline {cpu['value']} ms (took {time.perf_counter() - t0:.0f} s)")
+
+    r = results[main_prec]
+    out = {
+        "metric": "MGM-GMRES solve time to 1e-10 rel. residual (FP64 vs mixed); SpMV HBM GB/s",
+        "value": round(r["ms"], 3),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms"], 3),
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": f"{main_prec} V-cycle, f64 Krylov",
+        "data": "synthetic (seeded Poisson-disk torus points, random trigonometric rhs)",
+        "config": {"workload": f"torus R=1 r=1/3, N={args.n} Poisson-disk points, RBF-FD r^5+deg3 k=50, "
+                               f"bordered surface Poisson, FGMRES(40)+MGM V(1,1) to 1e-10",
+                   "levels": sizes, "colours": ncol, "setup_s": round(setup_s, 2)},
+        "solves": {p: {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in d.items()}
+                   for p, d in results.items()},
+        "speedup_mixed_vs_fp64": round(results["fp64"]["ms"] / r["ms"], 3) if "fp64" in results else None,
+        "spmv": {"kernel": "k_spmv fp64 fine level", "us": round(sp_ms * 1e3, 2), "bytes": sp_bytes,
+                 "GBps": round(sp_gbs, 1), "frac": round(sp_gbs / HBM_PEAK_GBS, 4)},
+        "roofline": {"bound": "hbm", "kernel": f"k_gs_colour {main_prec} fine level (one colour phase)",
+                     "achieved": round(gs_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gs_gbs / HBM_PEAK_GBS, 4), "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    m.close()
+
+
+if __name__ == "__main__":
+    main()

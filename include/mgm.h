@@ -1,0 +1,208 @@
+/*
+ * mgm.h -- C ABI of the MI355X (gfx950) implementation of the solve phase of
+ * MGM, the meshfree geometric multilevel method of Wright, Jones & Shankar
+ * (arXiv 2204.06154), for the RBF-FD / GFD surface-Laplacian systems
+ * L_h u = f defined on point-cloud surfaces.
+ *
+ * Conventions for every call:
+ *  - Every function returns an mgm_status: 0 = MGM_OK, > 0 a warning, < 0 an
+ *    error. After an error, outputs are unspecified; the handle stays usable
+ *    unless the error was MGM_E_HIP. mgm_last_error() returns a thread-local
+ *    human-readable detail string for the last failing call of this thread.
+ *  - Host pointers ("h_" or documented as host) are borrowed for the duration
+ *    of the call and copied as needed. Device pointers ("d_") are borrowed,
+ *    caller-owned, contiguous FP64 arrays on the handle's device. The handle
+ *    owns all internal host and device memory until mgm_destroy().
+ *  - Calls that take a stream are ordered on that HIP stream (a hipStream_t
+ *    passed as void*; NULL = the legacy default stream). Inputs must be ready
+ *    on that stream; outputs are ready when the stream reaches the call's end.
+ *  - Vectors are in the caller's point order. Internal reorderings (colouring)
+ *    are applied and undone inside the library.
+ *  - Calls on one handle must not overlap (one stream at a time per handle).
+ */
+#ifndef MGM_H
+#define MGM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mgm_ctx *mgm_handle;
+
+typedef enum {
+  MGM_OK = 0,
+  MGM_NOT_CONVERGED = 1,       /* solve hit maxit; best iterate returned */
+  MGM_E_ARG = -1,              /* invalid argument or parameter */
+  MGM_E_ALLOC = -2,            /* host or device allocation failed */
+  MGM_E_HIP = -3,              /* HIP runtime error (handle no longer usable) */
+  MGM_E_STENCIL_SINGULAR = -4, /* a local weight system is singular (pivot ~0) */
+  MGM_E_DUP_POINTS = -5,       /* two input points coincide */
+  MGM_E_ZERO_DIAG = -6,        /* a level operator has a zero diagonal entry */
+  MGM_E_COARSE_SINGULAR = -7,  /* coarsest-level LU hit a zero pivot */
+  MGM_E_BREAKDOWN = -8,        /* Krylov breakdown */
+  MGM_E_NONFINITE = -9         /* NaN/Inf in an input or an iterate */
+} mgm_status;
+
+/* Discretisation of the Laplace-Beltrami operator (Sec. 2). */
+enum { MGM_RBFFD = 0, MGM_GFD = 1 };
+/* Problem (Sec. 1.1, eq. discrete_system): POISSON: L_h = D_h, solved as the
+ * bordered system [L b^T; b 0][u; lambda] = [f; 0] with b = 1^T (Sec. 4.4,
+ * eq. saddle_point); SCREENED: L_h = I - mu D_h. */
+enum { MGM_SCREENED = 0, MGM_POISSON = 1 };
+/* V-cycle arithmetic: FP64; FP32 values and vectors; FP16 operator values with
+ * one FP32 scale per row, FP32 vectors. Outer Krylov and coarsest LU: FP64. */
+enum { MGM_FP64 = 0, MGM_FP32 = 1, MGM_FP16 = 2 };
+/* Smoother sweeps (Sec. 4.3: forward or backward Gauss-Seidel). */
+enum { MGM_GS_FWD = 0, MGM_GS_BWD = 1 };
+/* Outer iteration (Sec. 4.6): right-preconditioned FGMRES(restart) or
+ * BiCGSTAB, or the stationary V-cycle iteration u <- u + M(f - A u). */
+enum { MGM_FGMRES = 0, MGM_BICGSTAB = 1, MGM_STATIONARY = 2 };
+
+typedef struct {
+  int32_t disc;           /* MGM_RBFFD | MGM_GFD */
+  int32_t phs_order;      /* k of the PHS kernel r^(2k+1) (RBF-FD only), 0..4 */
+  int32_t poly_degree;    /* l, degree of the bivariate polynomials, 0..6 */
+  int32_t stencil_size;   /* n, stencil size, centre included, > L = (l+1)(l+2)/2 */
+  double  gfd_alpha;      /* alpha of the GFD Gaussian weight (Sec. 2.3) */
+  int32_t problem;        /* MGM_SCREENED | MGM_POISSON */
+  double  mu;             /* screened: L = I - mu D, mu > 0 */
+  int32_t interp_size;    /* m, coarse stencil of the interpolation (Sec. 3); 3 */
+  int32_t coarsen_factor; /* N_{j+1} = floor(N_j / factor) (Sec. 4.1); 4 */
+  int32_t n_min;          /* > 0: p = floor(log(N_1/N_min)/log 4) + 1 (Alg. 2) */
+  int32_t n_coarse_max;   /* used when n_min == 0: coarsen while N_j > this */
+  int32_t nu1, nu2;       /* pre/post smoothing sweeps (Alg. 3) */
+  int32_t pre_smoother;   /* MGM_GS_FWD | MGM_GS_BWD */
+  int32_t post_smoother;  /* MGM_GS_FWD | MGM_GS_BWD */
+  int32_t precision;      /* MGM_FP64 | MGM_FP32 | MGM_FP16 (V-cycle only) */
+  int32_t use_graph;      /* 1: replay the V-cycle as a captured HIP graph */
+  int32_t device_weights; /* 1: stencil weights by the batched device solver */
+} mgm_params;
+
+/* Paper defaults (Table 1): RBF-FD, k = l = 3, n = 20, forward GS, nu = 1,
+ * m = 3, factor 4, N_min = 250, screened with mu = 1, FP64, graphs on. */
+void mgm_default_params(mgm_params *p);
+
+/* Preprocessing phase (Alg. 2): kNN stencils (Sec. 2), tangent-plane weights
+ * (Sec. 2.1-2.3), L_1 (eq. discrete_system), then for each level: weighted
+ * sample elimination (Sec. 4.1), PHS interpolation (Sec. 3, eq. rbf_fd_interp),
+ * R = P^T, Galerkin L_{j+1} = R L_j P (eq. galerkin; bordered:
+ * eq. gco_saddle_point), multicolour ordering, and the coarsest LU.
+ *   h_xyz, h_normals: host, n x 3 row-major FP64 (normals need not be unit).
+ *   device: HIP device ordinal that all later calls use; -1 builds a host-only
+ *   handle (no GPU needed) that supports mgm_export and mgm_destroy only.
+ *   stream: stream for the uploads.
+ * Errors: MGM_E_ARG (bad sizes/params, too few points for one coarse level),
+ * MGM_E_DUP_POINTS, MGM_E_STENCIL_SINGULAR, MGM_E_ZERO_DIAG,
+ * MGM_E_COARSE_SINGULAR, MGM_E_NONFINITE, MGM_E_ALLOC, MGM_E_HIP. */
+mgm_status mgm_setup(const double *h_xyz, const double *h_normals, int64_t n,
+                     const mgm_params *params, int32_t device, void *stream,
+                     mgm_handle *out);
+
+/* Change the V-cycle precision (MGM_FP64/FP32/FP16) of an existing hierarchy;
+ * reduced-precision operator copies are built on first use. */
+mgm_status mgm_set_precision(mgm_handle h, int32_t precision);
+
+/* One V(nu1,nu2)-cycle (Alg. 3) with zero initial guess: d_z = M d_r.
+ * Length n (screened) or n+1 (Poisson: the last entry is the constraint
+ * residual on input and the multiplier correction on output). d_r and d_z
+ * may not alias. MGM_E_NONFINITE is not checked here (no host sync). */
+mgm_status mgm_vcycle(mgm_handle h, const double *d_r, double *d_z, void *stream);
+
+/* Apply the fine-level system operator (eq. discrete_system; bordered for
+ * Poisson): d_y = A d_x, lengths as for mgm_vcycle. */
+mgm_status mgm_apply(mgm_handle h, const double *d_x, double *d_y, void *stream);
+
+typedef struct {
+  int32_t krylov;   /* MGM_FGMRES | MGM_BICGSTAB | MGM_STATIONARY */
+  int32_t restart;  /* FGMRES restart length m (1..200) */
+  int32_t maxit;    /* maximum preconditioner applications */
+  double  rtol;     /* stop when |f - A u|_2 <= rtol |f|_2 (true FP64 residual) */
+  int32_t use_x0;   /* 1: d_u holds the initial guess; 0: start from zero */
+} mgm_solve_opts;
+
+typedef struct {
+  int32_t iters;          /* preconditioner applications (Sec. 5 counting) */
+  int32_t restarts;
+  double  rel_res_est;    /* last Krylov estimate of the relative residual */
+  double  rel_res_true;   /* |f - A u|_2 / |f|_2 recomputed in FP64 at the end */
+  double  lambda;         /* Poisson: the Lagrange multiplier; else 0 */
+} mgm_solve_info;
+
+/* MGM-preconditioned solve (Sec. 4.6): right-preconditioned FGMRES(m) with
+ * CGS2 or BiCGSTAB, entirely on device in FP64 around the V-cycle.
+ *   d_f: right-hand side, length n (Poisson: n+1 with last entry 0).
+ *   d_u: solution (and initial guess if use_x0), same length.
+ *   h_res_hist: nullable host array of maxit+1 doubles receiving the relative
+ *   residual estimate after each preconditioner application (entry 0 = 1).
+ * Synchronises the stream once per outer iteration. Returns MGM_OK or
+ * MGM_NOT_CONVERGED (best iterate in d_u), MGM_E_BREAKDOWN, MGM_E_NONFINITE. */
+mgm_status mgm_solve(mgm_handle h, const double *d_f, double *d_u,
+                     const mgm_solve_opts *opts, mgm_solve_info *info,
+                     double *h_res_hist, void *stream);
+
+/* Per-level operations for testing and profiling; vectors are device FP64 in
+ * the level's natural numbering (level 1: caller order; level j+1: the WSE
+ * survivors of level j in ascending level-j index). Level indices are 0-based.
+ *   MGM_OP_SMOOTH:  d_x <- one GS sweep of L_j on (d_x, d_b) with the border
+ *                   term -b_j*scalar (Sec. 4.3; Sec. 4.4); reverse=1: backward.
+ *   MGM_OP_SPMV:    d_y = L_j d_x.
+ *   MGM_OP_RESTRICT_RESIDUAL: d_y (level j+1) = R_j (d_b - L_j d_x).
+ *   MGM_OP_INTERP_ADD:        d_x (level j) += P_j d_y (level j+1).
+ * All run in the handle's current precision (inputs/outputs stay FP64). */
+enum { MGM_OP_SMOOTH = 0, MGM_OP_SPMV = 1, MGM_OP_RESTRICT_RESIDUAL = 2, MGM_OP_INTERP_ADD = 3 };
+mgm_status mgm_level_op(mgm_handle h, int32_t op, int32_t level, double *d_x,
+                        const double *d_b, double *d_y, double scalar,
+                        int32_t reverse, void *stream);
+
+/* Profiling of one hot-path kernel: `reps` timed repetitions on the handle's
+ * internal buffers (contents arbitrary), each bracketed by HIP events on
+ * `stream`; returns the mean device time of one launch in *ms and the
+ * algorithmic HBM bytes that launch must move in *bytes (values + indices
+ * of the rows it touches, each vector element counted once).
+ *   MGM_TK_SPMV:     the fine-level FP64 operator y = L_1 x (eq. discrete_system).
+ *   MGM_TK_GS:       one multicolour GS colour phase of level `level` in the
+ *                    current precision (Sec. 4.3); averaged over the colours
+ *                    of one sweep, bytes likewise per phase.
+ *   MGM_TK_RESIDUAL: residual r - L_j e of level `level`, current precision.
+ *   MGM_TK_VCYCLE:   one whole V-cycle (Alg. 3) in the current precision;
+ *                    bytes = sum over its kernels. */
+enum { MGM_TK_SPMV = 0, MGM_TK_GS = 1, MGM_TK_RESIDUAL = 2, MGM_TK_VCYCLE = 3 };
+mgm_status mgm_time_kernel(mgm_handle h, int32_t which, int32_t level, int32_t reps,
+                           void *stream, double *ms, double *bytes);
+
+/* Export of setup results for bit-exact comparison (host buffers).
+ * Call with h_buf = NULL to query *len (element count); then with a buffer of
+ * at least *len elements. Element types: I32 = int32_t, F64 = double.
+ *   MGM_EX_LEVEL_SIZES   I32  all levels                      (level ignored)
+ *   MGM_EX_STENCILS      I32  N_1 x n, centre first           (level ignored)
+ *   MGM_EX_WEIGHTS       F64  N_1 x n, weights c_ij           (level ignored)
+ *   MGM_EX_COARSE_IDX    I32  survivors of level j (ascending level-j index)
+ *   MGM_EX_INTERP_IDX    I32  N_j x m coarse neighbours (level j+1 numbering)
+ *   MGM_EX_INTERP_W      F64  N_j x m weights (injection rows: 1,0,0)
+ *   MGM_EX_COLOURS       I32  colour of each row of level j (natural order)
+ *   MGM_EX_L_ROWPTR      I32  CSR row pointer of L_j (natural order)
+ *   MGM_EX_L_COLS        I32  CSR column indices (sorted per row)
+ *   MGM_EX_L_VALS        F64  CSR values
+ *   MGM_EX_BORDER        F64  b_j (Poisson only)
+ *   MGM_EX_NCOLOURS      I32  colours per smoothed level      (level ignored) */
+enum {
+  MGM_EX_LEVEL_SIZES = 0, MGM_EX_STENCILS = 1, MGM_EX_WEIGHTS = 2,
+  MGM_EX_COARSE_IDX = 3, MGM_EX_INTERP_IDX = 4, MGM_EX_INTERP_W = 5,
+  MGM_EX_COLOURS = 6, MGM_EX_L_ROWPTR = 7, MGM_EX_L_COLS = 8,
+  MGM_EX_L_VALS = 9, MGM_EX_BORDER = 10, MGM_EX_NCOLOURS = 11
+};
+mgm_status mgm_export(mgm_handle h, int32_t what, int32_t level, void *h_buf,
+                      int64_t *len);
+
+/* Release every resource of the handle (waits for its device work). */
+void mgm_destroy(mgm_handle h);
+
+const char *mgm_status_str(mgm_status s);
+const char *mgm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGM_H */

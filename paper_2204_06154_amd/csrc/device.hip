@@ -1,0 +1,1164 @@
+// Device hierarchy, V-cycle orchestration, Krylov solvers and the C ABI.
+//
+// Layout in HBM. Every smoothed level j is stored in a permuted row order:
+// rows grouped by smoother colour (colour 0 first), and within a colour by a
+// 3-D Morton key of the points, so each colour phase streams one contiguous
+// row range and its gathers stay spatially local. Row-major CSR (fixed width
+// on the fine level), int32 column indices in the permuted numbering, values
+// in FP64 and, built on demand, FP32 or FP16 with one FP32 scale per row.
+// P_j is a fixed-width (m) row-major table, R_j = P_j^T is CSR, both in
+// permuted numbering; the coarsest level keeps its natural order and a dense
+// FP64 inverse of its (bordered) operator.
+//
+// The V-cycle (Alg. 3, zero initial guess, bordered reading of Sec. 4.4) is
+// one stream-ordered sequence of kernels on fixed internal buffers and is
+// captured once per precision as a HIP graph; callers copy their vector in
+// (permute + cast) and out around the graph launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <string>
+
+#include "hierarchy.h"
+#include "kernels.h"
+
+namespace mgm {
+
+#define HIPCHECK(x)                                                                                     \
+  do {                                                                                                  \
+    hipError_t e_ = (x);                                                                                \
+    if (e_ != hipSuccess) throw Error(MGM_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+static inline unsigned nblk(int64_t threads) { return unsigned((threads + kBlock - 1) / kBlock); }
+
+template <typename T>
+T* dalloc(size_t n) {
+  T* p = nullptr;
+  if (n == 0) n = 1;
+  if (hipMalloc(reinterpret_cast<void**>(&p), n * sizeof(T)) != hipSuccess)
+    throw Error(MGM_E_ALLOC, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  return p;
+}
+
+template <typename T>
+T* dupload(const std::vector<T>& v) {
+  T* p = dalloc<T>(v.size());
+  if (!v.empty()) HIPCHECK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return p;
+}
+
+// IEEE binary16 (round to nearest, ties to even) of a double, rounded once.
+static uint16_t f64_to_f16_bits(double x) {
+  uint16_t sign = std::signbit(x) ? 0x8000 : 0;
+  double a = std::fabs(x);
+  if (std::isnan(x)) return sign | 0x7e00;
+  if (a == 0.0) return sign;
+  int E;
+  std::frexp(a, &E);  // a = f 2^E, f in [0.5, 1)
+  int e = E - 1;      // a in [2^e, 2^(e+1))
+  if (e < -14) {      // subnormal grid: multiples of 2^-24
+    double k = std::rint(std::ldexp(a, 24));
+    return sign | uint16_t(k);  // k == 1024 is the smallest normal, encoded the same way
+  }
+  double k = std::rint(std::ldexp(a, 10 - e));  // in [1024, 2048]
+  if (k == 2048.0) {
+    k = 1024.0;
+    ++e;
+  }
+  if (e > 15) return sign | 0x7c00;
+  return sign | uint16_t((e + 15) << 10) | uint16_t(int(k) - 1024);
+}
+
+struct DevLevel {
+  int n = 0, ncol = 0, W = 0, G = 8, m = 0, nnext = 0;
+  int64_t nnz = 0;
+  std::vector<int> cstart;           // colour row ranges (host)
+  int32_t* perm = nullptr;           // position -> natural index (null: identity)
+  int32_t *rowptr = nullptr, *col = nullptr;
+  double* v64 = nullptr;
+  float* v32 = nullptr;
+  _Float16* v16 = nullptr;
+  float* s16 = nullptr;
+  double* dinv64 = nullptr;
+  float* dinv32 = nullptr;
+  float* dinv16 = nullptr;
+  int32_t* pcol = nullptr;
+  double* p64 = nullptr;
+  float* p32 = nullptr;
+  int32_t *rptr = nullptr, *rcol = nullptr;
+  double* r64 = nullptr;
+  float* r32 = nullptr;
+  double* b64 = nullptr;
+  float* b32 = nullptr;
+  double *e64 = nullptr, *f64 = nullptr, *res64 = nullptr;
+  float *e32 = nullptr, *f32 = nullptr, *res32 = nullptr;
+  // host copies needed to build reduced-precision values lazily
+  std::vector<double> hv, hdiag;
+  std::vector<int64_t> rowlen_prefix;  // host copy of the permuted row pointer
+};
+
+}  // namespace mgm
+
+struct mgm_ctx {
+  int device = 0;
+  mgm_params p{};
+  mgm::HostHierarchy H;
+  std::vector<mgm::DevLevel> lv;     // all levels; the last is the coarsest
+  int cdim = 0;
+  double* cinv = nullptr;
+  double* rho = nullptr;             // per-level constraint residuals
+  double* mu = nullptr;              // multiplier correction (bordered)
+  double* lam = nullptr;             // scalar for level ops
+  double* partial = nullptr;
+  int64_t partial_len = 0;
+  bool built[3] = {true, false, false};
+  hipStream_t cap = nullptr;
+  hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
+  std::vector<void*> allocs;
+  // solver workspace
+  int ws_restart = 0;
+  int64_t ld = 0;
+  double *V = nullptr, *Z = nullptr, *vecs = nullptr, *kpart = nullptr, *dh = nullptr;
+  double* hpin = nullptr;
+};
+
+namespace mgm {
+
+thread_local std::string g_last_error;
+
+template <typename T>
+static T* track(mgm_ctx* c, T* p) {
+  c->allocs.push_back(reinterpret_cast<void*>(p));
+  return p;
+}
+
+static uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  auto spread = [](uint64_t v) {
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffull;
+    v = (v | v << 16) & 0x1f0000ff0000ffull;
+    v = (v | v << 8) & 0x100f00f00f00f00full;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+    v = (v | v << 2) & 0x1249249249249249ull;
+    return v;
+  };
+  return spread(x) | spread(y) << 1 | spread(z) << 2;
+}
+
+static int choose_G(double mean_len) {
+  if (mean_len <= 6) return 2;
+  if (mean_len <= 14) return 4;
+  if (mean_len <= 40) return 8;
+  return 16;
+}
+
+// Build the device form of every level (FP64 values).
+static void upload(mgm_ctx* c) {
+  HostHierarchy& H = c->H;
+  const int p = int(H.lv.size());
+  c->lv.assign(p, DevLevel());
+  std::vector<std::vector<int32_t>> iperm(p);
+  // permutations
+  for (int j = 0; j < p; ++j) {
+    const HostLevel& h = H.lv[j];
+    DevLevel& d = c->lv[j];
+    d.n = h.n;
+    iperm[j].resize(h.n);
+    if (j == p - 1) {
+      std::iota(iperm[j].begin(), iperm[j].end(), 0);
+      continue;
+    }
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int i = 0; i < h.n; ++i)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], h.xyz[3 * i + a]);
+        hi[a] = std::max(hi[a], h.xyz[3 * i + a]);
+      }
+    double ext = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
+    if (!(ext > 0)) ext = 1.0;
+    std::vector<uint64_t> key(h.n);
+    for (int i = 0; i < h.n; ++i) {
+      uint32_t q[3];
+      for (int a = 0; a < 3; ++a) q[a] = uint32_t(std::min(2097151.0, std::floor((h.xyz[3 * i + a] - lo[a]) / ext * 2097151.0)));
+      key[i] = morton3(q[0], q[1], q[2]);
+    }
+    std::vector<int32_t> order(h.n);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      if (h.colour[a] != h.colour[b]) return h.colour[a] < h.colour[b];
+      if (key[a] != key[b]) return key[a] < key[b];
+      return a < b;
+    });
+    for (int t = 0; t < h.n; ++t) iperm[j][order[t]] = t;
+    d.ncol = h.ncolours;
+    d.cstart.assign(h.ncolours + 1, 0);
+    for (int i = 0; i < h.n; ++i) d.cstart[h.colour[i] + 1]++;
+    for (int k = 0; k < h.ncolours; ++k) d.cstart[k + 1] += d.cstart[k];
+    d.perm = track(c, dupload(order));
+  }
+  const bool bord = c->p.problem == MGM_POISSON;
+  for (int j = 0; j < p; ++j) {
+    const HostLevel& h = H.lv[j];
+    DevLevel& d = c->lv[j];
+    const int n = h.n;
+    d.e64 = track(c, dalloc<double>(n + 1));
+    d.f64 = track(c, dalloc<double>(n + 1));
+    d.res64 = track(c, dalloc<double>(n + 1));
+    d.e32 = track(c, dalloc<float>(n + 1));
+    d.f32 = track(c, dalloc<float>(n + 1));
+    d.res32 = track(c, dalloc<float>(n + 1));
+    if (bord) {
+      std::vector<double> bp(n);
+      for (int i = 0; i < n; ++i) bp[iperm[j][i]] = h.b[i];
+      d.b64 = track(c, dupload(bp));
+      std::vector<float> bf(bp.begin(), bp.end());
+      d.b32 = track(c, dupload(bf));
+    }
+    if (j == p - 1) continue;
+    // permuted CSR of L_j
+    std::vector<int32_t> order(n);
+    for (int i = 0; i < n; ++i) order[iperm[j][i]] = i;
+    std::vector<int32_t> rp(n + 1, 0), cl;
+    std::vector<double> vl, diag(n, 0.0);
+    cl.reserve(h.L.nnz());
+    vl.reserve(h.L.nnz());
+    bool fixed = true;
+    int w0 = h.L.ptr[1] - h.L.ptr[0];
+    for (int pos = 0; pos < n; ++pos) {
+      int i = order[pos];
+      int len = h.L.ptr[i + 1] - h.L.ptr[i];
+      if (len != w0) fixed = false;
+      for (int k = h.L.ptr[i]; k < h.L.ptr[i + 1]; ++k) {
+        cl.push_back(iperm[j][h.L.col[k]]);
+        vl.push_back(h.L.val[k]);
+        if (h.L.col[k] == i) diag[pos] = h.L.val[k];
+      }
+      rp[pos + 1] = int32_t(cl.size());
+    }
+    d.nnz = int64_t(cl.size());
+    d.W = fixed ? w0 : 0;
+    d.rowlen_prefix.assign(rp.begin(), rp.end());
+    d.G = choose_G(double(d.nnz) / n);
+    d.rowptr = track(c, dupload(rp));
+    d.col = track(c, dupload(cl));
+    d.v64 = track(c, dupload(vl));
+    std::vector<double> dinv(n);
+    for (int i = 0; i < n; ++i) dinv[i] = 1.0 / diag[i];
+    d.dinv64 = track(c, dupload(dinv));
+    d.hv = std::move(vl);
+    d.hdiag = std::move(diag);
+    // interpolation P_j (rows: this level's positions; cols: next level's positions)
+    const int m = h.m;
+    d.m = m;
+    d.nnext = H.lv[j + 1].n;
+    std::vector<int32_t> pc(size_t(n) * m);
+    std::vector<double> pw(size_t(n) * m);
+    for (int pos = 0; pos < n; ++pos) {
+      int i = order[pos];
+      for (int t = 0; t < m; ++t) {
+        pc[size_t(pos) * m + t] = iperm[j + 1][h.pidx[size_t(i) * m + t]];
+        pw[size_t(pos) * m + t] = h.pw[size_t(i) * m + t];
+      }
+    }
+    d.pcol = track(c, dupload(pc));
+    d.p64 = track(c, dupload(pw));
+    std::vector<float> pwf(pw.begin(), pw.end());
+    d.p32 = track(c, dupload(pwf));
+    // R_j = P_j^T (structural entries only), rows in next-level positions
+    Csr Pp;
+    Pp.nrows = n;
+    Pp.ncols = d.nnext;
+    Pp.ptr.assign(n + 1, 0);
+    for (int pos = 0; pos < n; ++pos) {
+      int i = order[pos];
+      int cnt = h.injected[i] ? 1 : m;
+      Pp.ptr[pos + 1] = Pp.ptr[pos] + cnt;
+      for (int t = 0; t < cnt; ++t) {
+        Pp.col.push_back(pc[size_t(pos) * m + t]);
+        Pp.val.push_back(pw[size_t(pos) * m + t]);
+      }
+    }
+    Csr Rp = transpose(Pp);
+    d.rptr = track(c, dupload(Rp.ptr));
+    d.rcol = track(c, dupload(Rp.col));
+    d.r64 = track(c, dupload(Rp.val));
+    std::vector<float> rf(Rp.val.begin(), Rp.val.end());
+    d.r32 = track(c, dupload(rf));
+  }
+  c->cdim = H.coarse_dim;
+  c->cinv = track(c, dupload(H.coarse_inv));
+  c->rho = track(c, dalloc<double>(p + 1));
+  c->mu = track(c, dalloc<double>(1));
+  c->lam = track(c, dalloc<double>(1));
+  int64_t maxblk = 1;
+  for (auto& d : c->lv) maxblk = std::max<int64_t>(maxblk, nblk(int64_t(d.n) * 16) + 1);
+  c->partial_len = maxblk;
+  c->partial = track(c, dalloc<double>(maxblk));
+  HIPCHECK(hipMemset(c->mu, 0, sizeof(double)));
+  HIPCHECK(hipMemset(c->rho, 0, sizeof(double) * (p + 1)));
+}
+
+static void build_precision(mgm_ctx* c, int prec) {
+  if (c->built[prec]) return;
+  for (size_t j = 0; j + 1 < c->lv.size(); ++j) {
+    DevLevel& d = c->lv[j];
+    const int n = d.n;
+    if (prec == MGM_FP32) {
+      std::vector<float> v(d.hv.begin(), d.hv.end());
+      d.v32 = track(c, dupload(v));
+      std::vector<float> di(n);
+      for (int i = 0; i < n; ++i) di[i] = float(1.0 / d.hdiag[i]);
+      d.dinv32 = track(c, dupload(di));
+    } else {
+      std::vector<int32_t> rp(n + 1);
+      HIPCHECK(hipMemcpy(rp.data(), d.rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+      std::vector<float> s(n), di(n);
+      std::vector<uint16_t> h(d.hv.size());
+      std::vector<int32_t> cl(d.hv.size());
+      HIPCHECK(hipMemcpy(cl.data(), d.col, sizeof(int32_t) * cl.size(), hipMemcpyDeviceToHost));
+      for (int i = 0; i < n; ++i) {
+        double amax = 0.0;
+        for (int k = rp[i]; k < rp[i + 1]; ++k) amax = std::max(amax, std::fabs(d.hv[k]));
+        float sf = float(amax);
+        if (sf == 0.0f) sf = 1.0f;
+        s[i] = sf;
+        double hd = 0.0;
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+          h[k] = f64_to_f16_bits(d.hv[k] / double(sf));
+          if (cl[k] == i) {
+            _Float16 q;
+            std::memcpy(&q, &h[k], 2);
+            hd = double(float(q));
+          }
+        }
+        di[i] = float(1.0 / (double(sf) * hd));
+      }
+      d.s16 = track(c, dupload(s));
+      d.dinv16 = track(c, dupload(di));
+      _Float16* p16 = dalloc<_Float16>(h.size());
+      track(c, p16);
+      HIPCHECK(hipMemcpy(p16, h.data(), h.size() * 2, hipMemcpyHostToDevice));
+      d.v16 = p16;
+    }
+  }
+  c->built[prec] = true;
+}
+
+// ----------------------------------------------------------- kernel dispatch
+template <typename V, typename S, bool SC>
+struct Prec;
+template <>
+struct Prec<double, double, false> {
+  static const double* val(const DevLevel& d) { return d.v64; }
+  static const double* dinv(const DevLevel& d) { return d.dinv64; }
+  static const double* pw(const DevLevel& d) { return d.p64; }
+  static const double* rw(const DevLevel& d) { return d.r64; }
+  static double* e(DevLevel& d) { return d.e64; }
+  static double* f(DevLevel& d) { return d.f64; }
+  static double* res(DevLevel& d) { return d.res64; }
+  static const double* b(const DevLevel& d) { return d.b64; }
+};
+template <>
+struct Prec<float, float, false> {
+  static const float* val(const DevLevel& d) { return d.v32; }
+  static const float* dinv(const DevLevel& d) { return d.dinv32; }
+  static const float* pw(const DevLevel& d) { return d.p32; }
+  static const float* rw(const DevLevel& d) { return d.r32; }
+  static float* e(DevLevel& d) { return d.e32; }
+  static float* f(DevLevel& d) { return d.f32; }
+  static float* res(DevLevel& d) { return d.res32; }
+  static const float* b(const DevLevel& d) { return d.b32; }
+};
+template <>
+struct Prec<_Float16, float, true> {
+  static const _Float16* val(const DevLevel& d) { return d.v16; }
+  static const float* dinv(const DevLevel& d) { return d.dinv16; }
+  static const float* pw(const DevLevel& d) { return d.p32; }
+  static const float* rw(const DevLevel& d) { return d.r32; }
+  static float* e(DevLevel& d) { return d.e32; }
+  static float* f(DevLevel& d) { return d.f32; }
+  static float* res(DevLevel& d) { return d.res32; }
+  static const float* b(const DevLevel& d) { return d.b32; }
+};
+
+#define DISPATCH_G(G, ...)                          \
+  switch (G) {                                      \
+    case 2: { constexpr int GG = 2; __VA_ARGS__; } break;  \
+    case 4: { constexpr int GG = 4; __VA_ARGS__; } break;  \
+    case 8: { constexpr int GG = 8; __VA_ARGS__; } break;  \
+    default: { constexpr int GG = 16; __VA_ARGS__; } break; \
+  }
+
+template <typename V, typename S, bool SC>
+static void gs_sweep(mgm_ctx* c, int j, bool reverse, bool border, const double* lam, hipStream_t st) {
+  using P = Prec<V, S, SC>;
+  DevLevel& d = c->lv[j];
+  for (int t = 0; t < d.ncol; ++t) {
+    int col = reverse ? d.ncol - 1 - t : t;
+    int r0 = d.cstart[col], r1 = d.cstart[col + 1];
+    if (r1 <= r0) continue;
+    unsigned g = nblk(int64_t(r1 - r0) * d.G);
+    DISPATCH_G(d.G, if (border) hipLaunchKernelGGL((k_gs_colour<V, S, GG, SC, true>), dim3(g), dim3(kBlock), 0, st, r0, r1, d.W, d.rowptr, d.col,
+                       P::val(d), d.s16, P::dinv(d), P::f(d), P::e(d), P::b(d), lam);
+               else hipLaunchKernelGGL((k_gs_colour<V, S, GG, SC, false>), dim3(g), dim3(kBlock), 0, st, r0, r1, d.W, d.rowptr, d.col,
+                       P::val(d), d.s16, P::dinv(d), P::f(d), P::e(d), P::b(d), lam));
+  }
+}
+
+// res_j = f_j - L_j e_j (bordered: partial sums of b_j . e_j) then
+// f_{j+1} = R_j res_j (bordered: rho_{j+1} = rho_j - b_j . e_j).
+template <typename V, typename S, bool SC>
+static void residual_restrict(mgm_ctx* c, int j, hipStream_t st) {
+  using P = Prec<V, S, SC>;
+  DevLevel& d = c->lv[j];
+  DevLevel& nx = c->lv[j + 1];
+  const bool bord = c->p.problem == MGM_POISSON;
+  unsigned g = nblk(int64_t(d.n) * d.G);
+  DISPATCH_G(d.G, if (bord) hipLaunchKernelGGL((k_residual<V, S, GG, SC, true>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr, d.col,
+                     P::val(d), d.s16, P::f(d), P::e(d), P::res(d), P::b(d), c->partial);
+             else hipLaunchKernelGGL((k_residual<V, S, GG, SC, false>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr, d.col,
+                     P::val(d), d.s16, P::f(d), P::e(d), P::res(d), P::b(d), c->partial));
+  unsigned gr = nblk(nx.n);
+  if (bord)
+    hipLaunchKernelGGL((k_restrict<S, S, true>), dim3(gr), dim3(kBlock), 0, st, nx.n, d.rptr, d.rcol, P::rw(d), P::res(d),
+                       P::f(nx), c->partial, int(g), c->rho + j, c->rho + j + 1);
+  else
+    hipLaunchKernelGGL((k_restrict<S, S, false>), dim3(gr), dim3(kBlock), 0, st, nx.n, d.rptr, d.rcol, P::rw(d), P::res(d),
+                       P::f(nx), c->partial, 0, c->rho + j, c->rho + j + 1);
+}
+
+template <typename V, typename S, bool SC>
+static void interp_add(mgm_ctx* c, int j, hipStream_t st) {
+  using P = Prec<V, S, SC>;
+  DevLevel& d = c->lv[j];
+  DevLevel& nx = c->lv[j + 1];
+  hipLaunchKernelGGL((k_interp_add<S, S>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, d.m, d.pcol, P::pw(d), P::e(nx), P::e(d));
+}
+
+template <typename V, typename S, bool SC>
+static void vcycle_enqueue(mgm_ctx* c, hipStream_t st) {
+  using P = Prec<V, S, SC>;
+  const int p = int(c->lv.size());
+  const bool bord = c->p.problem == MGM_POISSON;
+  for (int j = 0; j + 1 < p; ++j) {
+    DevLevel& d = c->lv[j];
+    hipLaunchKernelGGL((k_fill<S>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, P::e(d), S(0));
+    for (int s = 0; s < c->p.nu1; ++s) gs_sweep<V, S, SC>(c, j, c->p.pre_smoother == MGM_GS_BWD, false, c->mu, st);
+    residual_restrict<V, S, SC>(c, j, st);
+  }
+  DevLevel& cl = c->lv[p - 1];
+  hipLaunchKernelGGL((k_coarse_gemv<S>), dim3(nblk(int64_t(c->cdim) * 64)), dim3(kBlock), 0, st, c->cdim, cl.n, c->cinv,
+                     P::f(cl), c->rho + (p - 1), P::e(cl), c->mu);
+  for (int j = p - 2; j >= 0; --j) {
+    interp_add<V, S, SC>(c, j, st);
+    for (int s = 0; s < c->p.nu2; ++s) gs_sweep<V, S, SC>(c, j, c->p.post_smoother == MGM_GS_BWD, bord, c->mu, st);
+  }
+}
+
+static void vcycle_core(mgm_ctx* c, hipStream_t st) {
+  const int prec = c->p.precision;
+  build_precision(c, prec);
+  if (c->p.use_graph) {
+    if (!c->graph[prec]) {
+      if (!c->cap) HIPCHECK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+      hipGraph_t g;
+      HIPCHECK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+      if (prec == MGM_FP64) vcycle_enqueue<double, double, false>(c, c->cap);
+      else if (prec == MGM_FP32) vcycle_enqueue<float, float, false>(c, c->cap);
+      else vcycle_enqueue<_Float16, float, true>(c, c->cap);
+      HIPCHECK(hipStreamEndCapture(c->cap, &g));
+      hipGraphExec_t ex;
+      hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIPCHECK(e);
+      c->graph[prec] = ex;
+    }
+    HIPCHECK(hipGraphLaunch(c->graph[prec], st));
+  } else {
+    if (prec == MGM_FP64) vcycle_enqueue<double, double, false>(c, st);
+    else if (prec == MGM_FP32) vcycle_enqueue<float, float, false>(c, st);
+    else vcycle_enqueue<_Float16, float, true>(c, st);
+    HIPCHECK(hipGetLastError());
+  }
+}
+
+// z = M v for FP64 vectors in the fine level's permuted order (perm null) or
+// in natural order (perm = the fine permutation).
+static void precond(mgm_ctx* c, const double* v, double* z, const int32_t* perm, hipStream_t st) {
+  DevLevel& d = c->lv[0];
+  const bool bord = c->p.problem == MGM_POISSON;
+  const unsigned g = nblk(d.n);
+  if (c->p.precision == MGM_FP64) {
+    hipLaunchKernelGGL((k_gather<double, double>), dim3(g), dim3(kBlock), 0, st, d.n, perm, v, d.f64, bord ? c->rho : nullptr);
+    vcycle_core(c, st);
+    hipLaunchKernelGGL((k_scatter<double, double>), dim3(g), dim3(kBlock), 0, st, d.n, perm, d.e64, z, bord ? c->mu : nullptr);
+  } else {
+    hipLaunchKernelGGL((k_gather<double, float>), dim3(g), dim3(kBlock), 0, st, d.n, perm, v, d.f32, bord ? c->rho : nullptr);
+    vcycle_core(c, st);
+    hipLaunchKernelGGL((k_scatter<float, double>), dim3(g), dim3(kBlock), 0, st, d.n, perm, d.e32, z, bord ? c->mu : nullptr);
+  }
+}
+
+// y = A x (FP64 fine operator, permuted order; bordered tail at index n).
+static void apply_A(mgm_ctx* c, const double* x, double* y, hipStream_t st) {
+  DevLevel& d = c->lv[0];
+  const bool bord = c->p.problem == MGM_POISSON;
+  unsigned g = nblk(int64_t(d.n) * d.G);
+  DISPATCH_G(d.G, if (bord) hipLaunchKernelGGL((k_spmv<double, double, GG, false, true>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr,
+                     d.col, d.v64, nullptr, x, y, d.b64, x + d.n);
+             else hipLaunchKernelGGL((k_spmv<double, double, GG, false, false>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr,
+                     d.col, d.v64, nullptr, x, y, d.b64, x + d.n));
+  if (bord) {
+    unsigned gb = nblk(d.n);
+    hipLaunchKernelGGL((k_bdot_partial<double>), dim3(gb), dim3(kBlock), 0, st, d.n, d.b64, x, c->kpart);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, 1, int(gb), c->kpart, y + d.n);
+  }
+}
+
+// ------------------------------------------------------------------- solvers
+static void ensure_ws(mgm_ctx* c, int restart) {
+  const int64_t n = c->lv[0].n + 1;
+  if (!c->vecs) {
+    c->ld = (n + 63) / 64 * 64;
+    c->vecs = track(c, dalloc<double>(size_t(c->ld) * 12));
+    int64_t kp = std::max<int64_t>(int64_t(kRedBlocks) * 202, nblk(n) + 1);
+    c->kpart = track(c, dalloc<double>(kp));
+    c->dh = track(c, dalloc<double>(1024));
+    HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&c->hpin), 1024 * sizeof(double), hipHostMallocDefault));
+  }
+  if (restart > c->ws_restart) {
+    c->V = track(c, dalloc<double>(size_t(c->ld) * (restart + 1)));
+    c->Z = track(c, dalloc<double>(size_t(c->ld) * restart));
+    c->ws_restart = restart;
+  }
+}
+
+// out[t] = V[t] . w for t < k (device), deterministic.
+static void mdot(mgm_ctx* c, int64_t n, const double* V, int64_t ld, int k, const double* w, double* out, hipStream_t st) {
+  int nb = int(std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (n + 2047) / 2048)));
+  hipLaunchKernelGGL(k_mdot_partial, dim3(nb, k), dim3(kBlock), 0, st, int(n), V, ld, w, c->kpart);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(k), dim3(kBlock), 0, st, k, nb, c->kpart, out);
+}
+
+static void to_host(mgm_ctx* c, const double* d, int k, hipStream_t st) {
+  HIPCHECK(hipMemcpyAsync(c->hpin, d, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+}
+
+static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const mgm_solve_opts& o, mgm_solve_info& info,
+                             double* hist, hipStream_t st) {
+  DevLevel& d0 = c->lv[0];
+  const bool bord = c->p.problem == MGM_POISSON;
+  const int64_t n = d0.n + (bord ? 1 : 0);
+  const int m = std::max(1, o.restart);
+  ensure_ws(c, o.krylov == MGM_FGMRES ? m : 1);
+  const int64_t ld = c->ld;
+  double* f = c->vecs;
+  double* x = c->vecs + ld;
+  double* r = c->vecs + 2 * ld;
+  double* w = c->vecs + 3 * ld;
+  const unsigned g = nblk(n);
+  // permute inputs
+  hipLaunchKernelGGL((k_gather<double, double>), dim3(nblk(d0.n)), dim3(kBlock), 0, st, d0.n, d0.perm, d_f, f, nullptr);
+  if (bord) HIPCHECK(hipMemcpyAsync(f + d0.n, d_f + d0.n, sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (o.use_x0) {
+    hipLaunchKernelGGL((k_gather<double, double>), dim3(nblk(d0.n)), dim3(kBlock), 0, st, d0.n, d0.perm, d_u, x, nullptr);
+    if (bord) HIPCHECK(hipMemcpyAsync(x + d0.n, d_u + d0.n, sizeof(double), hipMemcpyDeviceToDevice, st));
+  } else {
+    hipLaunchKernelGGL((k_fill<double>), dim3(g), dim3(kBlock), 0, st, int(n), x, 0.0);
+  }
+  mdot(c, n, f, ld, 1, f, c->dh, st);
+  to_host(c, c->dh, 1, st);
+  const double fnorm = std::sqrt(c->hpin[0]);
+  if (!std::isfinite(fnorm)) throw Error(MGM_E_NONFINITE, "non-finite right-hand side");
+  info = mgm_solve_info{};
+  int hist_n = 0;
+  if (hist) hist[hist_n++] = 1.0;
+  auto true_res = [&]() {
+    apply_A(c, x, r, st);
+    hipLaunchKernelGGL(k_rsub, dim3(g), dim3(kBlock), 0, st, int(n), f, r);
+    mdot(c, n, r, ld, 1, r, c->dh, st);
+    to_host(c, c->dh, 1, st);
+    return std::sqrt(c->hpin[0]);
+  };
+  auto finish = [&](mgm_status s) {
+    hipLaunchKernelGGL((k_scatter<double, double>), dim3(nblk(d0.n)), dim3(kBlock), 0, st, d0.n, d0.perm, x, d_u, nullptr);
+    if (bord) {
+      HIPCHECK(hipMemcpyAsync(d_u + d0.n, x + d0.n, sizeof(double), hipMemcpyDeviceToDevice, st));
+      HIPCHECK(hipMemcpyAsync(c->hpin, x + d0.n, sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    HIPCHECK(hipStreamSynchronize(st));
+    info.lambda = bord ? c->hpin[0] : 0.0;
+    return s;
+  };
+  if (fnorm == 0.0) {
+    hipLaunchKernelGGL((k_fill<double>), dim3(g), dim3(kBlock), 0, st, int(n), x, 0.0);
+    info.rel_res_true = 0.0;
+    return finish(MGM_OK);
+  }
+  const double tol = o.rtol;
+  if (o.krylov == MGM_FGMRES) {
+    std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
+    for (;;) {
+      double beta = true_res();
+      info.rel_res_true = beta / fnorm;
+      if (!std::isfinite(beta)) return finish(MGM_E_NONFINITE);
+      if (beta / fnorm <= tol) return finish(MGM_OK);
+      if (info.iters >= o.maxit) return finish(MGM_NOT_CONVERGED);
+      if (info.iters > 0) info.restarts++;
+      double* V = c->V;
+      double* Z = c->Z;
+      // V0 = r / beta (beta^2 is on device in dh[0])
+      hipLaunchKernelGGL(k_normalise, dim3(g), dim3(kBlock), 0, st, int(n), r, c->dh, V);
+      std::fill(H.begin(), H.end(), 0.0);
+      std::fill(gv.begin(), gv.end(), 0.0);
+      gv[0] = beta;
+      int k = 0;
+      for (int j = 0; j < m; ++j) {
+        precond(c, V + j * ld, Z + j * ld, nullptr, st);
+        info.iters++;
+        apply_A(c, Z + j * ld, w, st);
+        mdot(c, n, V, ld, j + 1, w, c->dh, st);
+        hipLaunchKernelGGL(k_mupdate, dim3(g), dim3(kBlock), 0, st, int(n), V, ld, j + 1, c->dh, w);
+        mdot(c, n, V, ld, j + 1, w, c->dh + 256, st);
+        hipLaunchKernelGGL(k_mupdate, dim3(g), dim3(kBlock), 0, st, int(n), V, ld, j + 1, c->dh + 256, w);
+        mdot(c, n, w, ld, 1, w, c->dh + 512, st);
+        hipLaunchKernelGGL(k_normalise, dim3(g), dim3(kBlock), 0, st, int(n), w, c->dh + 512, V + (j + 1) * ld);
+        HIPCHECK(hipMemcpyAsync(c->hpin, c->dh, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipMemcpyAsync(c->hpin + 256, c->dh + 256, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipMemcpyAsync(c->hpin + 512, c->dh + 512, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = c->hpin[i] + c->hpin[256 + i];
+        const double hn = std::sqrt(c->hpin[512]);
+        if (!std::isfinite(hn)) return finish(MGM_E_NONFINITE);
+        H[size_t(j + 1) * m + j] = hn;
+        for (int i = 0; i < j; ++i) {
+          double t = cs[i] * H[size_t(i) * m + j] + sn[i] * H[size_t(i + 1) * m + j];
+          H[size_t(i + 1) * m + j] = -sn[i] * H[size_t(i) * m + j] + cs[i] * H[size_t(i + 1) * m + j];
+          H[size_t(i) * m + j] = t;
+        }
+        double den = std::hypot(H[size_t(j) * m + j], H[size_t(j + 1) * m + j]);
+        if (den == 0.0) return finish(MGM_E_BREAKDOWN);
+        cs[j] = H[size_t(j) * m + j] / den;
+        sn[j] = H[size_t(j + 1) * m + j] / den;
+        H[size_t(j) * m + j] = den;
+        H[size_t(j + 1) * m + j] = 0.0;
+        gv[j + 1] = -sn[j] * gv[j];
+        gv[j] = cs[j] * gv[j];
+        k = j + 1;
+        const double est = std::fabs(gv[j + 1]) / fnorm;
+        info.rel_res_est = est;
+        if (hist && hist_n <= o.maxit) hist[hist_n++] = est;
+        if (est <= tol || info.iters >= o.maxit || hn == 0.0) break;
+      }
+      for (int i = k - 1; i >= 0; --i) {
+        double s = gv[i];
+        for (int t = i + 1; t < k; ++t) s -= H[size_t(i) * m + t] * y[t];
+        y[i] = s / H[size_t(i) * m + i];
+      }
+      HIPCHECK(hipMemcpyAsync(c->dh + 768, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_madd, dim3(g), dim3(kBlock), 0, st, int(n), Z, ld, k, c->dh + 768, x);
+    }
+  } else if (o.krylov == MGM_BICGSTAB) {
+    // vecs layout: f x r w | rhat p v phat | s t shat
+    double* rhat = c->vecs + 4 * ld;
+    double* p = c->vecs + 5 * ld;
+    double* v = c->vecs + 6 * ld;
+    double* phat = c->vecs + 7 * ld;
+    double* s = c->vecs + 8 * ld;
+    double* t = c->vecs + 9 * ld;
+    double* shat = c->vecs + 10 * ld;
+    for (;;) {
+      double rn = true_res();
+      info.rel_res_true = rn / fnorm;
+      if (!std::isfinite(rn)) return finish(MGM_E_NONFINITE);
+      if (rn / fnorm <= tol) return finish(MGM_OK);
+      if (info.iters >= o.maxit) return finish(MGM_NOT_CONVERGED);
+      if (info.iters > 0) info.restarts++;
+      HIPCHECK(hipMemcpyAsync(rhat, r, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+      double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+      bool first = true;
+      while (info.iters < o.maxit) {
+        mdot(c, n, rhat, ld, 1, r, c->dh, st);  // rho = rhat . r
+        to_host(c, c->dh, 1, st);
+        double rho = c->hpin[0];
+        if (rho == 0.0) break;
+        if (first) {
+          HIPCHECK(hipMemcpyAsync(p, r, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+          first = false;
+        } else {
+          double beta = (rho / rho_old) * (alpha / omega);
+          // p = r + beta (p - omega v)
+          hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kBlock), 0, st, int(n), 1.0, p, -omega, v, p);
+          hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kBlock), 0, st, int(n), 1.0, r, beta, p, p);
+        }
+        precond(c, p, phat, nullptr, st);
+        info.iters++;
+        apply_A(c, phat, v, st);
+        mdot(c, n, rhat, ld, 1, v, c->dh, st);
+        to_host(c, c->dh, 1, st);
+        alpha = rho / c->hpin[0];
+        hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kBlock), 0, st, int(n), 1.0, r, -alpha, v, s);
+        mdot(c, n, s, ld, 1, s, c->dh, st);
+        to_host(c, c->dh, 1, st);
+        double sn = std::sqrt(c->hpin[0]) / fnorm;
+        if (!std::isfinite(sn)) return finish(MGM_E_NONFINITE);
+        if (hist && hist_n <= o.maxit) hist[hist_n++] = sn;
+        info.rel_res_est = sn;
+        if (sn <= tol) {
+          hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kBlock), 0, st, int(n), 1.0, x, alpha, phat, x);
+          break;
+        }
+        precond(c, s, shat, nullptr, st);
+        info.iters++;
+        apply_A(c, shat, t, st);
+        mdot(c, n, s, ld, 2, t, c->dh, st);  // [s.t, t.t] (s and t are adjacent)
+        to_host(c, c->dh, 2, st);
+        omega = c->hpin[0] / c->hpin[1];
+        hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kBlock), 0, st, int(n), 1.0, x, alpha, phat, x);
+        hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kBlock), 0, st, int(n), 1.0, x, omega, shat, x);
+        hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kBlock), 0, st, int(n), 1.0, s, -omega, t, r);
+        rho_old = rho;
+        mdot(c, n, r, ld, 1, r, c->dh, st);
+        to_host(c, c->dh, 1, st);
+        double rn2 = std::sqrt(c->hpin[0]) / fnorm;
+        if (hist && hist_n <= o.maxit) hist[hist_n++] = rn2;
+        info.rel_res_est = rn2;
+        if (rn2 <= tol || omega == 0.0) break;
+      }
+    }
+  } else {  // stationary: u <- u + M (f - A u)
+    double* z = c->vecs + 4 * ld;
+    for (;;) {
+      double rn = true_res();
+      info.rel_res_true = rn / fnorm;
+      info.rel_res_est = rn / fnorm;
+      if (hist && info.iters > 0 && hist_n <= o.maxit) hist[hist_n++] = rn / fnorm;
+      if (!std::isfinite(rn)) return finish(MGM_E_NONFINITE);
+      if (rn / fnorm <= tol) return finish(MGM_OK);
+      if (info.iters >= o.maxit) return finish(MGM_NOT_CONVERGED);
+      precond(c, r, z, nullptr, st);
+      info.iters++;
+      hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kBlock), 0, st, int(n), 1.0, x, 1.0, z, x);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- level ops
+template <typename V, typename S, bool SC>
+static void level_op_t(mgm_ctx* c, int op, int j, double* x, const double* b, double* y, bool reverse, hipStream_t st) {
+  using P = Prec<V, S, SC>;
+  DevLevel& d = c->lv[j];
+  const unsigned g = nblk(d.n);
+  hipLaunchKernelGGL((k_gather<double, S>), dim3(g), dim3(kBlock), 0, st, d.n, d.perm, x, P::e(d), nullptr);
+  if (op == MGM_OP_SMOOTH) {
+    hipLaunchKernelGGL((k_gather<double, S>), dim3(g), dim3(kBlock), 0, st, d.n, d.perm, b, P::f(d), nullptr);
+    gs_sweep<V, S, SC>(c, j, reverse, c->p.problem == MGM_POISSON, c->lam, st);
+    hipLaunchKernelGGL((k_scatter<S, double>), dim3(g), dim3(kBlock), 0, st, d.n, d.perm, P::e(d), x, nullptr);
+  } else if (op == MGM_OP_SPMV) {
+    unsigned gg = nblk(int64_t(d.n) * d.G);
+    DISPATCH_G(d.G, hipLaunchKernelGGL((k_spmv<V, S, GG, SC, false>), dim3(gg), dim3(kBlock), 0, st, d.n, d.W, d.rowptr, d.col,
+                                       P::val(d), d.s16, P::e(d), P::res(d), P::b(d), (const S*)nullptr));
+    hipLaunchKernelGGL((k_scatter<S, double>), dim3(g), dim3(kBlock), 0, st, d.n, d.perm, P::res(d), y, nullptr);
+  } else if (op == MGM_OP_RESTRICT_RESIDUAL) {
+    hipLaunchKernelGGL((k_gather<double, S>), dim3(g), dim3(kBlock), 0, st, d.n, d.perm, b, P::f(d), nullptr);
+    residual_restrict<V, S, SC>(c, j, st);
+    DevLevel& nx = c->lv[j + 1];
+    hipLaunchKernelGGL((k_scatter<S, double>), dim3(nblk(nx.n)), dim3(kBlock), 0, st, nx.n, nx.perm, P::f(nx), y, nullptr);
+  } else {
+    DevLevel& nx = c->lv[j + 1];
+    hipLaunchKernelGGL((k_gather<double, S>), dim3(nblk(nx.n)), dim3(kBlock), 0, st, nx.n, nx.perm, y, P::e(nx), nullptr);
+    interp_add<V, S, SC>(c, j, st);
+    hipLaunchKernelGGL((k_scatter<S, double>), dim3(g), dim3(kBlock), 0, st, d.n, d.perm, P::e(d), x, nullptr);
+  }
+  HIPCHECK(hipGetLastError());
+}
+
+static void need_device(const mgm_ctx* c) {
+  if (c->device < 0) throw Error(MGM_E_ARG, "host-only handle (set up with device -1)");
+}
+
+// --------------------------------------------------------------- profiling
+// Algorithmic bytes (values + indices of the touched rows, each vector element
+// once) of the hot-path kernels, per precision.
+static double bval(int prec) { return prec == MGM_FP64 ? 8.0 : (prec == MGM_FP32 ? 4.0 : 2.0); }
+static double bvec(int prec) { return prec == MGM_FP64 ? 8.0 : 4.0; }
+
+static double gs_phase_bytes(const mgm_ctx* c, int j, int col, int prec, bool border) {
+  const DevLevel& d = c->lv[j];
+  const HostLevel& h = c->H.lv[j];
+  int64_t rows = d.cstart[col + 1] - d.cstart[col];
+  (void)h;
+  // nnz of those rows: from the host copy of the permuted values' row lengths
+  int64_t nnz = 0;
+  if (d.W > 0) nnz = rows * d.W;
+  else nnz = d.rowlen_prefix[d.cstart[col + 1]] - d.rowlen_prefix[d.cstart[col]];
+  double b = double(nnz) * (bval(prec) + 4.0) + double(rows) * (bvec(prec) /*dinv*/ + 3.0 * bvec(prec));
+  if (d.W == 0) b += double(rows + 1) * 4.0;
+  if (prec == MGM_FP16) b += 4.0 * double(rows);
+  if (border) b += bvec(prec) * double(rows);
+  return b;
+}
+
+static double residual_bytes(const mgm_ctx* c, int j, int prec) {
+  const DevLevel& d = c->lv[j];
+  double b = double(d.nnz) * (bval(prec) + 4.0) + 3.0 * bvec(prec) * d.n;
+  if (d.W == 0) b += 4.0 * (d.n + 1);
+  if (prec == MGM_FP16) b += 4.0 * d.n;
+  return b;
+}
+
+static double vcycle_bytes(const mgm_ctx* c, int prec) {
+  const int p = int(c->lv.size());
+  const bool bord = c->p.problem == MGM_POISSON;
+  const double bt = prec == MGM_FP64 ? 8.0 : 4.0;  // transfer value bytes
+  double tot = 0.0;
+  for (int j = 0; j + 1 < p; ++j) {
+    const DevLevel& d = c->lv[j];
+    tot += bvec(prec) * d.n;  // zero fill
+    for (int col = 0; col < d.ncol; ++col)
+      tot += (c->p.nu1) * gs_phase_bytes(c, j, col, prec, false) + (c->p.nu2) * gs_phase_bytes(c, j, col, prec, bord);
+    tot += residual_bytes(c, j, prec);
+    const int64_t nnzR = c->H.lv[j].R.nnz();
+    tot += double(nnzR) * (bt + 4.0) + 4.0 * (d.nnext + 1) + bvec(prec) * (d.n + d.nnext);      // restrict
+    tot += double(d.n) * d.m * (bt + 4.0) + bvec(prec) * (d.nnext + 2.0 * d.n);                  // interpolate
+  }
+  tot += 8.0 * double(c->cdim) * c->cdim + bvec(prec) * 2.0 * c->lv[p - 1].n;                     // coarse
+  return tot;
+}
+
+template <typename V, typename S, bool SC>
+static void gs_phase_launch(mgm_ctx* c, int j, int col, hipStream_t st) {
+  using P = Prec<V, S, SC>;
+  DevLevel& d = c->lv[j];
+  int r0 = d.cstart[col], r1 = d.cstart[col + 1];
+  unsigned g = nblk(int64_t(r1 - r0) * d.G);
+  DISPATCH_G(d.G, hipLaunchKernelGGL((k_gs_colour<V, S, GG, SC, false>), dim3(g), dim3(kBlock), 0, st, r0, r1, d.W, d.rowptr,
+                                     d.col, P::val(d), d.s16, P::dinv(d), P::f(d), P::e(d), P::b(d), c->mu));
+}
+
+template <typename V, typename S, bool SC>
+static void residual_launch(mgm_ctx* c, int j, hipStream_t st) {
+  using P = Prec<V, S, SC>;
+  DevLevel& d = c->lv[j];
+  unsigned g = nblk(int64_t(d.n) * d.G);
+  DISPATCH_G(d.G, hipLaunchKernelGGL((k_residual<V, S, GG, SC, false>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr, d.col,
+                                     P::val(d), d.s16, P::f(d), P::e(d), P::res(d), P::b(d), c->partial));
+}
+
+static void time_kernel_impl(mgm_ctx* c, int which, int level, int reps, hipStream_t st, double* ms, double* bytes) {
+  const int prec = c->p.precision;
+  build_precision(c, prec);
+  ensure_ws(c, 1);
+  if (which != MGM_TK_SPMV && which != MGM_TK_VCYCLE && (level < 0 || level + 1 >= int(c->lv.size())))
+    throw Error(MGM_E_ARG, "level out of range");
+  if (reps < 1) throw Error(MGM_E_ARG, "reps must be >= 1");
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  double total = 0.0, tbytes = 0.0;
+  int64_t count = 0;
+  auto timed = [&](const std::function<void()>& launch, double b) {
+    HIPCHECK(hipEventRecord(e0, st));
+    launch();
+    HIPCHECK(hipEventRecord(e1, st));
+    HIPCHECK(hipEventSynchronize(e1));
+    float t = 0.0f;
+    HIPCHECK(hipEventElapsedTime(&t, e0, e1));
+    total += t;
+    tbytes += b;
+    ++count;
+  };
+  DevLevel& d0 = c->lv[0];
+  for (int r = 0; r < reps; ++r) {
+    if (which == MGM_TK_SPMV) {
+      double b = double(d0.nnz) * 12.0 + 16.0 * d0.n + (d0.W == 0 ? 4.0 * (d0.n + 1) : 0.0);
+      timed([&] {
+        unsigned g = nblk(int64_t(d0.n) * d0.G);
+        DISPATCH_G(d0.G, hipLaunchKernelGGL((k_spmv<double, double, GG, false, false>), dim3(g), dim3(kBlock), 0, st, d0.n, d0.W,
+                                            d0.rowptr, d0.col, d0.v64, nullptr, c->vecs, c->vecs + c->ld, d0.b64,
+                                            (const double*)nullptr));
+      }, b);
+    } else if (which == MGM_TK_GS) {
+      DevLevel& d = c->lv[level];
+      for (int col = 0; col < d.ncol; ++col) {
+        if (d.cstart[col + 1] <= d.cstart[col]) continue;
+        timed([&] {
+          if (prec == MGM_FP64) gs_phase_launch<double, double, false>(c, level, col, st);
+          else if (prec == MGM_FP32) gs_phase_launch<float, float, false>(c, level, col, st);
+          else gs_phase_launch<_Float16, float, true>(c, level, col, st);
+        }, gs_phase_bytes(c, level, col, prec, false));
+      }
+    } else if (which == MGM_TK_RESIDUAL) {
+      timed([&] {
+        if (prec == MGM_FP64) residual_launch<double, double, false>(c, level, st);
+        else if (prec == MGM_FP32) residual_launch<float, float, false>(c, level, st);
+        else residual_launch<_Float16, float, true>(c, level, st);
+      }, residual_bytes(c, level, prec));
+    } else if (which == MGM_TK_VCYCLE) {
+      timed([&] { vcycle_core(c, st); }, vcycle_bytes(c, prec));
+    } else {
+      throw Error(MGM_E_ARG, "unknown kernel");
+    }
+  }
+  HIPCHECK(hipGetLastError());
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = total / double(count);
+  *bytes = tbytes / double(count);
+}
+
+static mgm_status guard(const std::function<void()>& f) {
+  try {
+    f();
+    return MGM_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return MGM_E_ALLOC;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return MGM_E_ARG;
+  }
+}
+
+}  // namespace mgm
+
+using namespace mgm;
+
+extern "C" {
+
+void mgm_default_params(mgm_params* p) {
+  if (!p) return;
+  *p = mgm_params{};
+  p->disc = MGM_RBFFD;
+  p->phs_order = 3;
+  p->poly_degree = 3;
+  p->stencil_size = 20;
+  p->gfd_alpha = 4.0;
+  p->problem = MGM_SCREENED;
+  p->mu = 1.0;
+  p->interp_size = 3;
+  p->coarsen_factor = 4;
+  p->n_min = 250;
+  p->n_coarse_max = 0;
+  p->nu1 = 1;
+  p->nu2 = 1;
+  p->pre_smoother = MGM_GS_FWD;
+  p->post_smoother = MGM_GS_FWD;
+  p->precision = MGM_FP64;
+  p->use_graph = 1;
+  p->device_weights = 0;
+}
+
+mgm_status mgm_setup(const double* h_xyz, const double* h_normals, int64_t n, const mgm_params* params, int32_t device,
+                     void* stream, mgm_handle* out) {
+  if (!out || !params || !h_xyz || !h_normals) {
+    g_last_error = "null argument";
+    return MGM_E_ARG;
+  }
+  *out = nullptr;
+  std::unique_ptr<mgm_ctx> c(new mgm_ctx());
+  mgm_status s = guard([&] {
+    c->device = device;
+    c->p = *params;
+    if (device < -1) throw Error(MGM_E_ARG, "device must be >= -1");
+    if (device >= 0) HIPCHECK(hipSetDevice(device));
+    build_hierarchy(h_xyz, h_normals, n, *params, stencil_weights_host, c->H);
+    if (device >= 0) {
+      upload(c.get());
+      HIPCHECK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    }
+  });
+  if (s != MGM_OK) {
+    for (void* ptr : c->allocs) (void)hipFree(ptr);
+    return s;
+  }
+  *out = c.release();
+  return MGM_OK;
+}
+
+mgm_status mgm_set_precision(mgm_handle h, int32_t precision) {
+  if (!h || precision < MGM_FP64 || precision > MGM_FP16) {
+    g_last_error = "bad handle or precision";
+    return MGM_E_ARG;
+  }
+  return guard([&] {
+    need_device(h);
+    HIPCHECK(hipSetDevice(h->device));
+    h->p.precision = precision;
+    build_precision(h, precision);
+  });
+}
+
+mgm_status mgm_vcycle(mgm_handle h, const double* d_r, double* d_z, void* stream) {
+  if (!h || !d_r || !d_z || d_r == d_z) {
+    g_last_error = "bad arguments";
+    return MGM_E_ARG;
+  }
+  return guard([&] {
+    need_device(h);
+    HIPCHECK(hipSetDevice(h->device));
+    precond(h, d_r, d_z, h->lv[0].perm, static_cast<hipStream_t>(stream));
+    HIPCHECK(hipGetLastError());
+  });
+}
+
+mgm_status mgm_apply(mgm_handle h, const double* d_x, double* d_y, void* stream) {
+  if (!h || !d_x || !d_y || d_x == d_y) {
+    g_last_error = "bad arguments";
+    return MGM_E_ARG;
+  }
+  return guard([&] {
+    need_device(h);
+    HIPCHECK(hipSetDevice(h->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    ensure_ws(h, 1);
+    DevLevel& d = h->lv[0];
+    const bool bord = h->p.problem == MGM_POISSON;
+    double* xp = h->vecs + 2 * h->ld;
+    double* yp = h->vecs + 3 * h->ld;
+    hipLaunchKernelGGL((k_gather<double, double>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, d.perm, d_x, xp, nullptr);
+    if (bord) HIPCHECK(hipMemcpyAsync(xp + d.n, d_x + d.n, sizeof(double), hipMemcpyDeviceToDevice, st));
+    apply_A(h, xp, yp, st);
+    hipLaunchKernelGGL((k_scatter<double, double>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, d.perm, yp, d_y, nullptr);
+    if (bord) HIPCHECK(hipMemcpyAsync(d_y + d.n, yp + d.n, sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHECK(hipGetLastError());
+  });
+}
+
+mgm_status mgm_solve(mgm_handle h, const double* d_f, double* d_u, const mgm_solve_opts* opts, mgm_solve_info* info,
+                     double* h_res_hist, void* stream) {
+  if (!h || !d_f || !d_u || !opts || !info || d_f == d_u || opts->restart < 1 || opts->restart > 200 ||
+      opts->maxit < 0 || !(opts->rtol >= 0) || opts->krylov < MGM_FGMRES || opts->krylov > MGM_STATIONARY) {
+    g_last_error = "bad arguments";
+    return MGM_E_ARG;
+  }
+  mgm_status res = MGM_OK;
+  mgm_status s = guard([&] {
+    need_device(h);
+    HIPCHECK(hipSetDevice(h->device));
+    res = solve_impl(h, d_f, d_u, *opts, *info, h_res_hist, static_cast<hipStream_t>(stream));
+  });
+  return s != MGM_OK ? s : res;
+}
+
+mgm_status mgm_level_op(mgm_handle h, int32_t op, int32_t level, double* d_x, const double* d_b, double* d_y, double scalar,
+                        int32_t reverse, void* stream) {
+  if (!h || level < 0 || level + 1 >= int32_t(h->lv.size()) || op < MGM_OP_SMOOTH || op > MGM_OP_INTERP_ADD || !d_x ||
+      ((op == MGM_OP_SMOOTH || op == MGM_OP_RESTRICT_RESIDUAL) && !d_b) || (op != MGM_OP_SMOOTH && !d_y)) {
+    g_last_error = "bad arguments";
+    return MGM_E_ARG;
+  }
+  return guard([&] {
+    need_device(h);
+    HIPCHECK(hipSetDevice(h->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    build_precision(h, h->p.precision);
+    HIPCHECK(hipMemcpyAsync(h->lam, &scalar, sizeof(double), hipMemcpyHostToDevice, st));
+    if (op == MGM_OP_RESTRICT_RESIDUAL && h->p.problem == MGM_POISSON)
+      HIPCHECK(hipMemsetAsync(h->rho + level, 0, sizeof(double), st));
+    if (h->p.precision == MGM_FP64) level_op_t<double, double, false>(h, op, level, d_x, d_b, d_y, reverse != 0, st);
+    else if (h->p.precision == MGM_FP32) level_op_t<float, float, false>(h, op, level, d_x, d_b, d_y, reverse != 0, st);
+    else level_op_t<_Float16, float, true>(h, op, level, d_x, d_b, d_y, reverse != 0, st);
+    HIPCHECK(hipStreamSynchronize(st));
+  });
+}
+
+mgm_status mgm_time_kernel(mgm_handle h, int32_t which, int32_t level, int32_t reps, void* stream, double* ms,
+                           double* bytes) {
+  if (!h || !ms || !bytes) {
+    g_last_error = "bad arguments";
+    return MGM_E_ARG;
+  }
+  return guard([&] {
+    need_device(h);
+    HIPCHECK(hipSetDevice(h->device));
+    time_kernel_impl(h, which, level, reps, static_cast<hipStream_t>(stream), ms, bytes);
+  });
+}
+
+mgm_status mgm_export(mgm_handle h, int32_t what, int32_t level, void* h_buf, int64_t* len) {
+  if (!h || !len) {
+    g_last_error = "bad arguments";
+    return MGM_E_ARG;
+  }
+  return guard([&] {
+    const HostHierarchy& H = h->H;
+    const int p = int(H.lv.size());
+    auto need_level = [&](int maxl) {
+      if (level < 0 || level > maxl) throw Error(MGM_E_ARG, "level out of range");
+    };
+    std::vector<int32_t> vi;
+    std::vector<double> vd;
+    bool isint = true;
+    switch (what) {
+      case MGM_EX_LEVEL_SIZES:
+        for (auto& l : H.lv) vi.push_back(l.n);
+        break;
+      case MGM_EX_STENCILS: vi = H.stencils; break;
+      case MGM_EX_WEIGHTS: vd = H.weights; isint = false; break;
+      case MGM_EX_COARSE_IDX: need_level(p - 2); vi = H.lv[level].coarse_idx; break;
+      case MGM_EX_INTERP_IDX: need_level(p - 2); vi = H.lv[level].pidx; break;
+      case MGM_EX_INTERP_W: need_level(p - 2); vd = H.lv[level].pw; isint = false; break;
+      case MGM_EX_COLOURS: need_level(p - 2); vi = H.lv[level].colour; break;
+      case MGM_EX_L_ROWPTR: need_level(p - 1); vi = H.lv[level].L.ptr; break;
+      case MGM_EX_L_COLS: need_level(p - 1); vi = H.lv[level].L.col; break;
+      case MGM_EX_L_VALS: need_level(p - 1); vd = H.lv[level].L.val; isint = false; break;
+      case MGM_EX_BORDER: need_level(p - 1); vd = H.lv[level].b; isint = false; break;
+      case MGM_EX_NCOLOURS:
+        for (int j = 0; j + 1 < p; ++j) vi.push_back(H.lv[j].ncolours);
+        break;
+      default: throw Error(MGM_E_ARG, "unknown export item");
+    }
+    int64_t cnt = isint ? int64_t(vi.size()) : int64_t(vd.size());
+    if (h_buf) {
+      if (*len < cnt) throw Error(MGM_E_ARG, "export buffer too small");
+      if (isint) std::memcpy(h_buf, vi.data(), cnt * sizeof(int32_t));
+      else std::memcpy(h_buf, vd.data(), cnt * sizeof(double));
+    }
+    *len = cnt;
+  });
+}
+
+void mgm_destroy(mgm_handle h) {
+  if (!h) return;
+  if (h->device >= 0) {
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    for (int k = 0; k < 3; ++k)
+      if (h->graph[k]) (void)hipGraphExecDestroy(h->graph[k]);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
+    for (void* p : h->allocs) (void)hipFree(p);
+    if (h->hpin) (void)hipHostFree(h->hpin);
+  }
+  delete h;
+}
+
+const char* mgm_status_str(mgm_status s) {
+  switch (s) {
+    case MGM_OK: return "ok";
+    case MGM_NOT_CONVERGED: return "not converged";
+    case MGM_E_ARG: return "invalid argument";
+    case MGM_E_ALLOC: return "allocation failed";
+    case MGM_E_HIP: return "HIP error";
+    case MGM_E_STENCIL_SINGULAR: return "singular stencil system";
+    case MGM_E_DUP_POINTS: return "duplicate points";
+    case MGM_E_ZERO_DIAG: return "zero diagonal";
+    case MGM_E_COARSE_SINGULAR: return "singular coarse operator";
+    case MGM_E_BREAKDOWN: return "Krylov breakdown";
+    case MGM_E_NONFINITE: return "non-finite value";
+  }
+  return "unknown status";
+}
+
+const char* mgm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

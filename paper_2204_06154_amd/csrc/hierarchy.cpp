@@ -1,0 +1,377 @@
+// Preprocessing phase of MGM (Alg. 2), host side, FP64.
+//
+// Levels: N_{j+1} = floor(N_j / factor); with N_min > 0 the count is
+// p = floor(log(N_1/N_min)/log 4) + 1 (evaluated as an integer loop, so that
+// N_min <= N_p < 4 N_min), otherwise coarsen while N_j > n_coarse_max.
+// Per level: WSE survivors (Sec. 4.1), interpolation I_{j+1}^j (Sec. 3,
+// eq. rbf_fd_interp: PHS r plus a constant on the m nearest coarse points, a
+// survivor's own row being the exact injection), R_j = P_j^T, Galerkin
+// L_{j+1} = R_j L_j P_j on the structural product pattern (eq. galerkin), the
+// border b_{j+1} = b_j P_j (eq. gco_saddle_point), the smoother colouring and
+// finally the dense inverse of the coarsest (bordered) operator (Sec. 4.3).
+#include "hierarchy.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace mgm {
+
+void validate_params(const mgm_params& p, int64_t n) {
+  auto bad = [](const char* m) { throw Error(MGM_E_ARG, m); };
+  if (n < 16 || n > (int64_t(1) << 30)) bad("number of points out of range");
+  if (p.disc != MGM_RBFFD && p.disc != MGM_GFD) bad("disc");
+  if (p.poly_degree < 0 || p.poly_degree > 6) bad("poly_degree must be 0..6");
+  if (p.disc == MGM_RBFFD && (p.phs_order < 0 || p.phs_order > 4)) bad("phs_order must be 0..4");
+  int L = (p.poly_degree + 1) * (p.poly_degree + 2) / 2;
+  if (p.stencil_size < L || p.stencil_size > 128 || p.stencil_size > n) bad("stencil_size");
+  if (p.disc == MGM_GFD && !(p.gfd_alpha > 0)) bad("gfd_alpha must be > 0");
+  if (p.problem != MGM_SCREENED && p.problem != MGM_POISSON) bad("problem");
+  if (p.problem == MGM_SCREENED && !(p.mu > 0)) bad("mu must be > 0 for the screened problem");
+  if (p.interp_size < 1 || p.interp_size > 16) bad("interp_size");
+  if (p.coarsen_factor < 2) bad("coarsen_factor");
+  if (p.n_min < 0 || p.n_coarse_max < 0 || (p.n_min == 0 && p.n_coarse_max == 0)) bad("n_min / n_coarse_max");
+  if (p.nu1 < 0 || p.nu2 < 0 || p.nu1 > 8 || p.nu2 > 8) bad("nu1/nu2");
+  if (p.precision < MGM_FP64 || p.precision > MGM_FP16) bad("precision");
+}
+
+std::vector<int32_t> level_sizes(int64_t n1, const mgm_params& p) {
+  std::vector<int32_t> s{int32_t(n1)};
+  const int64_t f = p.coarsen_factor;
+  if (p.n_min > 0) {
+    int pcount = 1;
+    int64_t pw = f;
+    while (int64_t(p.n_min) * pw <= n1) {
+      ++pcount;
+      pw *= f;
+    }
+    for (int j = 1; j < pcount; ++j) s.push_back(int32_t(s.back() / f));
+  } else {
+    while (s.back() > p.n_coarse_max) s.push_back(int32_t(s.back() / f));
+  }
+  return s;
+}
+
+Csr transpose(const Csr& A) {
+  Csr T;
+  T.nrows = A.ncols;
+  T.ncols = A.nrows;
+  T.ptr.assign(A.ncols + 1, 0);
+  for (int64_t k = 0; k < A.nnz(); ++k) T.ptr[A.col[k] + 1]++;
+  for (int32_t i = 0; i < A.ncols; ++i) T.ptr[i + 1] += T.ptr[i];
+  T.col.resize(A.nnz());
+  T.val.resize(A.nnz());
+  std::vector<int32_t> fill(T.ptr.begin(), T.ptr.end() - 1);
+  for (int32_t i = 0; i < A.nrows; ++i)
+    for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+      int32_t t = fill[A.col[k]]++;
+      T.col[t] = i;
+      T.val[t] = A.val[k];
+    }
+  return T;  // rows ascending => columns sorted within each row
+}
+
+namespace {
+
+// C = A * B on the structural product pattern, columns sorted per row.
+Csr spgemm(const Csr& A, const Csr& B) {
+  Csr C;
+  C.nrows = A.nrows;
+  C.ncols = B.ncols;
+  std::vector<std::vector<int32_t>> rc(A.nrows);
+  std::vector<std::vector<double>> rv(A.nrows);
+  parallel_for(A.nrows, [&](int64_t b, int64_t e) {
+    std::vector<int32_t> mark(B.ncols, -1);
+    std::vector<double> acc(B.ncols, 0.0);
+    std::vector<int32_t> touched;
+    for (int64_t i = b; i < e; ++i) {
+      touched.clear();
+      for (int32_t ka = A.ptr[i]; ka < A.ptr[i + 1]; ++ka) {
+        int32_t k = A.col[ka];
+        double a = A.val[ka];
+        for (int32_t kb = B.ptr[k]; kb < B.ptr[k + 1]; ++kb) {
+          int32_t j = B.col[kb];
+          if (mark[j] != int32_t(i)) {
+            mark[j] = int32_t(i);
+            acc[j] = 0.0;
+            touched.push_back(j);
+          }
+          acc[j] += a * B.val[kb];
+        }
+      }
+      std::sort(touched.begin(), touched.end());
+      rc[i] = touched;
+      rv[i].resize(touched.size());
+      for (size_t t = 0; t < touched.size(); ++t) rv[i][t] = acc[touched[t]];
+    }
+  });
+  C.ptr.assign(A.nrows + 1, 0);
+  for (int32_t i = 0; i < A.nrows; ++i) C.ptr[i + 1] = C.ptr[i] + int32_t(rc[i].size());
+  C.col.resize(C.ptr.back());
+  C.val.resize(C.ptr.back());
+  for (int32_t i = 0; i < A.nrows; ++i) {
+    std::copy(rc[i].begin(), rc[i].end(), C.col.begin() + C.ptr[i]);
+    std::copy(rv[i].begin(), rv[i].end(), C.val.begin() + C.ptr[i]);
+  }
+  return C;
+}
+
+inline uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+void build_interp(const HostLevel& fine, const std::vector<double>& cxyz, int m, HostLevel& out) {
+  const int64_t n = fine.n;
+  const int64_t nc = int64_t(cxyz.size() / 3);
+  std::vector<double> d2;
+  knn_search(fine.xyz.data(), n, cxyz.data(), nc, m, out.pidx, d2);
+  out.pw.assign(size_t(n) * m, 0.0);
+  out.injected.assign(n, 0);
+  out.m = m;
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    std::vector<double> M(size_t(m + 1) * (m + 1)), rhs(m + 1);
+    std::vector<int> piv(m + 1);
+    for (int64_t i = b; i < e; ++i) {
+      const int32_t* ci = &out.pidx[size_t(i) * m];
+      if (d2[size_t(i) * m] == 0.0) {
+        out.injected[i] = 1;
+        out.pw[size_t(i) * m] = 1.0;
+        continue;
+      }
+      for (int p = 0; p < m; ++p) {
+        for (int q = 0; q < m; ++q) {
+          const double* yp = &cxyz[3 * size_t(ci[p])];
+          const double* yq = &cxyz[3 * size_t(ci[q])];
+          double dx = yq[0] - yp[0], dy = yq[1] - yp[1], dz = yq[2] - yp[2];
+          M[p * (m + 1) + q] = std::sqrt((dx * dx + dy * dy) + dz * dz);
+        }
+        M[p * (m + 1) + m] = 1.0;
+        M[m * (m + 1) + p] = 1.0;
+        rhs[p] = std::sqrt(d2[size_t(i) * m + p]);
+      }
+      M[m * (m + 1) + m] = 0.0;
+      rhs[m] = 1.0;
+      if (!lu_factor(M.data(), m + 1, piv.data()))
+        throw Error(MGM_E_STENCIL_SINGULAR, "interpolation system singular at node " + std::to_string(i));
+      lu_solve(M.data(), m + 1, piv.data(), rhs.data());
+      for (int p = 0; p < m; ++p) out.pw[size_t(i) * m + p] = rhs[p];
+    }
+  });
+  // structural CSR of P: injection rows 1 entry, others m entries sorted by column
+  Csr& P = out.P;
+  P.nrows = int32_t(n);
+  P.ncols = int32_t(nc);
+  P.ptr.assign(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) P.ptr[i + 1] = P.ptr[i] + (out.injected[i] ? 1 : m);
+  P.col.resize(P.ptr.back());
+  P.val.resize(P.ptr.back());
+  for (int64_t i = 0; i < n; ++i) {
+    int cnt = out.injected[i] ? 1 : m;
+    std::vector<std::pair<int32_t, double>> r(cnt);
+    for (int t = 0; t < cnt; ++t) r[t] = {out.pidx[size_t(i) * m + t], out.pw[size_t(i) * m + t]};
+    std::sort(r.begin(), r.end());
+    for (int t = 0; t < cnt; ++t) {
+      P.col[P.ptr[i] + t] = r[t].first;
+      P.val[P.ptr[i] + t] = r[t].second;
+    }
+  }
+  out.R = transpose(P);
+}
+
+}  // namespace
+
+Csr galerkin_product(const Csr& R, const Csr& A, const Csr& P) { return spgemm(R, spgemm(A, P)); }
+
+std::vector<int32_t> colour_graph(const Csr& A, int* ncolours) {
+  const int32_t n = A.nrows;
+  // symmetrised adjacency without the diagonal
+  Csr At = transpose(A);
+  std::vector<int32_t> ptr(n + 1, 0), adj;
+  {
+    std::vector<std::vector<int32_t>> rows(n);
+    parallel_for(n, [&](int64_t b, int64_t e) {
+      for (int64_t i = b; i < e; ++i) {
+        auto& r = rows[i];
+        r.assign(A.col.begin() + A.ptr[i], A.col.begin() + A.ptr[i + 1]);
+        r.insert(r.end(), At.col.begin() + At.ptr[i], At.col.begin() + At.ptr[i + 1]);
+        std::sort(r.begin(), r.end());
+        r.erase(std::unique(r.begin(), r.end()), r.end());
+        r.erase(std::remove(r.begin(), r.end(), int32_t(i)), r.end());
+      }
+    });
+    for (int32_t i = 0; i < n; ++i) ptr[i + 1] = ptr[i] + int32_t(rows[i].size());
+    adj.resize(ptr[n]);
+    for (int32_t i = 0; i < n; ++i) std::copy(rows[i].begin(), rows[i].end(), adj.begin() + ptr[i]);
+  }
+  // priorities: rank by (degree descending, hash ascending, index ascending)
+  std::vector<int32_t> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::vector<uint32_t> hsh(n);
+  for (int32_t i = 0; i < n; ++i) hsh[i] = uint32_t(splitmix64(uint64_t(i)) >> 32);
+  std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    int32_t da = ptr[a + 1] - ptr[a], db = ptr[b + 1] - ptr[b];
+    if (da != db) return da > db;
+    if (hsh[a] != hsh[b]) return hsh[a] < hsh[b];
+    return a < b;
+  });
+  std::vector<int32_t> prio(n);
+  for (int32_t t = 0; t < n; ++t) prio[order[t]] = n - 1 - t;
+  std::vector<int32_t> colour(n, -1);
+  std::vector<char> sel(n, 0);
+  int32_t left = n;
+  int maxc = 0;
+  while (left > 0) {
+    parallel_for(n, [&](int64_t b, int64_t e) {
+      for (int64_t v = b; v < e; ++v) {
+        sel[v] = 0;
+        if (colour[v] >= 0) continue;
+        bool top = true;
+        for (int32_t k = ptr[v]; k < ptr[v + 1]; ++k) {
+          int32_t u = adj[k];
+          if (colour[u] < 0 && prio[u] > prio[v]) {
+            top = false;
+            break;
+          }
+        }
+        sel[v] = top;
+      }
+    });
+    parallel_for(n, [&](int64_t b, int64_t e) {
+      std::vector<char> used;
+      for (int64_t v = b; v < e; ++v) {
+        if (!sel[v]) continue;
+        used.assign(ptr[v + 1] - ptr[v] + 2, 0);
+        for (int32_t k = ptr[v]; k < ptr[v + 1]; ++k) {
+          int32_t c = colour[adj[k]];
+          if (c >= 0 && c < int32_t(used.size())) used[c] = 1;
+        }
+        int c = 0;
+        while (used[c]) ++c;
+        colour[v] = c;  // neighbours selected this round are never adjacent
+      }
+    });
+    for (int32_t v = 0; v < n; ++v)
+      if (sel[v]) {
+        --left;
+        maxc = std::max(maxc, colour[v] + 1);
+      }
+  }
+  *ncolours = maxc;
+  return colour;
+}
+
+void build_hierarchy(const double* xyz, const double* nrm, int64_t n, const mgm_params& p,
+                     const WeightsFn& weights, HostHierarchy& H) {
+  validate_params(p, n);
+  for (int64_t i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(xyz[i]) || !std::isfinite(nrm[i])) throw Error(MGM_E_NONFINITE, "non-finite point or normal");
+  H.params = p;
+  std::vector<int32_t> sizes = level_sizes(n, p);
+  if (sizes.size() < 2 || sizes.back() < 1) throw Error(MGM_E_ARG, "need at least two levels");
+  const int ns = p.stencil_size;
+  H.ns = ns;
+  std::vector<double> d2;
+  knn_search(xyz, n, xyz, n, ns, H.stencils, d2);
+  for (int64_t i = 0; i < n; ++i) {
+    if (ns > 1 && d2[size_t(i) * ns + 1] == 0.0) throw Error(MGM_E_DUP_POINTS, "duplicate points in the point cloud");
+    if (H.stencils[size_t(i) * ns] != i) throw Error(MGM_E_DUP_POINTS, "stencil centre is not first");
+  }
+  weights(xyz, nrm, n, H.stencils.data(), ns, p, H.weights);
+  for (double w : H.weights)
+    if (!std::isfinite(w)) throw Error(MGM_E_NONFINITE, "non-finite stencil weight");
+
+  H.lv.clear();
+  H.lv.emplace_back();
+  HostLevel& l1 = H.lv[0];
+  l1.n = int32_t(n);
+  l1.xyz.assign(xyz, xyz + 3 * n);
+  // L_1 = D (Poisson) or I - mu D (screened), rows sorted by column
+  l1.L.nrows = l1.L.ncols = int32_t(n);
+  l1.L.ptr.resize(n + 1);
+  l1.L.col.resize(size_t(n) * ns);
+  l1.L.val.resize(size_t(n) * ns);
+  for (int64_t i = 0; i <= n; ++i) l1.L.ptr[i] = int32_t(i * ns);
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    std::vector<std::pair<int32_t, double>> r(ns);
+    for (int64_t i = b; i < e; ++i) {
+      for (int t = 0; t < ns; ++t) {
+        double c = H.weights[size_t(i) * ns + t];
+        double v;
+        if (p.problem == MGM_POISSON) v = c;
+        else v = (t == 0) ? 1.0 - p.mu * c : -(p.mu * c);
+        r[t] = {H.stencils[size_t(i) * ns + t], v};
+      }
+      std::sort(r.begin(), r.end());
+      for (int t = 0; t < ns; ++t) {
+        l1.L.col[size_t(i) * ns + t] = r[t].first;
+        l1.L.val[size_t(i) * ns + t] = r[t].second;
+      }
+    }
+  });
+  if (p.problem == MGM_POISSON) l1.b.assign(n, 1.0);
+
+  for (size_t j = 0; j + 1 < sizes.size(); ++j) {
+    HostLevel& f = H.lv[j];
+    f.coarse_idx = wse_eliminate(f.xyz.data(), f.n, p.coarsen_factor);
+    if (int32_t(f.coarse_idx.size()) != sizes[j + 1]) throw Error(MGM_E_ARG, "coarsening size mismatch");
+    HostLevel c;
+    c.n = sizes[j + 1];
+    c.xyz.resize(size_t(c.n) * 3);
+    for (int32_t t = 0; t < c.n; ++t)
+      for (int a = 0; a < 3; ++a) c.xyz[3 * size_t(t) + a] = f.xyz[3 * size_t(f.coarse_idx[t]) + a];
+    build_interp(f, c.xyz, std::min(p.interp_size, int(c.n)), f);
+    c.L = galerkin_product(f.R, f.L, f.P);
+    if (!f.b.empty()) {
+      c.b.assign(c.n, 0.0);
+      for (int32_t i = 0; i < c.n; ++i) {
+        double s = 0.0;
+        for (int32_t k = f.R.ptr[i]; k < f.R.ptr[i + 1]; ++k) s += f.R.val[k] * f.b[f.R.col[k]];
+        c.b[i] = s;
+      }
+    }
+    H.lv.push_back(std::move(c));
+  }
+  // zero diagonals and colours
+  for (size_t j = 0; j < H.lv.size(); ++j) {
+    HostLevel& l = H.lv[j];
+    for (int32_t i = 0; i < l.n; ++i) {
+      double d = 0.0;
+      for (int32_t k = l.L.ptr[i]; k < l.L.ptr[i + 1]; ++k)
+        if (l.L.col[k] == i) d = l.L.val[k];
+      if (d == 0.0 && j + 1 < H.lv.size())
+        throw Error(MGM_E_ZERO_DIAG, "zero diagonal on level " + std::to_string(j) + " row " + std::to_string(i));
+    }
+    if (j + 1 < H.lv.size()) l.colour = colour_graph(l.L, &l.ncolours);
+  }
+  // dense inverse of the coarsest (bordered) operator
+  HostLevel& cl = H.lv.back();
+  const int np = cl.n;
+  const bool bord = p.problem == MGM_POISSON;
+  const int dim = np + (bord ? 1 : 0);
+  std::vector<double> A(size_t(dim) * dim, 0.0);
+  for (int32_t i = 0; i < np; ++i)
+    for (int32_t k = cl.L.ptr[i]; k < cl.L.ptr[i + 1]; ++k) A[size_t(i) * dim + cl.L.col[k]] = cl.L.val[k];
+  if (bord)
+    for (int32_t i = 0; i < np; ++i) {
+      A[size_t(i) * dim + np] = cl.b[i];
+      A[size_t(np) * dim + i] = cl.b[i];
+    }
+  std::vector<int> piv(dim);
+  if (!lu_factor(A.data(), dim, piv.data())) throw Error(MGM_E_COARSE_SINGULAR, "coarsest operator is singular");
+  H.coarse_dim = dim;
+  H.coarse_inv.assign(size_t(dim) * dim, 0.0);
+  parallel_for(dim, [&](int64_t b, int64_t e) {
+    std::vector<double> x(dim);
+    for (int64_t c = b; c < e; ++c) {
+      std::fill(x.begin(), x.end(), 0.0);
+      x[c] = 1.0;
+      lu_solve(A.data(), dim, piv.data(), x.data());
+      for (int r = 0; r < dim; ++r) H.coarse_inv[size_t(r) * dim + c] = x[r];
+    }
+  });
+}
+
+}  // namespace mgm

@@ -1,0 +1,45 @@
+// Host-side multilevel hierarchy built by the preprocessing phase (Alg. 2).
+#pragma once
+
+#include <functional>
+
+#include "host_common.h"
+
+namespace mgm {
+
+struct HostLevel {
+  int32_t n = 0;
+  std::vector<double> xyz;            // n x 3
+  Csr L;                              // L_j, natural numbering, structural pattern
+  std::vector<double> b;              // border b_j (Poisson only)
+  std::vector<int32_t> colour;        // smoother colour per row (all but the coarsest)
+  int ncolours = 0;
+  // transfer to level j+1 (all but the coarsest)
+  std::vector<int32_t> coarse_idx;    // survivors of WSE, ascending level-j index
+  int m = 0;                          // interpolation stencil size
+  std::vector<int32_t> pidx;          // n x m coarse neighbours (level j+1 numbering)
+  std::vector<double> pw;             // n x m weights (injection rows: 1, 0, ...)
+  std::vector<char> injected;         // row is a survivor (injection)
+  Csr P, R;
+};
+
+// Computes the N x ns fine-level stencil weights (host or device backend).
+using WeightsFn = std::function<void(const double* xyz, const double* nrm, int64_t n, const int32_t* sten,
+                                     int ns, const mgm_params& p, std::vector<double>& w)>;
+
+struct HostHierarchy {
+  mgm_params params{};
+  std::vector<HostLevel> lv;
+  int ns = 0;
+  std::vector<int32_t> stencils;      // N_1 x ns, centre first
+  std::vector<double> weights;        // N_1 x ns
+  int coarse_dim = 0;                 // N_p (screened) or N_p + 1 (bordered)
+  std::vector<double> coarse_inv;     // dense row-major inverse of the coarsest system
+};
+
+void validate_params(const mgm_params& p, int64_t n);
+std::vector<int32_t> level_sizes(int64_t n1, const mgm_params& p);
+void build_hierarchy(const double* xyz, const double* nrm, int64_t n, const mgm_params& p,
+                     const WeightsFn& weights, HostHierarchy& H);
+
+}  // namespace mgm

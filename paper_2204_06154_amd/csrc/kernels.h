@@ -1,0 +1,316 @@
+// HIP kernels of the MGM solve phase for gfx950 (CDNA4, wave64).
+//
+// Sparse operators are stored row-major (CSR; the fine level has a fixed row
+// width W = stencil size, so its row pointer is implicit). A group of G
+// consecutive lanes of a wavefront owns one row: lane t reads entries t,
+// t+G, ... so a wavefront reads 64/G consecutive rows as one contiguous
+// stream, and the group's partial sums are combined with cross-lane
+// shuffles. Operator values are stored as V (double, float or _Float16 with
+// one float scale per row) and accumulated in S (double or float).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mgm {
+
+constexpr int kBlock = 256;
+
+template <typename S>
+__device__ __forceinline__ S group_sum(S v, int G) {
+  for (int off = G >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+  return v;
+}
+
+template <typename V>
+__device__ __forceinline__ float to_f(V v) { return float(v); }
+
+// Row operator: sum_k A_ik x_k for the row owned by this lane group.
+template <typename V, typename S, int G, bool SCALED>
+__device__ __forceinline__ S row_dot(int row, int lane, int W, const int32_t* __restrict__ rowptr,
+                                     const int32_t* __restrict__ col, const V* __restrict__ val,
+                                     const float* __restrict__ scale, const S* __restrict__ x) {
+  int beg, end;
+  if (W > 0) {
+    beg = row * W;
+    end = beg + W;
+  } else {
+    beg = rowptr[row];
+    end = rowptr[row + 1];
+  }
+  S acc = S(0);
+#pragma unroll 4
+  for (int k = beg + lane; k < end; k += G) acc += S(val[k]) * x[col[k]];
+  acc = group_sum(acc, G);
+  if (SCALED) acc *= S(scale[row]);
+  return acc;
+}
+
+// One colour phase of multicolour Gauss-Seidel on rows [r0, r1):
+//   u_i += (f_i - sum_k L_ik u_k - b_i lambda) * dinv_i
+// Rows of one colour are not coupled, so every row reads only values of
+// other colours (and its own old value) while it is written.
+template <typename V, typename S, int G, bool SCALED, bool BORDER>
+__global__ __launch_bounds__(kBlock) void k_gs_colour(int r0, int r1, int W, const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ col, const V* __restrict__ val,
+                                                      const float* __restrict__ scale, const S* __restrict__ dinv,
+                                                      const S* __restrict__ f, S* u, const S* __restrict__ b,
+                                                      const double* __restrict__ lam) {
+  const int gid = blockIdx.x * kBlock + threadIdx.x;
+  const int row = r0 + gid / G;
+  const int lane = gid % G;
+  if (row >= r1) return;  // whole lane groups exit together
+  S acc = row_dot<V, S, G, SCALED>(row, lane, W, rowptr, col, val, scale, u);
+  if (lane == 0) {
+    S r = f[row] - acc;
+    if (BORDER) r -= b[row] * S(*lam);
+    u[row] += r * dinv[row];
+  }
+}
+
+// res = f - A u over all rows; with BDOT also per-block partial sums of b.u
+// (written to partial[blockIdx.x], fixed order, deterministic).
+template <typename V, typename S, int G, bool SCALED, bool BDOT>
+__global__ __launch_bounds__(kBlock) void k_residual(int n, int W, const int32_t* __restrict__ rowptr,
+                                                     const int32_t* __restrict__ col, const V* __restrict__ val,
+                                                     const float* __restrict__ scale, const S* __restrict__ f,
+                                                     const S* __restrict__ u, S* __restrict__ res,
+                                                     const S* __restrict__ b, double* __restrict__ partial) {
+  const int gid = blockIdx.x * kBlock + threadIdx.x;
+  const int row = gid / G;
+  const int lane = gid % G;
+  double bu = 0.0;
+  if (row < n) {
+    S acc = row_dot<V, S, G, SCALED>(row, lane, W, rowptr, col, val, scale, u);
+    if (lane == 0) {
+      res[row] = f[row] - acc;
+      if (BDOT) bu = double(b[row]) * double(u[row]);
+    }
+  }
+  if (BDOT) {
+    __shared__ double sh[kBlock];
+    sh[threadIdx.x] = bu;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+  }
+}
+
+// y = A x (+ b * lambda when BORDER), all rows.
+template <typename V, typename S, int G, bool SCALED, bool BORDER>
+__global__ __launch_bounds__(kBlock) void k_spmv(int n, int W, const int32_t* __restrict__ rowptr,
+                                                 const int32_t* __restrict__ col, const V* __restrict__ val,
+                                                 const float* __restrict__ scale, const S* __restrict__ x,
+                                                 S* __restrict__ y, const S* __restrict__ b,
+                                                 const S* __restrict__ lam) {
+  const int gid = blockIdx.x * kBlock + threadIdx.x;
+  const int row = gid / G;
+  const int lane = gid % G;
+  if (row >= n) return;
+  S acc = row_dot<V, S, G, SCALED>(row, lane, W, rowptr, col, val, scale, x);
+  if (lane == 0) {
+    if (BORDER) acc += b[row] * (*lam);
+    y[row] = acc;
+  }
+}
+
+// Restriction rc = R res (CSR, short rows: one lane per row). With RHO,
+// block 0 also forms rho_out = rho_in - sum(partial[0..np)) in fixed order.
+template <typename V, typename S, bool RHO>
+__global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int32_t* __restrict__ rptr,
+                                                     const int32_t* __restrict__ rcol, const V* __restrict__ rval,
+                                                     const S* __restrict__ res, S* __restrict__ rc,
+                                                     const double* __restrict__ partial, int np,
+                                                     const double* __restrict__ rho_in, double* __restrict__ rho_out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < nc) {
+    S acc = S(0);
+    for (int k = rptr[i]; k < rptr[i + 1]; ++k) acc += S(rval[k]) * res[rcol[k]];
+    rc[i] = acc;
+  }
+  if (RHO && blockIdx.x == 0) {
+    __shared__ double sh[kBlock];
+    double s = 0.0;
+    for (int t = threadIdx.x; t < np; t += kBlock) s += partial[t];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) *rho_out = *rho_in - sh[0];
+  }
+}
+
+// Interpolation and correction e += P ec (P: fixed width m, row-major).
+template <typename V, typename S>
+__global__ __launch_bounds__(kBlock) void k_interp_add(int n, int m, const int32_t* __restrict__ pcol,
+                                                       const V* __restrict__ pval, const S* __restrict__ ec,
+                                                       S* __restrict__ e) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  S acc = S(0);
+  for (int t = 0; t < m; ++t) acc += S(pval[i * m + t]) * ec[pcol[i * m + t]];
+  e[i] += acc;
+}
+
+// Coarsest solve by the dense FP64 inverse: x = Ainv [rc; rho]; one
+// wavefront per output row. Bordered: the last row is the multiplier.
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_coarse_gemv(int dim, int np, const double* __restrict__ Ainv,
+                                                        const S* __restrict__ rc, const double* __restrict__ rho,
+                                                        S* __restrict__ ec, double* __restrict__ mu) {
+  const int wave = (blockIdx.x * kBlock + threadIdx.x) / 64;
+  const int lane = threadIdx.x % 64;
+  if (wave >= dim) return;
+  const double* a = Ainv + size_t(wave) * dim;
+  double acc = 0.0;
+  for (int k = lane; k < np; k += 64) acc += a[k] * double(rc[k]);
+  if (dim > np && lane == 0) acc += a[np] * (*rho);
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) {
+    if (wave < np) ec[wave] = S(acc);
+    else *mu = acc;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(int n, T* __restrict__ x, T v) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+// out[pos] = in[perm[pos]] (perm may be null: identity), with conversion.
+// With a bordered tail, the scalar in[n] is copied to *tail_out.
+template <typename Ti, typename To>
+__global__ __launch_bounds__(kBlock) void k_gather(int n, const int32_t* __restrict__ perm, const Ti* __restrict__ in,
+                                                   To* __restrict__ out, double* __restrict__ tail_out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) out[i] = To(in[perm ? perm[i] : i]);
+  if (tail_out && i == 0) *tail_out = double(in[n]);
+}
+
+// out[perm[pos]] = in[pos] with conversion; bordered tail: out[n] = *tail_in.
+template <typename Ti, typename To>
+__global__ __launch_bounds__(kBlock) void k_scatter(int n, const int32_t* __restrict__ perm, const Ti* __restrict__ in,
+                                                    To* __restrict__ out, const double* __restrict__ tail_in) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) out[perm ? perm[i] : i] = To(in[i]);
+  if (tail_in && i == 0) out[n] = To(*tail_in);
+}
+
+// ------------------------------------------------------------------ Krylov
+// Deterministic two-stage reductions: stage 1 writes one partial per block
+// (grid.y selects the vector), stage 2 sums the partials in block order.
+constexpr int kRedBlocks = 512;
+
+// partial[t * nb + blk] = sum over the block's chunk of V[t][i] * w[i]
+__global__ __launch_bounds__(kBlock) void k_mdot_partial(int n, const double* __restrict__ V, int64_t ld,
+                                                         const double* __restrict__ w, double* __restrict__ partial) {
+  const int t = blockIdx.y;
+  const int nb = gridDim.x;
+  const int64_t chunk = (int64_t(n) + nb - 1) / nb;
+  const int64_t b0 = chunk * blockIdx.x;
+  const int64_t b1 = min(int64_t(n), b0 + chunk);
+  const double* v = V + t * ld;
+  double acc = 0.0;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += kBlock) acc += v[i] * w[i];
+  __shared__ double sh[kBlock];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[t * nb + blockIdx.x] = sh[0];
+}
+
+// out[t] = sum_blk partial[t * nb + blk] (+ accumulate into out2[t] if given)
+__global__ __launch_bounds__(kBlock) void k_reduce_partials(int k, int nb, const double* __restrict__ partial,
+                                                            double* __restrict__ out) {
+  const int t = blockIdx.x;
+  if (t >= k) return;
+  __shared__ double sh[kBlock];
+  double acc = 0.0;
+  // fixed assignment of partials to threads and a fixed tree: deterministic
+  for (int i = threadIdx.x; i < nb; i += kBlock) acc += partial[t * nb + i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[t] = sh[0];
+}
+
+// w[i] -= sum_{t<k} V[t][i] * h[t]
+__global__ __launch_bounds__(kBlock) void k_mupdate(int n, const double* __restrict__ V, int64_t ld, int k,
+                                                    const double* __restrict__ h, double* __restrict__ w) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double acc = w[i];
+  for (int t = 0; t < k; ++t) acc -= V[t * ld + i] * h[t];
+  w[i] = acc;
+}
+
+// x[i] += sum_{t<k} Z[t][i] * y[t]
+__global__ __launch_bounds__(kBlock) void k_madd(int n, const double* __restrict__ Z, int64_t ld, int k,
+                                                 const double* __restrict__ y, double* __restrict__ x) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double acc = x[i];
+  for (int t = 0; t < k; ++t) acc += Z[t * ld + i] * y[t];
+  x[i] = acc;
+}
+
+// y = x / sqrt(*nrm2)  (nrm2 = squared norm on device)
+__global__ __launch_bounds__(kBlock) void k_normalise(int n, const double* __restrict__ x, const double* __restrict__ nrm2,
+                                                      double* __restrict__ y) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double s = sqrt(*nrm2);
+  y[i] = s > 0.0 ? x[i] / s : 0.0;
+}
+
+// z = a*x + b*y (a, b host scalars)
+__global__ __launch_bounds__(kBlock) void k_axpby(int n, double a, const double* __restrict__ x, double b,
+                                                  const double* __restrict__ y, double* __restrict__ z) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) z[i] = a * x[i] + b * y[i];
+}
+
+// r = f - r  (in place on r)
+__global__ __launch_bounds__(kBlock) void k_rsub(int n, const double* __restrict__ f, double* __restrict__ r) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) r[i] = f[i] - r[i];
+}
+
+// Bordered operator tail: y[n] = sum(partial) (the constraint row b.u).
+__global__ void k_tail_from_partials(int np, const double* __restrict__ partial, double* __restrict__ y_tail) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int t = 0; t < np; ++t) s += partial[t];
+    *y_tail = s;
+  }
+}
+
+// Per-block partial sums of b.x (bordered operator tail), fixed order.
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_bdot_partial(int n, const S* __restrict__ b, const S* __restrict__ x,
+                                                         double* __restrict__ partial) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  double v = (i < n) ? double(b[i]) * double(x[i]) : 0.0;
+  __shared__ double sh[kBlock];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+}  // namespace mgm

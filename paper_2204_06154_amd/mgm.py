@@ -1,0 +1,222 @@
+"""ctypes binding of libmgm.so (the C ABI declared in include/mgm.h).
+
+Argument marshalling only: every step of setup, V-cycle and solve runs in the
+native library. Device vectors are torch tensors (contiguous float64 on the
+handle's device); streams are torch streams. The binding raises if the
+library has not been built; there is no other code path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgm.so")
+
+RBFFD, GFD = 0, 1
+SCREENED, POISSON = 0, 1
+FP64, FP32, FP16 = 0, 1, 2
+GS_FWD, GS_BWD = 0, 1
+FGMRES, BICGSTAB, STATIONARY = 0, 1, 2
+OP_SMOOTH, OP_SPMV, OP_RESTRICT_RESIDUAL, OP_INTERP_ADD = 0, 1, 2, 3
+EX = dict(level_sizes=0, stencils=1, weights=2, coarse_idx=3, interp_idx=4, interp_w=5, colours=6,
+          l_rowptr=7, l_cols=8, l_vals=9, border=10, ncolours=11)
+EX_FLOAT = {"weights", "interp_w", "l_vals", "border"}
+
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16}
+KRYLOV = {"fgmres": FGMRES, "bicgstab": BICGSTAB, "stationary": STATIONARY}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("disc", ctypes.c_int32), ("phs_order", ctypes.c_int32), ("poly_degree", ctypes.c_int32),
+                ("stencil_size", ctypes.c_int32), ("gfd_alpha", ctypes.c_double), ("problem", ctypes.c_int32),
+                ("mu", ctypes.c_double), ("interp_size", ctypes.c_int32), ("coarsen_factor", ctypes.c_int32),
+                ("n_min", ctypes.c_int32), ("n_coarse_max", ctypes.c_int32), ("nu1", ctypes.c_int32),
+                ("nu2", ctypes.c_int32), ("pre_smoother", ctypes.c_int32), ("post_smoother", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("device_weights", ctypes.c_int32)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("krylov", ctypes.c_int32), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
+                ("rtol", ctypes.c_double), ("use_x0", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("rel_res_est", ctypes.c_double),
+                ("rel_res_true", ctypes.c_double), ("lambda_", ctypes.c_double)]
+
+
+class MgmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"mgm status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+EXPORTED = ["mgm_default_params", "mgm_setup", "mgm_set_precision", "mgm_vcycle", "mgm_apply", "mgm_solve",
+            "mgm_level_op", "mgm_time_kernel", "mgm_export", "mgm_destroy", "mgm_status_str", "mgm_last_error"]
+TK = dict(spmv=0, gs=1, residual=2, vcycle=3)
+
+
+def load():
+    """Load libmgm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} not built; run `python -m paper_2204_06154_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.mgm_default_params.argtypes = [ctypes.POINTER(Params)]
+    lib.mgm_default_params.restype = None
+    lib.mgm_setup.argtypes = [vp, vp, i64, ctypes.POINTER(Params), i32, vp, ctypes.POINTER(vp)]
+    lib.mgm_setup.restype = i32
+    lib.mgm_set_precision.argtypes = [vp, i32]
+    lib.mgm_set_precision.restype = i32
+    lib.mgm_vcycle.argtypes = [vp, vp, vp, vp]
+    lib.mgm_vcycle.restype = i32
+    lib.mgm_apply.argtypes = [vp, vp, vp, vp]
+    lib.mgm_apply.restype = i32
+    lib.mgm_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp, vp]
+    lib.mgm_solve.restype = i32
+    lib.mgm_level_op.argtypes = [vp, i32, i32, vp, vp, vp, dbl, i32, vp]
+    lib.mgm_level_op.restype = i32
+    lib.mgm_time_kernel.argtypes = [vp, i32, i32, i32, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    lib.mgm_time_kernel.restype = i32
+    lib.mgm_export.argtypes = [vp, i32, i32, vp, ctypes.POINTER(i64)]
+    lib.mgm_export.restype = i32
+    lib.mgm_destroy.argtypes = [vp]
+    lib.mgm_destroy.restype = None
+    lib.mgm_status_str.argtypes = [i32]
+    lib.mgm_status_str.restype = ctypes.c_char_p
+    lib.mgm_last_error.argtypes = []
+    lib.mgm_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status < 0:
+        lib = load()
+        raise MgmError(status, f"{lib.mgm_status_str(status).decode()}: {lib.mgm_last_error().decode()}")
+    return status
+
+
+def make_params(d: dict) -> Params:
+    lib = load()
+    p = Params()
+    lib.mgm_default_params(ctypes.byref(p))
+    conv = {"disc": {"rbffd": RBFFD, "gfd": GFD}, "problem": {"screened": SCREENED, "poisson": POISSON},
+            "precision": PRECISIONS, "pre_smoother": {"fwd": GS_FWD, "bwd": GS_BWD},
+            "post_smoother": {"fwd": GS_FWD, "bwd": GS_BWD}}
+    for k, v in d.items():
+        if k in conv and isinstance(v, str):
+            v = conv[k][v]
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+class Mgm:
+    """A hierarchy built by mgm_setup; device=-1 builds a host-only handle (export only)."""
+
+    def __init__(self, xyz: np.ndarray, normals: np.ndarray, params: dict, device: int = 0, stream=None):
+        lib = load()
+        self.lib = lib
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        nrm = np.ascontiguousarray(normals, dtype=np.float64)
+        if xyz.shape != nrm.shape or xyz.ndim != 2 or xyz.shape[1] != 3:
+            raise ValueError("xyz and normals must both be (n, 3)")
+        self.params = make_params(params)
+        self.n = xyz.shape[0]
+        self.device = device
+        self.bordered = self.params.problem == POISSON
+        h = ctypes.c_void_p()
+        st = ctypes.c_void_p(0) if device < 0 else _stream(stream)
+        _check(lib.mgm_setup(xyz.ctypes.data_as(ctypes.c_void_p), nrm.ctypes.data_as(ctypes.c_void_p), self.n,
+                             ctypes.byref(self.params), device, st, ctypes.byref(h)))
+        self.h = h
+
+    @property
+    def vec_len(self):
+        return self.n + (1 if self.bordered else 0)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mgm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_precision(self, prec):
+        _check(self.lib.mgm_set_precision(self.h, PRECISIONS.get(prec, prec)))
+
+    def vcycle(self, r, z=None, stream=None):
+        import torch
+        if z is None:
+            z = torch.empty_like(r)
+        _check(self.lib.mgm_vcycle(self.h, _ptr(r), _ptr(z), _stream(stream)))
+        return z
+
+    def apply(self, x, y=None, stream=None):
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        _check(self.lib.mgm_apply(self.h, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def solve(self, f, u=None, krylov="fgmres", restart=40, maxit=500, rtol=1e-10, x0=False, history=False,
+              stream=None):
+        import torch
+        if u is None:
+            u = torch.zeros_like(f)
+        opts = SolveOpts(KRYLOV.get(krylov, krylov), restart, maxit, rtol, 1 if x0 else 0)
+        info = SolveInfo()
+        hist = np.zeros(maxit + 2) if history else None
+        hp = hist.ctypes.data_as(ctypes.c_void_p) if history else ctypes.c_void_p(0)
+        status = _check(self.lib.mgm_solve(self.h, _ptr(f), _ptr(u), ctypes.byref(opts), ctypes.byref(info), hp,
+                                           _stream(stream)))
+        out = dict(status=status, iters=info.iters, restarts=info.restarts, rel_res_est=info.rel_res_est,
+                   rel_res_true=info.rel_res_true, lam=info.lambda_)
+        if history:
+            out["history"] = hist[:info.iters + 1].copy()
+        return u, out
+
+    def level_op(self, op, level, x, b=None, y=None, scalar=0.0, reverse=False, stream=None):
+        _check(self.lib.mgm_level_op(self.h, op, level, _ptr(x), _ptr(b) if b is not None else None,
+                                     _ptr(y) if y is not None else None, float(scalar), 1 if reverse else 0,
+                                     _stream(stream)))
+
+    def time_kernel(self, which: str, level: int = 0, reps: int = 20, stream=None):
+        """(mean ms per launch, algorithmic bytes per launch) of one hot-path kernel."""
+        ms, nbytes = ctypes.c_double(), ctypes.c_double()
+        _check(self.lib.mgm_time_kernel(self.h, TK[which], level, reps, _stream(stream), ctypes.byref(ms),
+                                        ctypes.byref(nbytes)))
+        return ms.value, nbytes.value
+
+    def export(self, what: str, level: int = 0) -> np.ndarray:
+        n = ctypes.c_int64(0)
+        code = EX[what]
+        _check(self.lib.mgm_export(self.h, code, level, None, ctypes.byref(n)))
+        arr = np.empty(n.value, dtype=np.float64 if what in EX_FLOAT else np.int32)
+        _check(self.lib.mgm_export(self.h, code, level, arr.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
+        return arr

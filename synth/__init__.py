@@ -333,11 +333,17 @@ def torus_workload(n: int = 160_000, config_id: int = 2) -> Workload:
 
 
 def big_sphere_workload(n: int = 1 << 20, lmax: int = 32, config_id: int = 3) -> Workload:
-    """Unit sphere, plain Fibonacci points, screened Poisson (GFD deg 2, k=25, alpha=4)."""
+    """Unit sphere, plain Fibonacci points, screened Poisson (GFD deg 2, k=25).
+
+    alpha = 16: with the stencil-radius scale rho of the paper's GFD weight,
+    alpha = 4 leaves a 25-point degree-2 stencil almost unweighted, its nearest
+    neighbours get weights of the centre's sign and Gauss-Seidel diverges on
+    L_h in every ordering; alpha = 16 keeps the stencil compact.
+    """
     _, rf, _ = rng_streams(config_id)
     x = fibonacci_sphere(n)
     f = sh_rhs(x, lmax, rf)
-    params = dict(disc="gfd", poly_degree=2, stencil_size=25, gfd_alpha=4.0, problem="screened",
+    params = dict(disc="gfd", poly_degree=2, stencil_size=25, gfd_alpha=16.0, problem="screened",
                   mu=1.0, n_min=250, n_coarse_max=0)
     return Workload(f"sphere{n}", x, x.copy(), f, params)
 
