@@ -76,6 +76,7 @@ def main():
     ap.add_argument("--precisions", default="fp64,fp32,fp16")
     ap.add_argument("--cpu-sample", type=int, default=40_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--weights-n", type=int, default=500_000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the MGM solve is not sharded across GPUs in this build "
@@ -134,6 +135,37 @@ def main():
     log(f"GS colour phase ({main_prec}, fine level): {gs_ms * 1e3:.2f} us, {gs_bytes / 1e6:.2f} MB -> {gs_gbs:.0f} GB/s")
     log(f"SpMV (fp64, fine level): {sp_ms * 1e3:.2f} us, {sp_bytes / 1e6:.1f} MB -> {sp_gbs:.0f} GB/s")
 
+    # batched per-node weight solves (500,000 star-surface stencils, n=50, r^3 + degree 3: 60x60 systems)
+    bw = None
+    if args.weights_n > 0:
+        t0 = time.perf_counter()
+        wl4 = synth.star_workload(args.weights_n)
+        sten = mgm.stencils(wl4.xyz, 50)
+        log(f"star surface N={args.weights_n} + stencils in {time.perf_counter() - t0:.1f} s")
+        d_x = torch.tensor(wl4.xyz, device="cuda")
+        d_n = torch.tensor(wl4.normals, device="cuda")
+        d_s = torch.tensor(sten, device="cuda")
+        d_w = torch.empty((args.weights_n, 50), dtype=torch.float64, device="cuda")
+        mgm.batched_weights(d_x, d_n, d_s, 1, 3, d_w)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        ts = []
+        for _ in range(reps):
+            ev0.record()
+            mgm.batched_weights(d_x, d_n, d_s, 1, 3, d_w)
+            ev1.record()
+            ev1.synchronize()
+            ts.append(ev0.elapsed_time(ev1))
+        wms = float(np.median(ts))
+        S = 60
+        flops = (2.0 / 3.0 * S ** 3 + 2.0 * S * S) * args.weights_n
+        bw = {"systems": args.weights_n, "system_size": S, "ms": round(wms, 3),
+              "systems_per_s": round(args.weights_n / (wms * 1e-3)),
+              "TFLOPs_lu_model": round(flops / (wms * 1e-3) / 1e12, 2),
+              "frac_fp64_peak": round(flops / (wms * 1e-3) / 1e12 / 78.6, 4),
+              "note": "FP64 Gauss-Jordan with partial pivoting, one wavefront per system; flops = (2/3)S^3 + 2S^2"}
+        log(f"batched weights: {wms:.2f} ms for {args.weights_n} systems ({bw['TFLOPs_lu_model']} TFLOP/s LU model)")
+
     cpu = None
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
@@ -165,6 +197,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": f"k_gs_colour {main_prec} fine level (one colour phase)",
                      "achieved": round(gs_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gs_gbs / HBM_PEAK_GBS, 4), "traffic": None},
+        "batched_weights": bw,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -172,6 +172,27 @@ enum { MGM_TK_SPMV = 0, MGM_TK_GS = 1, MGM_TK_RESIDUAL = 2, MGM_TK_VCYCLE = 3 };
 mgm_status mgm_time_kernel(mgm_handle h, int32_t which, int32_t level, int32_t reps,
                            void *stream, double *ms, double *bytes);
 
+/* Stencil selection (Sec. 2): the k nearest points of every point of the
+ * cloud, centre first, key (d2, index) with d2 = ((dx*dx)+(dy*dy))+dz*dz in
+ * IEEE double. h_xyz: host n x 3; h_idx: host n x k int32 output.
+ * Errors: MGM_E_ARG (k < 1 or k > n), MGM_E_DUP_POINTS. Host only. */
+mgm_status mgm_stencils(const double *h_xyz, int64_t n, int32_t k, int32_t *h_idx);
+
+/* Batched RBF-FD weights (Sec. 2.1-2.2, eq. rbf_fd_lap): for each of the
+ * n_systems stencils (rows of d_stencils, n_systems x stencil_size int32,
+ * centre first, indices into the n_points rows of d_xyz / d_normals, device
+ * FP64 n_points x 3) solve the PHS r^(2*phs_order+1) + degree-poly_degree
+ * saddle system in the tangent plane of the centre and write the stencil_size
+ * weights of row i to d_weights (device FP64, n_systems x stencil_size).
+ * One wavefront per system, FP64 Gauss-Jordan with partial pivoting; needs
+ * stencil_size + (poly_degree+1)(poly_degree+2)/2 <= 64. Synchronises the
+ * stream once to report MGM_E_STENCIL_SINGULAR (some system had a pivot below
+ * 1e-13 of its largest entry; the other rows are still written). */
+mgm_status mgm_batched_weights(const double *d_xyz, const double *d_normals, int64_t n_points,
+                               const int32_t *d_stencils, int64_t n_systems, int32_t stencil_size,
+                               int32_t phs_order, int32_t poly_degree, double *d_weights,
+                               void *stream);
+
 /* Export of setup results for bit-exact comparison (host buffers).
  * Call with h_buf = NULL to query *len (element count); then with a buffer of
  * at least *len elements. Element types: I32 = int32_t, F64 = double.

@@ -28,6 +28,9 @@
 
 namespace mgm {
 
+void batched_phs_weights_device(const double* d_xyz, const double* d_nrm, const int32_t* d_sten, int64_t nsys, int ns,
+                                int phs_order, int deg, double* d_w, int* d_status, hipStream_t st);
+
 #define HIPCHECK(x)                                                                                     \
   do {                                                                                                  \
     hipError_t e_ = (x);                                                                                \
@@ -423,7 +426,7 @@ static void residual_restrict(mgm_ctx* c, int j, hipStream_t st) {
                      P::val(d), d.s16, P::f(d), P::e(d), P::res(d), P::b(d), c->partial);
              else hipLaunchKernelGGL((k_residual<V, S, GG, SC, false>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr, d.col,
                      P::val(d), d.s16, P::f(d), P::e(d), P::res(d), P::b(d), c->partial));
-  unsigned gr = nblk(nx.n);
+  unsigned gr = nblk(int64_t(nx.n) * kRestrictG);
   if (bord)
     hipLaunchKernelGGL((k_restrict<S, S, true>), dim3(gr), dim3(kBlock), 0, st, nx.n, d.rptr, d.rcol, P::rw(d), P::res(d),
                        P::f(nx), c->partial, int(g), c->rho + j, c->rho + j + 1);
@@ -779,6 +782,46 @@ static void level_op_t(mgm_ctx* c, int op, int j, double* x, const double* b, do
   HIPCHECK(hipGetLastError());
 }
 
+// Stencil weights by the batched device solver (RBF-FD, S <= 64); host FP64
+// path otherwise.
+static WeightsFn device_weights_fn(hipStream_t st) {
+  return [st](const double* xyz, const double* nrm, int64_t n, const int32_t* sten, int ns, const mgm_params& p,
+              std::vector<double>& w) {
+    const int L = (p.poly_degree + 1) * (p.poly_degree + 2) / 2;
+    if (p.disc != MGM_RBFFD || ns + L > 64) {
+      stencil_weights_host(xyz, nrm, n, sten, ns, p, w);
+      return;
+    }
+    double *dx = dalloc<double>(3 * n), *dn = dalloc<double>(3 * n), *dw = dalloc<double>(size_t(n) * ns);
+    int32_t* ds = dalloc<int32_t>(size_t(n) * ns);
+    int* dst = dalloc<int>(1);
+    auto release = [&] {
+      (void)hipFree(dx);
+      (void)hipFree(dn);
+      (void)hipFree(dw);
+      (void)hipFree(ds);
+      (void)hipFree(dst);
+    };
+    try {
+      HIPCHECK(hipMemcpyAsync(dx, xyz, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st));
+      HIPCHECK(hipMemcpyAsync(dn, nrm, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st));
+      HIPCHECK(hipMemcpyAsync(ds, sten, sizeof(int32_t) * n * ns, hipMemcpyHostToDevice, st));
+      HIPCHECK(hipMemsetAsync(dst, 0, sizeof(int), st));
+      batched_phs_weights_device(dx, dn, ds, n, ns, p.phs_order, p.poly_degree, dw, dst, st);
+      w.resize(size_t(n) * ns);
+      int status = 0;
+      HIPCHECK(hipMemcpyAsync(w.data(), dw, sizeof(double) * n * ns, hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipMemcpyAsync(&status, dst, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipStreamSynchronize(st));
+      if (status) throw Error(MGM_E_STENCIL_SINGULAR, "RBF-FD stencil system singular (device solver)");
+    } catch (...) {
+      release();
+      throw;
+    }
+    release();
+  };
+}
+
 static void need_device(const mgm_ctx* c) {
   if (c->device < 0) throw Error(MGM_E_ARG, "host-only handle (set up with device -1)");
 }
@@ -955,7 +998,7 @@ void mgm_default_params(mgm_params* p) {
   p->post_smoother = MGM_GS_FWD;
   p->precision = MGM_FP64;
   p->use_graph = 1;
-  p->device_weights = 0;
+  p->device_weights = 1;
 }
 
 mgm_status mgm_setup(const double* h_xyz, const double* h_normals, int64_t n, const mgm_params* params, int32_t device,
@@ -971,7 +1014,10 @@ mgm_status mgm_setup(const double* h_xyz, const double* h_normals, int64_t n, co
     c->p = *params;
     if (device < -1) throw Error(MGM_E_ARG, "device must be >= -1");
     if (device >= 0) HIPCHECK(hipSetDevice(device));
-    build_hierarchy(h_xyz, h_normals, n, *params, stencil_weights_host, c->H);
+    if (device >= 0 && params->device_weights)
+      build_hierarchy(h_xyz, h_normals, n, *params, device_weights_fn(static_cast<hipStream_t>(stream)), c->H);
+    else
+      build_hierarchy(h_xyz, h_normals, n, *params, stencil_weights_host, c->H);
     if (device >= 0) {
       upload(c.get());
       HIPCHECK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
@@ -1083,6 +1129,54 @@ mgm_status mgm_time_kernel(mgm_handle h, int32_t which, int32_t level, int32_t r
     HIPCHECK(hipSetDevice(h->device));
     time_kernel_impl(h, which, level, reps, static_cast<hipStream_t>(stream), ms, bytes);
   });
+}
+
+mgm_status mgm_stencils(const double* h_xyz, int64_t n, int32_t k, int32_t* h_idx) {
+  if (!h_xyz || !h_idx || n < 1 || k < 1 || k > n) {
+    g_last_error = "bad arguments";
+    return MGM_E_ARG;
+  }
+  return guard([&] {
+    std::vector<int32_t> idx;
+    std::vector<double> d2;
+    knn_search(h_xyz, n, h_xyz, n, k, idx, d2);
+    for (int64_t i = 0; i < n; ++i)
+      if ((k > 1 && d2[size_t(i) * k + 1] == 0.0) || idx[size_t(i) * k] != i)
+        throw Error(MGM_E_DUP_POINTS, "duplicate points in the point cloud");
+    std::memcpy(h_idx, idx.data(), idx.size() * sizeof(int32_t));
+  });
+}
+
+mgm_status mgm_batched_weights(const double* d_xyz, const double* d_normals, int64_t n_points, const int32_t* d_stencils,
+                               int64_t n_systems, int32_t stencil_size, int32_t phs_order, int32_t poly_degree,
+                               double* d_weights, void* stream) {
+  if (!d_xyz || !d_normals || !d_stencils || !d_weights || n_points < 1 || n_systems < 0 || stencil_size < 1 ||
+      stencil_size > n_points) {
+    g_last_error = "bad arguments";
+    return MGM_E_ARG;
+  }
+  mgm_status res = MGM_OK;
+  mgm_status s = guard([&] {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int* dst = dalloc<int>(1);
+    int status = 0;
+    try {
+      HIPCHECK(hipMemsetAsync(dst, 0, sizeof(int), st));
+      batched_phs_weights_device(d_xyz, d_normals, d_stencils, n_systems, stencil_size, phs_order, poly_degree,
+                                 d_weights, dst, st);
+      HIPCHECK(hipMemcpyAsync(&status, dst, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipStreamSynchronize(st));
+    } catch (...) {
+      (void)hipFree(dst);
+      throw;
+    }
+    (void)hipFree(dst);
+    if (status) {
+      g_last_error = "a stencil system is singular";
+      res = MGM_E_STENCIL_SINGULAR;
+    }
+  });
+  return s != MGM_OK ? s : res;
 }
 
 mgm_status mgm_export(mgm_handle h, int32_t what, int32_t level, void* h_buf, int64_t* len) {

@@ -60,12 +60,12 @@ __global__ __launch_bounds__(kBlock) void k_gs_colour(int r0, int r1, int W, con
   const int row = r0 + gid / G;
   const int lane = gid % G;
   if (row >= r1) return;  // whole lane groups exit together
+  // issue the row's own loads before the dependent gather chain
+  S fr = f[row], di = dinv[row], ui = u[row];
+  S bl = S(0);
+  if (BORDER) bl = b[row] * S(*lam);
   S acc = row_dot<V, S, G, SCALED>(row, lane, W, rowptr, col, val, scale, u);
-  if (lane == 0) {
-    S r = f[row] - acc;
-    if (BORDER) r -= b[row] * S(*lam);
-    u[row] += r * dinv[row];
-  }
+  if (lane == 0) u[row] = ui + ((fr - acc) - bl) * di;
 }
 
 // res = f - A u over all rows; with BDOT also per-block partial sums of b.u
@@ -117,19 +117,23 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int n, int W, const int32_t* __
   }
 }
 
-// Restriction rc = R res (CSR, short rows: one lane per row). With RHO,
-// block 0 also forms rho_out = rho_in - sum(partial[0..np)) in fixed order.
+// Restriction rc = R res (CSR, ~12 entries per row: 4 lanes per row). With
+// RHO, block 0 also forms rho_out = rho_in - sum(partial[0..np)) in fixed order.
+constexpr int kRestrictG = 4;
 template <typename V, typename S, bool RHO>
 __global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int32_t* __restrict__ rptr,
                                                      const int32_t* __restrict__ rcol, const V* __restrict__ rval,
                                                      const S* __restrict__ res, S* __restrict__ rc,
                                                      const double* __restrict__ partial, int np,
                                                      const double* __restrict__ rho_in, double* __restrict__ rho_out) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int gid = blockIdx.x * kBlock + threadIdx.x;
+  const int i = gid / kRestrictG;
+  const int lane = gid % kRestrictG;
   if (i < nc) {
     S acc = S(0);
-    for (int k = rptr[i]; k < rptr[i + 1]; ++k) acc += S(rval[k]) * res[rcol[k]];
-    rc[i] = acc;
+    for (int k = rptr[i] + lane; k < rptr[i + 1]; k += kRestrictG) acc += S(rval[k]) * res[rcol[k]];
+    acc = group_sum(acc, kRestrictG);
+    if (lane == 0) rc[i] = acc;
   }
   if (RHO && blockIdx.x == 0) {
     __shared__ double sh[kBlock];

@@ -1,0 +1,203 @@
+// Batched RBF-FD stencil weights of the Laplace-Beltrami operator on the GPU.
+//
+// For every node i: project its stencil onto the tangent plane (Sec. 2.1,
+// eq. tp_pts), scale by the stencil radius, and solve the PHS saddle-point
+// system of eq. rbf_fd_lap,
+//     [A P; P^T 0][c; lambda] = [Lap phi; Lap p],
+// A_jk = |xi_j - xi_k|^(2k+1), P_jq = monomials (total degree, then
+// descending power of x), Lap r^m = m^2 r^(m-2), Lap p(0) = 2 for x^2, y^2.
+//
+// One wavefront per system: lane r keeps row r of the augmented matrix
+// [M | rhs] in registers (S = n + L <= 64 rows). Gauss-Jordan elimination
+// with partial pivoting: at step k the lanes that have not yet been a pivot
+// compete for max |a_rk| (wave-wide argmax, ties to the lower lane), the
+// pivot row is broadcast with v_readlane, and every other row eliminates
+// column k. Afterwards each row holds one diagonal entry and the solution is
+// rhs / diag. The column loops are fully unrolled, so every register index
+// is a compile-time constant (no scratch).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/mgm.h"
+#include "host_common.h"
+
+namespace mgm {
+
+namespace {
+
+constexpr int kWaves = 4;  // wavefronts (systems) per block
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double ipow_d(double x, int e) {
+  double r = 1.0;
+  for (int t = 0; t < e; ++t) r *= x;
+  return r;
+}
+
+// exponents (a, b) of monomial q: by total degree, then descending a
+__device__ __forceinline__ void mono_exp(int q, int& a, int& b) {
+  int d = 0;
+  while ((d + 1) * (d + 2) / 2 <= q) ++d;
+  b = q - d * (d + 1) / 2;
+  a = d - b;
+}
+
+template <int SMAX>
+__global__ __launch_bounds__(64 * kWaves) void k_phs_weights(int64_t nsys, int ns, int L, int m,
+                                                            const double* __restrict__ xyz,
+                                                            const double* __restrict__ nrm,
+                                                            const int32_t* __restrict__ sten,
+                                                            double* __restrict__ w, int* __restrict__ status) {
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int64_t sys = int64_t(blockIdx.x) * kWaves + wv;
+  const bool active = sys < nsys;  // uniform per wavefront
+  const int S = ns + L;
+  __shared__ double xs[kWaves][64][2];
+
+  // tangent frame of the centre (Sec. 2.1) and this lane's projected point
+  double px = 0.0, py = 0.0;
+  if (active) {
+    const int32_t* st = sten + sys * ns;
+    const int ci = st[0];
+    double n0 = nrm[3 * ci], n1 = nrm[3 * ci + 1], n2 = nrm[3 * ci + 2];
+    double nn = sqrt(fma(n0, n0, fma(n1, n1, n2 * n2)));
+    n0 /= nn;
+    n1 /= nn;
+    n2 /= nn;
+    int ax = 0;
+    if (fabs(n1) < fabs(n0)) ax = 1;
+    if (fabs(n2) < fabs(ax == 0 ? n0 : n1)) ax = 2;
+    double nax = ax == 0 ? n0 : (ax == 1 ? n1 : n2);
+    double t1x = (ax == 0 ? 1.0 : 0.0) - nax * n0;
+    double t1y = (ax == 1 ? 1.0 : 0.0) - nax * n1;
+    double t1z = (ax == 2 ? 1.0 : 0.0) - nax * n2;
+    double l1 = sqrt(t1x * t1x + t1y * t1y + t1z * t1z);
+    t1x /= l1;
+    t1y /= l1;
+    t1z /= l1;
+    double t2x = n1 * t1z - n2 * t1y, t2y = n2 * t1x - n0 * t1z, t2z = n0 * t1y - n1 * t1x;
+    if (lane < ns) {
+      const int j = st[lane];
+      double dx = xyz[3 * j] - xyz[3 * ci], dy = xyz[3 * j + 1] - xyz[3 * ci + 1], dz = xyz[3 * j + 2] - xyz[3 * ci + 2];
+      px = t1x * dx + t1y * dy + t1z * dz;
+      py = t2x * dx + t2y * dy + t2z * dz;
+    }
+  }
+  double r = sqrt(px * px + py * py);
+  double s = r;
+  for (int off = 32; off > 0; off >>= 1) s = fmax(s, __shfl_xor(s, off, 64));
+  if (!(s > 0.0)) s = 1.0;
+  px /= s;
+  py /= s;
+  r /= s;
+  xs[wv][lane][0] = px;
+  xs[wv][lane][1] = py;
+  __syncthreads();
+
+  // row `lane` of [M | rhs]; columns S..SMAX-1 are zero padding, rhs in a[SMAX]
+  double a[SMAX + 1];
+  int qa = 0, qb = 0;
+  if (lane >= ns && lane < S) mono_exp(lane - ns, qa, qb);
+#pragma unroll
+  for (int k = 0; k < SMAX; ++k) {
+    double v = 0.0;
+    if (k < S) {
+      const double xk = xs[wv][k][0], yk = xs[wv][k][1];
+      if (lane < ns) {
+        if (k < ns) {
+          double dx = px - xk, dy = py - yk;
+          v = ipow_d(sqrt(dx * dx + dy * dy), m);
+        } else {
+          int ea, eb;
+          mono_exp(k - ns, ea, eb);
+          v = ipow_d(px, ea) * ipow_d(py, eb);
+        }
+      } else if (lane < S && k < ns) {
+        v = ipow_d(xk, qa) * ipow_d(yk, qb);
+      }
+    }
+    a[k] = v;
+  }
+  a[SMAX] = lane < ns ? double(m) * double(m) * ipow_d(r, m - 2)
+                      : ((lane < S && ((qa == 2 && qb == 0) || (qa == 0 && qb == 2))) ? 2.0 : 0.0);
+
+  double amax = 0.0;
+#pragma unroll
+  for (int k = 0; k < SMAX; ++k) amax = fmax(amax, fabs(a[k]));
+  for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+  const double tiny = amax * 1e-13;
+
+  bool used = lane >= S;
+  int kpos = -1;
+  bool singular = false;
+#pragma unroll
+  for (int k = 0; k < SMAX; ++k) {
+    if (k < S) {
+      const double v = a[k];
+      double bv = used ? -1.0 : fabs(v);
+      int bl = lane;
+      for (int off = 32; off > 0; off >>= 1) {
+        double ov = __shfl_xor(bv, off, 64);
+        int ol = __shfl_xor(bl, off, 64);
+        if (ov > bv || (ov == bv && ol < bl)) {
+          bv = ov;
+          bl = ol;
+        }
+      }
+      bl = __builtin_amdgcn_readfirstlane(bl);
+      if (!(bv > tiny)) singular = true;
+      const double piv = readlane_d(v, bl);
+      const double mlt = (lane == bl) ? 0.0 : v / piv;
+#pragma unroll
+      for (int j = k + 1; j <= SMAX; ++j) a[j] = fma(-mlt, readlane_d(a[j], bl), a[j]);
+      if (lane == bl) {
+        used = true;
+        kpos = k;
+      }
+    }
+  }
+  // solution component of this row: rhs / diagonal
+  double diag = 1.0;
+#pragma unroll
+  for (int k = 0; k < SMAX; ++k)
+    if (k == kpos) diag = a[k];
+  if (active) {
+    if (singular) {
+      if (lane == 0) atomicMax(status, 1);
+    } else if (kpos >= 0 && kpos < ns) {
+      w[sys * ns + kpos] = (a[SMAX] / diag) / (s * s);
+    }
+  }
+}
+
+#define HIPOK(x)                                                                                   \
+  do {                                                                                             \
+    hipError_t e_ = (x);                                                                           \
+    if (e_ != hipSuccess) throw Error(MGM_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace
+
+// Device pointers; launches on `st`. Throws on invalid sizes.
+void batched_phs_weights_device(const double* d_xyz, const double* d_nrm, const int32_t* d_sten, int64_t nsys, int ns,
+                                int phs_order, int deg, double* d_w, int* d_status, hipStream_t st) {
+  const int L = (deg + 1) * (deg + 2) / 2;
+  if (ns < 1 || ns + L > 64) throw Error(MGM_E_ARG, "device weights need stencil_size + L <= 64");
+  if (deg < 0 || deg > 6 || phs_order < 0 || phs_order > 4) throw Error(MGM_E_ARG, "phs_order/poly_degree out of range");
+  if (nsys <= 0) return;
+  const int m = 2 * phs_order + 1;
+  const unsigned blocks = unsigned((nsys + kWaves - 1) / kWaves);
+  hipLaunchKernelGGL(k_phs_weights<64>, dim3(blocks), dim3(64 * kWaves), 0, st, nsys, ns, L, m, d_xyz, d_nrm, d_sten,
+                     d_w, d_status);
+  HIPOK(hipGetLastError());
+}
+
+}  // namespace mgm

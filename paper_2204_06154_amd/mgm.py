@@ -57,7 +57,8 @@ class MgmError(RuntimeError):
 _lib = None
 
 EXPORTED = ["mgm_default_params", "mgm_setup", "mgm_set_precision", "mgm_vcycle", "mgm_apply", "mgm_solve",
-            "mgm_level_op", "mgm_time_kernel", "mgm_export", "mgm_destroy", "mgm_status_str", "mgm_last_error"]
+            "mgm_level_op", "mgm_time_kernel", "mgm_stencils", "mgm_batched_weights", "mgm_export", "mgm_destroy",
+            "mgm_status_str", "mgm_last_error"]
 TK = dict(spmv=0, gs=1, residual=2, vcycle=3)
 
 
@@ -86,6 +87,10 @@ def load():
     lib.mgm_level_op.restype = i32
     lib.mgm_time_kernel.argtypes = [vp, i32, i32, i32, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     lib.mgm_time_kernel.restype = i32
+    lib.mgm_stencils.argtypes = [vp, i64, i32, vp]
+    lib.mgm_stencils.restype = i32
+    lib.mgm_batched_weights.argtypes = [vp, vp, i64, vp, i64, i32, i32, i32, vp, vp]
+    lib.mgm_batched_weights.restype = i32
     lib.mgm_export.argtypes = [vp, i32, i32, vp, ctypes.POINTER(i64)]
     lib.mgm_export.restype = i32
     lib.mgm_destroy.argtypes = [vp]
@@ -220,3 +225,23 @@ class Mgm:
         arr = np.empty(n.value, dtype=np.float64 if what in EX_FLOAT else np.int32)
         _check(self.lib.mgm_export(self.h, code, level, arr.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
         return arr
+
+
+def stencils(xyz: np.ndarray, k: int) -> np.ndarray:
+    """The library's kNN stencils (n x k int32, centre first)."""
+    lib = load()
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    out = np.empty((xyz.shape[0], k), dtype=np.int32)
+    _check(lib.mgm_stencils(xyz.ctypes.data_as(ctypes.c_void_p), xyz.shape[0], k, out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def batched_weights(d_xyz, d_normals, d_stencils, phs_order: int, poly_degree: int, d_weights=None, stream=None):
+    """Device batched RBF-FD weights: torch tensors (n x 3 f64, n x 3 f64, m x ns int32) -> (m x ns f64)."""
+    import torch
+    m, ns = d_stencils.shape
+    if d_weights is None:
+        d_weights = torch.empty((m, ns), dtype=torch.float64, device=d_stencils.device)
+    _check(load().mgm_batched_weights(_ptr(d_xyz), _ptr(d_normals), d_xyz.shape[0], _ptr(d_stencils), m, ns,
+                                      phs_order, poly_degree, _ptr(d_weights), _stream(stream)))
+    return d_weights

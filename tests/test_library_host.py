@@ -134,3 +134,10 @@ def test_failure_injection(mutate, status):
     with pytest.raises(mgm.MgmError) as ei:
         mgm.Mgm(x, nrm, p, device=-1)
     assert ei.value.status == status
+
+
+def test_library_stencils_bit_exact():
+    from oracle import knn
+    x = synth.torus_workload(5000).xyz
+    for k in (2, 3, 25, 50):
+        assert np.array_equal(mgm.stencils(x, k), knn.stencils(x, k)), k
