@@ -77,6 +77,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=40_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--weights-n", type=int, default=500_000)
+    ap.add_argument("--gs-block", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the MGM solve is not sharded across GPUs in this build "
@@ -94,7 +95,7 @@ def main():
     wl = synth.torus_workload(args.n)
     log(f"inputs N={args.n} generated in {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
-    m = mgm.Mgm(wl.xyz, wl.normals, wl.params, device=0)
+    m = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, gs_block=args.gs_block), device=0)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     sizes = [int(s) for s in m.export("level_sizes")]

@@ -78,10 +78,15 @@ typedef struct {
   int32_t precision;      /* MGM_FP64 | MGM_FP32 | MGM_FP16 (V-cycle only) */
   int32_t use_graph;      /* 1: replay the V-cycle as a captured HIP graph */
   int32_t device_weights; /* 1: stencil weights by the batched device solver */
+  int32_t gs_block;       /* smoother blocking: 0 = plain multicolour GS; B in 1..256 =
+                             patch-blocked multicolour GS with patches of B
+                             Morton-consecutive points (one workgroup per patch);
+                             levels with rows longer than 96 entries stay plain */
 } mgm_params;
 
 /* Paper defaults (Table 1): RBF-FD, k = l = 3, n = 20, forward GS, nu = 1,
- * m = 3, factor 4, N_min = 250, screened with mu = 1, FP64, graphs on. */
+ * m = 3, factor 4, N_min = 250, screened with mu = 1; FP64 V-cycle, graphs
+ * on, device weights on, gs_block = 256. */
 void mgm_default_params(mgm_params *p);
 
 /* Preprocessing phase (Alg. 2): kNN stencils (Sec. 2), tangent-plane weights
@@ -162,9 +167,10 @@ mgm_status mgm_level_op(mgm_handle h, int32_t op, int32_t level, double *d_x,
  * algorithmic HBM bytes that launch must move in *bytes (values + indices
  * of the rows it touches, each vector element counted once).
  *   MGM_TK_SPMV:     the fine-level FP64 operator y = L_1 x (eq. discrete_system).
- *   MGM_TK_GS:       one multicolour GS colour phase of level `level` in the
- *                    current precision (Sec. 4.3); averaged over the colours
- *                    of one sweep, bytes likewise per phase.
+ *   MGM_TK_GS:       one smoother launch of level `level` in the current
+ *                    precision (Sec. 4.3): a colour phase (plain multicolour)
+ *                    or a patch-colour launch (patch-blocked); averaged over
+ *                    the launches of one sweep, bytes likewise per launch.
  *   MGM_TK_RESIDUAL: residual r - L_j e of level `level`, current precision.
  *   MGM_TK_VCYCLE:   one whole V-cycle (Alg. 3) in the current precision;
  *                    bytes = sum over its kernels. */
@@ -207,12 +213,14 @@ mgm_status mgm_batched_weights(const double *d_xyz, const double *d_normals, int
  *   MGM_EX_L_COLS        I32  CSR column indices (sorted per row)
  *   MGM_EX_L_VALS        F64  CSR values
  *   MGM_EX_BORDER        F64  b_j (Poisson only)
- *   MGM_EX_NCOLOURS      I32  colours per smoothed level      (level ignored) */
+ *   MGM_EX_NCOLOURS      I32  colours per smoothed level      (level ignored)
+ *   MGM_EX_PATCH         I32  smoother patch of each row of level j (empty when
+ *                             the level is not patch-blocked) */
 enum {
   MGM_EX_LEVEL_SIZES = 0, MGM_EX_STENCILS = 1, MGM_EX_WEIGHTS = 2,
   MGM_EX_COARSE_IDX = 3, MGM_EX_INTERP_IDX = 4, MGM_EX_INTERP_W = 5,
   MGM_EX_COLOURS = 6, MGM_EX_L_ROWPTR = 7, MGM_EX_L_COLS = 8,
-  MGM_EX_L_VALS = 9, MGM_EX_BORDER = 10, MGM_EX_NCOLOURS = 11
+  MGM_EX_L_VALS = 9, MGM_EX_BORDER = 10, MGM_EX_NCOLOURS = 11, MGM_EX_PATCH = 12
 };
 mgm_status mgm_export(mgm_handle h, int32_t what, int32_t level, void *h_buf,
                       int64_t *len);

@@ -86,6 +86,82 @@ def colour_level(pat: sp.csr_matrix) -> np.ndarray:
     return jp_colouring(symmetric_graph(pat))
 
 
+# ------------------------------------------------------------------ patches
+def _spread21(v: np.ndarray) -> np.ndarray:
+    """Spread the low 21 bits of v to every third bit (Morton interleave)."""
+    v = v.astype(np.uint64) & np.uint64(0x1FFFFF)
+    v = (v | (v << np.uint64(32))) & np.uint64(0x1F00000000FFFF)
+    v = (v | (v << np.uint64(16))) & np.uint64(0x1F0000FF0000FF)
+    v = (v | (v << np.uint64(8))) & np.uint64(0x100F00F00F00F00F)
+    v = (v | (v << np.uint64(4))) & np.uint64(0x10C30C30C30C30C3)
+    v = (v | (v << np.uint64(2))) & np.uint64(0x1249249249249249)
+    return v
+
+
+def morton_order(xyz: np.ndarray) -> np.ndarray:
+    """Points sorted by (3-D Morton key, index). Coordinates are quantised to
+    21 bits as floor((x - lo) / ext * (2^21 - 1)) on a cube of side ext (the
+    largest bounding-box extent), each operation rounded in IEEE double."""
+    lo = xyz.min(axis=0)
+    ext = float(np.max(xyz.max(axis=0) - lo))
+    if not ext > 0.0:
+        ext = 1.0
+    q = np.minimum(2097151.0, np.floor((xyz - lo) / ext * 2097151.0)).astype(np.uint64)
+    key = _spread21(q[:, 0]) | (_spread21(q[:, 1]) << np.uint64(1)) | (_spread21(q[:, 2]) << np.uint64(2))
+    return np.lexsort((np.arange(len(xyz)), key))
+
+
+def patch_colouring(pat: sp.csr_matrix, xyz: np.ndarray, block: int):
+    """Patch-blocked multicolour ordering.
+
+    Rows are cut into patches of `block` consecutive points of the Morton
+    order; the patch graph (patches coupled by any entry of the symmetrised
+    pattern) is coloured by the rule above, and so is the graph of the
+    couplings inside patches. Rows with equal (patch colour, local colour)
+    never couple, so GS over the composite colour pcolour * C + lcolour
+    (C = number of local colours) is sequential GS in a permutation: one pass
+    over the patch colours, each patch visiting its local colours in turn.
+    Returns (composite colour, patch id per row, patch colour per patch,
+    local colour per row).
+    """
+    G = symmetric_graph(pat)
+    N = G.shape[0]
+    order = morton_order(xyz)
+    patch = np.empty(N, dtype=np.int64)
+    patch[order] = np.arange(N) // block
+    npatch = int(patch.max()) + 1
+    row_of = np.repeat(np.arange(N), np.diff(G.indptr))
+    pi, pj = patch[row_of], patch[G.indices]
+    cross = pi != pj
+    PG = sp.csr_matrix((np.ones(int(cross.sum()), dtype=np.int64), (pi[cross], pj[cross])), shape=(npatch, npatch))
+    PG.sum_duplicates()
+    PG.sort_indices()
+    PG.data[:] = 1
+    pcol = jp_colouring(PG)
+    inner = ~cross
+    GI = sp.csr_matrix((np.ones(int(inner.sum()), dtype=np.int64), (row_of[inner], G.indices[inner])), shape=(N, N))
+    GI.sort_indices()
+    lcol = jp_colouring(GI)
+    C = int(lcol.max()) + 1
+    comp = pcol[patch].astype(np.int64) * C + lcol
+    return comp.astype(np.int64), patch, pcol, lcol
+
+
+def max_row_length(pat: sp.csr_matrix) -> int:
+    return int(np.diff(pat.indptr).max())
+
+
+def smoother_colouring(pat: sp.csr_matrix, xyz: np.ndarray, block: int, max_width: int = 96):
+    """Colouring used by the smoother of one level: patch-blocked when
+    block > 0 and every row has at most max_width entries, else plain."""
+    if block > 0 and max_row_length(pat) <= max_width:
+        comp, patch, pcol, lcol = patch_colouring(pat, xyz, block)
+        # relabel the composite colours densely (empty combinations dropped)
+        used, dense = np.unique(comp, return_inverse=True)
+        return dense.astype(np.int32), dict(patch=patch, pcolour=pcol, lcolour=lcol)
+    return colour_level(pat), None
+
+
 def is_valid_colouring(pat: sp.csr_matrix, colour: np.ndarray) -> bool:
     G = symmetric_graph(pat)
     row_of = np.repeat(np.arange(G.shape[0]), np.diff(G.indptr))

@@ -103,6 +103,19 @@ struct DevLevel {
   // host copies needed to build reduced-precision values lazily
   std::vector<double> hv, hdiag;
   std::vector<int64_t> rowlen_prefix;  // host copy of the permuted row pointer
+  // patch-blocked smoother (see k_gs_patch)
+  bool patched = false;
+  int wmax = 0;                      // register width class of the patch kernel (32/64/96)
+  std::vector<int> pc_start;         // slot range of each patch colour (host)
+  std::vector<int64_t> pc_nnz;       // stored entries (incl. padding) per patch colour (host)
+  std::vector<int32_t> pc_rows;      // rows per patch colour (host)
+  int32_t *pstart = nullptr, *pwidth = nullptr, *pncl = nullptr, *lcol = nullptr, *pcolidx = nullptr;
+  int64_t* poff = nullptr;
+  double* pv64 = nullptr;
+  float* pv32 = nullptr;
+  _Float16* pv16 = nullptr;
+  std::vector<double> hpv;           // host copy of the patch values (FP64)
+  std::vector<int32_t> hprow;        // permuted row of each patch entry (host)
 };
 
 }  // namespace mgm
@@ -192,16 +205,30 @@ static void upload(mgm_ctx* c) {
     }
     std::vector<int32_t> order(h.n);
     std::iota(order.begin(), order.end(), 0);
-    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-      if (h.colour[a] != h.colour[b]) return h.colour[a] < h.colour[b];
-      if (key[a] != key[b]) return key[a] < key[b];
-      return a < b;
-    });
-    for (int t = 0; t < h.n; ++t) iperm[j][order[t]] = t;
     d.ncol = h.ncolours;
-    d.cstart.assign(h.ncolours + 1, 0);
-    for (int i = 0; i < h.n; ++i) d.cstart[h.colour[i] + 1]++;
-    for (int k = 0; k < h.ncolours; ++k) d.cstart[k + 1] += d.cstart[k];
+    if (h.patched) {
+      // rows by (patch colour, patch, local colour, Morton rank): patches contiguous
+      std::vector<int32_t> mrank(h.n);
+      for (int t = 0; t < h.n; ++t) mrank[h.morton[t]] = t;
+      std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        int pa = h.pcolour[h.patch[a]], pb = h.pcolour[h.patch[b]];
+        if (pa != pb) return pa < pb;
+        if (h.patch[a] != h.patch[b]) return h.patch[a] < h.patch[b];
+        if (h.lcolour[a] != h.lcolour[b]) return h.lcolour[a] < h.lcolour[b];
+        return mrank[a] < mrank[b];
+      });
+      d.patched = true;
+    } else {
+      std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        if (h.colour[a] != h.colour[b]) return h.colour[a] < h.colour[b];
+        if (key[a] != key[b]) return key[a] < key[b];
+        return a < b;
+      });
+      d.cstart.assign(h.ncolours + 1, 0);
+      for (int i = 0; i < h.n; ++i) d.cstart[h.colour[i] + 1]++;
+      for (int k = 0; k < h.ncolours; ++k) d.cstart[k + 1] += d.cstart[k];
+    }
+    for (int t = 0; t < h.n; ++t) iperm[j][order[t]] = t;
     d.perm = track(c, dupload(order));
   }
   const bool bord = c->p.problem == MGM_POISSON;
@@ -253,6 +280,82 @@ static void upload(mgm_ctx* c) {
     std::vector<double> dinv(n);
     for (int i = 0; i < n; ++i) dinv[i] = 1.0 / diag[i];
     d.dinv64 = track(c, dupload(dinv));
+    if (d.patched) {
+      // slots = patches in permuted order; ELL (column-major) values per patch
+      std::vector<int32_t> ps, pw_, pn, lc(n), pci;
+      std::vector<int64_t> po;
+      std::vector<double> pv;
+      std::vector<int32_t> prow;
+      int maxw = 0;
+      d.pc_start.assign(1, 0);
+      int prev_pc = -1;
+      for (int pos = 0; pos < n;) {
+        const int i0 = order[pos];
+        const int patch = h.patch[i0];
+        const int pcol = h.pcolour[patch];
+        while (prev_pc < pcol) {
+          if (prev_pc >= 0) d.pc_start.push_back(int(ps.size()));
+          ++prev_pc;
+        }
+        int end = pos;
+        while (end < n && h.patch[order[end]] == patch) ++end;
+        const int nr = end - pos;
+        int w = 0, ncl = 0;
+        for (int t = 0; t < nr; ++t) {
+          w = std::max(w, rp[pos + t + 1] - rp[pos + t]);
+          ncl = std::max(ncl, h.lcolour[order[pos + t]] + 1);
+        }
+        maxw = std::max(maxw, w);
+        w = (w + kPatchG - 1) / kPatchG * kPatchG;  // padded to whole lane chunks
+        ps.push_back(pos);
+        pw_.push_back(w);
+        pn.push_back(ncl);
+        po.push_back(int64_t(pv.size()));
+        const size_t base = pv.size();
+        pv.resize(base + size_t(w) * nr, 0.0);
+        pci.resize(base + size_t(w) * nr);
+        prow.resize(base + size_t(w) * nr);
+        for (int t = 0; t < nr; ++t) {
+          const int r = pos + t;
+          const int len = rp[r + 1] - rp[r];
+          for (int k = 0; k < w; ++k) {
+            const size_t e = base + (size_t(k / kPatchG) * nr + t) * kPatchG + (k % kPatchG);
+            prow[e] = r;
+            if (k < len) {
+              pv[e] = vl[rp[r] + k];
+              pci[e] = cl[rp[r] + k];
+            } else {
+              pci[e] = r;
+            }
+          }
+        }
+        pos = end;
+      }
+      while (prev_pc < h.npcolours) {
+        d.pc_start.push_back(int(ps.size()));
+        ++prev_pc;
+      }
+      d.pc_start.resize(h.npcolours + 1);
+      ps.push_back(n);
+      for (int pos = 0; pos < n; ++pos) lc[pos] = h.lcolour[order[pos]];
+      d.wmax = maxw <= 32 ? 32 : (maxw <= 64 ? 64 : 96);
+      d.pc_nnz.assign(h.npcolours, 0);
+      d.pc_rows.assign(h.npcolours, 0);
+      for (int pc = 0; pc < h.npcolours; ++pc)
+        for (int s = d.pc_start[pc]; s < d.pc_start[pc + 1]; ++s) {
+          d.pc_nnz[pc] += int64_t(rp[ps[s + 1]] - rp[ps[s]]);
+          d.pc_rows[pc] += ps[s + 1] - ps[s];
+        }
+      d.pstart = track(c, dupload(ps));
+      d.pwidth = track(c, dupload(pw_));
+      d.pncl = track(c, dupload(pn));
+      d.poff = track(c, dupload(po));
+      d.lcol = track(c, dupload(lc));
+      d.pcolidx = track(c, dupload(pci));
+      d.pv64 = track(c, dupload(pv));
+      d.hpv = std::move(pv);
+      d.hprow = std::move(prow);
+    }
     d.hv = std::move(vl);
     d.hdiag = std::move(diag);
     // interpolation P_j (rows: this level's positions; cols: next level's positions)
@@ -317,6 +420,10 @@ static void build_precision(mgm_ctx* c, int prec) {
       std::vector<float> di(n);
       for (int i = 0; i < n; ++i) di[i] = float(1.0 / d.hdiag[i]);
       d.dinv32 = track(c, dupload(di));
+      if (d.patched) {
+        std::vector<float> pv(d.hpv.begin(), d.hpv.end());
+        d.pv32 = track(c, dupload(pv));
+      }
     } else {
       std::vector<int32_t> rp(n + 1);
       HIPCHECK(hipMemcpy(rp.data(), d.rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
@@ -343,6 +450,14 @@ static void build_precision(mgm_ctx* c, int prec) {
       }
       d.s16 = track(c, dupload(s));
       d.dinv16 = track(c, dupload(di));
+      if (d.patched) {
+        std::vector<uint16_t> ph(d.hpv.size());
+        for (size_t e = 0; e < ph.size(); ++e) ph[e] = f64_to_f16_bits(d.hpv[e] / double(s[d.hprow[e]]));
+        _Float16* q16 = dalloc<_Float16>(ph.size());
+        track(c, q16);
+        HIPCHECK(hipMemcpy(q16, ph.data(), ph.size() * 2, hipMemcpyHostToDevice));
+        d.pv16 = q16;
+      }
       _Float16* p16 = dalloc<_Float16>(h.size());
       track(c, p16);
       HIPCHECK(hipMemcpy(p16, h.data(), h.size() * 2, hipMemcpyHostToDevice));
@@ -358,6 +473,7 @@ struct Prec;
 template <>
 struct Prec<double, double, false> {
   static const double* val(const DevLevel& d) { return d.v64; }
+  static const double* pval(const DevLevel& d) { return d.pv64; }
   static const double* dinv(const DevLevel& d) { return d.dinv64; }
   static const double* pw(const DevLevel& d) { return d.p64; }
   static const double* rw(const DevLevel& d) { return d.r64; }
@@ -369,6 +485,7 @@ struct Prec<double, double, false> {
 template <>
 struct Prec<float, float, false> {
   static const float* val(const DevLevel& d) { return d.v32; }
+  static const float* pval(const DevLevel& d) { return d.pv32; }
   static const float* dinv(const DevLevel& d) { return d.dinv32; }
   static const float* pw(const DevLevel& d) { return d.p32; }
   static const float* rw(const DevLevel& d) { return d.r32; }
@@ -380,6 +497,7 @@ struct Prec<float, float, false> {
 template <>
 struct Prec<_Float16, float, true> {
   static const _Float16* val(const DevLevel& d) { return d.v16; }
+  static const _Float16* pval(const DevLevel& d) { return d.pv16; }
   static const float* dinv(const DevLevel& d) { return d.dinv16; }
   static const float* pw(const DevLevel& d) { return d.p32; }
   static const float* rw(const DevLevel& d) { return d.r32; }
@@ -398,9 +516,35 @@ struct Prec<_Float16, float, true> {
   }
 
 template <typename V, typename S, bool SC>
+static void gs_patch_launch(mgm_ctx* c, int j, int pc, bool reverse, bool border, const double* lam, hipStream_t st) {
+  using P = Prec<V, S, SC>;
+  DevLevel& d = c->lv[j];
+  const int s0 = d.pc_start[pc], ns = d.pc_start[pc + 1] - s0;
+  if (ns <= 0) return;
+#define GS_PATCH(WM, BD)                                                                                 \
+  hipLaunchKernelGGL((k_gs_patch<V, S, WM / kPatchG, SC, BD>), dim3(ns), dim3(kPatch * kPatchG), 0, st, s0, \
+                     reverse ? 1 : 0, d.pstart, \
+                     d.pwidth, d.poff, d.pncl, d.lcol, P::pval(d), d.pcolidx, d.s16, P::dinv(d), P::f(d), P::e(d),  \
+                     P::b(d), lam)
+  if (d.wmax == 32) {
+    if (border) GS_PATCH(32, true); else GS_PATCH(32, false);
+  } else if (d.wmax == 64) {
+    if (border) GS_PATCH(64, true); else GS_PATCH(64, false);
+  } else {
+    if (border) GS_PATCH(96, true); else GS_PATCH(96, false);
+  }
+#undef GS_PATCH
+}
+
+template <typename V, typename S, bool SC>
 static void gs_sweep(mgm_ctx* c, int j, bool reverse, bool border, const double* lam, hipStream_t st) {
   using P = Prec<V, S, SC>;
   DevLevel& d = c->lv[j];
+  if (d.patched) {
+    const int npc = int(d.pc_start.size()) - 1;
+    for (int t = 0; t < npc; ++t) gs_patch_launch<V, S, SC>(c, j, reverse ? npc - 1 - t : t, reverse, border, lam, st);
+    return;
+  }
   for (int t = 0; t < d.ncol; ++t) {
     int col = reverse ? d.ncol - 1 - t : t;
     int r0 = d.cstart[col], r1 = d.cstart[col + 1];
@@ -848,6 +992,27 @@ static double gs_phase_bytes(const mgm_ctx* c, int j, int col, int prec, bool bo
   return b;
 }
 
+// one patch-colour launch of the patch-blocked smoother
+static double gs_patch_bytes(const mgm_ctx* c, int j, int pc, int prec, bool border) {
+  const DevLevel& d = c->lv[j];
+  const double rows = d.pc_rows[pc];
+  double b = double(d.pc_nnz[pc]) * (bval(prec) + 4.0) + rows * (bvec(prec) + 3.0 * bvec(prec) + 4.0);
+  if (prec == MGM_FP16) b += 4.0 * rows;
+  if (border) b += bvec(prec) * rows;
+  return b;
+}
+
+static double gs_sweep_bytes(const mgm_ctx* c, int j, int prec, bool border) {
+  const DevLevel& d = c->lv[j];
+  double b = 0.0;
+  if (d.patched) {
+    for (int pc = 0; pc + 1 < int(d.pc_start.size()); ++pc) b += gs_patch_bytes(c, j, pc, prec, border);
+  } else {
+    for (int col = 0; col < d.ncol; ++col) b += gs_phase_bytes(c, j, col, prec, border);
+  }
+  return b;
+}
+
 static double residual_bytes(const mgm_ctx* c, int j, int prec) {
   const DevLevel& d = c->lv[j];
   double b = double(d.nnz) * (bval(prec) + 4.0) + 3.0 * bvec(prec) * d.n;
@@ -864,8 +1029,7 @@ static double vcycle_bytes(const mgm_ctx* c, int prec) {
   for (int j = 0; j + 1 < p; ++j) {
     const DevLevel& d = c->lv[j];
     tot += bvec(prec) * d.n;  // zero fill
-    for (int col = 0; col < d.ncol; ++col)
-      tot += (c->p.nu1) * gs_phase_bytes(c, j, col, prec, false) + (c->p.nu2) * gs_phase_bytes(c, j, col, prec, bord);
+    tot += c->p.nu1 * gs_sweep_bytes(c, j, prec, false) + c->p.nu2 * gs_sweep_bytes(c, j, prec, bord);
     tot += residual_bytes(c, j, prec);
     const int64_t nnzR = c->H.lv[j].R.nnz();
     tot += double(nnzR) * (bt + 4.0) + 4.0 * (d.nnext + 1) + bvec(prec) * (d.n + d.nnext);      // restrict
@@ -927,6 +1091,15 @@ static void time_kernel_impl(mgm_ctx* c, int which, int level, int reps, hipStre
                                             d0.rowptr, d0.col, d0.v64, nullptr, c->vecs, c->vecs + c->ld, d0.b64,
                                             (const double*)nullptr));
       }, b);
+    } else if (which == MGM_TK_GS && c->lv[level].patched) {
+      DevLevel& d = c->lv[level];
+      for (int pc = 0; pc + 1 < int(d.pc_start.size()); ++pc) {
+        timed([&] {
+          if (prec == MGM_FP64) gs_patch_launch<double, double, false>(c, level, pc, false, false, c->mu, st);
+          else if (prec == MGM_FP32) gs_patch_launch<float, float, false>(c, level, pc, false, false, c->mu, st);
+          else gs_patch_launch<_Float16, float, true>(c, level, pc, false, false, c->mu, st);
+        }, gs_patch_bytes(c, level, pc, prec, false));
+      }
     } else if (which == MGM_TK_GS) {
       DevLevel& d = c->lv[level];
       for (int col = 0; col < d.ncol; ++col) {
@@ -999,6 +1172,7 @@ void mgm_default_params(mgm_params* p) {
   p->precision = MGM_FP64;
   p->use_graph = 1;
   p->device_weights = 1;
+  p->gs_block = 256;
 }
 
 mgm_status mgm_setup(const double* h_xyz, const double* h_normals, int64_t n, const mgm_params* params, int32_t device,
@@ -1207,6 +1381,7 @@ mgm_status mgm_export(mgm_handle h, int32_t what, int32_t level, void* h_buf, in
       case MGM_EX_L_COLS: need_level(p - 1); vi = H.lv[level].L.col; break;
       case MGM_EX_L_VALS: need_level(p - 1); vd = H.lv[level].L.val; isint = false; break;
       case MGM_EX_BORDER: need_level(p - 1); vd = H.lv[level].b; isint = false; break;
+      case MGM_EX_PATCH: need_level(p - 2); vi = H.lv[level].patch; break;
       case MGM_EX_NCOLOURS:
         for (int j = 0; j + 1 < p; ++j) vi.push_back(H.lv[j].ncolours);
         break;

@@ -33,6 +33,7 @@ void validate_params(const mgm_params& p, int64_t n) {
   if (p.n_min < 0 || p.n_coarse_max < 0 || (p.n_min == 0 && p.n_coarse_max == 0)) bad("n_min / n_coarse_max");
   if (p.nu1 < 0 || p.nu2 < 0 || p.nu1 > 8 || p.nu2 > 8) bad("nu1/nu2");
   if (p.precision < MGM_FP64 || p.precision > MGM_FP16) bad("precision");
+  if (p.gs_block < 0 || p.gs_block > 256) bad("gs_block must be 0..256");
 }
 
 std::vector<int32_t> level_sizes(int64_t n1, const mgm_params& p) {
@@ -185,28 +186,33 @@ void build_interp(const HostLevel& fine, const std::vector<double>& cxyz, int m,
 
 Csr galerkin_product(const Csr& R, const Csr& A, const Csr& P) { return spgemm(R, spgemm(A, P)); }
 
-std::vector<int32_t> colour_graph(const Csr& A, int* ncolours) {
+// Symmetrised adjacency of A without the diagonal (sorted rows).
+static void symmetric_adjacency(const Csr& A, std::vector<int32_t>& ptr, std::vector<int32_t>& adj) {
   const int32_t n = A.nrows;
-  // symmetrised adjacency without the diagonal
   Csr At = transpose(A);
-  std::vector<int32_t> ptr(n + 1, 0), adj;
-  {
-    std::vector<std::vector<int32_t>> rows(n);
-    parallel_for(n, [&](int64_t b, int64_t e) {
-      for (int64_t i = b; i < e; ++i) {
-        auto& r = rows[i];
-        r.assign(A.col.begin() + A.ptr[i], A.col.begin() + A.ptr[i + 1]);
-        r.insert(r.end(), At.col.begin() + At.ptr[i], At.col.begin() + At.ptr[i + 1]);
-        std::sort(r.begin(), r.end());
-        r.erase(std::unique(r.begin(), r.end()), r.end());
-        r.erase(std::remove(r.begin(), r.end(), int32_t(i)), r.end());
-      }
-    });
-    for (int32_t i = 0; i < n; ++i) ptr[i + 1] = ptr[i] + int32_t(rows[i].size());
-    adj.resize(ptr[n]);
-    for (int32_t i = 0; i < n; ++i) std::copy(rows[i].begin(), rows[i].end(), adj.begin() + ptr[i]);
-  }
-  // priorities: rank by (degree descending, hash ascending, index ascending)
+  std::vector<std::vector<int32_t>> rows(n);
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i) {
+      auto& r = rows[i];
+      r.assign(A.col.begin() + A.ptr[i], A.col.begin() + A.ptr[i + 1]);
+      r.insert(r.end(), At.col.begin() + At.ptr[i], At.col.begin() + At.ptr[i + 1]);
+      std::sort(r.begin(), r.end());
+      r.erase(std::unique(r.begin(), r.end()), r.end());
+      r.erase(std::remove(r.begin(), r.end(), int32_t(i)), r.end());
+    }
+  });
+  ptr.assign(n + 1, 0);
+  for (int32_t i = 0; i < n; ++i) ptr[i + 1] = ptr[i] + int32_t(rows[i].size());
+  adj.resize(ptr[n]);
+  for (int32_t i = 0; i < n; ++i) std::copy(rows[i].begin(), rows[i].end(), adj.begin() + ptr[i]);
+}
+
+// Jones-Plassmann colouring with largest-degree-first priorities: rank by
+// (degree descending, splitmix64(i) >> 32 ascending, i ascending); each round,
+// every uncoloured node above all its uncoloured neighbours takes the smallest
+// colour not used by a coloured neighbour.
+static std::vector<int32_t> jp_colour(const std::vector<int32_t>& ptr, const std::vector<int32_t>& adj, int* ncolours) {
+  const int32_t n = int32_t(ptr.size()) - 1;
   std::vector<int32_t> order(n);
   std::iota(order.begin(), order.end(), 0);
   std::vector<uint32_t> hsh(n);
@@ -261,6 +267,98 @@ std::vector<int32_t> colour_graph(const Csr& A, int* ncolours) {
   }
   *ncolours = maxc;
   return colour;
+}
+
+std::vector<int32_t> colour_graph(const Csr& A, int* ncolours) {
+  std::vector<int32_t> ptr, adj;
+  symmetric_adjacency(A, ptr, adj);
+  return jp_colour(ptr, adj, ncolours);
+}
+
+static uint64_t spread21(uint64_t v) {
+  v &= 0x1fffff;
+  v = (v | v << 32) & 0x1f00000000ffffull;
+  v = (v | v << 16) & 0x1f0000ff0000ffull;
+  v = (v | v << 8) & 0x100f00f00f00f00full;
+  v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+  v = (v | v << 2) & 0x1249249249249249ull;
+  return v;
+}
+
+// Points sorted by (3-D Morton key, index); coordinates quantised to 21 bits as
+// floor((x - lo) / ext * (2^21 - 1)), ext the largest bounding-box extent.
+std::vector<int32_t> morton_order(const double* xyz, int32_t n) {
+  double lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) lo[a] = hi[a] = xyz[a];
+  for (int32_t i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], xyz[3 * i + a]);
+      hi[a] = std::max(hi[a], xyz[3 * i + a]);
+    }
+  double ext = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
+  if (!(ext > 0.0)) ext = 1.0;
+  std::vector<uint64_t> key(n);
+  for (int32_t i = 0; i < n; ++i) {
+    uint64_t q[3];
+    for (int a = 0; a < 3; ++a) q[a] = uint64_t(std::min(2097151.0, std::floor((xyz[3 * i + a] - lo[a]) / ext * 2097151.0)));
+    key[i] = spread21(q[0]) | (spread21(q[1]) << 1) | (spread21(q[2]) << 2);
+  }
+  std::vector<int32_t> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b] || (key[a] == key[b] && a < b); });
+  return order;
+}
+
+// Smoother colouring of one level: patch-blocked (block > 0 and every row at
+// most kMaxPatchWidth entries) or plain multicolour.
+void smoother_colouring(HostLevel& l, int block) {
+  int32_t maxw = 0;
+  for (int32_t i = 0; i < l.n; ++i) maxw = std::max(maxw, l.L.ptr[i + 1] - l.L.ptr[i]);
+  std::vector<int32_t> ptr, adj;
+  symmetric_adjacency(l.L, ptr, adj);
+  l.patched = block > 0 && maxw <= kMaxPatchWidth;
+  if (!l.patched) {
+    l.colour = jp_colour(ptr, adj, &l.ncolours);
+    return;
+  }
+  const int32_t n = l.n;
+  l.morton = morton_order(l.xyz.data(), n);
+  l.patch.assign(n, 0);
+  for (int32_t t = 0; t < n; ++t) l.patch[l.morton[t]] = t / block;
+  l.npatch = (n + block - 1) / block;
+  // patch graph and intra-patch graph
+  std::vector<std::vector<int32_t>> pn(l.npatch);
+  std::vector<int32_t> iptr(n + 1, 0), iadj;
+  iadj.reserve(adj.size());
+  for (int32_t i = 0; i < n; ++i) {
+    for (int32_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+      int32_t j = adj[k];
+      if (l.patch[j] != l.patch[i]) pn[l.patch[i]].push_back(l.patch[j]);
+      else iadj.push_back(j);
+    }
+    iptr[i + 1] = int32_t(iadj.size());
+  }
+  std::vector<int32_t> pptr(l.npatch + 1, 0), padj;
+  for (int32_t p = 0; p < l.npatch; ++p) {
+    auto& r = pn[p];
+    std::sort(r.begin(), r.end());
+    r.erase(std::unique(r.begin(), r.end()), r.end());
+    pptr[p + 1] = pptr[p] + int32_t(r.size());
+    padj.insert(padj.end(), r.begin(), r.end());
+  }
+  int npc = 0, nlc = 0;
+  l.pcolour = jp_colour(pptr, padj, &npc);
+  l.lcolour = jp_colour(iptr, iadj, &nlc);
+  l.npcolours = npc;
+  // composite colour pcolour * nlc + lcolour, relabelled densely in order
+  std::vector<int64_t> comp(n), used;
+  for (int32_t i = 0; i < n; ++i) comp[i] = int64_t(l.pcolour[l.patch[i]]) * nlc + l.lcolour[i];
+  used = comp;
+  std::sort(used.begin(), used.end());
+  used.erase(std::unique(used.begin(), used.end()), used.end());
+  l.colour.resize(n);
+  for (int32_t i = 0; i < n; ++i) l.colour[i] = int32_t(std::lower_bound(used.begin(), used.end(), comp[i]) - used.begin());
+  l.ncolours = int(used.size());
 }
 
 void build_hierarchy(const double* xyz, const double* nrm, int64_t n, const mgm_params& p,
@@ -344,7 +442,7 @@ void build_hierarchy(const double* xyz, const double* nrm, int64_t n, const mgm_
       if (d == 0.0 && j + 1 < H.lv.size())
         throw Error(MGM_E_ZERO_DIAG, "zero diagonal on level " + std::to_string(j) + " row " + std::to_string(i));
     }
-    if (j + 1 < H.lv.size()) l.colour = colour_graph(l.L, &l.ncolours);
+    if (j + 1 < H.lv.size()) smoother_colouring(l, p.gs_block);
   }
   // dense inverse of the coarsest (bordered) operator
   HostLevel& cl = H.lv.back();

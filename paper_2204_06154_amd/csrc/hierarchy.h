@@ -14,6 +14,14 @@ struct HostLevel {
   std::vector<double> b;              // border b_j (Poisson only)
   std::vector<int32_t> colour;        // smoother colour per row (all but the coarsest)
   int ncolours = 0;
+  // patch-blocked smoother ordering (see smoother_colouring)
+  bool patched = false;
+  std::vector<int32_t> morton;        // points sorted by Morton key
+  std::vector<int32_t> patch;         // patch of each row
+  std::vector<int32_t> pcolour;       // colour of each patch
+  std::vector<int32_t> lcolour;       // colour of each row inside its patch
+  int32_t npatch = 0;
+  int npcolours = 0;
   // transfer to level j+1 (all but the coarsest)
   std::vector<int32_t> coarse_idx;    // survivors of WSE, ascending level-j index
   int m = 0;                          // interpolation stencil size
@@ -36,6 +44,8 @@ struct HostHierarchy {
   int coarse_dim = 0;                 // N_p (screened) or N_p + 1 (bordered)
   std::vector<double> coarse_inv;     // dense row-major inverse of the coarsest system
 };
+
+constexpr int kMaxPatchWidth = 96;   // rows longer than this disable patch blocking on a level
 
 void validate_params(const mgm_params& p, int64_t n);
 std::vector<int32_t> level_sizes(int64_t n1, const mgm_params& p);

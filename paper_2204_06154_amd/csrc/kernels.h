@@ -68,6 +68,90 @@ __global__ __launch_bounds__(kBlock) void k_gs_colour(int r0, int r1, int W, con
   if (lane == 0) u[row] = ui + ((fr - acc) - bl) * di;
 }
 
+// Patch-blocked Gauss-Seidel: one workgroup sweeps one patch (<= kPatch rows)
+// of the current patch colour, kPatchG consecutive lanes per row. Patches of
+// one colour never couple, so the values outside the patch ("halo") are
+// constant during the launch: the lanes of a row fold its halo entries into
+// the right-hand side once, keep the in-patch entries (value, local column)
+// in registers, and the patch values live in LDS. The local colours are then
+// visited in order (reverse for a backward sweep), one barrier each: rows of
+// one local colour never couple, so this is sequential GS in the order
+// (patch colour, patch, local colour).
+// Operator storage per patch: ELL of width w (a multiple of kPatchG) with
+// entry i*kPatchG + g of local row t at off + (i*nr + t)*kPatchG + g, so the
+// lanes of a workgroup read consecutive addresses; padding entries have value
+// zero and point at the row itself.
+constexpr int kPatch = 256;
+constexpr int kPatchG = 4;
+template <typename V, typename S, int WL, bool SCALED, bool BORDER>
+__global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
+    int slot0, int reverse, const int32_t* __restrict__ pstart, const int32_t* __restrict__ pwidth,
+    const int64_t* __restrict__ poff, const int32_t* __restrict__ pncl, const int32_t* __restrict__ lcol,
+    const V* __restrict__ pval, const int32_t* __restrict__ pcol, const float* __restrict__ scale,
+    const S* __restrict__ dinv, const S* __restrict__ f, S* u, const S* __restrict__ b,
+    const double* __restrict__ lam) {
+  __shared__ S ul[kPatch];
+  const int slot = slot0 + blockIdx.x;
+  const int r0 = pstart[slot];
+  const int nr = pstart[slot + 1] - r0;
+  const int nw = pwidth[slot] / kPatchG;  // entries per lane
+  const int64_t off = poff[slot];
+  const int ncl = pncl[slot];
+  const int t = threadIdx.x / kPatchG;
+  const int g = threadIdx.x % kPatchG;
+  const bool act = t < nr;
+  const int row = r0 + t;
+  S iv[WL];
+  int ic[WL];
+  S rhs = S(0), di = S(0), sc = S(1);
+  int myc = -1;
+  if (act) {
+    if (g == 0) ul[t] = u[row];
+    myc = lcol[row];
+    di = dinv[row];
+    rhs = f[row];
+    if (SCALED) sc = S(scale[row]);
+    if (BORDER) rhs -= b[row] * S(*lam);
+    // branch-free loads: all columns/values first (chunks >= nw clamped and
+    // zeroed), then all gathers, so the whole row is in flight at once
+    int cc[WL];
+#pragma unroll
+    for (int i = 0; i < WL; ++i) {
+      const int ii = i < nw ? i : nw - 1;
+      const int64_t e = off + (int64_t(ii) * nr + t) * kPatchG + g;
+      cc[i] = pcol[e];
+      iv[i] = i < nw ? S(pval[e]) : S(0);
+    }
+    S halo = S(0);
+#pragma unroll
+    for (int i = 0; i < WL; ++i) {
+      const bool in = unsigned(cc[i] - r0) < unsigned(nr);
+      const S uv = u[cc[i]];
+      halo += in ? S(0) : iv[i] * uv;
+      ic[i] = in ? cc[i] - r0 : t;
+      iv[i] = in ? iv[i] : S(0);
+    }
+    halo = group_sum(halo, kPatchG);
+    rhs -= sc * halo;
+  }
+  __syncthreads();
+  for (int step = 0; step < ncl; ++step) {
+    const int c = reverse ? ncl - 1 - step : step;
+    if (myc == c) {  // all lanes of a row agree
+      S a0 = S(0), a1 = S(0);
+#pragma unroll
+      for (int i = 0; i < WL; i += 2) {
+        a0 += iv[i] * ul[ic[i]];
+        a1 += iv[i + 1] * ul[ic[i + 1]];
+      }
+      const S acc = group_sum(a0 + a1, kPatchG);
+      if (g == 0) ul[t] = ul[t] + (rhs - sc * acc) * di;
+    }
+    __syncthreads();
+  }
+  if (act && g == 0) u[row] = ul[t];
+}
+
 // res = f - A u over all rows; with BDOT also per-block partial sums of b.u
 // (written to partial[blockIdx.x], fixed order, deterministic).
 template <typename V, typename S, int G, bool SCALED, bool BDOT>

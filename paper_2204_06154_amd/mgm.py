@@ -22,7 +22,7 @@ GS_FWD, GS_BWD = 0, 1
 FGMRES, BICGSTAB, STATIONARY = 0, 1, 2
 OP_SMOOTH, OP_SPMV, OP_RESTRICT_RESIDUAL, OP_INTERP_ADD = 0, 1, 2, 3
 EX = dict(level_sizes=0, stencils=1, weights=2, coarse_idx=3, interp_idx=4, interp_w=5, colours=6,
-          l_rowptr=7, l_cols=8, l_vals=9, border=10, ncolours=11)
+          l_rowptr=7, l_cols=8, l_vals=9, border=10, ncolours=11, patch=12)
 EX_FLOAT = {"weights", "interp_w", "l_vals", "border"}
 
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16}
@@ -35,7 +35,8 @@ class Params(ctypes.Structure):
                 ("mu", ctypes.c_double), ("interp_size", ctypes.c_int32), ("coarsen_factor", ctypes.c_int32),
                 ("n_min", ctypes.c_int32), ("n_coarse_max", ctypes.c_int32), ("nu1", ctypes.c_int32),
                 ("nu2", ctypes.c_int32), ("pre_smoother", ctypes.c_int32), ("post_smoother", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("device_weights", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("device_weights", ctypes.c_int32),
+                ("gs_block", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):

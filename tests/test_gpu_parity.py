@@ -28,6 +28,8 @@ CASES = {
     "torus8000": (lambda: synth.torus_workload(8000), {"n_min": 250}),
     # GFD deg 2, k=25 on a ragged-size plain Fibonacci sphere (config-3 family)
     "gfd9001": (lambda: synth.big_sphere_workload(9001), {"n_min": 150}),
+    # plain multicolour GS (no patch blocking), bordered Poisson
+    "torus6000plain": (lambda: synth.torus_workload(6000), {"n_min": 300, "gs_block": 0}),
 }
 
 

@@ -265,11 +265,60 @@ def _jp_sequential(G):
 def test_colouring_matches_plain_loops_and_is_valid():
     wl = synth.sphere_workload(1500)
     wl.params["n_coarse_max"] = 100
+    wl.params["gs_block"] = 0
     H = hierarchy.build(wl.xyz, wl.normals, wl.params)
     for lv in H.levels[:-1]:
         assert colouring.is_valid_colouring(lv.pat, lv.colour)
         G = colouring.symmetric_graph(lv.pat)
         assert np.array_equal(lv.colour, _jp_sequential(G))
+
+
+def _morton_bits(q):
+    """Interleave three 21-bit integers bit by bit (x in bit 0, y in bit 1, z in bit 2)."""
+    key = 0
+    for bit in range(21):
+        for a in range(3):
+            key |= ((int(q[a]) >> bit) & 1) << (3 * bit + a)
+    return key
+
+
+def test_patch_colouring_pins():
+    wl = synth.sphere_workload(3000)
+    wl.params["n_coarse_max"] = 150
+    wl.params["gs_block"] = 64
+    H = hierarchy.build(wl.xyz, wl.normals, wl.params)
+    for lv in H.levels[:-1]:
+        assert lv.patches is not None
+        # composite colours are a valid colouring (rows of one colour never couple)
+        assert colouring.is_valid_colouring(lv.pat, lv.colour)
+        # patches are consecutive chunks of the Morton order (key by plain bit loops)
+        x = lv.xyz
+        lo = x.min(axis=0)
+        ext = float(np.max(x.max(axis=0) - lo))
+        keys = []
+        for i in range(len(x)):
+            q = [min(2097151, int(np.floor((x[i, a] - lo[a]) / ext * 2097151.0))) for a in range(3)]
+            keys.append((_morton_bits(q), i))
+        order = [i for _, i in sorted(keys)]
+        patch = np.empty(len(x), dtype=np.int64)
+        patch[order] = np.arange(len(x)) // 64
+        assert np.array_equal(patch, lv.patches["patch"])
+        # patch colours and local colours follow the Jones-Plassmann rule
+        G = colouring.symmetric_graph(lv.pat)
+        rows = np.repeat(np.arange(G.shape[0]), np.diff(G.indptr))
+        cross = patch[rows] != patch[G.indices]
+        npatch = patch.max() + 1
+        PG = sp.csr_matrix((np.ones(cross.sum()), (patch[rows][cross], patch[G.indices][cross])),
+                           shape=(npatch, npatch))
+        PG.sum_duplicates()
+        PG.sort_indices()
+        assert np.array_equal(lv.patches["pcolour"], _jp_sequential(PG))
+        GI = sp.csr_matrix((np.ones((~cross).sum()), (rows[~cross], G.indices[~cross])), shape=G.shape)
+        GI.sort_indices()
+        assert np.array_equal(lv.patches["lcolour"], _jp_sequential(GI))
+        # the GS order is (patch colour, local colour): check the relabelling keeps it
+        comp = lv.patches["pcolour"][patch] * (lv.patches["lcolour"].max() + 1) + lv.patches["lcolour"]
+        assert np.all(np.diff(comp[np.argsort(lv.colour, kind="stable")]) >= 0)
 
 
 def test_priorities_largest_degree_first():
