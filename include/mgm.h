@@ -161,6 +161,59 @@ mgm_status mgm_level_op(mgm_handle h, int32_t op, int32_t level, double *d_x,
                         const double *d_b, double *d_y, double scalar,
                         int32_t reverse, void *stream);
 
+/* Learned per-node Chebyshev smoother for the fine level (an extension; the
+ * paper smooths with Gauss-Seidel, Sec. 4.3). Screened problems only.
+ * Smoother: s Richardson steps e <- e + omega_{q,i} D^-1 (f - L e), with
+ * omega_{q,i} = omega_q (1 + 0.5 tanh(o_{q,i})), omega_q = 1/theta_q the
+ * reciprocal Chebyshev roots on [lam/4, 1.1 lam] (lam: 20-step power
+ * estimate of rho(D^-1 L)), o = MLP(features) with 3n -> 64 -> 64 -> s ReLU
+ * layers in FP32; features of node i: its stencil's tangent-plane offsets
+ * (Sec. 2.1) over the stencil radius and its weights (Sec. 2.2-2.3) over
+ * |c_ii|. Training snapshots: fine-level errors right after the coarse-grid
+ * correction of MGM iterations (Gauss-Seidel V-cycle, FP64) on L e = 0;
+ * loss mean_t |L S e_t|^2 / |L e_t|^2; adjoint-smoother backward; Adam. */
+typedef struct {
+  int32_t  steps;           /* Adam steps (0: prepare snapshots/estimate only) */
+  double   lr;              /* Adam learning rate, e.g. 1e-3 */
+  int32_t  s;               /* Richardson steps per smoothing sweep, 1..8 */
+  int32_t  n_starts;        /* random starts (rows of d_starts) */
+  int32_t  iters_per_start; /* MGM iterations per start; one snapshot each */
+  uint64_t seed;            /* counter-based weight initialisation */
+  int32_t  init;            /* 1: (re)initialise the MLP from seed */
+  int32_t  activate;        /* 0: keep GS; 1: use the learned smoother when its
+                               stationary convergence factor beats GS (measured
+                               over 6 iterations from the first start); 2: always */
+} mgm_train_opts;
+
+typedef struct {
+  double  lam;                    /* spectral estimate of D^-1 L */
+  double  loss_first, loss_last;  /* training loss before / after */
+  double  rate_gs, rate_learned;  /* measured convergence factors (activate == 1) */
+  int32_t active;                 /* 1 if the V-cycle now uses the learned smoother */
+} mgm_train_info;
+
+/* Prepare and/or train the learned smoother.
+ *   d_starts: device FP64, n_starts x n random start errors (caller order);
+ *   h_loss_hist: nullable host array of steps+1 losses (entry k: before the
+ *   (k+1)-th Adam step; the last: after training).
+ * Errors: MGM_E_ARG (Poisson problem, bad options, layer too wide: stencil
+ * size above 31). Synchronises the stream. */
+mgm_status mgm_train_smoother(mgm_handle h, const mgm_train_opts *opts, const double *d_starts,
+                              mgm_train_info *info, double *h_loss_hist, void *stream);
+
+/* Get (set = 0) or set (set = 1) the MLP parameters, FP32 row-major with each
+ * layer's bias as its last row: W1 (3n+1) x 64 | W2 65 x 64 | W3 65 x s.
+ * h_params = NULL queries *len. Setting resets the Adam state and recomputes
+ * the step weights. */
+mgm_status mgm_smoother_params(mgm_handle h, int32_t set, float *h_params, int64_t *len);
+
+/* Loss and its gradient (same layout as the parameters, host FP32) at the
+ * current parameters on the current snapshots, without an update. */
+mgm_status mgm_smoother_grad(mgm_handle h, float *h_grad, double *loss, void *stream);
+
+/* Select the fine-level smoother: 0 = Gauss-Seidel, 1 = learned (trained). */
+mgm_status mgm_set_smoother(mgm_handle h, int32_t learned);
+
 /* Profiling of one hot-path kernel: `reps` timed repetitions on the handle's
  * internal buffers (contents arbitrary), each bracketed by HIP events on
  * `stream`; returns the mean device time of one launch in *ms and the
@@ -215,12 +268,14 @@ mgm_status mgm_batched_weights(const double *d_xyz, const double *d_normals, int
  *   MGM_EX_BORDER        F64  b_j (Poisson only)
  *   MGM_EX_NCOLOURS      I32  colours per smoothed level      (level ignored)
  *   MGM_EX_PATCH         I32  smoother patch of each row of level j (empty when
- *                             the level is not patch-blocked) */
+ *                             the level is not patch-blocked)
+ *   MGM_EX_OMEGA         F64  N_1 x s learned step weights (caller order) */
 enum {
   MGM_EX_LEVEL_SIZES = 0, MGM_EX_STENCILS = 1, MGM_EX_WEIGHTS = 2,
   MGM_EX_COARSE_IDX = 3, MGM_EX_INTERP_IDX = 4, MGM_EX_INTERP_W = 5,
   MGM_EX_COLOURS = 6, MGM_EX_L_ROWPTR = 7, MGM_EX_L_COLS = 8,
-  MGM_EX_L_VALS = 9, MGM_EX_BORDER = 10, MGM_EX_NCOLOURS = 11, MGM_EX_PATCH = 12
+  MGM_EX_L_VALS = 9, MGM_EX_BORDER = 10, MGM_EX_NCOLOURS = 11, MGM_EX_PATCH = 12,
+  MGM_EX_OMEGA = 13
 };
 mgm_status mgm_export(mgm_handle h, int32_t what, int32_t level, void *h_buf,
                       int64_t *len);

@@ -53,6 +53,7 @@ class Hierarchy:
     weights: np.ndarray
     coarse_lu: tuple
     params: dict
+    normals: np.ndarray | None = None
 
 
 DEFAULTS = dict(disc="rbffd", phs_order=1, poly_degree=2, stencil_size=30, gfd_alpha=4.0,
@@ -109,4 +110,5 @@ def build(xyz: np.ndarray, normals: np.ndarray, params: dict) -> Hierarchy:
         lu = sla.lu_factor(M)
     else:
         lu = sla.lu_factor(Lp)
-    return Hierarchy(levels=levels, problem=p["problem"], stencils=sten, weights=w, coarse_lu=lu, params=p)
+    return Hierarchy(levels=levels, problem=p["problem"], stencils=sten, weights=w, coarse_lu=lu, params=p,
+                     normals=normals)

@@ -55,6 +55,9 @@ class Fp32Ops(Fp64Ops):
     def gs_correction(self, j, rows, resid):
         return resid * self.dinv[j][rows]
 
+    def dinv_learned(self):
+        return self.dinv[0]
+
     def P(self, j, e):
         return self.P32[j] @ e
 

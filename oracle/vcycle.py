@@ -58,6 +58,11 @@ class Fp64Ops:
     def gs_correction(self, j, rows, resid):
         return resid / self.diag[j][rows]
 
+    learned = None
+
+    def dinv_learned(self):
+        return 1.0 / self.diag[0]
+
     def P(self, j, e):
         return self.H.levels[j].P @ e
 
@@ -89,8 +94,21 @@ def gs_sweep(ops, j, u, f, lam=0.0, reverse=False):
     return u
 
 
-def vcycle(ops, r, rho=None, nu1=1, nu2=1, post_reverse=False):
-    """z = M r (Alg. 3 with zero initial guess). Bordered: returns (z, lambda)."""
+def learned_sweep(ops, u, f):
+    """Fine-level learned smoother: for q = 1..s, u <- u + omega_q D^-1 (f - L u)."""
+    omega = ops.learned
+    for q in range(omega.shape[1]):
+        u += (omega[:, q] * ops.dinv_learned()) * (f - ops.L(0, u))
+    return u
+
+
+def vcycle(ops, r, rho=None, nu1=1, nu2=1, post_reverse=False, capture=None):
+    """z = M r (Alg. 3 with zero initial guess). Bordered: returns (z, lambda).
+
+    With `ops.learned` set (an N_1 x s array of step weights) the fine level
+    is smoothed by `learned_sweep` instead of Gauss-Seidel. `capture`, if a
+    list, receives a copy of the fine-level vector right after the coarse-grid
+    correction (before post-smoothing)."""
     p = ops.nlevels()
     dt = ops.dtype
     rhs = [None] * p
@@ -102,7 +120,10 @@ def vcycle(ops, r, rho=None, nu1=1, nu2=1, post_reverse=False):
     for j in range(p - 1):
         e[j] = np.zeros(ops.size(j), dtype=dt)
         for _ in range(nu1):
-            gs_sweep(ops, j, e[j], rhs[j], 0.0, reverse=False)
+            if j == 0 and getattr(ops, "learned", None) is not None:
+                learned_sweep(ops, e[j], rhs[j])
+            else:
+                gs_sweep(ops, j, e[j], rhs[j], 0.0, reverse=False)
         res = rhs[j] - ops.L(j, e[j])
         rhs[j + 1] = ops.R(j, res)
         if bordered:
@@ -111,8 +132,13 @@ def vcycle(ops, r, rho=None, nu1=1, nu2=1, post_reverse=False):
     e[p - 1] = np.asarray(e[p - 1], dtype=dt)
     for j in range(p - 2, -1, -1):
         e[j] += ops.P(j, e[j + 1])
+        if j == 0 and capture is not None:
+            capture.append(np.array(e[0], dtype=np.float64))
         for _ in range(nu2):
-            gs_sweep(ops, j, e[j], rhs[j], mu if bordered else 0.0, reverse=post_reverse)
+            if j == 0 and getattr(ops, "learned", None) is not None:
+                learned_sweep(ops, e[j], rhs[j])
+            else:
+                gs_sweep(ops, j, e[j], rhs[j], mu if bordered else 0.0, reverse=post_reverse)
     if bordered:
         return e[0], mu
     return e[0]

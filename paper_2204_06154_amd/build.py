@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libmgm.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SOURCES = ["knn.cpp", "weights.cpp", "wse.cpp", "hierarchy.cpp"]
-HIP_SOURCES = ["device.hip", "phs_batched.hip"]
+HIP_SOURCES = ["device.hip", "phs_batched.hip", "learned.hip"]
 
 
 def _run(cmd):

@@ -1,0 +1,175 @@
+// Internal device-side context of the MGM library (shared by the HIP
+// translation units; not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "hierarchy.h"
+#include "kernels.h"
+
+namespace mgm {
+
+void batched_phs_weights_device(const double* d_xyz, const double* d_nrm, const int32_t* d_sten, int64_t nsys, int ns,
+                                int phs_order, int deg, double* d_w, int* d_status, hipStream_t st);
+
+#define HIPCHECK(x)                                                                                     \
+  do {                                                                                                  \
+    hipError_t e_ = (x);                                                                                \
+    if (e_ != hipSuccess) throw Error(MGM_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+inline unsigned nblk(int64_t threads) { return unsigned((threads + kBlock - 1) / kBlock); }
+
+template <typename T>
+T* dalloc(size_t n) {
+  T* p = nullptr;
+  if (n == 0) n = 1;
+  if (hipMalloc(reinterpret_cast<void**>(&p), n * sizeof(T)) != hipSuccess)
+    throw Error(MGM_E_ALLOC, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  return p;
+}
+
+template <typename T>
+T* dupload(const std::vector<T>& v) {
+  T* p = dalloc<T>(v.size());
+  if (!v.empty()) HIPCHECK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return p;
+}
+
+// IEEE binary16 (round to nearest, ties to even) of a double, rounded once.
+inline uint16_t f64_to_f16_bits(double x) {
+  uint16_t sign = std::signbit(x) ? 0x8000 : 0;
+  double a = std::fabs(x);
+  if (std::isnan(x)) return sign | 0x7e00;
+  if (a == 0.0) return sign;
+  int E;
+  std::frexp(a, &E);  // a = f 2^E, f in [0.5, 1)
+  int e = E - 1;      // a in [2^e, 2^(e+1))
+  if (e < -14) {      // subnormal grid: multiples of 2^-24
+    double k = std::rint(std::ldexp(a, 24));
+    return sign | uint16_t(k);  // k == 1024 is the smallest normal, encoded the same way
+  }
+  double k = std::rint(std::ldexp(a, 10 - e));  // in [1024, 2048]
+  if (k == 2048.0) {
+    k = 1024.0;
+    ++e;
+  }
+  if (e > 15) return sign | 0x7c00;
+  return sign | uint16_t((e + 15) << 10) | uint16_t(int(k) - 1024);
+}
+
+struct DevLevel {
+  int n = 0, ncol = 0, W = 0, G = 8, m = 0, nnext = 0;
+  int64_t nnz = 0;
+  std::vector<int> cstart;           // colour row ranges (host)
+  int32_t* perm = nullptr;           // position -> natural index (null: identity)
+  int32_t *rowptr = nullptr, *col = nullptr;
+  double* v64 = nullptr;
+  float* v32 = nullptr;
+  _Float16* v16 = nullptr;
+  float* s16 = nullptr;
+  double* dinv64 = nullptr;
+  float* dinv32 = nullptr;
+  float* dinv16 = nullptr;
+  int32_t* pcol = nullptr;
+  double* p64 = nullptr;
+  float* p32 = nullptr;
+  int32_t *rptr = nullptr, *rcol = nullptr;
+  double* r64 = nullptr;
+  float* r32 = nullptr;
+  double* b64 = nullptr;
+  float* b32 = nullptr;
+  double *e64 = nullptr, *f64 = nullptr, *res64 = nullptr;
+  float *e32 = nullptr, *f32 = nullptr, *res32 = nullptr;
+  // host copies needed to build reduced-precision values lazily
+  std::vector<double> hv, hdiag;
+  std::vector<int64_t> rowlen_prefix;  // host copy of the permuted row pointer
+  // patch-blocked smoother (see k_gs_patch)
+  bool patched = false;
+  int wmax = 0;                      // register width class of the patch kernel (32/64/96)
+  std::vector<int> pc_start;         // slot range of each patch colour (host)
+  std::vector<int64_t> pc_nnz;       // stored entries (incl. padding) per patch colour (host)
+  std::vector<int32_t> pc_rows;      // rows per patch colour (host)
+  int32_t *pstart = nullptr, *pwidth = nullptr, *pncl = nullptr, *lcol = nullptr, *pcolidx = nullptr;
+  int64_t* poff = nullptr;
+  double* pv64 = nullptr;
+  float* pv32 = nullptr;
+  _Float16* pv16 = nullptr;
+  std::vector<double> hpv;           // host copy of the patch values (FP64)
+  std::vector<int32_t> hprow;        // permuted row of each patch entry (host)
+};
+
+}  // namespace mgm
+
+struct mgm_ctx {
+  int device = 0;
+  mgm_params p{};
+  mgm::HostHierarchy H;
+  std::vector<mgm::DevLevel> lv;     // all levels; the last is the coarsest
+  int cdim = 0;
+  double* cinv = nullptr;
+  double* rho = nullptr;             // per-level constraint residuals
+  double* mu = nullptr;              // multiplier correction (bordered)
+  double* lam = nullptr;             // scalar for level ops
+  double* partial = nullptr;
+  int64_t partial_len = 0;
+  bool built[3] = {true, false, false};
+  hipStream_t cap = nullptr;
+  hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
+  std::vector<void*> allocs;
+  // solver workspace
+  int ws_restart = 0;
+  int64_t ld = 0;
+  double *V = nullptr, *Z = nullptr, *vecs = nullptr, *kpart = nullptr, *dh = nullptr;
+  double* hpin = nullptr;
+  double* capture = nullptr;         // when set: fine-level vector after the coarse correction (eager V-cycle)
+  // learned fine-level smoother
+  bool ls_active = false;
+  int ls_s = 0, ls_nin = 0, ls_T = 0, ls_adam_t = 0;
+  double ls_lam = 0.0;
+  std::vector<double> ls_wcheb;
+  double* ls_wcheb_d = nullptr;
+  float *ls_params = nullptr, *ls_m = nullptr, *ls_v = nullptr, *ls_grad = nullptr;
+  double* ls_om64 = nullptr;
+  float* ls_om32 = nullptr;
+  double* e_tmp64 = nullptr;
+  float* e_tmp32 = nullptr;
+  float *ls_X = nullptr, *ls_O = nullptr, *ls_H1 = nullptr, *ls_H2 = nullptr, *ls_dO = nullptr, *ls_dH1 = nullptr,
+        *ls_dH2 = nullptr, *ls_domega = nullptr, *ls_omt = nullptr;
+  float *ls_snap = nullptr, *ls_z = nullptr, *ls_e = nullptr, *ls_y = nullptr, *ls_g = nullptr, *ls_t = nullptr;
+  int32_t *ls_tptr = nullptr, *ls_tcol = nullptr;
+  float* ls_tval = nullptr;
+  double *ls_c = nullptr, *ls_loss = nullptr, *ls_scal = nullptr;
+  float* ls_atb = nullptr;
+  int ls_steps_cap = 0;
+};
+
+namespace mgm {
+
+extern thread_local std::string g_last_error;
+
+template <typename T>
+inline T* track(mgm_ctx* c, T* p) {
+  c->allocs.push_back(reinterpret_cast<void*>(p));
+  return p;
+}
+
+// shared helpers of the HIP translation units (defined in device.hip)
+void build_precision(mgm_ctx* c, int prec);
+void vcycle_core(mgm_ctx* c, hipStream_t st);
+void precond(mgm_ctx* c, const double* v, double* z, const int32_t* perm, hipStream_t st);
+void apply_A(mgm_ctx* c, const double* x, double* y, hipStream_t st);
+void ensure_ws(mgm_ctx* c, int restart);
+void mdot(mgm_ctx* c, int64_t n, const double* V, int64_t ld, int k, const double* w, double* out, hipStream_t st);
+void to_host(mgm_ctx* c, const double* d, int k, hipStream_t st);
+void need_device(const mgm_ctx* c);
+mgm_status guard(const std::function<void()>& f);
+void invalidate_graphs(mgm_ctx* c);
+
+}  // namespace mgm

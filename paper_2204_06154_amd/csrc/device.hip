@@ -23,135 +23,12 @@
 #include <numeric>
 #include <string>
 
-#include "hierarchy.h"
-#include "kernels.h"
-
-namespace mgm {
-
-void batched_phs_weights_device(const double* d_xyz, const double* d_nrm, const int32_t* d_sten, int64_t nsys, int ns,
-                                int phs_order, int deg, double* d_w, int* d_status, hipStream_t st);
-
-#define HIPCHECK(x)                                                                                     \
-  do {                                                                                                  \
-    hipError_t e_ = (x);                                                                                \
-    if (e_ != hipSuccess) throw Error(MGM_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_));      \
-  } while (0)
-
-static inline unsigned nblk(int64_t threads) { return unsigned((threads + kBlock - 1) / kBlock); }
-
-template <typename T>
-T* dalloc(size_t n) {
-  T* p = nullptr;
-  if (n == 0) n = 1;
-  if (hipMalloc(reinterpret_cast<void**>(&p), n * sizeof(T)) != hipSuccess)
-    throw Error(MGM_E_ALLOC, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
-  return p;
-}
-
-template <typename T>
-T* dupload(const std::vector<T>& v) {
-  T* p = dalloc<T>(v.size());
-  if (!v.empty()) HIPCHECK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-  return p;
-}
-
-// IEEE binary16 (round to nearest, ties to even) of a double, rounded once.
-static uint16_t f64_to_f16_bits(double x) {
-  uint16_t sign = std::signbit(x) ? 0x8000 : 0;
-  double a = std::fabs(x);
-  if (std::isnan(x)) return sign | 0x7e00;
-  if (a == 0.0) return sign;
-  int E;
-  std::frexp(a, &E);  // a = f 2^E, f in [0.5, 1)
-  int e = E - 1;      // a in [2^e, 2^(e+1))
-  if (e < -14) {      // subnormal grid: multiples of 2^-24
-    double k = std::rint(std::ldexp(a, 24));
-    return sign | uint16_t(k);  // k == 1024 is the smallest normal, encoded the same way
-  }
-  double k = std::rint(std::ldexp(a, 10 - e));  // in [1024, 2048]
-  if (k == 2048.0) {
-    k = 1024.0;
-    ++e;
-  }
-  if (e > 15) return sign | 0x7c00;
-  return sign | uint16_t((e + 15) << 10) | uint16_t(int(k) - 1024);
-}
-
-struct DevLevel {
-  int n = 0, ncol = 0, W = 0, G = 8, m = 0, nnext = 0;
-  int64_t nnz = 0;
-  std::vector<int> cstart;           // colour row ranges (host)
-  int32_t* perm = nullptr;           // position -> natural index (null: identity)
-  int32_t *rowptr = nullptr, *col = nullptr;
-  double* v64 = nullptr;
-  float* v32 = nullptr;
-  _Float16* v16 = nullptr;
-  float* s16 = nullptr;
-  double* dinv64 = nullptr;
-  float* dinv32 = nullptr;
-  float* dinv16 = nullptr;
-  int32_t* pcol = nullptr;
-  double* p64 = nullptr;
-  float* p32 = nullptr;
-  int32_t *rptr = nullptr, *rcol = nullptr;
-  double* r64 = nullptr;
-  float* r32 = nullptr;
-  double* b64 = nullptr;
-  float* b32 = nullptr;
-  double *e64 = nullptr, *f64 = nullptr, *res64 = nullptr;
-  float *e32 = nullptr, *f32 = nullptr, *res32 = nullptr;
-  // host copies needed to build reduced-precision values lazily
-  std::vector<double> hv, hdiag;
-  std::vector<int64_t> rowlen_prefix;  // host copy of the permuted row pointer
-  // patch-blocked smoother (see k_gs_patch)
-  bool patched = false;
-  int wmax = 0;                      // register width class of the patch kernel (32/64/96)
-  std::vector<int> pc_start;         // slot range of each patch colour (host)
-  std::vector<int64_t> pc_nnz;       // stored entries (incl. padding) per patch colour (host)
-  std::vector<int32_t> pc_rows;      // rows per patch colour (host)
-  int32_t *pstart = nullptr, *pwidth = nullptr, *pncl = nullptr, *lcol = nullptr, *pcolidx = nullptr;
-  int64_t* poff = nullptr;
-  double* pv64 = nullptr;
-  float* pv32 = nullptr;
-  _Float16* pv16 = nullptr;
-  std::vector<double> hpv;           // host copy of the patch values (FP64)
-  std::vector<int32_t> hprow;        // permuted row of each patch entry (host)
-};
-
-}  // namespace mgm
-
-struct mgm_ctx {
-  int device = 0;
-  mgm_params p{};
-  mgm::HostHierarchy H;
-  std::vector<mgm::DevLevel> lv;     // all levels; the last is the coarsest
-  int cdim = 0;
-  double* cinv = nullptr;
-  double* rho = nullptr;             // per-level constraint residuals
-  double* mu = nullptr;              // multiplier correction (bordered)
-  double* lam = nullptr;             // scalar for level ops
-  double* partial = nullptr;
-  int64_t partial_len = 0;
-  bool built[3] = {true, false, false};
-  hipStream_t cap = nullptr;
-  hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
-  std::vector<void*> allocs;
-  // solver workspace
-  int ws_restart = 0;
-  int64_t ld = 0;
-  double *V = nullptr, *Z = nullptr, *vecs = nullptr, *kpart = nullptr, *dh = nullptr;
-  double* hpin = nullptr;
-};
+#include "ctx.h"
+#include "kernels_learned.h"
 
 namespace mgm {
 
 thread_local std::string g_last_error;
-
-template <typename T>
-static T* track(mgm_ctx* c, T* p) {
-  c->allocs.push_back(reinterpret_cast<void*>(p));
-  return p;
-}
 
 static uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
   auto spread = [](uint64_t v) {
@@ -409,7 +286,7 @@ static void upload(mgm_ctx* c) {
   HIPCHECK(hipMemset(c->rho, 0, sizeof(double) * (p + 1)));
 }
 
-static void build_precision(mgm_ctx* c, int prec) {
+void build_precision(mgm_ctx* c, int prec) {
   if (c->built[prec]) return;
   for (size_t j = 0; j + 1 < c->lv.size(); ++j) {
     DevLevel& d = c->lv[j];
@@ -587,6 +464,28 @@ static void interp_add(mgm_ctx* c, int j, hipStream_t st) {
   hipLaunchKernelGGL((k_interp_add<S, S>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, d.m, d.pcol, P::pw(d), P::e(nx), P::e(d));
 }
 
+// Fine-level learned smoother: s Richardson steps with per-node step weights
+// (ping-pong between e and a scratch vector, the result left in e).
+template <typename V, typename S, bool SC>
+static void learned_sweep(mgm_ctx* c, hipStream_t st) {
+  using P = Prec<V, S, SC>;
+  DevLevel& d = c->lv[0];
+  S* e = P::e(d);
+  S* tmp = reinterpret_cast<S*>(sizeof(S) == 8 ? static_cast<void*>(c->e_tmp64) : static_cast<void*>(c->e_tmp32));
+  const S* om = reinterpret_cast<const S*>(sizeof(S) == 8 ? static_cast<const void*>(c->ls_om64)
+                                                           : static_cast<const void*>(c->ls_om32));
+  S* a = e;
+  S* b = tmp;
+  const unsigned g = nblk(int64_t(d.n) * d.G);
+  for (int q = 0; q < c->ls_s; ++q) {
+    DISPATCH_G(d.G, hipLaunchKernelGGL((k_richardson<V, S, GG, SC>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr,
+                                       d.col, P::val(d), d.s16, P::dinv(d), om + size_t(q) * d.n, P::f(d), a, b));
+    std::swap(a, b);
+  }
+  if (a != e) hipLaunchKernelGGL((k_gather<S, S>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, (const int32_t*)nullptr, a, e,
+                                 (double*)nullptr);
+}
+
 template <typename V, typename S, bool SC>
 static void vcycle_enqueue(mgm_ctx* c, hipStream_t st) {
   using P = Prec<V, S, SC>;
@@ -595,7 +494,10 @@ static void vcycle_enqueue(mgm_ctx* c, hipStream_t st) {
   for (int j = 0; j + 1 < p; ++j) {
     DevLevel& d = c->lv[j];
     hipLaunchKernelGGL((k_fill<S>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, P::e(d), S(0));
-    for (int s = 0; s < c->p.nu1; ++s) gs_sweep<V, S, SC>(c, j, c->p.pre_smoother == MGM_GS_BWD, false, c->mu, st);
+    for (int s = 0; s < c->p.nu1; ++s) {
+      if (j == 0 && c->ls_active) learned_sweep<V, S, SC>(c, st);
+      else gs_sweep<V, S, SC>(c, j, c->p.pre_smoother == MGM_GS_BWD, false, c->mu, st);
+    }
     residual_restrict<V, S, SC>(c, j, st);
   }
   DevLevel& cl = c->lv[p - 1];
@@ -603,14 +505,28 @@ static void vcycle_enqueue(mgm_ctx* c, hipStream_t st) {
                      P::f(cl), c->rho + (p - 1), P::e(cl), c->mu);
   for (int j = p - 2; j >= 0; --j) {
     interp_add<V, S, SC>(c, j, st);
-    for (int s = 0; s < c->p.nu2; ++s) gs_sweep<V, S, SC>(c, j, c->p.post_smoother == MGM_GS_BWD, bord, c->mu, st);
+    if (j == 0 && c->capture)
+      hipLaunchKernelGGL((k_gather<S, double>), dim3(nblk(c->lv[0].n)), dim3(kBlock), 0, st,
+                         c->lv[0].n, (const int32_t*)nullptr, P::e(c->lv[0]), c->capture, (double*)nullptr);
+    for (int s = 0; s < c->p.nu2; ++s) {
+      if (j == 0 && c->ls_active) learned_sweep<V, S, SC>(c, st);
+      else gs_sweep<V, S, SC>(c, j, c->p.post_smoother == MGM_GS_BWD, bord, c->mu, st);
+    }
   }
 }
 
-static void vcycle_core(mgm_ctx* c, hipStream_t st) {
+void invalidate_graphs(mgm_ctx* c) {
+  for (int k = 0; k < 3; ++k)
+    if (c->graph[k]) {
+      (void)hipGraphExecDestroy(c->graph[k]);
+      c->graph[k] = nullptr;
+    }
+}
+
+void vcycle_core(mgm_ctx* c, hipStream_t st) {
   const int prec = c->p.precision;
   build_precision(c, prec);
-  if (c->p.use_graph) {
+  if (c->p.use_graph && !c->capture) {
     if (!c->graph[prec]) {
       if (!c->cap) HIPCHECK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
       hipGraph_t g;
@@ -636,7 +552,7 @@ static void vcycle_core(mgm_ctx* c, hipStream_t st) {
 
 // z = M v for FP64 vectors in the fine level's permuted order (perm null) or
 // in natural order (perm = the fine permutation).
-static void precond(mgm_ctx* c, const double* v, double* z, const int32_t* perm, hipStream_t st) {
+void precond(mgm_ctx* c, const double* v, double* z, const int32_t* perm, hipStream_t st) {
   DevLevel& d = c->lv[0];
   const bool bord = c->p.problem == MGM_POISSON;
   const unsigned g = nblk(d.n);
@@ -652,7 +568,7 @@ static void precond(mgm_ctx* c, const double* v, double* z, const int32_t* perm,
 }
 
 // y = A x (FP64 fine operator, permuted order; bordered tail at index n).
-static void apply_A(mgm_ctx* c, const double* x, double* y, hipStream_t st) {
+void apply_A(mgm_ctx* c, const double* x, double* y, hipStream_t st) {
   DevLevel& d = c->lv[0];
   const bool bord = c->p.problem == MGM_POISSON;
   unsigned g = nblk(int64_t(d.n) * d.G);
@@ -668,7 +584,7 @@ static void apply_A(mgm_ctx* c, const double* x, double* y, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------- solvers
-static void ensure_ws(mgm_ctx* c, int restart) {
+void ensure_ws(mgm_ctx* c, int restart) {
   const int64_t n = c->lv[0].n + 1;
   if (!c->vecs) {
     c->ld = (n + 63) / 64 * 64;
@@ -686,13 +602,13 @@ static void ensure_ws(mgm_ctx* c, int restart) {
 }
 
 // out[t] = V[t] . w for t < k (device), deterministic.
-static void mdot(mgm_ctx* c, int64_t n, const double* V, int64_t ld, int k, const double* w, double* out, hipStream_t st) {
+void mdot(mgm_ctx* c, int64_t n, const double* V, int64_t ld, int k, const double* w, double* out, hipStream_t st) {
   int nb = int(std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (n + 2047) / 2048)));
   hipLaunchKernelGGL(k_mdot_partial, dim3(nb, k), dim3(kBlock), 0, st, int(n), V, ld, w, c->kpart);
   hipLaunchKernelGGL(k_reduce_partials, dim3(k), dim3(kBlock), 0, st, k, nb, c->kpart, out);
 }
 
-static void to_host(mgm_ctx* c, const double* d, int k, hipStream_t st) {
+void to_host(mgm_ctx* c, const double* d, int k, hipStream_t st) {
   HIPCHECK(hipMemcpyAsync(c->hpin, d, sizeof(double) * k, hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
 }
@@ -966,7 +882,7 @@ static WeightsFn device_weights_fn(hipStream_t st) {
   };
 }
 
-static void need_device(const mgm_ctx* c) {
+void need_device(const mgm_ctx* c) {
   if (c->device < 0) throw Error(MGM_E_ARG, "host-only handle (set up with device -1)");
 }
 
@@ -1029,7 +945,12 @@ static double vcycle_bytes(const mgm_ctx* c, int prec) {
   for (int j = 0; j + 1 < p; ++j) {
     const DevLevel& d = c->lv[j];
     tot += bvec(prec) * d.n;  // zero fill
-    tot += c->p.nu1 * gs_sweep_bytes(c, j, prec, false) + c->p.nu2 * gs_sweep_bytes(c, j, prec, bord);
+    if (j == 0 && c->ls_active) {
+      const double step = double(d.nnz) * (bval(prec) + 4.0) + double(d.n) * (5.0 * bvec(prec));
+      tot += (c->p.nu1 + c->p.nu2) * c->ls_s * step;
+    } else {
+      tot += c->p.nu1 * gs_sweep_bytes(c, j, prec, false) + c->p.nu2 * gs_sweep_bytes(c, j, prec, bord);
+    }
     tot += residual_bytes(c, j, prec);
     const int64_t nnzR = c->H.lv[j].R.nnz();
     tot += double(nnzR) * (bt + 4.0) + 4.0 * (d.nnext + 1) + bvec(prec) * (d.n + d.nnext);      // restrict
@@ -1129,7 +1050,7 @@ static void time_kernel_impl(mgm_ctx* c, int which, int level, int reps, hipStre
   *bytes = tbytes / double(count);
 }
 
-static mgm_status guard(const std::function<void()>& f) {
+mgm_status guard(const std::function<void()>& f) {
   try {
     f();
     return MGM_OK;
@@ -1382,6 +1303,19 @@ mgm_status mgm_export(mgm_handle h, int32_t what, int32_t level, void* h_buf, in
       case MGM_EX_L_VALS: need_level(p - 1); vd = H.lv[level].L.val; isint = false; break;
       case MGM_EX_BORDER: need_level(p - 1); vd = H.lv[level].b; isint = false; break;
       case MGM_EX_PATCH: need_level(p - 2); vi = H.lv[level].patch; break;
+      case MGM_EX_OMEGA: {
+        if (!h->ls_om64) throw Error(MGM_E_ARG, "learned smoother not trained");
+        const int n = h->lv[0].n, s = h->ls_s;
+        std::vector<double> om(size_t(n) * s);
+        std::vector<int32_t> perm(n);
+        HIPCHECK(hipMemcpy(om.data(), h->ls_om64, om.size() * sizeof(double), hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(perm.data(), h->lv[0].perm, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+        vd.assign(size_t(n) * s, 0.0);
+        for (int q = 0; q < s; ++q)
+          for (int pos = 0; pos < n; ++pos) vd[size_t(perm[pos]) * s + q] = om[size_t(q) * n + pos];
+        isint = false;
+        break;
+      }
       case MGM_EX_NCOLOURS:
         for (int j = 0; j + 1 < p; ++j) vi.push_back(H.lv[j].ncolours);
         break;

@@ -367,6 +367,7 @@ void build_hierarchy(const double* xyz, const double* nrm, int64_t n, const mgm_
   for (int64_t i = 0; i < 3 * n; ++i)
     if (!std::isfinite(xyz[i]) || !std::isfinite(nrm[i])) throw Error(MGM_E_NONFINITE, "non-finite point or normal");
   H.params = p;
+  H.normals.assign(nrm, nrm + 3 * n);
   std::vector<int32_t> sizes = level_sizes(n, p);
   if (sizes.size() < 2 || sizes.back() < 1) throw Error(MGM_E_ARG, "need at least two levels");
   const int ns = p.stencil_size;

@@ -41,6 +41,7 @@ struct HostHierarchy {
   int ns = 0;
   std::vector<int32_t> stencils;      // N_1 x ns, centre first
   std::vector<double> weights;        // N_1 x ns
+  std::vector<double> normals;        // N_1 x 3 (as given)
   int coarse_dim = 0;                 // N_p (screened) or N_p + 1 (bordered)
   std::vector<double> coarse_inv;     // dense row-major inverse of the coarsest system
 };

@@ -70,6 +70,9 @@ void knn_search(const double* queries, int64_t nq, const double* data, int64_t n
 void stencil_weights_host(const double* xyz, const double* nrm, int64_t n, const int32_t* sten,
                           int ns, const mgm_params& p, std::vector<double>& w);
 
+// Tangent-plane coordinates (ns x 2) of the stencil st of node i (Sec. 2.1).
+void project_stencil(const double* xyz, const double* nrm, int64_t i, const int32_t* st, int ns, double* xh);
+
 // Survivor indices (ascending) of weighted sample elimination (Sec. 4.1).
 std::vector<int32_t> wse_eliminate(const double* xyz, int64_t n, int factor);
 

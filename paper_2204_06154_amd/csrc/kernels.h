@@ -13,6 +13,7 @@
 #include <stdint.h>
 
 namespace mgm {
+namespace {  // kernels have internal linkage: each translation unit owns its copies
 
 constexpr int kBlock = 256;
 
@@ -401,4 +402,5 @@ __global__ __launch_bounds__(kBlock) void k_bdot_partial(int n, const S* __restr
   if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
+}  // namespace
 }  // namespace mgm

@@ -87,7 +87,9 @@ void tangent_basis(const double* nrm, double t1[3], double t2[3]) {
   t2[2] = n[0] * t1[1] - n[1] * t1[0];
 }
 
-void project(const double* xyz, const double* nrm, int64_t i, const int32_t* st, int ns, double* xh) {
+}  // namespace
+
+void project_stencil(const double* xyz, const double* nrm, int64_t i, const int32_t* st, int ns, double* xh) {
   double t1[3], t2[3];
   tangent_basis(nrm + 3 * i, t1, t2);
   for (int j = 0; j < ns; ++j) {
@@ -97,6 +99,8 @@ void project(const double* xyz, const double* nrm, int64_t i, const int32_t* st,
     xh[2 * j + 1] = (t2[0] * d[0] + t2[1] * d[1]) + t2[2] * d[2];
   }
 }
+
+namespace {
 
 inline double ipow(double x, int e) {
   double r = 1.0;
@@ -132,7 +136,7 @@ void stencil_weights_host(const double* xyz, const double* nrm, int64_t n, const
       std::vector<int> piv(sz);
       for (int64_t i = b; i < e; ++i) {
         const int32_t* st = sten + i * ns;
-        project(xyz, nrm, i, st, ns, xh.data());
+        project_stencil(xyz, nrm, i, st, ns, xh.data());
         double s = 0.0;
         for (int j = 0; j < ns; ++j)
           s = std::max(s, std::sqrt(xh[2 * j] * xh[2 * j] + xh[2 * j + 1] * xh[2 * j + 1]));
@@ -166,7 +170,7 @@ void stencil_weights_host(const double* xyz, const double* nrm, int64_t n, const
     parallel_for(n, [&](int64_t b, int64_t e) {
       std::vector<double> xh(2 * ns);
       for (int64_t i = b; i < e; ++i) {
-        project(xyz, nrm, i, sten + i * ns, ns, xh.data());
+        project_stencil(xyz, nrm, i, sten + i * ns, ns, xh.data());
         double r2 = 0.0;
         for (int j = 0; j < ns; ++j) r2 = std::max(r2, xh[2 * j] * xh[2 * j] + xh[2 * j + 1] * xh[2 * j + 1]);
         rho[i] = std::sqrt(r2);
@@ -177,7 +181,7 @@ void stencil_weights_host(const double* xyz, const double* nrm, int64_t n, const
       std::vector<double> xh(2 * ns), B(size_t(ns) * L), sw(ns), v(ns), y(ns), z(L), lp(L), rdiag(L);
       for (int64_t i = b; i < e; ++i) {
         const int32_t* st = sten + i * ns;
-        project(xyz, nrm, i, st, ns, xh.data());
+        project_stencil(xyz, nrm, i, st, ns, xh.data());
         const double s = rho[i];
         for (int j = 0; j < ns; ++j) {
           double r2 = xh[2 * j] * xh[2 * j] + xh[2 * j + 1] * xh[2 * j + 1];

@@ -22,8 +22,8 @@ GS_FWD, GS_BWD = 0, 1
 FGMRES, BICGSTAB, STATIONARY = 0, 1, 2
 OP_SMOOTH, OP_SPMV, OP_RESTRICT_RESIDUAL, OP_INTERP_ADD = 0, 1, 2, 3
 EX = dict(level_sizes=0, stencils=1, weights=2, coarse_idx=3, interp_idx=4, interp_w=5, colours=6,
-          l_rowptr=7, l_cols=8, l_vals=9, border=10, ncolours=11, patch=12)
-EX_FLOAT = {"weights", "interp_w", "l_vals", "border"}
+          l_rowptr=7, l_cols=8, l_vals=9, border=10, ncolours=11, patch=12, omega=13)
+EX_FLOAT = {"weights", "interp_w", "l_vals", "border", "omega"}
 
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16}
 KRYLOV = {"fgmres": FGMRES, "bicgstab": BICGSTAB, "stationary": STATIONARY}
@@ -49,6 +49,17 @@ class SolveInfo(ctypes.Structure):
                 ("rel_res_true", ctypes.c_double), ("lambda_", ctypes.c_double)]
 
 
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("lr", ctypes.c_double), ("s", ctypes.c_int32),
+                ("n_starts", ctypes.c_int32), ("iters_per_start", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("init", ctypes.c_int32), ("activate", ctypes.c_int32)]
+
+
+class TrainInfo(ctypes.Structure):
+    _fields_ = [("lam", ctypes.c_double), ("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
+                ("rate_gs", ctypes.c_double), ("rate_learned", ctypes.c_double), ("active", ctypes.c_int32)]
+
+
 class MgmError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"mgm status {status}: {msg}")
@@ -58,7 +69,8 @@ class MgmError(RuntimeError):
 _lib = None
 
 EXPORTED = ["mgm_default_params", "mgm_setup", "mgm_set_precision", "mgm_vcycle", "mgm_apply", "mgm_solve",
-            "mgm_level_op", "mgm_time_kernel", "mgm_stencils", "mgm_batched_weights", "mgm_export", "mgm_destroy",
+            "mgm_level_op", "mgm_time_kernel", "mgm_stencils", "mgm_batched_weights", "mgm_train_smoother",
+            "mgm_smoother_params", "mgm_smoother_grad", "mgm_set_smoother", "mgm_export", "mgm_destroy",
             "mgm_status_str", "mgm_last_error"]
 TK = dict(spmv=0, gs=1, residual=2, vcycle=3)
 
@@ -92,6 +104,14 @@ def load():
     lib.mgm_stencils.restype = i32
     lib.mgm_batched_weights.argtypes = [vp, vp, i64, vp, i64, i32, i32, i32, vp, vp]
     lib.mgm_batched_weights.restype = i32
+    lib.mgm_train_smoother.argtypes = [vp, ctypes.POINTER(TrainOpts), vp, ctypes.POINTER(TrainInfo), vp, vp]
+    lib.mgm_train_smoother.restype = i32
+    lib.mgm_smoother_params.argtypes = [vp, i32, vp, ctypes.POINTER(i64)]
+    lib.mgm_smoother_params.restype = i32
+    lib.mgm_smoother_grad.argtypes = [vp, vp, ctypes.POINTER(dbl), vp]
+    lib.mgm_smoother_grad.restype = i32
+    lib.mgm_set_smoother.argtypes = [vp, i32]
+    lib.mgm_set_smoother.restype = i32
     lib.mgm_export.argtypes = [vp, i32, i32, vp, ctypes.POINTER(i64)]
     lib.mgm_export.restype = i32
     lib.mgm_destroy.argtypes = [vp]
@@ -218,6 +238,45 @@ class Mgm:
         _check(self.lib.mgm_time_kernel(self.h, TK[which], level, reps, _stream(stream), ctypes.byref(ms),
                                         ctypes.byref(nbytes)))
         return ms.value, nbytes.value
+
+    def train_smoother(self, starts=None, steps=200, lr=1e-3, s=3, iters_per_start=2, seed=1, init=True,
+                       activate=1, history=False, stream=None):
+        """Prepare/train the learned fine-level smoother. `starts`: torch (n_starts x n) float64 on the device."""
+        n_starts = 0 if starts is None else int(starts.shape[0])
+        opts = TrainOpts(steps, lr, s, n_starts, iters_per_start, seed, 1 if init else 0, activate)
+        info = TrainInfo()
+        hist = np.zeros(steps + 1) if history else None
+        hp = hist.ctypes.data_as(ctypes.c_void_p) if history else ctypes.c_void_p(0)
+        _check(self.lib.mgm_train_smoother(self.h, ctypes.byref(opts), _ptr(starts) if starts is not None else None,
+                                           ctypes.byref(info), hp, _stream(stream)))
+        out = dict(lam=info.lam, loss_first=info.loss_first, loss_last=info.loss_last, rate_gs=info.rate_gs,
+                   rate_learned=info.rate_learned, active=bool(info.active))
+        if history:
+            out["history"] = hist
+        return out
+
+    def smoother_params(self, new=None):
+        n = ctypes.c_int64(0)
+        _check(self.lib.mgm_smoother_params(self.h, 0, None, ctypes.byref(n)))
+        if new is None:
+            buf = np.empty(n.value, dtype=np.float32)
+            _check(self.lib.mgm_smoother_params(self.h, 0, buf.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
+            return buf
+        buf = np.ascontiguousarray(new, dtype=np.float32)
+        assert buf.size == n.value
+        _check(self.lib.mgm_smoother_params(self.h, 1, buf.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
+        return buf
+
+    def smoother_grad(self, stream=None):
+        n = ctypes.c_int64(0)
+        _check(self.lib.mgm_smoother_params(self.h, 0, None, ctypes.byref(n)))
+        g = np.empty(n.value, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(self.lib.mgm_smoother_grad(self.h, g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss), _stream(stream)))
+        return loss.value, g
+
+    def set_smoother(self, learned: bool):
+        _check(self.lib.mgm_set_smoother(self.h, 1 if learned else 0))
 
     def export(self, what: str, level: int = 0) -> np.ndarray:
         n = ctypes.c_int64(0)
