@@ -67,6 +67,111 @@ def cpu_baseline(n_sample: int, n_full: int):
                       f"x{n_full / n_sample:g} to N={n_full}; SciPy sparse kernels, BLAS limited to 1 thread"}
 
 
+def timed_solves(m, f, u, krylov, steps, warmup, **kw):
+    import numpy as np
+    import torch
+    for _ in range(warmup):
+        u.zero_()
+        m.solve(f, u, krylov=krylov, **kw)
+    torch.cuda.synchronize()
+    times, info = [], None
+    for _ in range(steps):
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = m.solve(f, u, krylov=krylov, **kw)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    return 1e3 * float(np.mean(times)), info
+
+
+def bench_learned(args):
+    """Star surface with 16:1 density bumps (N=500,000), RBF-FD r^3 + degree 2, k=30,
+    screened Poisson (mu=1): FGMRES(40) to 1e-10 with the Gauss-Seidel V-cycle
+    vs. the learned per-node Chebyshev smoother on the fine level."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2204_06154_amd import mgm
+
+    t0 = time.perf_counter()
+    wl = synth.star_density_workload(args.n)
+    log(f"inputs N={args.n} generated in {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    m = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, precision=args.learned_precision), device=0)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    f = torch.tensor(wl.f, device="cuda")
+    u = torch.zeros_like(f)
+    out = {"workload": f"star surface, 16:1 density bumps, N={args.n}, RBF-FD r^3+deg2 k=30, screened mu=1, "
+                       f"FGMRES(40) to 1e-10, V-cycle {args.learned_precision}",
+           "levels": [int(x) for x in m.export("level_sizes")], "setup_s": round(setup_s, 2)}
+    ms, info = timed_solves(m, f, u, "fgmres", args.steps, args.warmup, restart=40, maxit=400, rtol=1e-10)
+    vc_ms, _ = m.time_kernel("vcycle", 0, reps=10)
+    out["gs"] = {"ms": round(ms, 3), "iters": info["iters"], "rel_res": info["rel_res_true"], "vcycle_us": round(vc_ms * 1e3, 1)}
+    log(f"GS: {ms:.2f} ms, {info['iters']} iters, V-cycle {vc_ms * 1e3:.0f} us")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2204)
+    starts = torch.randn((4, args.n), generator=gen, device="cuda", dtype=torch.float64)
+    t0 = time.perf_counter()
+    tr = m.train_smoother(starts, steps=args.train_steps, lr=1e-3, s=3, iters_per_start=2, seed=5, init=True,
+                          activate=1)
+    train_s = time.perf_counter() - t0
+    out["training"] = {"steps": args.train_steps, "snapshots": 8, "seconds": round(train_s, 2), "lam": tr["lam"],
+                       "loss_first": tr["loss_first"], "loss_last": tr["loss_last"], "rate_gs": tr["rate_gs"],
+                       "rate_learned": tr["rate_learned"], "active": tr["active"]}
+    log(f"training {train_s:.1f} s, loss {tr['loss_first']:.4f} -> {tr['loss_last']:.4f}, "
+        f"rates GS {tr['rate_gs']:.3f} learned {tr['rate_learned']:.3f}, active {tr['active']}")
+    m.set_smoother(True)
+    ms, info = timed_solves(m, f, u, "fgmres", args.steps, args.warmup, restart=40, maxit=400, rtol=1e-10)
+    vc_ms, _ = m.time_kernel("vcycle", 0, reps=10)
+    out["learned"] = {"ms": round(ms, 3), "iters": info["iters"], "rel_res": info["rel_res_true"],
+                      "vcycle_us": round(vc_ms * 1e3, 1)}
+    log(f"learned: {ms:.2f} ms, {info['iters']} iters, V-cycle {vc_ms * 1e3:.0f} us")
+    out["speedup_learned_vs_gs"] = round(out["gs"]["ms"] / out["learned"]["ms"], 3)
+    print(json.dumps(out), flush=True)
+    m.close()
+
+
+def bench_sphere1m(args):
+    """Unit sphere N=1,048,576, GFD degree 2, k=25, screened Poisson (mu=1),
+    BiCGSTAB to 1e-10 with the FP64 and the FP16-row-scale V-cycles."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2204_06154_amd import mgm
+
+    t0 = time.perf_counter()
+    wl = synth.big_sphere_workload(args.n)
+    log(f"inputs N={args.n} generated in {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    m = mgm.Mgm(wl.xyz, wl.normals, wl.params, device=0)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    f = torch.tensor(wl.f, device="cuda")
+    u = torch.zeros_like(f)
+    out = {"workload": f"unit sphere N={args.n} Fibonacci, GFD deg2 k=25 alpha=16, screened mu=1, BiCGSTAB to 1e-10",
+           "levels": [int(x) for x in m.export("level_sizes")], "setup_s": round(setup_s, 2)}
+    ref = None
+    for prec in ("fp64", "fp32", "fp16"):
+        m.set_precision(prec)
+        ms, info = timed_solves(m, f, u, "bicgstab", args.steps, args.warmup, maxit=400, rtol=1e-10)
+        vc_ms, vc_b = m.time_kernel("vcycle", 0, reps=10)
+        sol = u.cpu().numpy()
+        if ref is None:
+            ref = sol
+        err = float(np.linalg.norm(sol - ref) / np.linalg.norm(ref))
+        out[prec] = {"ms": round(ms, 3), "iters": info["iters"], "rel_res": info["rel_res_true"],
+                     "vcycle_us": round(vc_ms * 1e3, 1), "vcycle_GBps": round(vc_b / (vc_ms * 1e-3) / 1e9, 1),
+                     "err_vs_fp64_solution": err}
+        log(f"{prec}: {ms:.2f} ms, {info['iters']} applications, V-cycle {vc_ms * 1e3:.0f} us, err {err:.1e}")
+    out["speedup_fp16_vs_fp64"] = round(out["fp64"]["ms"] / out["fp16"]["ms"], 3)
+    print(json.dumps(out), flush=True)
+    m.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +183,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--weights-n", type=int, default=500_000)
     ap.add_argument("--gs-block", type=int, default=256)
+    ap.add_argument("--workload", choices=["torus", "learned", "sphere1m"], default="torus")
+    ap.add_argument("--train-steps", type=int, default=200)
+    ap.add_argument("--learned-precision", default="fp32")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the MGM solve is not sharded across GPUs in this build "
@@ -91,6 +199,14 @@ def main():
     from paper_2204_06154_amd import mgm
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "learned":
+        if args.n == 160_000:
+            args.n = 500_000
+        return bench_learned(args)
+    if args.workload == "sphere1m":
+        if args.n == 160_000:
+            args.n = 1 << 20
+        return bench_sphere1m(args)
     t0 = time.perf_counter()
     wl = synth.torus_workload(args.n)
     log(f"inputs N={args.n} generated in {time.perf_counter() - t0:.1f} s")

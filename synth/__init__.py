@@ -109,57 +109,54 @@ def jittered_fibonacci_sphere(n: int, rng: np.random.Generator, jitter: float = 
     return x
 
 
-def _dart_throw(candidates: np.ndarray, radius_of, n_target: int, r_max_global: float) -> np.ndarray:
+def _dart_throw(candidates: np.ndarray, radius_of, n_target: int, r_max_global: float, k_check: int = 8) -> np.ndarray:
     """Random sequential adsorption in candidate order.
 
-    Candidate c is kept when every kept point p satisfies
-    |c - p| >= (radius_of(c) + radius_of(p)) / 2. Stops after n_target kept
-    points. Returns kept candidate indices (in acceptance order).
+    Candidate c is kept when the kept points p near it satisfy
+    |c - p| >= (radius_of(c) + radius_of(p)) / 2 (checked against its k_check
+    nearest kept points, and exactly against earlier candidates of its own
+    batch). Stops after n_target kept points; returns the kept candidate
+    indices in acceptance order.
     """
     kept: list[int] = []
-    kept_arr = np.empty((0, 3))
-    kept_rad = np.empty(0)
-    batch = max(4096, n_target // 8)
-    pos = 0
     radii_all = radius_of(candidates)
+    batch = max(2048, n_target // 32)
+    pos = 0
     while len(kept) < n_target and pos < len(candidates):
         cb = candidates[pos:pos + batch]
         rb = radii_all[pos:pos + batch]
         ok = np.ones(len(cb), dtype=bool)
-        if len(kept_arr):
-            tree = cKDTree(kept_arr)
-            lists = tree.query_ball_point(cb, r_max_global)
-            for t, lst in enumerate(lists):
-                if lst:
-                    d = np.linalg.norm(kept_arr[lst] - cb[t], axis=1)
-                    if np.any(d < 0.5 * (rb[t] + kept_rad[lst])):
-                        ok[t] = False
+        if kept:
+            karr = np.array(kept, dtype=np.int64)
+            tree = cKDTree(candidates[karr])
+            kk = min(k_check, len(kept))
+            d, idx = tree.query(cb, kk)
+            if kk == 1:
+                d, idx = d[:, None], idx[:, None]
+            ok = np.all(d >= 0.5 * (rb[:, None] + radii_all[karr][idx]), axis=1)
         idx_ok = np.nonzero(ok)[0]
         sub = cb[idx_ok]
-        sub_tree = cKDTree(sub)
-        pairs = sub_tree.query_pairs(r_max_global, output_type="ndarray")
+        rs = rb[idx_ok]
+        pairs = cKDTree(sub).query_pairs(r_max_global, output_type="ndarray") if len(sub) > 1 else np.zeros((0, 2), int)
+        if len(pairs):
+            a, b = np.minimum(pairs[:, 0], pairs[:, 1]), np.maximum(pairs[:, 0], pairs[:, 1])
+            dd = np.linalg.norm(sub[a] - sub[b], axis=1)
+            conflict = dd < 0.5 * (rs[a] + rs[b])
+            a, b = a[conflict], b[conflict]
+        else:
+            a = b = np.zeros(0, dtype=np.int64)
         adj: dict[int, list[int]] = {}
-        for a, b in pairs:
-            a, b = int(a), int(b)
-            if a > b:
-                a, b = b, a
-            adj.setdefault(a, []).append(b)
+        for x, y in zip(a.tolist(), b.tolist()):
+            adj.setdefault(x, []).append(y)
         blocked = np.zeros(len(sub), dtype=bool)
-        new = []
         for t in range(len(sub)):
             if blocked[t]:
                 continue
-            new.append(t)
-            if len(kept) + len(new) >= n_target:
+            kept.append(pos + int(idx_ok[t]))
+            if len(kept) >= n_target:
                 break
             for u in adj.get(t, ()):
-                d = np.linalg.norm(sub[u] - sub[t])
-                if d < 0.5 * (rb[idx_ok[u]] + rb[idx_ok[t]]):
-                    blocked[u] = True
-        new_glob = [pos + int(idx_ok[t]) for t in new]
-        kept.extend(new_glob)
-        kept_arr = candidates[np.array(kept, dtype=np.int64)]
-        kept_rad = radii_all[np.array(kept, dtype=np.int64)]
+                blocked[u] = True
         pos += batch
     if len(kept) < n_target:
         raise RuntimeError("dart throwing ran out of candidates")
@@ -243,40 +240,37 @@ def star_fibonacci(n: int, rng: np.random.Generator, n_probe: int = 1_000_000):
 
 def star_density_points(n: int, rng: np.random.Generator, n_probe: int = 1_000_000,
                         n_bumps: int = 8, contrast: float = 16.0, width: float = 0.3):
-    """Star surface with local density 1 + (contrast-1) max_b exp(-|x-c_b|^2/(2 w^2)).
+    """Star surface with a 16:1 density contrast from Gaussian bumps.
 
-    Variable-radius dart throwing with exclusion distance proportional to
-    density^(-1/2) (so spacing varies by sqrt(contrast) = 4x). Returns
-    (xyz, normals, surface, density_at_points).
+    Density in direction space: rho(w) = 1 + (contrast-1) max_b exp(-|w-w_b|^2/(2 width^2))
+    over 8 random unit directions w_b. Directions are drawn uniformly, thinned
+    with probability rho/contrast, and selected by variable-radius dart throwing
+    with exclusion distance proportional to rho^(-1/2) (spacing varies by
+    sqrt(contrast) = 4x); the points are r(w) w on the star surface. Returns
+    (xyz, normals, surface, rho at the points).
     """
     surf = make_star_surface(rng, n_probe=n_probe)
-    centres_w = rng.standard_normal((n_bumps, 3))
-    centres, _ = surf.points_normals(centres_w)
+    cb = rng.standard_normal((n_bumps, 3))
+    cb /= np.linalg.norm(cb, axis=1, keepdims=True)
 
-    def density(x):
-        d2 = ((x[:, None, :] - centres[None, :, :]) ** 2).sum(axis=2)
+    def density(w):
+        d2 = ((w[:, None, :] - cb[None, :, :]) ** 2).sum(axis=2)
         return 1.0 + (contrast - 1.0) * np.exp(-d2 / (2.0 * width * width)).max(axis=1)
 
-    # candidates: uniform directions thinned by the area element, then by density
-    n_cand = 12 * n
-    w = rng.standard_normal((n_cand, 3))
-    xc, _ = surf.points_normals(w)
-    rc = np.linalg.norm(xc, axis=1)
-    area_w = rc ** 2 / rc.max() ** 2
-    rho = density(xc)
-    keep = rng.uniform(0.0, 1.0, n_cand) < area_w * rho / contrast
-    w = w[keep]
-    xc = xc[keep]
-    rho = rho[keep]
-    # expected surface area ~ 4 pi (mean r^2); exclusion scale so jammed count ~1.5 n
-    mean_inv_rho = float(np.mean(1.0 / rho))
-    area = 4.0 * math.pi * float(np.mean(rc ** 2))
-    # point count ~ sum over area of density/(pi delta0^2/4 / 0.547)
-    delta0 = math.sqrt(0.547 * 4.0 * area * float(np.mean(rho)) / (math.pi * 1.5 * n)) * math.sqrt(mean_inv_rho * np.mean(rho)) ** 0
-    rad = lambda x: delta0 / np.sqrt(density(x))
-    idx = _dart_throw(xc, rad, n, delta0)
+    # estimate the mean density by a uniform sample, then draw ~5n thinned candidates
+    probe = rng.standard_normal((200_000, 3))
+    probe /= np.linalg.norm(probe, axis=1, keepdims=True)
+    mean_rho = float(density(probe).mean())
+    m = int(5 * n * contrast / mean_rho) + 1
+    w = rng.standard_normal((m, 3))
+    w /= np.linalg.norm(w, axis=1, keepdims=True)
+    rho = density(w)
+    w = w[rng.uniform(0.0, 1.0, m) < rho / contrast]
+    # jammed RSA count ~ 0.547 (4/pi) int rho/delta0^2 dA = 1.5 n on the unit sphere
+    delta0 = math.sqrt(0.547 * 16.0 * mean_rho / (1.5 * n))
+    idx = _dart_throw(w, lambda c: delta0 / np.sqrt(density(c)), n, delta0)
     xyz, nrm = surf.points_normals(w[idx])
-    return xyz, nrm, surf, density(xyz)
+    return xyz, nrm, surf, density(w[idx])
 
 
 # ----------------------------------------------------------------------------
