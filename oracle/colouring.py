@@ -8,8 +8,10 @@ of one colour never couple, and run GS colour by colour. The result is exactly
 sequential GS in any permutation that lists the colours in increasing order,
 so it depends only on the colour of each row.
 
-Colouring rule (integer-only, so two implementations agree bit for bit):
-Jones-Plassmann with largest-degree-first priorities. Nodes are ranked by
+Colouring rules (integer-only, so two implementations agree bit for bit).
+Plain multicolour ordering uses Jones-Plassmann with largest-degree-first
+priorities; the patch-blocked ordering (below) uses DSATUR.
+Jones-Plassmann: nodes are ranked by
 (degree descending, h(i) ascending, i ascending) with
 h(i) = splitmix64(i) >> 32 (the SplitMix64 finaliser of Steele, Lea & Flood,
 2014); the first in that order has the highest priority. In every round, each
@@ -86,38 +88,71 @@ def colour_level(pat: sp.csr_matrix) -> np.ndarray:
     return jp_colouring(symmetric_graph(pat))
 
 
+def dsatur_colouring(G: sp.csr_matrix) -> np.ndarray:
+    """Brelaz's DSATUR rule (Comm. ACM 22, 1979): repeatedly take the
+    uncoloured node with the most distinct colours among its coloured
+    neighbours (its saturation), ties by larger degree, then smaller index, and
+    give it the smallest colour none of its neighbours has. A heap with stale
+    entries skipped on pop finds that node; the result is the rule's."""
+    import heapq
+    N = G.shape[0]
+    indptr, nbr = G.indptr, G.indices
+    deg = np.diff(indptr).astype(np.int64)
+    colour = np.full(N, -1, dtype=np.int64)
+    seen = [set() for _ in range(N)]
+    heap = [(0, -int(deg[v]), v) for v in range(N)]
+    heapq.heapify(heap)
+    while heap:
+        s, _, v = heapq.heappop(heap)
+        if colour[v] >= 0 or -s != len(seen[v]):
+            continue
+        c = 0
+        while c in seen[v]:
+            c += 1
+        colour[v] = c
+        for u in nbr[indptr[v]:indptr[v + 1]]:
+            if colour[u] < 0 and c not in seen[u]:
+                seen[u].add(c)
+                heapq.heappush(heap, (-len(seen[u]), -int(deg[u]), int(u)))
+    return colour.astype(np.int32)
+
+
 # ------------------------------------------------------------------ patches
-def _spread21(v: np.ndarray) -> np.ndarray:
-    """Spread the low 21 bits of v to every third bit (Morton interleave)."""
-    v = v.astype(np.uint64) & np.uint64(0x1FFFFF)
-    v = (v | (v << np.uint64(32))) & np.uint64(0x1F00000000FFFF)
-    v = (v | (v << np.uint64(16))) & np.uint64(0x1F0000FF0000FF)
-    v = (v | (v << np.uint64(8))) & np.uint64(0x100F00F00F00F00F)
-    v = (v | (v << np.uint64(4))) & np.uint64(0x10C30C30C30C30C3)
-    v = (v | (v << np.uint64(2))) & np.uint64(0x1249249249249249)
-    return v
+def rcb_patches(xyz: np.ndarray, block: int) -> np.ndarray:
+    """Patch id of every point by recursive coordinate bisection.
 
-
-def morton_order(xyz: np.ndarray) -> np.ndarray:
-    """Points sorted by (3-D Morton key, index). Coordinates are quantised to
-    21 bits as floor((x - lo) / ext * (2^21 - 1)) on a cube of side ext (the
-    largest bounding-box extent), each operation rounded in IEEE double."""
-    lo = xyz.min(axis=0)
-    ext = float(np.max(xyz.max(axis=0) - lo))
-    if not ext > 0.0:
-        ext = 1.0
-    q = np.minimum(2097151.0, np.floor((xyz - lo) / ext * 2097151.0)).astype(np.uint64)
-    key = _spread21(q[:, 0]) | (_spread21(q[:, 1]) << np.uint64(1)) | (_spread21(q[:, 2]) << np.uint64(2))
-    return np.lexsort((np.arange(len(xyz)), key))
+    A set of n > block points is sorted by (coordinate, index) along the axis
+    of its largest bounding-box extent (the first such axis on ties) and cut
+    after the first floor(nb/2)*block points, nb = ceil(n/block); both halves
+    are cut again, the first before the second, and the sets of <= block points
+    this ends in are numbered in that order. Every patch then holds exactly
+    `block` points except the last one."""
+    N = len(xyz)
+    patch = np.empty(N, dtype=np.int64)
+    nxt = 0
+    stack = [np.arange(N)]
+    while stack:
+        idx = stack.pop()
+        if len(idx) <= block:
+            patch[idx] = nxt
+            nxt += 1
+            continue
+        pts = xyz[idx]
+        axis = int(np.argmax(pts.max(axis=0) - pts.min(axis=0)))
+        idx = idx[np.lexsort((idx, pts[:, axis]))]
+        cut = ((len(idx) + block - 1) // block // 2) * block
+        stack.append(idx[cut:])
+        stack.append(idx[:cut])
+    return patch
 
 
 def patch_colouring(pat: sp.csr_matrix, xyz: np.ndarray, block: int):
     """Patch-blocked multicolour ordering.
 
-    Rows are cut into patches of `block` consecutive points of the Morton
-    order; the patch graph (patches coupled by any entry of the symmetrised
-    pattern) is coloured by the rule above, and so is the graph of the
-    couplings inside patches. Rows with equal (patch colour, local colour)
+    Rows are cut into compact patches of `block` points by recursive
+    coordinate bisection; the patch graph (patches coupled by any entry of the
+    symmetrised pattern) is coloured by the DSATUR rule, and so is the graph of
+    the couplings inside patches. Rows with equal (patch colour, local colour)
     never couple, so GS over the composite colour pcolour * C + lcolour
     (C = number of local colours) is sequential GS in a permutation: one pass
     over the patch colours, each patch visiting its local colours in turn.
@@ -126,9 +161,7 @@ def patch_colouring(pat: sp.csr_matrix, xyz: np.ndarray, block: int):
     """
     G = symmetric_graph(pat)
     N = G.shape[0]
-    order = morton_order(xyz)
-    patch = np.empty(N, dtype=np.int64)
-    patch[order] = np.arange(N) // block
+    patch = rcb_patches(xyz, block)
     npatch = int(patch.max()) + 1
     row_of = np.repeat(np.arange(N), np.diff(G.indptr))
     pi, pj = patch[row_of], patch[G.indices]
@@ -137,11 +170,11 @@ def patch_colouring(pat: sp.csr_matrix, xyz: np.ndarray, block: int):
     PG.sum_duplicates()
     PG.sort_indices()
     PG.data[:] = 1
-    pcol = jp_colouring(PG)
+    pcol = dsatur_colouring(PG)
     inner = ~cross
     GI = sp.csr_matrix((np.ones(int(inner.sum()), dtype=np.int64), (row_of[inner], G.indices[inner])), shape=(N, N))
     GI.sort_indices()
-    lcol = jp_colouring(GI)
+    lcol = dsatur_colouring(GI)
     C = int(lcol.max()) + 1
     comp = pcol[patch].astype(np.int64) * C + lcol
     return comp.astype(np.int64), patch, pcol, lcol

@@ -393,14 +393,15 @@ struct Prec<_Float16, float, true> {
   }
 
 template <typename V, typename S, bool SC>
-static void gs_patch_launch(mgm_ctx* c, int j, int pc, bool reverse, bool border, const double* lam, hipStream_t st) {
+static void gs_patch_launch(mgm_ctx* c, int j, int pc, bool reverse, bool border, const double* lam, hipStream_t st,
+                            bool zero_guess = false) {
   using P = Prec<V, S, SC>;
   DevLevel& d = c->lv[j];
   const int s0 = d.pc_start[pc], ns = d.pc_start[pc + 1] - s0;
   if (ns <= 0) return;
 #define GS_PATCH(WM, BD)                                                                                 \
   hipLaunchKernelGGL((k_gs_patch<V, S, WM / kPatchG, SC, BD>), dim3(ns), dim3(kPatch * kPatchG), 0, st, s0, \
-                     reverse ? 1 : 0, d.pstart, \
+                     reverse ? 1 : 0, zero_guess ? 1 : 0, d.pstart, \
                      d.pwidth, d.poff, d.pncl, d.lcol, P::pval(d), d.pcolidx, d.s16, P::dinv(d), P::f(d), P::e(d),  \
                      P::b(d), lam)
   if (d.wmax == 32) {
@@ -414,12 +415,14 @@ static void gs_patch_launch(mgm_ctx* c, int j, int pc, bool reverse, bool border
 }
 
 template <typename V, typename S, bool SC>
-static void gs_sweep(mgm_ctx* c, int j, bool reverse, bool border, const double* lam, hipStream_t st) {
+static void gs_sweep(mgm_ctx* c, int j, bool reverse, bool border, const double* lam, hipStream_t st,
+                     bool zero_guess = false) {
   using P = Prec<V, S, SC>;
   DevLevel& d = c->lv[j];
   if (d.patched) {
     const int npc = int(d.pc_start.size()) - 1;
-    for (int t = 0; t < npc; ++t) gs_patch_launch<V, S, SC>(c, j, reverse ? npc - 1 - t : t, reverse, border, lam, st);
+    for (int t = 0; t < npc; ++t)
+      gs_patch_launch<V, S, SC>(c, j, reverse ? npc - 1 - t : t, reverse, border, lam, st, zero_guess);
     return;
   }
   for (int t = 0; t < d.ncol; ++t) {
@@ -493,10 +496,13 @@ static void vcycle_enqueue(mgm_ctx* c, hipStream_t st) {
   const bool bord = c->p.problem == MGM_POISSON;
   for (int j = 0; j + 1 < p; ++j) {
     DevLevel& d = c->lv[j];
-    hipLaunchKernelGGL((k_fill<S>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, P::e(d), S(0));
+    // e_j starts at zero: a patch-blocked first sweep assumes it without reading e_j
+    const bool learned = j == 0 && c->ls_active;
+    const bool zg = d.patched && c->p.nu1 > 0 && !learned;
+    if (!zg) hipLaunchKernelGGL((k_fill<S>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, P::e(d), S(0));
     for (int s = 0; s < c->p.nu1; ++s) {
-      if (j == 0 && c->ls_active) learned_sweep<V, S, SC>(c, st);
-      else gs_sweep<V, S, SC>(c, j, c->p.pre_smoother == MGM_GS_BWD, false, c->mu, st);
+      if (learned) learned_sweep<V, S, SC>(c, st);
+      else gs_sweep<V, S, SC>(c, j, c->p.pre_smoother == MGM_GS_BWD, false, c->mu, st, zg && s == 0);
     }
     residual_restrict<V, S, SC>(c, j, st);
   }

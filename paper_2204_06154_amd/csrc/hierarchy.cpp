@@ -14,6 +14,8 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <queue>
+#include <tuple>
 
 namespace mgm {
 
@@ -309,6 +311,88 @@ std::vector<int32_t> morton_order(const double* xyz, int32_t n) {
   return order;
 }
 
+// DSATUR (Brelaz 1979) on the nodes [v0, v1) of a graph whose edges never
+// leave that range: repeatedly colour the uncoloured node with the most
+// distinct neighbour colours (saturation), ties by larger degree, then smaller
+// index, with the smallest colour no neighbour has. Stale heap entries (an
+// older saturation) are skipped when popped. Returns the number of colours.
+static int dsatur_range(const std::vector<int32_t>& ptr, const std::vector<int32_t>& adj, int32_t v0, int32_t v1,
+                        std::vector<int32_t>& colour) {
+  using Key = std::tuple<int32_t, int32_t, int32_t>;  // (saturation, degree, -index): largest first
+  std::priority_queue<Key> heap;
+  std::vector<std::vector<int32_t>> seen(v1 - v0);  // sorted distinct neighbour colours
+  for (int32_t v = v0; v < v1; ++v) {
+    colour[v] = -1;
+    heap.emplace(0, ptr[v + 1] - ptr[v], -v);
+  }
+  int maxc = 0;
+  while (!heap.empty()) {
+    auto [sat, deg, mv] = heap.top();
+    heap.pop();
+    const int32_t v = -mv;
+    auto& sv = seen[v - v0];
+    if (colour[v] >= 0 || sat != int32_t(sv.size())) continue;
+    int32_t c = 0;
+    for (int32_t x : sv) {  // sorted: the first gap is the smallest free colour
+      if (x != c) break;
+      ++c;
+    }
+    colour[v] = c;
+    maxc = std::max(maxc, c + 1);
+    for (int32_t k = ptr[v]; k < ptr[v + 1]; ++k) {
+      const int32_t u = adj[k];
+      if (colour[u] >= 0) continue;
+      auto& su = seen[u - v0];
+      auto it = std::lower_bound(su.begin(), su.end(), c);
+      if (it != su.end() && *it == c) continue;
+      su.insert(it, c);
+      heap.emplace(int32_t(su.size()), ptr[u + 1] - ptr[u], -u);
+    }
+  }
+  return maxc;
+}
+
+// Patch id of every point by recursive coordinate bisection: a set of more
+// than `block` points is sorted by (coordinate, index) along the axis of its
+// largest bounding-box extent (first such axis on ties) and cut after the
+// first floor(nb/2)*block points, nb = ceil(n/block); the first half is cut
+// before the second and the final sets are numbered in that order, so every
+// patch holds exactly `block` points except the last.
+static int32_t rcb_patches(const double* xyz, int32_t n, int block, std::vector<int32_t>& patch) {
+  patch.assign(n, 0);
+  std::vector<int32_t> ids(n);
+  std::iota(ids.begin(), ids.end(), 0);
+  int32_t next = 0;
+  std::vector<std::pair<int32_t, int32_t>> stack{{0, n}};  // [begin, end) ranges of ids
+  while (!stack.empty()) {
+    auto [b, e] = stack.back();
+    stack.pop_back();
+    if (e - b <= block) {
+      for (int32_t t = b; t < e; ++t) patch[ids[t]] = next;
+      ++next;
+      continue;
+    }
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = xyz[3 * size_t(ids[b]) + a];
+    for (int32_t t = b; t < e; ++t)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], xyz[3 * size_t(ids[t]) + a]);
+        hi[a] = std::max(hi[a], xyz[3 * size_t(ids[t]) + a]);
+      }
+    int axis = 0;
+    for (int a = 1; a < 3; ++a)
+      if (hi[a] - lo[a] > hi[axis] - lo[axis]) axis = a;
+    std::sort(ids.begin() + b, ids.begin() + e, [&](int32_t i, int32_t j) {
+      const double xi = xyz[3 * size_t(i) + axis], xj = xyz[3 * size_t(j) + axis];
+      return xi < xj || (xi == xj && i < j);
+    });
+    const int32_t cut = ((e - b + block - 1) / block / 2) * block;
+    stack.emplace_back(b + cut, e);
+    stack.emplace_back(b, b + cut);
+  }
+  return next;
+}
+
 // Smoother colouring of one level: patch-blocked (block > 0 and every row at
 // most kMaxPatchWidth entries) or plain multicolour.
 void smoother_colouring(HostLevel& l, int block) {
@@ -323,9 +407,7 @@ void smoother_colouring(HostLevel& l, int block) {
   }
   const int32_t n = l.n;
   l.morton = morton_order(l.xyz.data(), n);
-  l.patch.assign(n, 0);
-  for (int32_t t = 0; t < n; ++t) l.patch[l.morton[t]] = t / block;
-  l.npatch = (n + block - 1) / block;
+  l.npatch = rcb_patches(l.xyz.data(), n, block, l.patch);
   // patch graph and intra-patch graph
   std::vector<std::vector<int32_t>> pn(l.npatch);
   std::vector<int32_t> iptr(n + 1, 0), iadj;
@@ -346,9 +428,37 @@ void smoother_colouring(HostLevel& l, int block) {
     pptr[p + 1] = pptr[p] + int32_t(r.size());
     padj.insert(padj.end(), r.begin(), r.end());
   }
-  int npc = 0, nlc = 0;
-  l.pcolour = jp_colour(pptr, padj, &npc);
-  l.lcolour = jp_colour(iptr, iadj, &nlc);
+  l.pcolour.assign(l.npatch, -1);
+  const int npc = dsatur_range(pptr, padj, 0, l.npatch, l.pcolour);
+  // DSATUR on the union of the patch graphs = DSATUR on every patch alone (a
+  // choice in one patch never changes another's saturations): run them in
+  // parallel over the rows of each patch, renumbered to be contiguous.
+  std::vector<int32_t> byp(n), pstart(l.npatch + 1, 0);
+  for (int32_t i = 0; i < n; ++i) pstart[l.patch[i] + 1]++;
+  for (int32_t p = 0; p < l.npatch; ++p) pstart[p + 1] += pstart[p];
+  {
+    std::vector<int32_t> fill(pstart.begin(), pstart.end() - 1);
+    for (int32_t i = 0; i < n; ++i) byp[fill[l.patch[i]]++] = i;  // ascending index within a patch
+  }
+  std::vector<int32_t> pos(n);
+  for (int32_t t = 0; t < n; ++t) pos[byp[t]] = t;
+  std::vector<int32_t> lptr(n + 1, 0), ladj(iadj.size());
+  for (int32_t t = 0; t < n; ++t) lptr[t + 1] = lptr[t] + (iptr[byp[t] + 1] - iptr[byp[t]]);
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    for (int64_t t = b; t < e; ++t) {
+      const int32_t i = byp[t];
+      int32_t o = lptr[t];
+      for (int32_t k = iptr[i]; k < iptr[i + 1]; ++k) ladj[o++] = pos[iadj[k]];
+    }
+  });
+  std::vector<int32_t> lc(n, -1), pnlc(l.npatch, 0);
+  parallel_for(l.npatch, [&](int64_t b, int64_t e) {
+    for (int64_t p = b; p < e; ++p) pnlc[p] = dsatur_range(lptr, ladj, pstart[p], pstart[p + 1], lc);
+  });
+  l.lcolour.resize(n);
+  for (int32_t t = 0; t < n; ++t) l.lcolour[byp[t]] = lc[t];
+  int nlc = 0;
+  for (int32_t p = 0; p < l.npatch; ++p) nlc = std::max(nlc, pnlc[p]);
   l.npcolours = npc;
   // composite colour pcolour * nlc + lcolour, relabelled densely in order
   std::vector<int64_t> comp(n), used;

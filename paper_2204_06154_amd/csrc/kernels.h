@@ -12,14 +12,40 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <climits>
+
 namespace mgm {
 namespace {  // kernels have internal linkage: each translation unit owns its copies
 
 constexpr int kBlock = 256;
 
-template <typename S>
-__device__ __forceinline__ S group_sum(S v, int G) {
-  for (int off = G >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+// Lane exchange inside one DPP row of 16 lanes (no LDS round trip).
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(b)), CTRL, 0xF, 0xF, false));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(b >> 32)), CTRL, 0xF, 0xF, false));
+  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <- 7 - i within each 8
+constexpr int kDppMirror = 0x140;      // lane i <- 15 - i within each 16
+
+// Sum over each aligned group of G consecutive lanes (G = 1, 2, 4, 8, 16);
+// every lane of the group gets the same bits. All lanes of a group must be
+// active. Each stage adds two partial sums over disjoint lane sets.
+template <int G, typename S>
+__device__ __forceinline__ S group_sum(S v) {
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group of 1..16 lanes");
+  if constexpr (G >= 16) v += dpp_mov<kDppMirror>(v);
+  if constexpr (G >= 8) v += dpp_mov<kDppHalfMirror>(v);
+  if constexpr (G >= 4) v += dpp_mov<kDppXor2>(v);
+  if constexpr (G >= 2) v += dpp_mov<kDppXor1>(v);
   return v;
 }
 
@@ -42,7 +68,7 @@ __device__ __forceinline__ S row_dot(int row, int lane, int W, const int32_t* __
   S acc = S(0);
 #pragma unroll 4
   for (int k = beg + lane; k < end; k += G) acc += S(val[k]) * x[col[k]];
-  acc = group_sum(acc, G);
+  acc = group_sum<G>(acc);
   if (SCALED) acc *= S(scale[row]);
   return acc;
 }
@@ -78,6 +104,9 @@ __global__ __launch_bounds__(kBlock) void k_gs_colour(int r0, int r1, int W, con
 // visited in order (reverse for a backward sweep), one barrier each: rows of
 // one local colour never couple, so this is sequential GS in the order
 // (patch colour, patch, local colour).
+// With zero_guess the sweep starts from u = 0 without reading u: rows of patch
+// colours visited earlier in this sweep hold their new values, all others are
+// taken as zero (so no separate clearing pass is needed).
 // Operator storage per patch: ELL of width w (a multiple of kPatchG) with
 // entry i*kPatchG + g of local row t at off + (i*nr + t)*kPatchG + g, so the
 // lanes of a workgroup read consecutive addresses; padding entries have value
@@ -86,7 +115,7 @@ constexpr int kPatch = 256;
 constexpr int kPatchG = 4;
 template <typename V, typename S, int WL, bool SCALED, bool BORDER>
 __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
-    int slot0, int reverse, const int32_t* __restrict__ pstart, const int32_t* __restrict__ pwidth,
+    int slot0, int reverse, int zero_guess, const int32_t* __restrict__ pstart, const int32_t* __restrict__ pwidth,
     const int64_t* __restrict__ poff, const int32_t* __restrict__ pncl, const int32_t* __restrict__ lcol,
     const V* __restrict__ pval, const int32_t* __restrict__ pcol, const float* __restrict__ scale,
     const S* __restrict__ dinv, const S* __restrict__ f, S* u, const S* __restrict__ b,
@@ -98,6 +127,12 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
   const int nw = pwidth[slot] / kPatchG;  // entries per lane
   const int64_t off = poff[slot];
   const int ncl = pncl[slot];
+  // rows [upd_lo, upd_hi) hold current values (all rows unless zero_guess)
+  int upd_lo = 0, upd_hi = INT_MAX;
+  if (zero_guess) {
+    if (reverse) upd_lo = pstart[slot0 + gridDim.x];
+    else upd_hi = pstart[slot0];
+  }
   const int t = threadIdx.x / kPatchG;
   const int g = threadIdx.x % kPatchG;
   const bool act = t < nr;
@@ -107,7 +142,7 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
   S rhs = S(0), di = S(0), sc = S(1);
   int myc = -1;
   if (act) {
-    if (g == 0) ul[t] = u[row];
+    if (g == 0) ul[t] = zero_guess ? S(0) : u[row];
     myc = lcol[row];
     di = dinv[row];
     rhs = f[row];
@@ -127,12 +162,13 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
 #pragma unroll
     for (int i = 0; i < WL; ++i) {
       const bool in = unsigned(cc[i] - r0) < unsigned(nr);
-      const S uv = u[cc[i]];
-      halo += in ? S(0) : iv[i] * uv;
+      const bool cur = cc[i] >= upd_lo && cc[i] < upd_hi;
+      const S uv = (!in && cur) ? u[cc[i]] : S(0);
+      halo += iv[i] * uv;
       ic[i] = in ? cc[i] - r0 : t;
       iv[i] = in ? iv[i] : S(0);
     }
-    halo = group_sum(halo, kPatchG);
+    halo = group_sum<kPatchG>(halo);
     rhs -= sc * halo;
   }
   __syncthreads();
@@ -145,7 +181,7 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
         a0 += iv[i] * ul[ic[i]];
         a1 += iv[i + 1] * ul[ic[i + 1]];
       }
-      const S acc = group_sum(a0 + a1, kPatchG);
+      const S acc = group_sum<kPatchG>(a0 + a1);
       if (g == 0) ul[t] = ul[t] + (rhs - sc * acc) * di;
     }
     __syncthreads();
@@ -217,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int32_t* __re
   if (i < nc) {
     S acc = S(0);
     for (int k = rptr[i] + lane; k < rptr[i + 1]; k += kRestrictG) acc += S(rval[k]) * res[rcol[k]];
-    acc = group_sum(acc, kRestrictG);
+    acc = group_sum<kRestrictG>(acc);
     if (lane == 0) rc[i] = acc;
   }
   if (RHO && blockIdx.x == 0) {

@@ -67,6 +67,8 @@ def test_integer_setup_bit_exact(pair):
         assert np.array_equal(m.export("coarse_idx", j), lv.coarse_idx)
         assert np.array_equal(m.export("interp_idx", j).reshape(lv.N, -1), lv.interp_idx)
         assert np.array_equal(m.export("colours", j), lv.colour)
+        if lv.patches is not None:
+            assert np.array_equal(m.export("patch", j), lv.patches["patch"])
     assert list(m.export("ncolours")) == [lv.ncolours for lv in H.levels[:-1]]
     for j, lv in enumerate(H.levels):
         assert np.array_equal(m.export("l_rowptr", j), lv.pat.indptr)

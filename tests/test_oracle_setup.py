@@ -273,13 +273,77 @@ def test_colouring_matches_plain_loops_and_is_valid():
         assert np.array_equal(lv.colour, _jp_sequential(G))
 
 
-def _morton_bits(q):
-    """Interleave three 21-bit integers bit by bit (x in bit 0, y in bit 1, z in bit 2)."""
-    key = 0
-    for bit in range(21):
-        for a in range(3):
-            key |= ((int(q[a]) >> bit) & 1) << (3 * bit + a)
-    return key
+def _rcb_plain(x, ids, block, out, nxt):
+    """Recursive coordinate bisection written as plain recursion (tiny sets)."""
+    if len(ids) <= block:
+        for i in ids:
+            out[i] = nxt
+        return nxt + 1
+    ext = [max(x[i, a] for i in ids) - min(x[i, a] for i in ids) for a in range(3)]
+    axis = ext.index(max(ext))
+    ids = sorted(ids, key=lambda i: (x[i, axis], i))
+    cut = (-(-len(ids) // block) // 2) * block
+    nxt = _rcb_plain(x, ids[:cut], block, out, nxt)
+    return _rcb_plain(x, ids[cut:], block, out, nxt)
+
+
+def _dsatur_plain(G):
+    """DSATUR written as a plain scan over all nodes at every step (tiny graphs)."""
+    N = G.shape[0]
+    adj = [G.indices[G.indptr[i]:G.indptr[i + 1]].tolist() for i in range(N)]
+    colour = [-1] * N
+    for _ in range(N):
+        best = None
+        for v in range(N):
+            if colour[v] >= 0:
+                continue
+            key = (len({colour[u] for u in adj[v] if colour[u] >= 0}), len(adj[v]), -v)
+            if best is None or key > best[0]:
+                best = (key, v)
+        v = best[1]
+        used = {colour[u] for u in adj[v] if colour[u] >= 0}
+        c = 0
+        while c in used:
+            c += 1
+        colour[v] = c
+    return np.array(colour)
+
+
+def test_rcb_patches_on_a_grid_are_rectangles():
+    """A 32 x 16 grid in the plane cut into patches of 64 points: the longer
+    axis is halved until 8 x 8 squares remain, numbered left half first."""
+    gx, gy = np.meshgrid(np.arange(32.0), np.arange(16.0), indexing="ij")
+    x = np.stack([gx.ravel(), gy.ravel(), np.zeros(gx.size)], axis=1)
+    p = colouring.rcb_patches(x, 64)
+    assert p.max() + 1 == 8
+    for k in range(8):
+        sel = x[p == k]
+        assert len(sel) == 64
+        assert np.ptp(sel[:, 0]) == 7 and np.ptp(sel[:, 1]) == 7
+    # depth-first numbering: the first four patches cover x < 16
+    assert np.all(x[p < 4, 0] < 16) and np.all(x[p >= 4, 0] >= 16)
+
+
+def test_dsatur_known_cases():
+    rng = np.random.default_rng(5)
+    # bipartite graphs (a random tree, an even cycle, a grid) take exactly two colours (Brelaz 1979)
+    n = 60
+    parent = [int(rng.integers(i)) for i in range(1, n)]
+    T = sp.coo_matrix((np.ones(n - 1), (np.arange(1, n), parent)), shape=(n, n)).tocsr()
+    cyc = sp.coo_matrix((np.ones(20), (np.arange(20), (np.arange(20) + 1) % 20)), shape=(20, 20)).tocsr()
+    g = np.arange(48).reshape(6, 8)
+    rows = np.concatenate([g[:, :-1].ravel(), g[:-1, :].ravel()])
+    cols = np.concatenate([g[:, 1:].ravel(), g[1:, :].ravel()])
+    grid = sp.coo_matrix((np.ones(len(rows)), (rows, cols)), shape=(48, 48)).tocsr()
+    for A in (T, cyc, grid):
+        G = colouring.symmetric_graph(A)
+        c = colouring.dsatur_colouring(G)
+        assert c.max() == 1 and colouring.is_valid_colouring(A, c)
+    # odd cycle: three colours; complete graph K_7: seven
+    odd = sp.coo_matrix((np.ones(21), (np.arange(21), (np.arange(21) + 1) % 21)), shape=(21, 21)).tocsr()
+    assert colouring.dsatur_colouring(colouring.symmetric_graph(odd)).max() == 2
+    K = sp.csr_matrix(np.ones((7, 7)))
+    assert sorted(colouring.dsatur_colouring(colouring.symmetric_graph(K))) == list(range(7))
 
 
 def test_patch_colouring_pins():
@@ -291,19 +355,14 @@ def test_patch_colouring_pins():
         assert lv.patches is not None
         # composite colours are a valid colouring (rows of one colour never couple)
         assert colouring.is_valid_colouring(lv.pat, lv.colour)
-        # patches are consecutive chunks of the Morton order (key by plain bit loops)
+        # patches by recursive coordinate bisection (plain recursion)
         x = lv.xyz
-        lo = x.min(axis=0)
-        ext = float(np.max(x.max(axis=0) - lo))
-        keys = []
-        for i in range(len(x)):
-            q = [min(2097151, int(np.floor((x[i, a] - lo[a]) / ext * 2097151.0))) for a in range(3)]
-            keys.append((_morton_bits(q), i))
-        order = [i for _, i in sorted(keys)]
         patch = np.empty(len(x), dtype=np.int64)
-        patch[order] = np.arange(len(x)) // 64
+        _rcb_plain(x, list(range(len(x))), 64, patch, 0)
         assert np.array_equal(patch, lv.patches["patch"])
-        # patch colours and local colours follow the Jones-Plassmann rule
+        sizes = np.bincount(patch)
+        assert np.all(sizes[:-1] == 64) and 0 < sizes[-1] <= 64
+        # patch colours and local colours follow the DSATUR rule
         G = colouring.symmetric_graph(lv.pat)
         rows = np.repeat(np.arange(G.shape[0]), np.diff(G.indptr))
         cross = patch[rows] != patch[G.indices]
@@ -312,10 +371,15 @@ def test_patch_colouring_pins():
                            shape=(npatch, npatch))
         PG.sum_duplicates()
         PG.sort_indices()
-        assert np.array_equal(lv.patches["pcolour"], _jp_sequential(PG))
+        assert np.array_equal(lv.patches["pcolour"], _dsatur_plain(PG))
         GI = sp.csr_matrix((np.ones((~cross).sum()), (rows[~cross], G.indices[~cross])), shape=G.shape)
         GI.sort_indices()
-        assert np.array_equal(lv.patches["lcolour"], _jp_sequential(GI))
+        if G.shape[0] <= 800:  # the plain scan is quadratic
+            assert np.array_equal(lv.patches["lcolour"], _dsatur_plain(GI))
+        else:  # per patch: DSATUR never looks across the patch boundary
+            for k in range(0, npatch, max(1, npatch // 6)):
+                ids = np.nonzero(patch == k)[0]
+                assert np.array_equal(lv.patches["lcolour"][ids], _dsatur_plain(GI[ids][:, ids]))
         # the GS order is (patch colour, local colour): check the relabelling keeps it
         comp = lv.patches["pcolour"][patch] * (lv.patches["lcolour"].max() + 1) + lv.patches["lcolour"]
         assert np.all(np.diff(comp[np.argsort(lv.colour, kind="stable")]) >= 0)
