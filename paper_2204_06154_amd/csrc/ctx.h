@@ -96,8 +96,8 @@ struct DevLevel {
   std::vector<int> pc_start;         // slot range of each patch colour (host)
   std::vector<int64_t> pc_nnz;       // stored entries (incl. padding) per patch colour (host)
   std::vector<int32_t> pc_rows;      // rows per patch colour (host)
-  int32_t *pstart = nullptr, *pwidth = nullptr, *pncl = nullptr, *lcol = nullptr, *pcolidx = nullptr;
-  int64_t* poff = nullptr;
+  int32_t *pstart = nullptr, *pncl = nullptr, *lcol = nullptr, *pcolidx = nullptr;
+  int pw = 0, pblock = 0;  // patch ELL: entries per lane and rows per slot
   double* pv64 = nullptr;
   float* pv32 = nullptr;
   _Float16* pv16 = nullptr;
@@ -127,7 +127,7 @@ struct mgm_ctx {
   int ws_restart = 0;
   int64_t ld = 0;
   double *V = nullptr, *Z = nullptr, *vecs = nullptr, *kpart = nullptr, *dh = nullptr;
-  double* hpin = nullptr;
+  double* hpin = nullptr;  // pinned host copies of dot results
   double* capture = nullptr;         // when set: fine-level vector after the coarse correction (eager V-cycle)
   // learned fine-level smoother
   bool ls_active = false;
@@ -166,7 +166,9 @@ void vcycle_core(mgm_ctx* c, hipStream_t st);
 void precond(mgm_ctx* c, const double* v, double* z, const int32_t* perm, hipStream_t st);
 void apply_A(mgm_ctx* c, const double* x, double* y, hipStream_t st);
 void ensure_ws(mgm_ctx* c, int restart);
-void mdot(mgm_ctx* c, int64_t n, const double* V, int64_t ld, int k, const double* w, double* out, hipStream_t st);
+void mdot(mgm_ctx* c, int64_t n, const double* V, int64_t ld, int k, const double* w, double* out, hipStream_t st,
+          double* host_out = nullptr);
+void host_wait(hipStream_t st);
 void to_host(mgm_ctx* c, const double* d, int k, hipStream_t st);
 void need_device(const mgm_ctx* c);
 mgm_status guard(const std::function<void()>& f);

@@ -158,12 +158,18 @@ static void upload(mgm_ctx* c) {
     for (int i = 0; i < n; ++i) dinv[i] = 1.0 / diag[i];
     d.dinv64 = track(c, dupload(dinv));
     if (d.patched) {
-      // slots = patches in permuted order; ELL (column-major) values per patch
-      std::vector<int32_t> ps, pw_, pn, lc(n), pci;
-      std::vector<int64_t> po;
+      // slots = patches in permuted order. ELL per slot with the level's
+      // width w (a multiple of kPatchG) and a fixed stride of block rows, so
+      // an entry's address follows from (slot, entry, row) alone.
+      const int block = c->p.gs_block;
+      std::vector<int32_t> ps, pn, lc(n), pci;
       std::vector<double> pv;
       std::vector<int32_t> prow;
       int maxw = 0;
+      for (int r = 0; r < n; ++r) maxw = std::max(maxw, rp[r + 1] - rp[r]);
+      const int w = (maxw + kPatchG - 1) / kPatchG * kPatchG;
+      d.pw = w / kPatchG;
+      d.pblock = block;
       d.pc_start.assign(1, 0);
       int prev_pc = -1;
       for (int pos = 0; pos < n;) {
@@ -177,26 +183,20 @@ static void upload(mgm_ctx* c) {
         int end = pos;
         while (end < n && h.patch[order[end]] == patch) ++end;
         const int nr = end - pos;
-        int w = 0, ncl = 0;
-        for (int t = 0; t < nr; ++t) {
-          w = std::max(w, rp[pos + t + 1] - rp[pos + t]);
-          ncl = std::max(ncl, h.lcolour[order[pos + t]] + 1);
-        }
-        maxw = std::max(maxw, w);
-        w = (w + kPatchG - 1) / kPatchG * kPatchG;  // padded to whole lane chunks
+        if (nr > block) throw Error(MGM_E_ARG, "patch larger than the block size");
+        int ncl = 0;
+        for (int t = 0; t < nr; ++t) ncl = std::max(ncl, h.lcolour[order[pos + t]] + 1);
         ps.push_back(pos);
-        pw_.push_back(w);
         pn.push_back(ncl);
-        po.push_back(int64_t(pv.size()));
         const size_t base = pv.size();
-        pv.resize(base + size_t(w) * nr, 0.0);
-        pci.resize(base + size_t(w) * nr);
-        prow.resize(base + size_t(w) * nr);
+        pv.resize(base + size_t(w) * block, 0.0);
+        pci.resize(base + size_t(w) * block, pos);   // padding entries: value 0, a valid column
+        prow.resize(base + size_t(w) * block, pos);
         for (int t = 0; t < nr; ++t) {
           const int r = pos + t;
           const int len = rp[r + 1] - rp[r];
           for (int k = 0; k < w; ++k) {
-            const size_t e = base + (size_t(k / kPatchG) * nr + t) * kPatchG + (k % kPatchG);
+            const size_t e = base + (size_t(k / kPatchG) * block + t) * kPatchG + (k % kPatchG);
             prow[e] = r;
             if (k < len) {
               pv[e] = vl[rp[r] + k];
@@ -224,9 +224,7 @@ static void upload(mgm_ctx* c) {
           d.pc_rows[pc] += ps[s + 1] - ps[s];
         }
       d.pstart = track(c, dupload(ps));
-      d.pwidth = track(c, dupload(pw_));
       d.pncl = track(c, dupload(pn));
-      d.poff = track(c, dupload(po));
       d.lcol = track(c, dupload(lc));
       d.pcolidx = track(c, dupload(pci));
       d.pv64 = track(c, dupload(pv));
@@ -401,8 +399,8 @@ static void gs_patch_launch(mgm_ctx* c, int j, int pc, bool reverse, bool border
   if (ns <= 0) return;
 #define GS_PATCH(WM, BD)                                                                                 \
   hipLaunchKernelGGL((k_gs_patch<V, S, WM / kPatchG, SC, BD>), dim3(ns), dim3(kPatch * kPatchG), 0, st, s0, \
-                     reverse ? 1 : 0, zero_guess ? 1 : 0, d.pstart, \
-                     d.pwidth, d.poff, d.pncl, d.lcol, P::pval(d), d.pcolidx, d.s16, P::dinv(d), P::f(d), P::e(d),  \
+                     reverse ? 1 : 0, zero_guess ? 1 : 0, d.pw, d.pblock, d.pstart, \
+                     d.pncl, d.lcol, P::pval(d), d.pcolidx, d.s16, P::dinv(d), P::f(d), P::e(d),  \
                      P::b(d), lam)
   if (d.wmax == 32) {
     if (border) GS_PATCH(32, true); else GS_PATCH(32, false);
@@ -582,11 +580,7 @@ void apply_A(mgm_ctx* c, const double* x, double* y, hipStream_t st) {
                      d.col, d.v64, nullptr, x, y, d.b64, x + d.n);
              else hipLaunchKernelGGL((k_spmv<double, double, GG, false, false>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr,
                      d.col, d.v64, nullptr, x, y, d.b64, x + d.n));
-  if (bord) {
-    unsigned gb = nblk(d.n);
-    hipLaunchKernelGGL((k_bdot_partial<double>), dim3(gb), dim3(kBlock), 0, st, d.n, d.b64, x, c->kpart);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, 1, int(gb), c->kpart, y + d.n);
-  }
+  if (bord) mdot(c, d.n, d.b64, 0, 1, x, y + d.n, st);  // constraint row b . x
 }
 
 // ------------------------------------------------------------------- solvers
@@ -608,11 +602,16 @@ void ensure_ws(mgm_ctx* c, int restart) {
 }
 
 // out[t] = V[t] . w for t < k (device), deterministic.
-void mdot(mgm_ctx* c, int64_t n, const double* V, int64_t ld, int k, const double* w, double* out, hipStream_t st) {
+void mdot(mgm_ctx* c, int64_t n, const double* V, int64_t ld, int k, const double* w, double* out, hipStream_t st,
+          double* host_out) {
+  if (k < 1 || k > kMaxDots) throw Error(MGM_E_ARG, "too many simultaneous dot products");
   int nb = int(std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (n + 2047) / 2048)));
   hipLaunchKernelGGL(k_mdot_partial, dim3(nb, k), dim3(kBlock), 0, st, int(n), V, ld, w, c->kpart);
-  hipLaunchKernelGGL(k_reduce_partials, dim3(k), dim3(kBlock), 0, st, k, nb, c->kpart, out);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(k), dim3(kBlock), 0, st, k, nb, c->kpart, out, host_out);
 }
+
+// Wait for the stream: the host mirrors written by mdot are then current.
+void host_wait(hipStream_t st) { HIPCHECK(hipStreamSynchronize(st)); }
 
 void to_host(mgm_ctx* c, const double* d, int k, hipStream_t st) {
   HIPCHECK(hipMemcpyAsync(c->hpin, d, sizeof(double) * k, hipMemcpyDeviceToHost, st));
@@ -641,8 +640,8 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
   } else {
     hipLaunchKernelGGL((k_fill<double>), dim3(g), dim3(kBlock), 0, st, int(n), x, 0.0);
   }
-  mdot(c, n, f, ld, 1, f, c->dh, st);
-  to_host(c, c->dh, 1, st);
+  mdot(c, n, f, ld, 1, f, c->dh, st, c->hpin);
+  host_wait(st);
   const double fnorm = std::sqrt(c->hpin[0]);
   if (!std::isfinite(fnorm)) throw Error(MGM_E_NONFINITE, "non-finite right-hand side");
   info = mgm_solve_info{};
@@ -651,8 +650,8 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
   auto true_res = [&]() {
     apply_A(c, x, r, st);
     hipLaunchKernelGGL(k_rsub, dim3(g), dim3(kBlock), 0, st, int(n), f, r);
-    mdot(c, n, r, ld, 1, r, c->dh, st);
-    to_host(c, c->dh, 1, st);
+    mdot(c, n, r, ld, 1, r, c->dh, st, c->hpin);
+    host_wait(st);
     return std::sqrt(c->hpin[0]);
   };
   auto finish = [&](mgm_status s) {
@@ -692,18 +691,17 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
         precond(c, V + j * ld, Z + j * ld, nullptr, st);
         info.iters++;
         apply_A(c, Z + j * ld, w, st);
-        mdot(c, n, V, ld, j + 1, w, c->dh, st);
+        // CGS2: two projections, then the norm; the dots land on the host directly
+        const double* hp = c->hpin;
+        mdot(c, n, V, ld, j + 1, w, c->dh, st, c->hpin);
         hipLaunchKernelGGL(k_mupdate, dim3(g), dim3(kBlock), 0, st, int(n), V, ld, j + 1, c->dh, w);
-        mdot(c, n, V, ld, j + 1, w, c->dh + 256, st);
+        mdot(c, n, V, ld, j + 1, w, c->dh + 256, st, c->hpin + 256);
         hipLaunchKernelGGL(k_mupdate, dim3(g), dim3(kBlock), 0, st, int(n), V, ld, j + 1, c->dh + 256, w);
-        mdot(c, n, w, ld, 1, w, c->dh + 512, st);
+        mdot(c, n, w, ld, 1, w, c->dh + 512, st, c->hpin + 512);
         hipLaunchKernelGGL(k_normalise, dim3(g), dim3(kBlock), 0, st, int(n), w, c->dh + 512, V + (j + 1) * ld);
-        HIPCHECK(hipMemcpyAsync(c->hpin, c->dh, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st));
-        HIPCHECK(hipMemcpyAsync(c->hpin + 256, c->dh + 256, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st));
-        HIPCHECK(hipMemcpyAsync(c->hpin + 512, c->dh + 512, sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHECK(hipStreamSynchronize(st));
-        for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = c->hpin[i] + c->hpin[256 + i];
-        const double hn = std::sqrt(c->hpin[512]);
+        host_wait(st);
+        for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = hp[i] + hp[256 + i];
+        const double hn = std::sqrt(hp[512]);
         if (!std::isfinite(hn)) return finish(MGM_E_NONFINITE);
         H[size_t(j + 1) * m + j] = hn;
         for (int i = 0; i < j; ++i) {
@@ -753,8 +751,8 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
       double rho_old = 1.0, alpha = 1.0, omega = 1.0;
       bool first = true;
       while (info.iters < o.maxit) {
-        mdot(c, n, rhat, ld, 1, r, c->dh, st);  // rho = rhat . r
-        to_host(c, c->dh, 1, st);
+        mdot(c, n, rhat, ld, 1, r, c->dh, st, c->hpin);  // rho = rhat . r
+        host_wait(st);
         double rho = c->hpin[0];
         if (rho == 0.0) break;
         if (first) {
@@ -769,12 +767,12 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
         precond(c, p, phat, nullptr, st);
         info.iters++;
         apply_A(c, phat, v, st);
-        mdot(c, n, rhat, ld, 1, v, c->dh, st);
-        to_host(c, c->dh, 1, st);
+        mdot(c, n, rhat, ld, 1, v, c->dh, st, c->hpin);
+        host_wait(st);
         alpha = rho / c->hpin[0];
         hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kBlock), 0, st, int(n), 1.0, r, -alpha, v, s);
-        mdot(c, n, s, ld, 1, s, c->dh, st);
-        to_host(c, c->dh, 1, st);
+        mdot(c, n, s, ld, 1, s, c->dh, st, c->hpin);
+        host_wait(st);
         double sn = std::sqrt(c->hpin[0]) / fnorm;
         if (!std::isfinite(sn)) return finish(MGM_E_NONFINITE);
         if (hist && hist_n <= o.maxit) hist[hist_n++] = sn;
@@ -786,15 +784,15 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
         precond(c, s, shat, nullptr, st);
         info.iters++;
         apply_A(c, shat, t, st);
-        mdot(c, n, s, ld, 2, t, c->dh, st);  // [s.t, t.t] (s and t are adjacent)
-        to_host(c, c->dh, 2, st);
+        mdot(c, n, s, ld, 2, t, c->dh, st, c->hpin);  // [s.t, t.t] (s and t are adjacent)
+        host_wait(st);
         omega = c->hpin[0] / c->hpin[1];
         hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kBlock), 0, st, int(n), 1.0, x, alpha, phat, x);
         hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kBlock), 0, st, int(n), 1.0, x, omega, shat, x);
         hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kBlock), 0, st, int(n), 1.0, s, -omega, t, r);
         rho_old = rho;
-        mdot(c, n, r, ld, 1, r, c->dh, st);
-        to_host(c, c->dh, 1, st);
+        mdot(c, n, r, ld, 1, r, c->dh, st, c->hpin);
+        host_wait(st);
         double rn2 = std::sqrt(c->hpin[0]) / fnorm;
         if (hist && hist_n <= o.maxit) hist[hist_n++] = rn2;
         info.rel_res_est = rn2;

@@ -107,25 +107,38 @@ __global__ __launch_bounds__(kBlock) void k_gs_colour(int r0, int r1, int W, con
 // With zero_guess the sweep starts from u = 0 without reading u: rows of patch
 // colours visited earlier in this sweep hold their new values, all others are
 // taken as zero (so no separate clearing pass is needed).
-// Operator storage per patch: ELL of width w (a multiple of kPatchG) with
-// entry i*kPatchG + g of local row t at off + (i*nr + t)*kPatchG + g, so the
-// lanes of a workgroup read consecutive addresses; padding entries have value
-// zero and point at the row itself.
+// Operator storage per patch slot: ELL with the level's width nw * kPatchG
+// and a fixed stride of `block` rows, entry i*kPatchG + g of local row t at
+// (slot * block * nw + i * block + t) * kPatchG + g, so the lanes of a
+// workgroup read consecutive addresses and the entry loads depend on no other
+// load; padding entries have value zero and a valid column.
 constexpr int kPatch = 256;
 constexpr int kPatchG = 4;
 template <typename V, typename S, int WL, bool SCALED, bool BORDER>
 __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
-    int slot0, int reverse, int zero_guess, const int32_t* __restrict__ pstart, const int32_t* __restrict__ pwidth,
-    const int64_t* __restrict__ poff, const int32_t* __restrict__ pncl, const int32_t* __restrict__ lcol,
+    int slot0, int reverse, int zero_guess, int nw, int block, const int32_t* __restrict__ pstart,
+    const int32_t* __restrict__ pncl, const int32_t* __restrict__ lcol,
     const V* __restrict__ pval, const int32_t* __restrict__ pcol, const float* __restrict__ scale,
     const S* __restrict__ dinv, const S* __restrict__ f, S* u, const S* __restrict__ b,
     const double* __restrict__ lam) {
   __shared__ S ul[kPatch];
   const int slot = slot0 + blockIdx.x;
+  const int t = threadIdx.x / kPatchG;
+  const int g = threadIdx.x % kPatchG;
+  const bool slot_row = t < block;
+  // entry loads first: their addresses need no other load
+  const int64_t base = (int64_t(slot) * block * nw + t) * kPatchG + g;
+  int cc[WL];
+  S iv[WL];
+#pragma unroll
+  for (int i = 0; i < WL; ++i) {
+    const int ii = i < nw ? i : nw - 1;  // chunks >= nw: re-read the last one, zeroed below
+    const int64_t e = base + int64_t(ii) * block * kPatchG;
+    cc[i] = slot_row ? pcol[e] : 0;
+    iv[i] = (slot_row && i < nw) ? S(pval[e]) : S(0);
+  }
   const int r0 = pstart[slot];
   const int nr = pstart[slot + 1] - r0;
-  const int nw = pwidth[slot] / kPatchG;  // entries per lane
-  const int64_t off = poff[slot];
   const int ncl = pncl[slot];
   // rows [upd_lo, upd_hi) hold current values (all rows unless zero_guess)
   int upd_lo = 0, upd_hi = INT_MAX;
@@ -133,60 +146,53 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
     if (reverse) upd_lo = pstart[slot0 + gridDim.x];
     else upd_hi = pstart[slot0];
   }
-  const int t = threadIdx.x / kPatchG;
-  const int g = threadIdx.x % kPatchG;
   const bool act = t < nr;
   const int row = r0 + t;
-  S iv[WL];
   int ic[WL];
-  S rhs = S(0), di = S(0), sc = S(1);
+  S rhs = S(0), di = S(0), sc = S(1), uown = S(0);
   int myc = -1;
   if (act) {
-    if (g == 0) ul[t] = zero_guess ? S(0) : u[row];
+    uown = zero_guess ? S(0) : u[row];
     myc = lcol[row];
     di = dinv[row];
     rhs = f[row];
     if (SCALED) sc = S(scale[row]);
     if (BORDER) rhs -= b[row] * S(*lam);
-    // branch-free loads: all columns/values first (chunks >= nw clamped and
-    // zeroed), then all gathers, so the whole row is in flight at once
-    int cc[WL];
-#pragma unroll
-    for (int i = 0; i < WL; ++i) {
-      const int ii = i < nw ? i : nw - 1;
-      const int64_t e = off + (int64_t(ii) * nr + t) * kPatchG + g;
-      cc[i] = pcol[e];
-      iv[i] = i < nw ? S(pval[e]) : S(0);
-    }
     S halo = S(0);
 #pragma unroll
     for (int i = 0; i < WL; ++i) {
-      const bool in = unsigned(cc[i] - r0) < unsigned(nr);
+      const bool live = i < nw;
+      const bool in = live && unsigned(cc[i] - r0) < unsigned(nr);
       const bool cur = cc[i] >= upd_lo && cc[i] < upd_hi;
-      const S uv = (!in && cur) ? u[cc[i]] : S(0);
+      const S uv = (live && !in && cur) ? u[cc[i]] : S(0);
       halo += iv[i] * uv;
       ic[i] = in ? cc[i] - r0 : t;
       iv[i] = in ? iv[i] : S(0);
     }
     halo = group_sum<kPatchG>(halo);
     rhs -= sc * halo;
+    if (g == 0) ul[t] = uown;
   }
   __syncthreads();
+  // Each row keeps its own value in a register (only that row writes it).
   for (int step = 0; step < ncl; ++step) {
     const int c = reverse ? ncl - 1 - step : step;
     if (myc == c) {  // all lanes of a row agree
-      S a0 = S(0), a1 = S(0);
+      S a0 = S(0), a1 = S(0), a2 = S(0), a3 = S(0);
 #pragma unroll
-      for (int i = 0; i < WL; i += 2) {
+      for (int i = 0; i < WL; i += 4) {
         a0 += iv[i] * ul[ic[i]];
         a1 += iv[i + 1] * ul[ic[i + 1]];
+        a2 += iv[i + 2] * ul[ic[i + 2]];
+        a3 += iv[i + 3] * ul[ic[i + 3]];
       }
-      const S acc = group_sum<kPatchG>(a0 + a1);
-      if (g == 0) ul[t] = ul[t] + (rhs - sc * acc) * di;
+      const S acc = group_sum<kPatchG>((a0 + a1) + (a2 + a3));
+      uown = uown + (rhs - sc * acc) * di;
+      if (g == 0) ul[t] = uown;
     }
     __syncthreads();
   }
-  if (act && g == 0) u[row] = ul[t];
+  if (act && g == 0) u[row] = uown;
 }
 
 // res = f - A u over all rows; with BDOT also per-block partial sums of b.u
@@ -331,10 +337,23 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int n, const int32_t* __rest
 // Deterministic two-stage reductions: stage 1 writes one partial per block
 // (grid.y selects the vector), stage 2 sums the partials in block order.
 constexpr int kRedBlocks = 512;
+constexpr int kMaxDots = 200;  // vectors of one dot launch (the FGMRES restart limit)
+
+// Fixed-tree sum over the kBlock threads of a block (result in thread 0).
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
 
 // partial[t * nb + blk] = sum over the block's chunk of V[t][i] * w[i]
 __global__ __launch_bounds__(kBlock) void k_mdot_partial(int n, const double* __restrict__ V, int64_t ld,
                                                          const double* __restrict__ w, double* __restrict__ partial) {
+  __shared__ double sh[kBlock];
   const int t = blockIdx.y;
   const int nb = gridDim.x;
   const int64_t chunk = (int64_t(n) + nb - 1) / nb;
@@ -343,33 +362,27 @@ __global__ __launch_bounds__(kBlock) void k_mdot_partial(int n, const double* __
   const double* v = V + t * ld;
   double acc = 0.0;
   for (int64_t i = b0 + threadIdx.x; i < b1; i += kBlock) acc += v[i] * w[i];
-  __shared__ double sh[kBlock];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[t * nb + blockIdx.x] = sh[0];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[t * nb + blockIdx.x] = s;
 }
 
-// out[t] = sum_blk partial[t * nb + blk] (+ accumulate into out2[t] if given)
+// out[t] = sum_blk partial[t * nb + blk]; host_out (pinned host memory, may
+// be null) receives a copy, so the host needs no separate transfer.
 __global__ __launch_bounds__(kBlock) void k_reduce_partials(int k, int nb, const double* __restrict__ partial,
-                                                            double* __restrict__ out) {
+                                                            double* __restrict__ out, double* __restrict__ host_out = nullptr) {
   const int t = blockIdx.x;
   if (t >= k) return;
   __shared__ double sh[kBlock];
   double acc = 0.0;
   // fixed assignment of partials to threads and a fixed tree: deterministic
   for (int i = threadIdx.x; i < nb; i += kBlock) acc += partial[t * nb + i];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    out[t] = r;
+    if (host_out) host_out[t] = r;
   }
-  if (threadIdx.x == 0) out[t] = sh[0];
 }
+
 
 // w[i] -= sum_{t<k} V[t][i] * h[t]
 __global__ __launch_bounds__(kBlock) void k_mupdate(int n, const double* __restrict__ V, int64_t ld, int k,
@@ -411,31 +424,6 @@ __global__ __launch_bounds__(kBlock) void k_axpby(int n, double a, const double*
 __global__ __launch_bounds__(kBlock) void k_rsub(int n, const double* __restrict__ f, double* __restrict__ r) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i < n) r[i] = f[i] - r[i];
-}
-
-// Bordered operator tail: y[n] = sum(partial) (the constraint row b.u).
-__global__ void k_tail_from_partials(int np, const double* __restrict__ partial, double* __restrict__ y_tail) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int t = 0; t < np; ++t) s += partial[t];
-    *y_tail = s;
-  }
-}
-
-// Per-block partial sums of b.x (bordered operator tail), fixed order.
-template <typename S>
-__global__ __launch_bounds__(kBlock) void k_bdot_partial(int n, const S* __restrict__ b, const S* __restrict__ x,
-                                                         double* __restrict__ partial) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  double v = (i < n) ? double(b[i]) * double(x[i]) : 0.0;
-  __shared__ double sh[kBlock];
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
 }  // namespace
