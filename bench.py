@@ -14,15 +14,24 @@ V-cycles (FP32; FP16 values with FP32 row scales) are timed in turn; `value`
 is the solve time with the FP32 V-cycle (FP64 Krylov), the FP64 solve time
 and the ratio are reported beside it.
 
-roofline: the dominant kernel (the multicolour Gauss-Seidel colour phase,
-the most frequently launched and longest-running kernel of the V-cycle) is
-timed live with HIP events on its launch stream through mgm_time_kernel;
-achieved = algorithmic bytes per launch / mean launch time.
+roofline: the dominant kernel is the patch-blocked Gauss-Seidel launch
+(k_gs_patch, FP32 here: about 70% of the V-cycle's device time). Every
+smoother launch of one V-cycle (all smoothed levels, pre- and post-sweeps) is
+queued back to back on the launch stream between two HIP events through
+mgm_time_kernel; achieved = algorithmic bytes per launch (operator values and
+column indices of the rows a launch updates, plus their f, u read, u write,
+inverse diagonal and local colour, each once) / mean launch time. `traffic`
+is the HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE and
+WRITE_SIZE, scaled by what they read for a plain copy of known size) over the
+same launches; it is reported only while the kernel source is the one that
+was measured (null otherwise).
 
 cpu_baseline: the CPU oracle's FGMRES solve (same algorithm, FP64, NumPy/SciPy,
-single thread) on a bounded sample of the same workload family (N=40,000
-torus points, same discretisation and solver), scaled linearly in N to
-N=160,000 (iteration counts are N-independent for MGM, Tables 2-3).
+single thread) on the same workload (N=160,000; one solve of about 3 s after a
+setup of about a minute that is not timed). `--cpu-sample N` runs it on a
+smaller torus instead and scales the time linearly in N (iteration counts are
+N-independent for MGM, Tables 2-3), which underestimates: at N=40,000 the
+scaled figure is 0.78 s against 2.6 s measured at N=160,000.
 """
 from __future__ import annotations
 
@@ -37,12 +46,30 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the dominant kernel from two rocprofv3 --pmc passes over
+# `bench.py --workload traffic` (summary and commands in
+# profiles/gs_patch_torus160k_traffic.md): bytes per launch, valid only for
+# the kernel source it was measured on (SHA-256 over lane_ops.h + gs_patch.h).
+GS_TRAFFIC = {"source_sha256": "1113c69712c6360f509beec63e027bcc499fc56a371b72ff3d816bb66ff30b04", "bytes_per_launch": 5040384,
+              "summary": "profiles/gs_patch_torus160k_traffic.md"}
+
+
+def gs_traffic():
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("lane_ops.h", "gs_patch.h"):
+        with open(os.path.join(ROOT, "paper_2204_06154_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != GS_TRAFFIC["source_sha256"]:
+        return None
+    return GS_TRAFFIC["bytes_per_launch"]
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n_sample: int, n_full: int):
+def cpu_baseline(n_sample: int, n_full: int, reps: int = 1):
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -50,21 +77,26 @@ def cpu_baseline(n_sample: int, n_full: int):
     from oracle import hierarchy, krylov, vcycle
 
     wl = synth.torus_workload(n_sample)
+    t0 = time.perf_counter()
     H = hierarchy.build(wl.xyz, wl.normals, wl.params)
+    setup_s = time.perf_counter() - t0
     A = vcycle.make_operator(H)
     M = vcycle.make_preconditioner(vcycle.Fp64Ops(H), H.problem)
     f = np.concatenate([wl.f, [0.0]])
     ts = []
     with threadpool_limits(limits=1):
-        for _ in range(3):
+        for _ in range(reps):
             t0 = time.perf_counter()
             _, info = krylov.fgmres(A, M, f, tol=1e-10, restart=40, maxit=400)
             ts.append(time.perf_counter() - t0)
     t = float(np.median(ts))
-    return {"value": round(t * 1e3 * n_full / n_sample, 1), "unit": "ms", "cores": 1, "kind": "oracle",
-            "sample": f"oracle FP64 FGMRES(40) solve to 1e-10 on the torus workload at N={n_sample} "
-                      f"({info.iters} iterations, median {t:.3f} s of 3 solves, setup excluded), scaled "
-                      f"x{n_full / n_sample:g} to N={n_full}; SciPy sparse kernels, BLAS limited to 1 thread"}
+    scale = n_full / n_sample
+    where = (f"the torus workload itself (N={n_full})" if n_sample == n_full else
+             f"the torus workload at N={n_sample}, scaled x{scale:g} to N={n_full}")
+    return {"value": round(t * 1e3 * scale, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+            "sample": f"oracle FP64 FGMRES(40) + V(1,1) solve to 1e-10 on {where}: {info.iters} iterations, "
+                      f"median of {reps} solve(s) {t:.3f} s, setup ({setup_s:.0f} s, multi-threaded) excluded; "
+                      f"SciPy sparse kernels, BLAS limited to 1 thread"}
 
 
 def timed_solves(m, f, u, krylov, steps, warmup, **kw):
@@ -172,6 +204,33 @@ def bench_sphere1m(args):
     m.close()
 
 
+def bench_traffic(args):
+    """Launch set for the HBM-traffic counters: FP32 patch-GS launches of the
+    torus workload as the roofline times them (every smoother launch of a
+    V-cycle, `--steps` times), then three 256 MiB device copies whose
+    FETCH_SIZE / WRITE_SIZE readings calibrate the counters (each copy moves
+    exactly 256 MiB in and 256 MiB out)."""
+    import torch
+
+    import synth
+    from paper_2204_06154_amd import mgm
+
+    wl = synth.torus_workload(args.n)
+    m = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, gs_block=args.gs_block, precision=mgm.FP32), device=0)
+    f = torch.tensor(__import__("numpy").concatenate([wl.f, [0.0]]), device="cuda")
+    m.vcycle(f)
+    ms, nbytes = m.time_kernel("gs", -1, reps=args.steps)
+    torch.cuda.synchronize()
+    x = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "traffic", "n": args.n, "gs_us_per_launch": round(ms * 1e3, 3),
+                      "gs_bytes_per_launch": round(nbytes), "copy_bytes_each_way": 256 * 1024 * 1024}), flush=True)
+    m.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,11 +238,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=160_000)
     ap.add_argument("--precisions", default="fp64,fp32,fp16")
-    ap.add_argument("--cpu-sample", type=int, default=40_000)
+    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle points (0 = the workload's N)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--weights-n", type=int, default=500_000)
     ap.add_argument("--gs-block", type=int, default=256)
-    ap.add_argument("--workload", choices=["torus", "learned", "sphere1m"], default="torus")
+    ap.add_argument("--workload", choices=["torus", "learned", "sphere1m", "traffic"], default="torus")
     ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--learned-precision", default="fp32")
     args = ap.parse_args()
@@ -203,6 +262,8 @@ def main():
         if args.n == 160_000:
             args.n = 500_000
         return bench_learned(args)
+    if args.workload == "traffic":
+        return bench_traffic(args)
     if args.workload == "sphere1m":
         if args.n == 160_000:
             args.n = 1 << 20
@@ -244,12 +305,15 @@ def main():
 
     main_prec = "fp32" if "fp32" in results else list(results)[0]
     m.set_precision(main_prec)
-    gs_ms, gs_bytes = m.time_kernel("gs", 0, reps=10)
+    gs_ms, gs_bytes = m.time_kernel("gs", -1, reps=20)      # every smoother launch of a V-cycle
+    gs0_ms, gs0_bytes = m.time_kernel("gs", 0, reps=10)     # fine-level launches alone
     m.set_precision("fp64")
     sp_ms, sp_bytes = m.time_kernel("spmv", 0, reps=50)
     gs_gbs = gs_bytes / (gs_ms * 1e-3) / 1e9
     sp_gbs = sp_bytes / (sp_ms * 1e-3) / 1e9
-    log(f"GS colour phase ({main_prec}, fine level): {gs_ms * 1e3:.2f} us, {gs_bytes / 1e6:.2f} MB -> {gs_gbs:.0f} GB/s")
+    gs0_gbs = gs0_bytes / (gs0_ms * 1e-3) / 1e9
+    log(f"GS launches ({main_prec}, all levels of a V-cycle): {gs_ms * 1e3:.2f} us, {gs_bytes / 1e6:.2f} MB "
+        f"-> {gs_gbs:.0f} GB/s; fine level alone {gs0_ms * 1e3:.2f} us, {gs0_bytes / 1e6:.2f} MB -> {gs0_gbs:.0f} GB/s")
     log(f"SpMV (fp64, fine level): {sp_ms * 1e3:.2f} us, {sp_bytes / 1e6:.1f} MB -> {sp_gbs:.0f} GB/s")
 
     # batched per-node weight solves (500,000 star-surface stencils, n=50, r^3 + degree 3: 60x60 systems)
@@ -286,7 +350,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
-        cpu = cpu_baseline(args.cpu_sample, args.n)
+        cpu = cpu_baseline(args.cpu_sample or args.n, args.n)
         log(f"cpu baseline {cpu['value']} ms (took {time.perf_counter() - t0:.0f} s)")
 
     r = results[main_prec]
@@ -311,9 +375,14 @@ def main():
         "speedup_mixed_vs_fp64": round(results["fp64"]["ms"] / r["ms"], 3) if "fp64" in results else None,
         "spmv": {"kernel": "k_spmv fp64 fine level", "us": round(sp_ms * 1e3, 2), "bytes": sp_bytes,
                  "GBps": round(sp_gbs, 1), "frac": round(sp_gbs / HBM_PEAK_GBS, 4)},
-        "roofline": {"bound": "hbm", "kernel": f"k_gs_colour {main_prec} fine level (one colour phase)",
+        "roofline": {"bound": "hbm",
+                     "kernel": f"k_gs_patch {main_prec}: mean over the smoother launches of one V-cycle",
                      "achieved": round(gs_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gs_gbs / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(gs_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": gs_traffic() if main_prec == "fp32" else None,
+                     "algorithmic_bytes_per_launch": round(gs_bytes), "us_per_launch": round(gs_ms * 1e3, 3),
+                     "fine_level": {"us_per_launch": round(gs0_ms * 1e3, 3), "bytes_per_launch": round(gs0_bytes),
+                                    "GBps": round(gs0_gbs, 1)}},
         "batched_weights": bw,
         "cpu_baseline": cpu,
     }

@@ -78,10 +78,12 @@ typedef struct {
   int32_t precision;      /* MGM_FP64 | MGM_FP32 | MGM_FP16 (V-cycle only) */
   int32_t use_graph;      /* 1: replay the V-cycle as a captured HIP graph */
   int32_t device_weights; /* 1: stencil weights by the batched device solver */
-  int32_t gs_block;       /* smoother blocking: 0 = plain multicolour GS; B in 1..256 =
-                             patch-blocked multicolour GS with patches of B
-                             Morton-consecutive points (one workgroup per patch);
-                             levels with rows longer than 96 entries stay plain */
+  int32_t gs_block;       /* smoother blocking: 0 = plain multicolour GS (Jones-
+                             Plassmann colours); B in 1..256 = patch-blocked
+                             multicolour GS: patches of B points by recursive
+                             coordinate bisection, patch graph and in-patch graphs
+                             coloured by DSATUR, one workgroup per patch; levels
+                             with rows longer than 96 entries stay plain */
 } mgm_params;
 
 /* Paper defaults (Table 1): RBF-FD, k = l = 3, n = 20, forward GS, nu = 1,
@@ -224,6 +226,10 @@ mgm_status mgm_set_smoother(mgm_handle h, int32_t learned);
  *                    precision (Sec. 4.3): a colour phase (plain multicolour)
  *                    or a patch-colour launch (patch-blocked); averaged over
  *                    the launches of one sweep, bytes likewise per launch.
+ *                    level = -1: every smoother launch of one V-cycle (all
+ *                    smoothed levels, pre- and post-sweeps as the V-cycle
+ *                    issues them) queued back to back between one pair of
+ *                    events; *ms and *bytes are per launch.
  *   MGM_TK_RESIDUAL: residual r - L_j e of level `level`, current precision.
  *   MGM_TK_VCYCLE:   one whole V-cycle (Alg. 3) in the current precision;
  *                    bytes = sum over its kernels. */

@@ -987,7 +987,8 @@ static void time_kernel_impl(mgm_ctx* c, int which, int level, int reps, hipStre
   const int prec = c->p.precision;
   build_precision(c, prec);
   ensure_ws(c, 1);
-  if (which != MGM_TK_SPMV && which != MGM_TK_VCYCLE && (level < 0 || level + 1 >= int(c->lv.size())))
+  const bool all_gs = which == MGM_TK_GS && level == -1;
+  if (which != MGM_TK_SPMV && which != MGM_TK_VCYCLE && !all_gs && (level < 0 || level + 1 >= int(c->lv.size())))
     throw Error(MGM_E_ARG, "level out of range");
   if (reps < 1) throw Error(MGM_E_ARG, "reps must be >= 1");
   hipEvent_t e0, e1;
@@ -1016,6 +1017,35 @@ static void time_kernel_impl(mgm_ctx* c, int which, int level, int reps, hipStre
                                             d0.rowptr, d0.col, d0.v64, nullptr, c->vecs, c->vecs + c->ld, d0.b64,
                                             (const double*)nullptr));
       }, b);
+    } else if (all_gs) {
+      // the smoother launches of one V-cycle, in its order, as one timed batch
+      const bool bord = c->p.problem == MGM_POISSON;
+      const int p = int(c->lv.size());
+      int64_t launches = 0;
+      double b = 0.0;
+      for (int j = 0; j + 1 < p; ++j) {
+        const DevLevel& d = c->lv[j];
+        const int per = d.patched ? int(d.pc_start.size()) - 1 : d.ncol;
+        launches += int64_t(c->p.nu1 + c->p.nu2) * per;
+        b += c->p.nu1 * gs_sweep_bytes(c, j, prec, false) + c->p.nu2 * gs_sweep_bytes(c, j, prec, bord);
+      }
+      auto sweeps = [&] {
+        for (int j = 0; j + 1 < p; ++j) {
+          const bool zg = c->lv[j].patched && c->p.nu1 > 0;
+          for (int s = 0; s < c->p.nu1; ++s) {
+            if (prec == MGM_FP64) gs_sweep<double, double, false>(c, j, c->p.pre_smoother == MGM_GS_BWD, false, c->mu, st, zg && s == 0);
+            else if (prec == MGM_FP32) gs_sweep<float, float, false>(c, j, c->p.pre_smoother == MGM_GS_BWD, false, c->mu, st, zg && s == 0);
+            else gs_sweep<_Float16, float, true>(c, j, c->p.pre_smoother == MGM_GS_BWD, false, c->mu, st, zg && s == 0);
+          }
+          for (int s = 0; s < c->p.nu2; ++s) {
+            if (prec == MGM_FP64) gs_sweep<double, double, false>(c, j, c->p.post_smoother == MGM_GS_BWD, bord, c->mu, st);
+            else if (prec == MGM_FP32) gs_sweep<float, float, false>(c, j, c->p.post_smoother == MGM_GS_BWD, bord, c->mu, st);
+            else gs_sweep<_Float16, float, true>(c, j, c->p.post_smoother == MGM_GS_BWD, bord, c->mu, st);
+          }
+        }
+      };
+      timed(sweeps, b);
+      count += launches - 1;  // timed() counted the batch once
     } else if (which == MGM_TK_GS && c->lv[level].patched) {
       DevLevel& d = c->lv[level];
       for (int pc = 0; pc + 1 < int(d.pc_start.size()); ++pc) {

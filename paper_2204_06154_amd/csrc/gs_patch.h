@@ -1,0 +1,115 @@
+// Patch-blocked multicolour Gauss-Seidel sweep kernel for gfx950.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <climits>
+
+#include "lane_ops.h"
+
+namespace mgm {
+namespace {
+
+// Patch-blocked Gauss-Seidel: one workgroup sweeps one patch (<= kPatch rows)
+// of the current patch colour, kPatchG consecutive lanes per row. Patches of
+// one colour never couple, so the values outside the patch ("halo") are
+// constant during the launch: the lanes of a row fold its halo entries into
+// the right-hand side once, keep the in-patch entries (value, local column)
+// in registers, and the patch values live in LDS. The local colours are then
+// visited in order (reverse for a backward sweep), one barrier each: rows of
+// one local colour never couple, so this is sequential GS in the order
+// (patch colour, patch, local colour).
+// With zero_guess the sweep starts from u = 0 without reading u: rows of patch
+// colours visited earlier in this sweep hold their new values, all others are
+// taken as zero (so no separate clearing pass is needed).
+// Operator storage per patch slot: ELL with the level's width nw * kPatchG
+// and a fixed stride of `block` rows, entry i*kPatchG + g of local row t at
+// (slot * block * nw + i * block + t) * kPatchG + g, so the lanes of a
+// workgroup read consecutive addresses and the entry loads depend on no other
+// load; padding entries have value zero and a valid column.
+constexpr int kPatch = 256;
+constexpr int kPatchG = 4;
+template <typename V, typename S, int WL, bool SCALED, bool BORDER>
+__global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
+    int slot0, int reverse, int zero_guess, int nw, int block, const int32_t* __restrict__ pstart,
+    const int32_t* __restrict__ pncl, const int32_t* __restrict__ lcol,
+    const V* __restrict__ pval, const int32_t* __restrict__ pcol, const float* __restrict__ scale,
+    const S* __restrict__ dinv, const S* __restrict__ f, S* u, const S* __restrict__ b,
+    const double* __restrict__ lam) {
+  __shared__ S ul[kPatch];
+  const int slot = slot0 + blockIdx.x;
+  const int t = threadIdx.x / kPatchG;
+  const int g = threadIdx.x % kPatchG;
+  const bool slot_row = t < block;
+  // entry loads first: their addresses need no other load
+  const int64_t base = (int64_t(slot) * block * nw + t) * kPatchG + g;
+  int cc[WL];
+  S iv[WL];
+#pragma unroll
+  for (int i = 0; i < WL; ++i) {
+    const int ii = i < nw ? i : nw - 1;  // chunks >= nw: re-read the last one, zeroed below
+    const int64_t e = base + int64_t(ii) * block * kPatchG;
+    cc[i] = slot_row ? pcol[e] : 0;
+    iv[i] = (slot_row && i < nw) ? S(pval[e]) : S(0);
+  }
+  const int r0 = pstart[slot];
+  const int nr = pstart[slot + 1] - r0;
+  const int ncl = pncl[slot];
+  // rows [upd_lo, upd_hi) hold current values (all rows unless zero_guess)
+  int upd_lo = 0, upd_hi = INT_MAX;
+  if (zero_guess) {
+    if (reverse) upd_lo = pstart[slot0 + gridDim.x];
+    else upd_hi = pstart[slot0];
+  }
+  const bool act = t < nr;
+  const int row = r0 + t;
+  int ic[WL];
+  S rhs = S(0), di = S(0), sc = S(1), uown = S(0);
+  int myc = -1;
+  if (act) {
+    uown = zero_guess ? S(0) : u[row];
+    myc = lcol[row];
+    di = dinv[row];
+    rhs = f[row];
+    if (SCALED) sc = S(scale[row]);
+    if (BORDER) rhs -= b[row] * S(*lam);
+    S halo = S(0);
+#pragma unroll
+    for (int i = 0; i < WL; ++i) {
+      const bool live = i < nw;
+      const bool in = live && unsigned(cc[i] - r0) < unsigned(nr);
+      const bool cur = cc[i] >= upd_lo && cc[i] < upd_hi;
+      const S uv = (live && !in && cur) ? u[cc[i]] : S(0);
+      halo += iv[i] * uv;
+      ic[i] = in ? cc[i] - r0 : t;
+      iv[i] = in ? iv[i] : S(0);
+    }
+    halo = group_sum<kPatchG>(halo);
+    rhs -= sc * halo;
+    if (g == 0) ul[t] = uown;
+  }
+  __syncthreads();
+  // Each row keeps its own value in a register (only that row writes it).
+  for (int step = 0; step < ncl; ++step) {
+    const int c = reverse ? ncl - 1 - step : step;
+    if (myc == c) {  // all lanes of a row agree
+      S a0 = S(0), a1 = S(0), a2 = S(0), a3 = S(0);
+#pragma unroll
+      for (int i = 0; i < WL; i += 4) {
+        a0 += iv[i] * ul[ic[i]];
+        a1 += iv[i + 1] * ul[ic[i + 1]];
+        a2 += iv[i + 2] * ul[ic[i + 2]];
+        a3 += iv[i + 3] * ul[ic[i + 3]];
+      }
+      const S acc = group_sum<kPatchG>((a0 + a1) + (a2 + a3));
+      uown = uown + (rhs - sc * acc) * di;
+      if (g == 0) ul[t] = uown;
+    }
+    __syncthreads();
+  }
+  if (act && g == 0) u[row] = uown;
+}
+
+}  // namespace
+}  // namespace mgm

@@ -4,8 +4,8 @@
 // width W = stencil size, so its row pointer is implicit). A group of G
 // consecutive lanes of a wavefront owns one row: lane t reads entries t,
 // t+G, ... so a wavefront reads 64/G consecutive rows as one contiguous
-// stream, and the group's partial sums are combined with cross-lane
-// shuffles. Operator values are stored as V (double, float or _Float16 with
+// stream, and the group's partial sums are combined with DPP lane moves
+// (lane_ops.h). The patch-blocked smoother kernel is in gs_patch.h. Operator values are stored as V (double, float or _Float16 with
 // one float scale per row) and accumulated in S (double or float).
 #pragma once
 
@@ -14,40 +14,12 @@
 
 #include <climits>
 
+#include "lane_ops.h"
+
 namespace mgm {
 namespace {  // kernels have internal linkage: each translation unit owns its copies
 
 constexpr int kBlock = 256;
-
-// Lane exchange inside one DPP row of 16 lanes (no LDS round trip).
-template <int CTRL>
-__device__ __forceinline__ float dpp_mov(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v) {
-  const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(b)), CTRL, 0xF, 0xF, false));
-  const uint32_t hi = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(b >> 32)), CTRL, 0xF, 0xF, false));
-  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
-}
-constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
-constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
-constexpr int kDppHalfMirror = 0x141;  // lane i <- 7 - i within each 8
-constexpr int kDppMirror = 0x140;      // lane i <- 15 - i within each 16
-
-// Sum over each aligned group of G consecutive lanes (G = 1, 2, 4, 8, 16);
-// every lane of the group gets the same bits. All lanes of a group must be
-// active. Each stage adds two partial sums over disjoint lane sets.
-template <int G, typename S>
-__device__ __forceinline__ S group_sum(S v) {
-  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group of 1..16 lanes");
-  if constexpr (G >= 16) v += dpp_mov<kDppMirror>(v);
-  if constexpr (G >= 8) v += dpp_mov<kDppHalfMirror>(v);
-  if constexpr (G >= 4) v += dpp_mov<kDppXor2>(v);
-  if constexpr (G >= 2) v += dpp_mov<kDppXor1>(v);
-  return v;
-}
 
 template <typename V>
 __device__ __forceinline__ float to_f(V v) { return float(v); }
@@ -95,105 +67,13 @@ __global__ __launch_bounds__(kBlock) void k_gs_colour(int r0, int r1, int W, con
   if (lane == 0) u[row] = ui + ((fr - acc) - bl) * di;
 }
 
-// Patch-blocked Gauss-Seidel: one workgroup sweeps one patch (<= kPatch rows)
-// of the current patch colour, kPatchG consecutive lanes per row. Patches of
-// one colour never couple, so the values outside the patch ("halo") are
-// constant during the launch: the lanes of a row fold its halo entries into
-// the right-hand side once, keep the in-patch entries (value, local column)
-// in registers, and the patch values live in LDS. The local colours are then
-// visited in order (reverse for a backward sweep), one barrier each: rows of
-// one local colour never couple, so this is sequential GS in the order
-// (patch colour, patch, local colour).
-// With zero_guess the sweep starts from u = 0 without reading u: rows of patch
-// colours visited earlier in this sweep hold their new values, all others are
-// taken as zero (so no separate clearing pass is needed).
-// Operator storage per patch slot: ELL with the level's width nw * kPatchG
-// and a fixed stride of `block` rows, entry i*kPatchG + g of local row t at
-// (slot * block * nw + i * block + t) * kPatchG + g, so the lanes of a
-// workgroup read consecutive addresses and the entry loads depend on no other
-// load; padding entries have value zero and a valid column.
-constexpr int kPatch = 256;
-constexpr int kPatchG = 4;
-template <typename V, typename S, int WL, bool SCALED, bool BORDER>
-__global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
-    int slot0, int reverse, int zero_guess, int nw, int block, const int32_t* __restrict__ pstart,
-    const int32_t* __restrict__ pncl, const int32_t* __restrict__ lcol,
-    const V* __restrict__ pval, const int32_t* __restrict__ pcol, const float* __restrict__ scale,
-    const S* __restrict__ dinv, const S* __restrict__ f, S* u, const S* __restrict__ b,
-    const double* __restrict__ lam) {
-  __shared__ S ul[kPatch];
-  const int slot = slot0 + blockIdx.x;
-  const int t = threadIdx.x / kPatchG;
-  const int g = threadIdx.x % kPatchG;
-  const bool slot_row = t < block;
-  // entry loads first: their addresses need no other load
-  const int64_t base = (int64_t(slot) * block * nw + t) * kPatchG + g;
-  int cc[WL];
-  S iv[WL];
-#pragma unroll
-  for (int i = 0; i < WL; ++i) {
-    const int ii = i < nw ? i : nw - 1;  // chunks >= nw: re-read the last one, zeroed below
-    const int64_t e = base + int64_t(ii) * block * kPatchG;
-    cc[i] = slot_row ? pcol[e] : 0;
-    iv[i] = (slot_row && i < nw) ? S(pval[e]) : S(0);
-  }
-  const int r0 = pstart[slot];
-  const int nr = pstart[slot + 1] - r0;
-  const int ncl = pncl[slot];
-  // rows [upd_lo, upd_hi) hold current values (all rows unless zero_guess)
-  int upd_lo = 0, upd_hi = INT_MAX;
-  if (zero_guess) {
-    if (reverse) upd_lo = pstart[slot0 + gridDim.x];
-    else upd_hi = pstart[slot0];
-  }
-  const bool act = t < nr;
-  const int row = r0 + t;
-  int ic[WL];
-  S rhs = S(0), di = S(0), sc = S(1), uown = S(0);
-  int myc = -1;
-  if (act) {
-    uown = zero_guess ? S(0) : u[row];
-    myc = lcol[row];
-    di = dinv[row];
-    rhs = f[row];
-    if (SCALED) sc = S(scale[row]);
-    if (BORDER) rhs -= b[row] * S(*lam);
-    S halo = S(0);
-#pragma unroll
-    for (int i = 0; i < WL; ++i) {
-      const bool live = i < nw;
-      const bool in = live && unsigned(cc[i] - r0) < unsigned(nr);
-      const bool cur = cc[i] >= upd_lo && cc[i] < upd_hi;
-      const S uv = (live && !in && cur) ? u[cc[i]] : S(0);
-      halo += iv[i] * uv;
-      ic[i] = in ? cc[i] - r0 : t;
-      iv[i] = in ? iv[i] : S(0);
-    }
-    halo = group_sum<kPatchG>(halo);
-    rhs -= sc * halo;
-    if (g == 0) ul[t] = uown;
-  }
-  __syncthreads();
-  // Each row keeps its own value in a register (only that row writes it).
-  for (int step = 0; step < ncl; ++step) {
-    const int c = reverse ? ncl - 1 - step : step;
-    if (myc == c) {  // all lanes of a row agree
-      S a0 = S(0), a1 = S(0), a2 = S(0), a3 = S(0);
-#pragma unroll
-      for (int i = 0; i < WL; i += 4) {
-        a0 += iv[i] * ul[ic[i]];
-        a1 += iv[i + 1] * ul[ic[i + 1]];
-        a2 += iv[i + 2] * ul[ic[i + 2]];
-        a3 += iv[i + 3] * ul[ic[i + 3]];
-      }
-      const S acc = group_sum<kPatchG>((a0 + a1) + (a2 + a3));
-      uown = uown + (rhs - sc * acc) * di;
-      if (g == 0) ul[t] = uown;
-    }
-    __syncthreads();
-  }
-  if (act && g == 0) u[row] = uown;
-}
+}  // namespace
+}  // namespace mgm
+
+#include "gs_patch.h"
+
+namespace mgm {
+namespace {
 
 // res = f - A u over all rows; with BDOT also per-block partial sums of b.u
 // (written to partial[blockIdx.x], fixed order, deterministic).

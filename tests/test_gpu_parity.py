@@ -256,3 +256,16 @@ def test_solver_error_paths(case):
     assert info["status"] == 1 and info["iters"] == 1
     u, info = m.solve(_dev(np.zeros_like(f)))
     assert info["status"] == 0 and float(torch.abs(u).max()) == 0.0
+
+
+def test_time_kernel_modes(case):
+    """Profiling entry point: every mode returns a positive time and the
+    algorithmic bytes; the whole-V-cycle smoother batch averages per launch."""
+    name, wl, H, m = case
+    for which, level in (("spmv", 0), ("gs", 0), ("gs", -1), ("residual", 0), ("vcycle", 0)):
+        ms, nbytes = m.time_kernel(which, level, reps=2)
+        assert ms > 0.0 and nbytes > 0.0, (which, level)
+    _, b_all = m.time_kernel("gs", -1, reps=1)
+    _, b_v = m.time_kernel("vcycle", 0, reps=1)
+    assert b_all < b_v
+
