@@ -98,6 +98,7 @@ struct DevLevel {
   std::vector<int32_t> pc_rows;      // rows per patch colour (host)
   int32_t *pstart = nullptr, *pncl = nullptr, *lcol = nullptr, *pcolidx = nullptr;
   int pw = 0, pblock = 0;  // patch ELL: entries per lane and rows per slot
+  int pstart_host_slots = 0;  // number of patch slots
   double* pv64 = nullptr;
   float* pv32 = nullptr;
   _Float16* pv16 = nullptr;

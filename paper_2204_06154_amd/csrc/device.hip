@@ -25,6 +25,7 @@
 
 #include "ctx.h"
 #include "kernels_learned.h"
+#include "patch_ops.h"
 
 namespace mgm {
 
@@ -223,6 +224,7 @@ static void upload(mgm_ctx* c) {
           d.pc_nnz[pc] += int64_t(rp[ps[s + 1]] - rp[ps[s]]);
           d.pc_rows[pc] += ps[s + 1] - ps[s];
         }
+      d.pstart_host_slots = int(ps.size()) - 1;
       d.pstart = track(c, dupload(ps));
       d.pncl = track(c, dupload(pn));
       d.lcol = track(c, dupload(lc));
@@ -412,6 +414,21 @@ static void gs_patch_launch(mgm_ctx* c, int j, int pc, bool reverse, bool border
 #undef GS_PATCH
 }
 
+// Whole-level residual (MODE kRowResidual) or product (kRowApply) of a
+// patched level from its patch ELL: one workgroup per slot.
+template <typename V, typename S, bool SC, int MODE, bool BDOT, bool BORDER>
+static void rowop_patch_launch(const DevLevel& d, const V* val, const S* f, const S* x, S* out, const S* b,
+                               const S* lam, double* partial, hipStream_t st) {
+  const unsigned ns = unsigned(d.pstart_host_slots);
+#define ROWOP(WM)                                                                                           \
+  hipLaunchKernelGGL((k_rowop_patch<V, S, WM / kPatchG, SC, MODE, BDOT, BORDER>), dim3(ns), dim3(kPatch * kPatchG), \
+                     0, st, d.pw, d.pblock, d.pstart, val, d.pcolidx, d.s16, f, x, out, b, lam, partial)
+  if (d.wmax == 32) ROWOP(32);
+  else if (d.wmax == 64) ROWOP(64);
+  else ROWOP(96);
+#undef ROWOP
+}
+
 template <typename V, typename S, bool SC>
 static void gs_sweep(mgm_ctx* c, int j, bool reverse, bool border, const double* lam, hipStream_t st,
                      bool zero_guess = false) {
@@ -443,11 +460,18 @@ static void residual_restrict(mgm_ctx* c, int j, hipStream_t st) {
   DevLevel& d = c->lv[j];
   DevLevel& nx = c->lv[j + 1];
   const bool bord = c->p.problem == MGM_POISSON;
-  unsigned g = nblk(int64_t(d.n) * d.G);
-  DISPATCH_G(d.G, if (bord) hipLaunchKernelGGL((k_residual<V, S, GG, SC, true>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr, d.col,
-                     P::val(d), d.s16, P::f(d), P::e(d), P::res(d), P::b(d), c->partial);
-             else hipLaunchKernelGGL((k_residual<V, S, GG, SC, false>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr, d.col,
-                     P::val(d), d.s16, P::f(d), P::e(d), P::res(d), P::b(d), c->partial));
+  unsigned g;  // residual blocks = partial sums of b . e
+  if (d.patched) {
+    g = unsigned(d.pstart_host_slots);
+    if (bord) rowop_patch_launch<V, S, SC, kRowResidual, true, false>(d, P::pval(d), P::f(d), P::e(d), P::res(d), P::b(d), nullptr, c->partial, st);
+    else rowop_patch_launch<V, S, SC, kRowResidual, false, false>(d, P::pval(d), P::f(d), P::e(d), P::res(d), P::b(d), nullptr, c->partial, st);
+  } else {
+    g = nblk(int64_t(d.n) * d.G);
+    DISPATCH_G(d.G, if (bord) hipLaunchKernelGGL((k_residual<V, S, GG, SC, true>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr, d.col,
+                       P::val(d), d.s16, P::f(d), P::e(d), P::res(d), P::b(d), c->partial);
+               else hipLaunchKernelGGL((k_residual<V, S, GG, SC, false>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr, d.col,
+                       P::val(d), d.s16, P::f(d), P::e(d), P::res(d), P::b(d), c->partial));
+  }
   unsigned gr = nblk(int64_t(nx.n) * kRestrictG);
   if (bord)
     hipLaunchKernelGGL((k_restrict<S, S, true>), dim3(gr), dim3(kBlock), 0, st, nx.n, d.rptr, d.rcol, P::rw(d), P::res(d),
@@ -575,11 +599,16 @@ void precond(mgm_ctx* c, const double* v, double* z, const int32_t* perm, hipStr
 void apply_A(mgm_ctx* c, const double* x, double* y, hipStream_t st) {
   DevLevel& d = c->lv[0];
   const bool bord = c->p.problem == MGM_POISSON;
-  unsigned g = nblk(int64_t(d.n) * d.G);
-  DISPATCH_G(d.G, if (bord) hipLaunchKernelGGL((k_spmv<double, double, GG, false, true>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr,
-                     d.col, d.v64, nullptr, x, y, d.b64, x + d.n);
-             else hipLaunchKernelGGL((k_spmv<double, double, GG, false, false>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr,
-                     d.col, d.v64, nullptr, x, y, d.b64, x + d.n));
+  if (d.patched) {
+    if (bord) rowop_patch_launch<double, double, false, kRowApply, false, true>(d, d.pv64, nullptr, x, y, d.b64, x + d.n, nullptr, st);
+    else rowop_patch_launch<double, double, false, kRowApply, false, false>(d, d.pv64, nullptr, x, y, d.b64, x + d.n, nullptr, st);
+  } else {
+    unsigned g = nblk(int64_t(d.n) * d.G);
+    DISPATCH_G(d.G, if (bord) hipLaunchKernelGGL((k_spmv<double, double, GG, false, true>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr,
+                       d.col, d.v64, nullptr, x, y, d.b64, x + d.n);
+               else hipLaunchKernelGGL((k_spmv<double, double, GG, false, false>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr,
+                       d.col, d.v64, nullptr, x, y, d.b64, x + d.n));
+  }
   if (bord) mdot(c, d.n, d.b64, 0, 1, x, y + d.n, st);  // constraint row b . x
 }
 
@@ -828,9 +857,14 @@ static void level_op_t(mgm_ctx* c, int op, int j, double* x, const double* b, do
     gs_sweep<V, S, SC>(c, j, reverse, c->p.problem == MGM_POISSON, c->lam, st);
     hipLaunchKernelGGL((k_scatter<S, double>), dim3(g), dim3(kBlock), 0, st, d.n, d.perm, P::e(d), x, nullptr);
   } else if (op == MGM_OP_SPMV) {
-    unsigned gg = nblk(int64_t(d.n) * d.G);
-    DISPATCH_G(d.G, hipLaunchKernelGGL((k_spmv<V, S, GG, SC, false>), dim3(gg), dim3(kBlock), 0, st, d.n, d.W, d.rowptr, d.col,
-                                       P::val(d), d.s16, P::e(d), P::res(d), P::b(d), (const S*)nullptr));
+    if (d.patched) {
+      rowop_patch_launch<V, S, SC, kRowApply, false, false>(d, P::pval(d), nullptr, P::e(d), P::res(d), P::b(d), nullptr,
+                                                            nullptr, st);
+    } else {
+      unsigned gg = nblk(int64_t(d.n) * d.G);
+      DISPATCH_G(d.G, hipLaunchKernelGGL((k_spmv<V, S, GG, SC, false>), dim3(gg), dim3(kBlock), 0, st, d.n, d.W, d.rowptr,
+                                         d.col, P::val(d), d.s16, P::e(d), P::res(d), P::b(d), (const S*)nullptr));
+    }
     hipLaunchKernelGGL((k_scatter<S, double>), dim3(g), dim3(kBlock), 0, st, d.n, d.perm, P::res(d), y, nullptr);
   } else if (op == MGM_OP_RESTRICT_RESIDUAL) {
     hipLaunchKernelGGL((k_gather<double, S>), dim3(g), dim3(kBlock), 0, st, d.n, d.perm, b, P::f(d), nullptr);
@@ -978,6 +1012,10 @@ template <typename V, typename S, bool SC>
 static void residual_launch(mgm_ctx* c, int j, hipStream_t st) {
   using P = Prec<V, S, SC>;
   DevLevel& d = c->lv[j];
+  if (d.patched) {
+    rowop_patch_launch<V, S, SC, kRowResidual, false, false>(d, P::pval(d), P::f(d), P::e(d), P::res(d), P::b(d), nullptr, c->partial, st);
+    return;
+  }
   unsigned g = nblk(int64_t(d.n) * d.G);
   DISPATCH_G(d.G, hipLaunchKernelGGL((k_residual<V, S, GG, SC, false>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr, d.col,
                                      P::val(d), d.s16, P::f(d), P::e(d), P::res(d), P::b(d), c->partial));
@@ -1012,6 +1050,11 @@ static void time_kernel_impl(mgm_ctx* c, int which, int level, int reps, hipStre
     if (which == MGM_TK_SPMV) {
       double b = double(d0.nnz) * 12.0 + 16.0 * d0.n + (d0.W == 0 ? 4.0 * (d0.n + 1) : 0.0);
       timed([&] {
+        if (d0.patched) {
+          rowop_patch_launch<double, double, false, kRowApply, false, false>(d0, d0.pv64, nullptr, c->vecs, c->vecs + c->ld,
+                                                                             d0.b64, nullptr, nullptr, st);
+          return;
+        }
         unsigned g = nblk(int64_t(d0.n) * d0.G);
         DISPATCH_G(d0.G, hipLaunchKernelGGL((k_spmv<double, double, GG, false, false>), dim3(g), dim3(kBlock), 0, st, d0.n, d0.W,
                                             d0.rowptr, d0.col, d0.v64, nullptr, c->vecs, c->vecs + c->ld, d0.b64,

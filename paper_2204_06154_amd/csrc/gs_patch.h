@@ -42,16 +42,20 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
   const int t = threadIdx.x / kPatchG;
   const int g = threadIdx.x % kPatchG;
   const bool slot_row = t < block;
+  const int tt = slot_row ? t : 0;  // lanes past the slot's rows read row 0's entries (in bounds, unused)
   // entry loads first: their addresses need no other load
-  const int64_t base = (int64_t(slot) * block * nw + t) * kPatchG + g;
+  const int64_t base = (int64_t(slot) * block * nw + tt) * kPatchG + g;
   int cc[WL];
   S iv[WL];
 #pragma unroll
   for (int i = 0; i < WL; ++i) {
     const int ii = i < nw ? i : nw - 1;  // chunks >= nw: re-read the last one, zeroed below
     const int64_t e = base + int64_t(ii) * block * kPatchG;
-    cc[i] = slot_row ? pcol[e] : 0;
-    iv[i] = (slot_row && i < nw) ? S(pval[e]) : S(0);
+    // unconditional loads: no branch forces a wait between them
+    const int32_t cv = pcol[e];
+    const V vv = pval[e];
+    cc[i] = cv;
+    iv[i] = (slot_row && i < nw) ? S(vv) : S(0);
   }
   const int r0 = pstart[slot];
   const int nr = pstart[slot + 1] - r0;

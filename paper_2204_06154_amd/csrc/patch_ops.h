@@ -1,0 +1,96 @@
+// Whole-level row operators that read the operator from the patch ELL of a
+// patch-blocked level (the smoother's storage): one workgroup per patch slot,
+// kPatchG lanes per row, so every entry load of a workgroup covers 1024
+// consecutive elements and the operator streams at full width.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gs_patch.h"
+#include "lane_ops.h"
+
+namespace mgm {
+namespace {
+
+// MODE kRowResidual: out = f - A x (SCALED: A = diag(scale) H), and with BDOT
+//   partial[slot] = sum over the slot's rows of b_i x_i (fixed tree).
+// MODE kRowApply:   out = A x, plus b_i * (*lam) when BORDER (the bordered
+//   operator's multiplier column).
+constexpr int kRowResidual = 0;
+constexpr int kRowApply = 1;
+template <typename V, typename S, int WL, bool SCALED, int MODE, bool BDOT, bool BORDER>
+__global__ __launch_bounds__(kPatch * kPatchG) void k_rowop_patch(
+    int nw, int block, const int32_t* __restrict__ pstart, const V* __restrict__ pval,
+    const int32_t* __restrict__ pcol, const float* __restrict__ scale, const S* __restrict__ f,
+    const S* __restrict__ x, S* __restrict__ out, const S* __restrict__ b, const S* __restrict__ lam,
+    double* __restrict__ partial) {
+  const int slot = blockIdx.x;
+  const int t = threadIdx.x / kPatchG;
+  const int g = threadIdx.x % kPatchG;
+  const bool slot_row = t < block;
+  const int tt = slot_row ? t : 0;  // lanes past the slot's rows read row 0's entries (in bounds, unused)
+  const int64_t base = (int64_t(slot) * block * nw + tt) * kPatchG + g;
+  int cc[WL];
+  S iv[WL];
+#pragma unroll
+  for (int i = 0; i < WL; ++i) {
+    const int ii = i < nw ? i : nw - 1;
+    const int64_t e = base + int64_t(ii) * block * kPatchG;
+    // unconditional loads: no branch forces a wait between them
+    const int32_t cv = pcol[e];
+    const V vv = pval[e];
+    cc[i] = cv;
+    iv[i] = (slot_row && i < nw) ? S(vv) : S(0);
+  }
+  const int r0 = pstart[slot];
+  const int nr = pstart[slot + 1] - r0;
+  const bool act = t < nr;
+  const int row = r0 + t;
+  // The slot's own rows are a contiguous range of x: stage it in LDS and take
+  // the in-patch columns (most of them) from there; only the halo columns go
+  // to the cache hierarchy, and those loads are issued before the barrier.
+  __shared__ S xl[kPatch];
+  if (act && g == 0) xl[t] = x[row];
+  S a0 = S(0), a1 = S(0);
+  if (act) {
+#pragma unroll
+    for (int i = 0; i < WL; i += 2) {
+      if (i < nw && unsigned(cc[i] - r0) >= unsigned(nr)) a0 += iv[i] * x[cc[i]];
+      if (i + 1 < nw && unsigned(cc[i + 1] - r0) >= unsigned(nr)) a1 += iv[i + 1] * x[cc[i + 1]];
+    }
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int i = 0; i < WL; i += 2) {
+      if (i < nw && unsigned(cc[i] - r0) < unsigned(nr)) a0 += iv[i] * xl[cc[i] - r0];
+      if (i + 1 < nw && unsigned(cc[i + 1] - r0) < unsigned(nr)) a1 += iv[i + 1] * xl[cc[i + 1] - r0];
+    }
+  }
+  S acc = group_sum<kPatchG>(a0 + a1);
+  double bx = 0.0;
+  if (act && g == 0) {
+    if (SCALED) acc *= S(scale[row]);
+    if (MODE == kRowResidual) {
+      out[row] = f[row] - acc;
+      if (BDOT) bx = double(b[row]) * double(x[row]);
+    } else {
+      if (BORDER) acc += b[row] * (*lam);
+      out[row] = acc;
+    }
+  }
+  if (BDOT) {
+    __shared__ double sh[kPatch * kPatchG];
+    sh[threadIdx.x] = bx;
+    __syncthreads();
+    for (int s = kPatch * kPatchG / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[slot] = sh[0];
+  }
+}
+
+}  // namespace
+}  // namespace mgm
