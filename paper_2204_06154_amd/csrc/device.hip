@@ -416,13 +416,15 @@ static void gs_patch_launch(mgm_ctx* c, int j, int pc, bool reverse, bool border
 
 // Whole-level residual (MODE kRowResidual) or product (kRowApply) of a
 // patched level from its patch ELL: one workgroup per slot.
-template <typename V, typename S, bool SC, int MODE, bool BDOT, bool BORDER>
-static void rowop_patch_launch(const DevLevel& d, const V* val, const S* f, const S* x, S* out, const S* b,
-                               const S* lam, double* partial, hipStream_t st) {
+template <typename V, typename S, bool SC, int MODE, bool BDOT, bool BORDER, typename X = S>
+static void rowop_patch_launch(const DevLevel& d, const V* val, const S* f, const X* x, S* out, const S* b,
+                               const S* lam, double* partial, hipStream_t st, const S* dinv = nullptr,
+                               const S* omega = nullptr, S* xcopy = nullptr) {
   const unsigned ns = unsigned(d.pstart_host_slots);
 #define ROWOP(WM)                                                                                           \
-  hipLaunchKernelGGL((k_rowop_patch<V, S, WM / kPatchG, SC, MODE, BDOT, BORDER>), dim3(ns), dim3(kPatch * kPatchG), \
-                     0, st, d.pw, d.pblock, d.pstart, val, d.pcolidx, d.s16, f, x, out, b, lam, partial)
+  hipLaunchKernelGGL((k_rowop_patch<V, S, X, WM / kPatchG, SC, MODE, BDOT, BORDER>), dim3(ns), dim3(kPatch * kPatchG), \
+                     0, st, d.pw, d.pblock, d.pstart, val, d.pcolidx, d.s16, f, x, out, b, lam, partial, dinv, omega, \
+                     xcopy, d.n)
   if (d.wmax == 32) ROWOP(32);
   else if (d.wmax == 64) ROWOP(64);
   else ROWOP(96);
@@ -492,19 +494,33 @@ static void interp_add(mgm_ctx* c, int j, hipStream_t st) {
 // Fine-level learned smoother: s Richardson steps with per-node step weights
 // (ping-pong between e and a scratch vector, the result left in e).
 template <typename V, typename S, bool SC>
-static void learned_sweep(mgm_ctx* c, hipStream_t st) {
+static void learned_sweep(mgm_ctx* c, hipStream_t st, bool zero_start = false) {
   using P = Prec<V, S, SC>;
   DevLevel& d = c->lv[0];
   S* e = P::e(d);
   S* tmp = reinterpret_cast<S*>(sizeof(S) == 8 ? static_cast<void*>(c->e_tmp64) : static_cast<void*>(c->e_tmp32));
   const S* om = reinterpret_cast<const S*>(sizeof(S) == 8 ? static_cast<const void*>(c->ls_om64)
                                                            : static_cast<const void*>(c->ls_om32));
+  const unsigned g = nblk(int64_t(d.n) * d.G);
+  auto step = [&](int q, const S* in, S* out) {
+    if (d.patched)
+      rowop_patch_launch<V, S, SC, kRowRichardson, false, false>(d, P::pval(d), P::f(d), in, out, nullptr, nullptr,
+                                                                 nullptr, st, P::dinv(d), om + size_t(q) * d.n);
+    else
+      DISPATCH_G(d.G, hipLaunchKernelGGL((k_richardson<V, S, GG, SC>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr,
+                                         d.col, P::val(d), d.s16, P::dinv(d), om + size_t(q) * d.n, P::f(d), in, out));
+  };
+  int q = 0;
   S* a = e;
   S* b = tmp;
-  const unsigned g = nblk(int64_t(d.n) * d.G);
-  for (int q = 0; q < c->ls_s; ++q) {
-    DISPATCH_G(d.G, hipLaunchKernelGGL((k_richardson<V, S, GG, SC>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr,
-                                       d.col, P::val(d), d.s16, P::dinv(d), om + size_t(q) * d.n, P::f(d), a, b));
+  if (zero_start) {
+    // from e = 0 the first step is e = omega_1 D^-1 f: no operator pass, written in place
+    hipLaunchKernelGGL((k_scale_start<S>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, om, P::dinv(d), P::f(d), e);
+    q = 1;
+  }
+  // the remaining steps ping-pong; with an odd count the result lands in tmp and is copied back
+  for (; q < c->ls_s; ++q) {
+    step(q, a, b);
     std::swap(a, b);
   }
   if (a != e) hipLaunchKernelGGL((k_gather<S, S>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, (const int32_t*)nullptr, a, e,
@@ -520,10 +536,10 @@ static void vcycle_enqueue(mgm_ctx* c, hipStream_t st) {
     DevLevel& d = c->lv[j];
     // e_j starts at zero: a patch-blocked first sweep assumes it without reading e_j
     const bool learned = j == 0 && c->ls_active;
-    const bool zg = d.patched && c->p.nu1 > 0 && !learned;
+    const bool zg = (d.patched || learned) && c->p.nu1 > 0;
     if (!zg) hipLaunchKernelGGL((k_fill<S>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, P::e(d), S(0));
     for (int s = 0; s < c->p.nu1; ++s) {
-      if (learned) learned_sweep<V, S, SC>(c, st);
+      if (learned) learned_sweep<V, S, SC>(c, st, s == 0);
       else gs_sweep<V, S, SC>(c, j, c->p.pre_smoother == MGM_GS_BWD, false, c->mu, st, zg && s == 0);
     }
     residual_restrict<V, S, SC>(c, j, st);
@@ -593,6 +609,32 @@ void precond(mgm_ctx* c, const double* v, double* z, const int32_t* perm, hipStr
     vcycle_core(c, st);
     hipLaunchKernelGGL((k_scatter<float, double>), dim3(g), dim3(kBlock), 0, st, d.n, perm, d.e32, z, bord ? c->mu : nullptr);
   }
+}
+
+// v = x / |x| (|x|^2 on the device) and the V-cycle's fine-level input cast
+// of v in one pass (FGMRES basis vectors are always the next V-cycle input).
+static void normalise_to_vcycle(mgm_ctx* c, int64_t n, const double* x, const double* nrm2, double* v, hipStream_t st) {
+  DevLevel& d = c->lv[0];
+  double* rho = c->p.problem == MGM_POISSON ? c->rho : nullptr;
+  if (c->p.precision == MGM_FP64)
+    hipLaunchKernelGGL((k_normalise_cast<double>), dim3(nblk(n)), dim3(kBlock), 0, st, int(n), x, nrm2, v, d.f64, d.n, rho);
+  else
+    hipLaunchKernelGGL((k_normalise_cast<float>), dim3(nblk(n)), dim3(kBlock), 0, st, int(n), x, nrm2, v, d.f32, d.n, rho);
+}
+
+// z = widened V-cycle output and y = A z in one pass over the operator
+// (patch-blocked fine level); the bordered constraint row follows as a dot.
+static void apply_from_vcycle(mgm_ctx* c, double* z, double* y, hipStream_t st) {
+  DevLevel& d = c->lv[0];
+  const bool bord = c->p.problem == MGM_POISSON;
+  if (c->p.precision == MGM_FP64) {
+    if (bord) rowop_patch_launch<double, double, false, kRowApply, false, true, double>(d, d.pv64, nullptr, d.e64, y, d.b64, c->mu, nullptr, st, nullptr, nullptr, z);
+    else rowop_patch_launch<double, double, false, kRowApply, false, false, double>(d, d.pv64, nullptr, d.e64, y, d.b64, c->mu, nullptr, st, nullptr, nullptr, z);
+  } else {
+    if (bord) rowop_patch_launch<double, double, false, kRowApply, false, true, float>(d, d.pv64, nullptr, d.e32, y, d.b64, c->mu, nullptr, st, nullptr, nullptr, z);
+    else rowop_patch_launch<double, double, false, kRowApply, false, false, float>(d, d.pv64, nullptr, d.e32, y, d.b64, c->mu, nullptr, st, nullptr, nullptr, z);
+  }
+  if (bord) mdot(c, d.n, d.b64, 0, 1, z, y + d.n, st);  // constraint row b . z
 }
 
 // y = A x (FP64 fine operator, permuted order; bordered tail at index n).
@@ -710,16 +752,25 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
       if (info.iters > 0) info.restarts++;
       double* V = c->V;
       double* Z = c->Z;
-      // V0 = r / beta (beta^2 is on device in dh[0])
-      hipLaunchKernelGGL(k_normalise, dim3(g), dim3(kBlock), 0, st, int(n), r, c->dh, V);
+      // V0 = r / beta (beta^2 is on device in dh[0]); on a patch-blocked fine
+      // level the basis vectors go straight into the V-cycle's input and its
+      // output is widened inside the operator pass (no separate casts)
+      const bool fused = d0.patched;
+      if (fused) normalise_to_vcycle(c, n, r, c->dh, V, st);
+      else hipLaunchKernelGGL(k_normalise, dim3(g), dim3(kBlock), 0, st, int(n), r, c->dh, V);
       std::fill(H.begin(), H.end(), 0.0);
       std::fill(gv.begin(), gv.end(), 0.0);
       gv[0] = beta;
       int k = 0;
       for (int j = 0; j < m; ++j) {
-        precond(c, V + j * ld, Z + j * ld, nullptr, st);
+        if (fused) {
+          vcycle_core(c, st);
+          apply_from_vcycle(c, Z + j * ld, w, st);
+        } else {
+          precond(c, V + j * ld, Z + j * ld, nullptr, st);
+          apply_A(c, Z + j * ld, w, st);
+        }
         info.iters++;
-        apply_A(c, Z + j * ld, w, st);
         // CGS2: two projections, then the norm; the dots land on the host directly
         const double* hp = c->hpin;
         mdot(c, n, V, ld, j + 1, w, c->dh, st, c->hpin);
@@ -727,7 +778,8 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
         mdot(c, n, V, ld, j + 1, w, c->dh + 256, st, c->hpin + 256);
         hipLaunchKernelGGL(k_mupdate, dim3(g), dim3(kBlock), 0, st, int(n), V, ld, j + 1, c->dh + 256, w);
         mdot(c, n, w, ld, 1, w, c->dh + 512, st, c->hpin + 512);
-        hipLaunchKernelGGL(k_normalise, dim3(g), dim3(kBlock), 0, st, int(n), w, c->dh + 512, V + (j + 1) * ld);
+        if (fused) normalise_to_vcycle(c, n, w, c->dh + 512, V + (j + 1) * ld, st);
+        else hipLaunchKernelGGL(k_normalise, dim3(g), dim3(kBlock), 0, st, int(n), w, c->dh + 512, V + (j + 1) * ld);
         host_wait(st);
         for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = hp[i] + hp[256 + i];
         const double hn = std::sqrt(hp[512]);
@@ -982,10 +1034,16 @@ static double vcycle_bytes(const mgm_ctx* c, int prec) {
   double tot = 0.0;
   for (int j = 0; j + 1 < p; ++j) {
     const DevLevel& d = c->lv[j];
-    tot += bvec(prec) * d.n;  // zero fill
-    if (j == 0 && c->ls_active) {
+    const bool learned = j == 0 && c->ls_active;
+    if (!((d.patched || learned) && c->p.nu1 > 0)) tot += bvec(prec) * d.n;  // zero fill
+    if (learned) {
       const double step = double(d.nnz) * (bval(prec) + 4.0) + double(d.n) * (5.0 * bvec(prec));
-      tot += (c->p.nu1 + c->p.nu2) * c->ls_s * step;
+      int steps = (c->p.nu1 + c->p.nu2) * c->ls_s;
+      if (c->p.nu1 > 0) {  // the first step from zero reads omega, dinv, f and writes e
+        --steps;
+        tot += 4.0 * bvec(prec) * d.n;
+      }
+      tot += steps * step;
     } else {
       tot += c->p.nu1 * gs_sweep_bytes(c, j, prec, false) + c->p.nu2 * gs_sweep_bytes(c, j, prec, bord);
     }

@@ -293,6 +293,22 @@ __global__ __launch_bounds__(kBlock) void k_normalise(int n, const double* __res
   y[i] = s > 0.0 ? x[i] / s : 0.0;
 }
 
+// k_normalise that also hands the result to the V-cycle: f0 = S(y) on the
+// first nf entries and, bordered, *rho = y[nf] (what the preconditioner's
+// input cast would write).
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_normalise_cast(int n, const double* __restrict__ x,
+                                                           const double* __restrict__ nrm2, double* __restrict__ y,
+                                                           S* __restrict__ f0, int nf, double* __restrict__ rho) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double s = sqrt(*nrm2);
+  const double v = s > 0.0 ? x[i] / s : 0.0;
+  y[i] = v;
+  if (i < nf) f0[i] = S(v);
+  else if (rho && i == nf) *rho = v;
+}
+
 // z = a*x + b*y (a, b host scalars)
 __global__ __launch_bounds__(kBlock) void k_axpby(int n, double a, const double* __restrict__ x, double b,
                                                   const double* __restrict__ y, double* __restrict__ z) {

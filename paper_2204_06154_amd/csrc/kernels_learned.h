@@ -37,6 +37,15 @@ __global__ __launch_bounds__(kBlock) void k_richardson(int n, int W, const int32
   if (lane == 0) eout[row] = er + om * di * (fr - acc);
 }
 
+// First Richardson step from e = 0: e = omega * dinv * f (same association
+// as k_richardson with e_in = 0).
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_scale_start(int n, const S* __restrict__ omega, const S* __restrict__ dinv,
+                                                        const S* __restrict__ f, S* __restrict__ e) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) e[i] = omega[i] * dinv[i] * f[i];
+}
+
 // training forward step: z = dinv * (A e_in); e_out = e_in - omega * z (FP32)
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_train_step(int n, int W, const int32_t* __restrict__ rowptr,

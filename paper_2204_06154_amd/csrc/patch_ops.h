@@ -17,14 +17,22 @@ namespace {
 //   partial[slot] = sum over the slot's rows of b_i x_i (fixed tree).
 // MODE kRowApply:   out = A x, plus b_i * (*lam) when BORDER (the bordered
 //   operator's multiplier column).
+// MODE kRowRichardson: out = x + omega_i dinv_i (f - A x), one step of the
+//   learned per-node smoother (out and x distinct).
 constexpr int kRowResidual = 0;
 constexpr int kRowApply = 1;
-template <typename V, typename S, int WL, bool SCALED, int MODE, bool BDOT, bool BORDER>
+constexpr int kRowRichardson = 2;
+// x may be stored in a narrower type X than the arithmetic type S; with xcopy
+// given, every row also writes S(x_i) there (and, bordered, xcopy[tail] =
+// *lam): the FGMRES step uses this to widen the preconditioner's FP32 output
+// while applying the operator to it.
+template <typename V, typename S, typename X, int WL, bool SCALED, int MODE, bool BDOT, bool BORDER>
 __global__ __launch_bounds__(kPatch * kPatchG) void k_rowop_patch(
     int nw, int block, const int32_t* __restrict__ pstart, const V* __restrict__ pval,
     const int32_t* __restrict__ pcol, const float* __restrict__ scale, const S* __restrict__ f,
-    const S* __restrict__ x, S* __restrict__ out, const S* __restrict__ b, const S* __restrict__ lam,
-    double* __restrict__ partial) {
+    const X* __restrict__ x, S* __restrict__ out, const S* __restrict__ b, const S* __restrict__ lam,
+    double* __restrict__ partial, const S* __restrict__ dinv, const S* __restrict__ omega,
+    S* __restrict__ xcopy, int tail) {
   const int slot = blockIdx.x;
   const int t = threadIdx.x / kPatchG;
   const int g = threadIdx.x % kPatchG;
@@ -51,13 +59,17 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_rowop_patch(
   // the in-patch columns (most of them) from there; only the halo columns go
   // to the cache hierarchy, and those loads are issued before the barrier.
   __shared__ S xl[kPatch];
-  if (act && g == 0) xl[t] = x[row];
+  if (act && g == 0) {
+    xl[t] = S(x[row]);
+    if (xcopy) xcopy[row] = S(x[row]);
+  }
+  if (BORDER && xcopy && slot == 0 && threadIdx.x == 0) xcopy[tail] = *lam;
   S a0 = S(0), a1 = S(0);
   if (act) {
 #pragma unroll
     for (int i = 0; i < WL; i += 2) {
-      if (i < nw && unsigned(cc[i] - r0) >= unsigned(nr)) a0 += iv[i] * x[cc[i]];
-      if (i + 1 < nw && unsigned(cc[i + 1] - r0) >= unsigned(nr)) a1 += iv[i + 1] * x[cc[i + 1]];
+      if (i < nw && unsigned(cc[i] - r0) >= unsigned(nr)) a0 += iv[i] * S(x[cc[i]]);
+      if (i + 1 < nw && unsigned(cc[i + 1] - r0) >= unsigned(nr)) a1 += iv[i + 1] * S(x[cc[i + 1]]);
     }
   }
   __syncthreads();
@@ -74,7 +86,9 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_rowop_patch(
     if (SCALED) acc *= S(scale[row]);
     if (MODE == kRowResidual) {
       out[row] = f[row] - acc;
-      if (BDOT) bx = double(b[row]) * double(x[row]);
+      if (BDOT) bx = double(b[row]) * double(xl[t]);
+    } else if (MODE == kRowRichardson) {
+      out[row] = xl[t] + omega[row] * dinv[row] * (f[row] - acc);
     } else {
       if (BORDER) acc += b[row] * (*lam);
       out[row] = acc;
