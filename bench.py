@@ -50,7 +50,7 @@ HBM_PEAK_GBS = 8000.0
 # `bench.py --workload traffic` (summary and commands in
 # profiles/gs_patch_torus160k_traffic.md): bytes per launch, valid only for
 # the kernel source it was measured on (SHA-256 over lane_ops.h + gs_patch.h).
-GS_TRAFFIC = {"source_sha256": "1113c69712c6360f509beec63e027bcc499fc56a371b72ff3d816bb66ff30b04", "bytes_per_launch": 5040384,
+GS_TRAFFIC = {"source_sha256": "c8931d11cd0e9109e853f706235d2d453b1e6b4b04aeaced6e9aa4dba94e61ac", "bytes_per_launch": 5034462,
               "summary": "profiles/gs_patch_torus160k_traffic.md"}
 
 
@@ -373,7 +373,8 @@ def main():
         "solves": {p: {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in d.items()}
                    for p, d in results.items()},
         "speedup_mixed_vs_fp64": round(results["fp64"]["ms"] / r["ms"], 3) if "fp64" in results else None,
-        "spmv": {"kernel": "k_spmv fp64 fine level", "us": round(sp_ms * 1e3, 2), "bytes": sp_bytes,
+        "spmv": {"kernel": "outer FP64 operator, fine level (k_rowop_patch on the patch ELL; k_spmv on plain levels)",
+                 "us": round(sp_ms * 1e3, 2), "bytes": sp_bytes,
                  "GBps": round(sp_gbs, 1), "frac": round(sp_gbs / HBM_PEAK_GBS, 4)},
         "roofline": {"bound": "hbm",
                      "kernel": f"k_gs_patch {main_prec}: mean over the smoother launches of one V-cycle",
