@@ -24,9 +24,19 @@ def _flat(params):
                            np.vstack([W3, b3[None]]).ravel()])
 
 
-@pytest.fixture(scope="module")
-def setup():
-    wl = synth.sphere_workload(4096)
+CASES = {
+    # jittered Fibonacci sphere N=4096, RBF-FD r^3 + deg 2, k=30 (screened)
+    "sphere4096": lambda: synth.sphere_workload(4096),
+    # the learned-smoother workload family at small N: star surface with 16:1
+    # density bumps, RBF-FD r^3 + deg 2, k=30, screened
+    "stardens6000": lambda: synth.star_density_workload(6000, n_probe=60_000),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES), ids=list(CASES))
+def setup(request):
+    wl = CASES[request.param]()
+    print(f"[gpu-learned] setting up {request.param}", flush=True)
     H = hierarchy.build(wl.xyz, wl.normals, wl.params)
     m = mgm.Mgm(wl.xyz, wl.normals, wl.params, device=0)
     starts = np.random.default_rng(21).standard_normal((2, len(wl.xyz)))

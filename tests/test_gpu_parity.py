@@ -218,6 +218,27 @@ def test_reduced_precision_solve(case, prec):
     assert abs(info["iters"] - info_ref.iters) <= 1, (info["iters"], info_ref.iters)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_reduced_precision_bicgstab(case, prec):
+    """The reduced-precision V-cycle inside BiCGSTAB (the 1M-point GFD sphere's
+    solver): true FP64 residual 1e-10, applications within +-2 of the FP64
+    oracle's (one BiCGSTAB step applies the preconditioner twice)."""
+    name, wl, H, m = case
+    f = _rhs(wl, H)
+    A = vcycle.make_operator(H)
+    M = vcycle.make_preconditioner(vcycle.Fp64Ops(H), H.problem)
+    _, info_ref = krylov.bicgstab(A, M, f, tol=1e-10, maxit=300)
+    m.set_precision(prec)
+    try:
+        u, info = m.solve(_dev(f), krylov="bicgstab", maxit=300, rtol=1e-10)
+    finally:
+        m.set_precision("fp64")
+    u = _host(u)
+    assert info["status"] == 0
+    assert np.linalg.norm(f - A(u)) <= 1.01e-10 * np.linalg.norm(f)
+    assert abs(info["iters"] - info_ref.iters) <= 2, (info["iters"], info_ref.iters)
+
+
 def test_stationary_iteration_matches_oracle(case):
     name, wl, H, m = case
     m.set_precision("fp64")
