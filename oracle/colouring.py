@@ -10,7 +10,8 @@ so it depends only on the colour of each row.
 
 Colouring rules (integer-only, so two implementations agree bit for bit).
 Plain multicolour ordering uses Jones-Plassmann with largest-degree-first
-priorities; the patch-blocked ordering (below) uses DSATUR.
+priorities; the patch-blocked ordering (below) uses recursive largest first
+for the patch graph and DSATUR inside patches.
 Jones-Plassmann: nodes are ranked by
 (degree descending, h(i) ascending, i ascending) with
 h(i) = splitmix64(i) >> 32 (the SplitMix64 finaliser of Steele, Lea & Flood,
@@ -117,6 +118,47 @@ def dsatur_colouring(G: sp.csr_matrix) -> np.ndarray:
     return colour.astype(np.int32)
 
 
+def rlf_colouring(G: sp.csr_matrix) -> np.ndarray:
+    """Leighton's recursive-largest-first rule (J. Res. NBS 84, 1979): colour
+    classes are filled one at a time. A class starts with the uncoloured node
+    that has the most uncoloured neighbours; the uncoloured neighbours of a
+    class member can no longer join the class ("excluded"). The class then
+    repeatedly takes the still-eligible node with the most excluded neighbours
+    (ties: fewer eligible neighbours, then smaller index) until no node is
+    eligible. Neighbour counts are kept up to date as nodes change state."""
+    N = G.shape[0]
+    indptr, nbr = G.indptr, G.indices
+    colour = np.full(N, -1, dtype=np.int64)
+    uncoloured = np.ones(N, dtype=bool)
+    n_unc = np.diff(indptr).astype(np.int64)  # uncoloured neighbours
+    c = 0
+    while uncoloured.any():
+        eligible = uncoloured.copy()
+        n_elig = n_unc.copy()                  # eligible neighbours
+        n_excl = np.zeros(N, dtype=np.int64)   # excluded neighbours
+        cand = np.nonzero(eligible)[0]
+        v = int(cand[np.lexsort((cand, -n_unc[cand]))[0]])
+        while True:
+            colour[v] = c
+            eligible[v] = False
+            uncoloured[v] = False
+            for u in nbr[indptr[v]:indptr[v + 1]]:
+                n_elig[u] -= 1
+                n_unc[u] -= 1
+            for u in nbr[indptr[v]:indptr[v + 1]]:
+                if eligible[u]:                 # u becomes excluded
+                    eligible[u] = False
+                    for x in nbr[indptr[u]:indptr[u + 1]]:
+                        n_elig[x] -= 1
+                        n_excl[x] += 1
+            cand = np.nonzero(eligible)[0]
+            if len(cand) == 0:
+                break
+            v = int(cand[np.lexsort((cand, n_elig[cand], -n_excl[cand]))[0]])
+        c += 1
+    return colour.astype(np.int32)
+
+
 # ------------------------------------------------------------------ patches
 def rcb_patches(xyz: np.ndarray, block: int) -> np.ndarray:
     """Patch id of every point by recursive coordinate bisection.
@@ -151,8 +193,9 @@ def patch_colouring(pat: sp.csr_matrix, xyz: np.ndarray, block: int):
 
     Rows are cut into compact patches of `block` points by recursive
     coordinate bisection; the patch graph (patches coupled by any entry of the
-    symmetrised pattern) is coloured by the DSATUR rule, and so is the graph of
-    the couplings inside patches. Rows with equal (patch colour, local colour)
+    symmetrised pattern) is coloured by the recursive-largest-first rule (it
+    needs fewer patch colours, i.e. launches, than DSATUR here), and the graph
+    of the couplings inside patches by DSATUR. Rows with equal (patch colour, local colour)
     never couple, so GS over the composite colour pcolour * C + lcolour
     (C = number of local colours) is sequential GS in a permutation: one pass
     over the patch colours, each patch visiting its local colours in turn.
@@ -170,7 +213,7 @@ def patch_colouring(pat: sp.csr_matrix, xyz: np.ndarray, block: int):
     PG.sum_duplicates()
     PG.sort_indices()
     PG.data[:] = 1
-    pcol = dsatur_colouring(PG)
+    pcol = rlf_colouring(PG)
     inner = ~cross
     GI = sp.csr_matrix((np.ones(int(inner.sum()), dtype=np.int64), (row_of[inner], G.indices[inner])), shape=(N, N))
     GI.sort_indices()

@@ -352,6 +352,58 @@ static int dsatur_range(const std::vector<int32_t>& ptr, const std::vector<int32
   return maxc;
 }
 
+// Recursive largest first (Leighton 1979): colour classes are filled one at a
+// time. A class starts with the uncoloured node with the most uncoloured
+// neighbours (ties: smaller index); the uncoloured neighbours of a member are
+// excluded from the class; the class then repeatedly takes the eligible node
+// with the most excluded neighbours (ties: fewer eligible neighbours, then
+// smaller index). Neighbour counts are updated as nodes change state. O(n^2)
+// per class: meant for the small patch graph. Returns the number of colours.
+static int rlf_colour(const std::vector<int32_t>& ptr, const std::vector<int32_t>& adj, std::vector<int32_t>& colour) {
+  const int32_t n = int32_t(ptr.size()) - 1;
+  colour.assign(n, -1);
+  std::vector<char> uncol(n, 1), elig(n);
+  std::vector<int32_t> n_unc(n), n_elig(n), n_excl(n);
+  for (int32_t v = 0; v < n; ++v) n_unc[v] = ptr[v + 1] - ptr[v];
+  int32_t left = n, c = 0;
+  while (left > 0) {
+    for (int32_t v = 0; v < n; ++v) {
+      elig[v] = uncol[v];
+      n_elig[v] = n_unc[v];
+      n_excl[v] = 0;
+    }
+    int32_t v = -1;
+    for (int32_t x = 0; x < n; ++x)
+      if (elig[x] && (v < 0 || n_unc[x] > n_unc[v])) v = x;
+    while (v >= 0) {
+      colour[v] = c;
+      elig[v] = 0;
+      uncol[v] = 0;
+      --left;
+      for (int32_t k = ptr[v]; k < ptr[v + 1]; ++k) {
+        --n_elig[adj[k]];
+        --n_unc[adj[k]];
+      }
+      for (int32_t k = ptr[v]; k < ptr[v + 1]; ++k) {
+        const int32_t u = adj[k];
+        if (!elig[u]) continue;
+        elig[u] = 0;  // excluded from this class
+        for (int32_t q = ptr[u]; q < ptr[u + 1]; ++q) {
+          --n_elig[adj[q]];
+          ++n_excl[adj[q]];
+        }
+      }
+      v = -1;
+      for (int32_t x = 0; x < n; ++x) {
+        if (!elig[x]) continue;
+        if (v < 0 || n_excl[x] > n_excl[v] || (n_excl[x] == n_excl[v] && n_elig[x] < n_elig[v])) v = x;
+      }
+    }
+    ++c;
+  }
+  return c;
+}
+
 // Patch id of every point by recursive coordinate bisection: a set of more
 // than `block` points is sorted by (coordinate, index) along the axis of its
 // largest bounding-box extent (first such axis on ties) and cut after the
@@ -428,8 +480,7 @@ void smoother_colouring(HostLevel& l, int block) {
     pptr[p + 1] = pptr[p] + int32_t(r.size());
     padj.insert(padj.end(), r.begin(), r.end());
   }
-  l.pcolour.assign(l.npatch, -1);
-  const int npc = dsatur_range(pptr, padj, 0, l.npatch, l.pcolour);
+  const int npc = rlf_colour(pptr, padj, l.pcolour);
   // DSATUR on the union of the patch graphs = DSATUR on every patch alone (a
   // choice in one patch never changes another's saturations): run them in
   // parallel over the rows of each patch, renumbered to be contiguous.

@@ -309,6 +309,52 @@ def _dsatur_plain(G):
     return np.array(colour)
 
 
+def _rlf_plain(G):
+    """Recursive largest first with every count recomputed from the sets at
+    every pick (tiny graphs)."""
+    N = G.shape[0]
+    adj = [set(G.indices[G.indptr[i]:G.indptr[i + 1]].tolist()) for i in range(N)]
+    colour = [-1] * N
+    uncol = set(range(N))
+    c = 0
+    while uncol:
+        elig, excl = set(uncol), set()
+        v = max(elig, key=lambda x: (len(adj[x] & uncol), -x))
+        while True:
+            colour[v] = c
+            uncol.discard(v)
+            elig.discard(v)
+            moved = adj[v] & elig
+            elig -= moved
+            excl |= moved
+            if not elig:
+                break
+            v = max(elig, key=lambda x: (len(adj[x] & excl), -len(adj[x] & elig), -x))
+        c += 1
+    return np.array(colour)
+
+
+def test_rlf_known_cases():
+    def graph(n, edges):
+        e = np.array(edges)
+        return colouring.symmetric_graph(sp.coo_matrix((np.ones(len(e)), (e[:, 0], e[:, 1])), shape=(n, n)).tocsr())
+    # path 0-1-2-3: the class of node 1 (largest degree, smaller index) takes 3 as well
+    assert colouring.rlf_colouring(graph(4, [(0, 1), (1, 2), (2, 3)])).tolist() == [1, 0, 1, 0]
+    # star with centre 4: the first class is the centre alone, then all leaves
+    assert colouring.rlf_colouring(graph(5, [(4, k) for k in range(4)])).tolist() == [1, 1, 1, 1, 0]
+    # odd cycle: three colours; complete graph K_6: six
+    assert colouring.rlf_colouring(graph(9, [(k, (k + 1) % 9) for k in range(9)])).max() == 2
+    assert sorted(colouring.rlf_colouring(colouring.symmetric_graph(sp.csr_matrix(np.ones((6, 6)))))) == list(range(6))
+    # random graphs: valid, and the same as the plain recount
+    rng = np.random.default_rng(11)
+    for n in (30, 60):
+        A = sp.random(n, n, density=0.12, random_state=rng, format="csr")
+        G = colouring.symmetric_graph(A)
+        c = colouring.rlf_colouring(G)
+        assert colouring.is_valid_colouring(A, c)
+        assert np.array_equal(c, _rlf_plain(G))
+
+
 def test_rcb_patches_on_a_grid_are_rectangles():
     """A 32 x 16 grid in the plane cut into patches of 64 points: the longer
     axis is halved until 8 x 8 squares remain, numbered left half first."""
@@ -362,7 +408,7 @@ def test_patch_colouring_pins():
         assert np.array_equal(patch, lv.patches["patch"])
         sizes = np.bincount(patch)
         assert np.all(sizes[:-1] == 64) and 0 < sizes[-1] <= 64
-        # patch colours and local colours follow the DSATUR rule
+        # patch colours follow recursive largest first, local colours DSATUR
         G = colouring.symmetric_graph(lv.pat)
         rows = np.repeat(np.arange(G.shape[0]), np.diff(G.indptr))
         cross = patch[rows] != patch[G.indices]
@@ -371,7 +417,7 @@ def test_patch_colouring_pins():
                            shape=(npatch, npatch))
         PG.sum_duplicates()
         PG.sort_indices()
-        assert np.array_equal(lv.patches["pcolour"], _dsatur_plain(PG))
+        assert np.array_equal(lv.patches["pcolour"], _rlf_plain(PG))
         GI = sp.csr_matrix((np.ones((~cross).sum()), (rows[~cross], G.indices[~cross])), shape=G.shape)
         GI.sort_indices()
         if G.shape[0] <= 800:  # the plain scan is quadratic
