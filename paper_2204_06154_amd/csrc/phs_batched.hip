@@ -35,6 +35,23 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
+// Maximum of an unsigned 32-bit value over the 64 lanes of a wavefront, all
+// lanes active, by DPP: prefix maxima within each row of 16 lanes (row_shr
+// 1, 2, 4, 8), then row_bcast:15 and row_bcast:31 carry the row maxima up to
+// lane 63, which is read back. Lanes without a DPP source read 0, the
+// identity of an unsigned maximum, so each step can fold into one v_max.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  auto mx = [](int x, int y) { return int(uint32_t(x) > uint32_t(y) ? uint32_t(x) : uint32_t(y)); };
+  int t = int(v);
+  t = mx(t, __builtin_amdgcn_update_dpp(0, t, 0x111, 0xF, 0xF, true));  // row_shr:1
+  t = mx(t, __builtin_amdgcn_update_dpp(0, t, 0x112, 0xF, 0xF, true));  // row_shr:2
+  t = mx(t, __builtin_amdgcn_update_dpp(0, t, 0x114, 0xF, 0xF, true));  // row_shr:4
+  t = mx(t, __builtin_amdgcn_update_dpp(0, t, 0x118, 0xF, 0xF, true));  // row_shr:8
+  t = mx(t, __builtin_amdgcn_update_dpp(0, t, 0x142, 0xA, 0xF, true));  // row_bcast:15 into rows 1, 3
+  t = mx(t, __builtin_amdgcn_update_dpp(0, t, 0x143, 0xC, 0xF, true));  // row_bcast:31 into rows 2, 3
+  return uint32_t(__builtin_amdgcn_readlane(t, 63));
+}
+
 __device__ __forceinline__ double ipow_d(double x, int e) {
   double r = 1.0;
   for (int t = 0; t < e; ++t) r *= x;
@@ -142,18 +159,18 @@ __global__ __launch_bounds__(64 * kWaves) void k_phs_weights(int64_t nsys, int n
   for (int k = 0; k < SMAX; ++k) {
     if (k < S) {
       const double v = a[k];
-      double bv = used ? -1.0 : fabs(v);
-      int bl = lane;
-      for (int off = 32; off > 0; off >>= 1) {
-        double ov = __shfl_xor(bv, off, 64);
-        int ol = __shfl_xor(bl, off, 64);
-        if (ov > bv || (ov == bv && ol < bl)) {
-          bv = ov;
-          bl = ol;
-        }
-      }
-      bl = __builtin_amdgcn_readfirstlane(bl);
-      if (!(bv > tiny)) singular = true;
+      // pivot: the unused lane with the largest |a_lk|, ties to the lower lane.
+      // |a| as a non-negative double orders like its bit pattern: compare the
+      // high words (+1 so that used lanes, keyed 0, never win), then the low
+      // words among the lanes holding the maximum, then take the lowest lane.
+      const uint64_t bits = __builtin_bit_cast(uint64_t, fabs(v));
+      const uint32_t khi = used ? 0u : uint32_t(bits >> 32) + 1u;
+      const uint32_t mhi = wave_max_u32(khi);
+      const bool top = khi == mhi;
+      const uint32_t mlo = wave_max_u32(top ? uint32_t(bits) : 0u);
+      const int bl = int(__builtin_ctzll(__ballot(top && uint32_t(bits) == mlo)));
+      const double bv = used ? -1.0 : fabs(v);
+      if (!(readlane_d(bv, bl) > tiny)) singular = true;
       const double piv = readlane_d(v, bl);
       const double mlt = (lane == bl) ? 0.0 : v / piv;
 #pragma unroll
@@ -195,8 +212,20 @@ void batched_phs_weights_device(const double* d_xyz, const double* d_nrm, const 
   if (nsys <= 0) return;
   const int m = 2 * phs_order + 1;
   const unsigned blocks = unsigned((nsys + kWaves - 1) / kWaves);
-  hipLaunchKernelGGL(k_phs_weights<64>, dim3(blocks), dim3(64 * kWaves), 0, st, nsys, ns, L, m, d_xyz, d_nrm, d_sten,
-                     d_w, d_status);
+  // the register row is sized for the system: S = 60 (50 points, degree 3) needs 61 doubles, not 65
+  const int S = ns + L;
+  if (S <= 32)
+    hipLaunchKernelGGL(k_phs_weights<32>, dim3(blocks), dim3(64 * kWaves), 0, st, nsys, ns, L, m, d_xyz, d_nrm, d_sten,
+                       d_w, d_status);
+  else if (S <= 48)
+    hipLaunchKernelGGL(k_phs_weights<48>, dim3(blocks), dim3(64 * kWaves), 0, st, nsys, ns, L, m, d_xyz, d_nrm, d_sten,
+                       d_w, d_status);
+  else if (S <= 60)
+    hipLaunchKernelGGL(k_phs_weights<60>, dim3(blocks), dim3(64 * kWaves), 0, st, nsys, ns, L, m, d_xyz, d_nrm, d_sten,
+                       d_w, d_status);
+  else
+    hipLaunchKernelGGL(k_phs_weights<64>, dim3(blocks), dim3(64 * kWaves), 0, st, nsys, ns, L, m, d_xyz, d_nrm, d_sten,
+                       d_w, d_status);
   HIPOK(hipGetLastError());
 }
 
