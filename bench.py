@@ -50,7 +50,7 @@ HBM_PEAK_GBS = 8000.0
 # `bench.py --workload traffic` (summary and commands in
 # profiles/gs_patch_torus160k_traffic.md): bytes per launch, valid only for
 # the kernel source it was measured on (SHA-256 over lane_ops.h + gs_patch.h).
-GS_TRAFFIC = {"source_sha256": "c8931d11cd0e9109e853f706235d2d453b1e6b4b04aeaced6e9aa4dba94e61ac", "bytes_per_launch": 5034462,
+GS_TRAFFIC = {"source_sha256": "c8931d11cd0e9109e853f706235d2d453b1e6b4b04aeaced6e9aa4dba94e61ac", "bytes_per_launch": 5314544,
               "summary": "profiles/gs_patch_torus160k_traffic.md"}
 
 
