@@ -131,13 +131,13 @@ def bench_learned(args):
     wl = synth.star_density_workload(args.n)
     log(f"inputs N={args.n} generated in {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
-    m = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, precision=args.learned_precision), device=0)
+    m = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, precision=args.vcycle_precision), device=0)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     f = torch.tensor(wl.f, device="cuda")
     u = torch.zeros_like(f)
     out = {"workload": f"star surface, 16:1 density bumps, N={args.n}, RBF-FD r^3+deg2 k=30, screened mu=1, "
-                       f"FGMRES(40) to 1e-10, V-cycle {args.learned_precision}",
+                       f"FGMRES(40) to 1e-10, V-cycle {args.vcycle_precision}",
            "levels": [int(x) for x in m.export("level_sizes")], "setup_s": round(setup_s, 2)}
     ms, info = timed_solves(m, f, u, "fgmres", args.steps, args.warmup, restart=40, maxit=400, rtol=1e-10)
     vc_ms, _ = m.time_kernel("vcycle", 0, reps=10)
@@ -204,6 +204,48 @@ def bench_sphere1m(args):
     m.close()
 
 
+def bench_sbdf2(args):
+    """Repeated screened solves: SBDF2 steps of u_t = Delta u on a sphere of N
+    points (RBF-FD r^3 + deg 2, k=30, dt = 0.05, so L = I - (2 dt / 3) D),
+    FGMRES + MGM to 1e-8 from the extrapolated guess 2u^n - u^{n-1} (warm)
+    and from zero (cold); the right-hand sides are formed on the device."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2204_06154_amd import mgm
+
+    t0 = time.perf_counter()
+    wl = synth.sbdf2_workload(args.n)
+    log(f"inputs N={args.n} generated in {time.perf_counter() - t0:.1f} s")
+    prec = args.vcycle_precision
+    m = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, precision=prec), device=0)
+    u0 = torch.tensor(wl.f, device="cuda")
+    out = {"workload": f"SBDF2 time stepping of u_t = Delta u, unit sphere N={args.n}, RBF-FD r^3+deg2 k=30, "
+                       f"dt=0.05, FGMRES(40)+MGM to 1e-8, V-cycle {prec}",
+           "levels": [int(x) for x in m.export("level_sizes")]}
+    nsteps = max(args.steps, 1) * 4
+    for mode in ("warm", "cold"):
+        u_prev, u_cur = u0.clone(), u0.clone()
+        iters, times = [], []
+        for k in range(nsteps + 1):      # step 0 warms the graphs up and is not timed
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rhs = (4.0 * u_cur - u_prev) / 3.0
+            u = 2.0 * u_cur - u_prev if mode == "warm" else torch.zeros_like(u_cur)
+            u, info = m.solve(rhs, u, krylov="fgmres", restart=40, maxit=200, rtol=1e-8, x0=(mode == "warm"))
+            torch.cuda.synchronize()
+            if k > 0:
+                times.append(time.perf_counter() - t0)
+                iters.append(info["iters"])
+            u_prev, u_cur = u_cur, u
+        out[mode] = {"steps": nsteps, "ms_per_step": round(1e3 * float(np.mean(times)), 3), "iters": iters}
+        log(f"{mode}: {out[mode]['ms_per_step']:.2f} ms per step, iterations {iters}")
+    out["speedup_warm_vs_cold"] = round(out["cold"]["ms_per_step"] / out["warm"]["ms_per_step"], 3)
+    print(json.dumps(out), flush=True)
+    m.close()
+
+
 def bench_traffic(args):
     """Launch set for the HBM-traffic counters: FP32 patch-GS launches of the
     torus workload as the roofline times them (every smoother launch of a
@@ -242,9 +284,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--weights-n", type=int, default=500_000)
     ap.add_argument("--gs-block", type=int, default=256)
-    ap.add_argument("--workload", choices=["torus", "learned", "sphere1m", "traffic"], default="torus")
+    ap.add_argument("--workload", choices=["torus", "learned", "sphere1m", "traffic", "sbdf2"], default="torus")
     ap.add_argument("--train-steps", type=int, default=200)
-    ap.add_argument("--learned-precision", default="fp32")
+    ap.add_argument("--vcycle-precision", default="fp32", help="V-cycle precision of the learned and sbdf2 workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the MGM solve is not sharded across GPUs in this build "
@@ -264,6 +306,10 @@ def main():
         return bench_learned(args)
     if args.workload == "traffic":
         return bench_traffic(args)
+    if args.workload == "sbdf2":
+        if args.n == 160_000:
+            args.n = 300_000
+        return bench_sbdf2(args)
     if args.workload == "sphere1m":
         if args.n == 160_000:
             args.n = 1 << 20

@@ -102,7 +102,7 @@ def learned_sweep(ops, u, f):
     return u
 
 
-def vcycle(ops, r, rho=None, nu1=1, nu2=1, post_reverse=False, capture=None):
+def vcycle(ops, r, rho=None, nu1=1, nu2=1, post_reverse=False, capture=None, pre_reverse=False):
     """z = M r (Alg. 3 with zero initial guess). Bordered: returns (z, lambda).
 
     With `ops.learned` set (an N_1 x s array of step weights) the fine level
@@ -123,7 +123,7 @@ def vcycle(ops, r, rho=None, nu1=1, nu2=1, post_reverse=False, capture=None):
             if j == 0 and getattr(ops, "learned", None) is not None:
                 learned_sweep(ops, e[j], rhs[j])
             else:
-                gs_sweep(ops, j, e[j], rhs[j], 0.0, reverse=False)
+                gs_sweep(ops, j, e[j], rhs[j], 0.0, reverse=pre_reverse)
         res = rhs[j] - ops.L(j, e[j])
         rhs[j + 1] = ops.R(j, res)
         if bordered:
@@ -144,15 +144,16 @@ def vcycle(ops, r, rho=None, nu1=1, nu2=1, post_reverse=False, capture=None):
     return e[0]
 
 
-def make_preconditioner(ops, problem, nu1=1, nu2=1, post_reverse=False):
-    """Preconditioner on FP64 vectors of length N (screened) or N+1 (bordered)."""
+def make_preconditioner(ops, problem, nu1=1, nu2=1, post_reverse=False, pre_reverse=False):
+    """Preconditioner on FP64 vectors of length N (screened) or N+1 (bordered).
+    pre_reverse / post_reverse select backward Gauss-Seidel sweeps (Sec. 4.3)."""
     if problem == "poisson":
         def M(v):
-            z, lam = vcycle(ops, v[:-1], float(v[-1]), nu1, nu2, post_reverse)
+            z, lam = vcycle(ops, v[:-1], float(v[-1]), nu1, nu2, post_reverse, pre_reverse=pre_reverse)
             return np.concatenate([np.asarray(z, dtype=np.float64), [lam]])
     else:
         def M(v):
-            return np.asarray(vcycle(ops, v, None, nu1, nu2, post_reverse), dtype=np.float64)
+            return np.asarray(vcycle(ops, v, None, nu1, nu2, post_reverse, pre_reverse=pre_reverse), dtype=np.float64)
     return M
 
 

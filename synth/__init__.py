@@ -316,6 +316,20 @@ def sphere_workload(n: int = 4096, jitter: float = 0.1, lmax: int = 8, config_id
     return Workload(f"sphere{n}", x, x.copy(), f, params)
 
 
+def sbdf2_workload(n: int = 300_000, dt: float = 0.05, jitter: float = 0.1, lmax: int = 8,
+                   config_id: int = 6) -> Workload:
+    """Repeated screened solves of SBDF2 time stepping for u_t = Delta u on the
+    unit sphere: (I - (2 dt / 3) Delta) u^{n+1} = (4 u^n - u^{n-1}) / 3.
+    Jittered Fibonacci points, RBF-FD r^3 + deg 2, k=30; `f` holds u^0, a
+    random spherical-harmonic field."""
+    rp, rf, _ = rng_streams(config_id)
+    x = jittered_fibonacci_sphere(n, rp, jitter)
+    u0 = sh_rhs(x, lmax, rf)
+    params = dict(disc="rbffd", phs_order=1, poly_degree=2, stencil_size=30, problem="screened",
+                  mu=2.0 * dt / 3.0, n_min=250, n_coarse_max=0)
+    return Workload(f"sbdf2_{n}", x, x.copy(), u0, params)
+
+
 def torus_workload(n: int = 160_000, config_id: int = 2) -> Workload:
     """Torus, Poisson-disk points, Poisson (bordered) with zero-mean trig f (RBF-FD r^5 + deg 3, k=50)."""
     rp, rf, _ = rng_streams(config_id)

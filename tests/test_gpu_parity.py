@@ -239,6 +239,47 @@ def test_reduced_precision_bicgstab(case, prec):
     assert abs(info["iters"] - info_ref.iters) <= 2, (info["iters"], info_ref.iters)
 
 
+@pytest.mark.parametrize("nu1,nu2,pre,post", [(2, 2, "fwd", "fwd"), (1, 1, "fwd", "bwd"), (0, 2, "fwd", "bwd"),
+                                               (2, 0, "bwd", "fwd")])
+def test_cycle_variants_match_oracle(case, nu1, nu2, pre, post):
+    """V(nu1, nu2) with forward or backward sweeps (Sec. 4.3; symmetric GS =
+    forward pre- and backward post-smoothing): V-cycle to 1e-10 and the FGMRES
+    iteration count of the oracle with the same cycle."""
+    name, wl, H, m = case
+    p = dict(wl.params, nu1=nu1, nu2=nu2, pre_smoother=pre, post_smoother=post)
+    mv = mgm.Mgm(wl.xyz, wl.normals, p, device=0)
+    try:
+        M = vcycle.make_preconditioner(vcycle.Fp64Ops(H), H.problem, nu1, nu2, post_reverse=post == "bwd",
+                                       pre_reverse=pre == "bwd")
+        f = _rhs(wl, H)
+        assert _rel(_host(mv.vcycle(_dev(f))), M(f)) < 1e-10
+        A = vcycle.make_operator(H)
+        _, info_ref = krylov.fgmres(A, M, f, tol=1e-10, maxit=300)
+        u, info = mv.solve(_dev(f), krylov="fgmres", restart=40, maxit=300, rtol=1e-10)
+        assert info["status"] == 0 and info["iters"] == info_ref.iters, (info["iters"], info_ref.iters)
+        assert np.linalg.norm(f - A(_host(u))) <= 1.01e-10 * np.linalg.norm(f)
+    finally:
+        mv.close()
+
+
+def test_warm_start_matches_oracle(case):
+    """FGMRES from a caller-supplied initial guess (a perturbed solution, as
+    a time-stepping solve would pass): the same iteration count as the
+    oracle's FGMRES from the same guess."""
+    name, wl, H, m = case
+    m.set_precision("fp64")
+    f = _rhs(wl, H)
+    A = vcycle.make_operator(H)
+    M = vcycle.make_preconditioner(vcycle.Fp64Ops(H), H.problem)
+    x_ref, _ = krylov.fgmres(A, M, f, tol=1e-10, maxit=300)
+    x0 = x_ref + 1e-4 * np.random.default_rng(16).standard_normal(len(f)) * np.abs(x_ref).max()
+    _, info_ref = krylov.fgmres(A, M, f, tol=1e-10, maxit=300, x0=x0)
+    u = _dev(x0)
+    u, info = m.solve(_dev(f), u, krylov="fgmres", restart=40, maxit=300, rtol=1e-10, x0=True)
+    assert info["status"] == 0 and info["iters"] == info_ref.iters, (info["iters"], info_ref.iters)
+    assert np.linalg.norm(f - A(_host(u))) <= 1.01e-10 * np.linalg.norm(f)
+
+
 def test_stationary_iteration_matches_oracle(case):
     name, wl, H, m = case
     m.set_precision("fp64")

@@ -82,14 +82,17 @@ def test_bordered_gs_holds_multiplier(torus_h):
 
 
 # ------------------------------------------------------------ V-cycle (Alg. 3)
-def _dense_two_level(L, P, B, nu1, nu2):
-    """Dense V(nu1,nu2) two-level operator M (zero initial guess) from its definition."""
+def _dense_two_level(L, P, B, nu1, nu2, B_post=None):
+    """Dense V(nu1,nu2) two-level operator M (zero initial guess) from its
+    definition; B (and B_post for the post-smoother, default B) is the matrix
+    whose inverse one Gauss-Seidel sweep applies."""
     n = L.shape[0]
     I = np.eye(n)
     S = I - np.linalg.solve(B, L)                   # error propagation of one smoothing step
+    Sp = S if B_post is None else I - np.linalg.solve(B_post, L)
     LH = P.T @ L @ P
     C = I - P @ np.linalg.solve(LH, P.T @ L)        # coarse-grid correction
-    E = np.linalg.matrix_power(S, nu2) @ C @ np.linalg.matrix_power(S, nu1)
+    E = np.linalg.matrix_power(Sp, nu2) @ C @ np.linalg.matrix_power(S, nu1)
     return (I - E) @ np.linalg.inv(L)
 
 
@@ -110,6 +113,28 @@ def test_two_level_cycle_matches_dense_definition(nu1, nu2):
     Md = _dense_two_level(L, lv.P.toarray(), B, nu1, nu2)
     r = np.random.default_rng(3).standard_normal(lv.N)
     z = vcycle.vcycle(ops, r, None, nu1, nu2)
+    assert np.max(np.abs(z - Md @ r)) <= 1e-10 * np.max(np.abs(Md @ r))
+
+
+@pytest.mark.parametrize("pre_rev,post_rev", [(False, True), (True, False), (True, True)])
+def test_two_level_backward_sweeps_match_dense_definition(pre_rev, post_rev):
+    """Backward GS is the triangular solve with the upper triangle in the
+    colour order, so symmetric GS (forward pre, backward post) is
+    (I - E) L^-1 with S_post = I - triu(L)^-1 L."""
+    wl = synth.sphere_workload(600)
+    wl.params["n_coarse_max"] = 160
+    H = hierarchy.build(wl.xyz, wl.normals, wl.params)
+    lv = H.levels[0]
+    ops = vcycle.Fp64Ops(H)
+    p = _perm(lv)
+    L = lv.L.toarray()
+    Lp = L[np.ix_(p, p)]
+    Bf, Bb = np.zeros_like(L), np.zeros_like(L)
+    Bf[np.ix_(p, p)] = np.tril(Lp)
+    Bb[np.ix_(p, p)] = np.triu(Lp)
+    Md = _dense_two_level(L, lv.P.toarray(), Bb if pre_rev else Bf, 1, 2, B_post=Bb if post_rev else Bf)
+    r = np.random.default_rng(4).standard_normal(lv.N)
+    z = vcycle.vcycle(ops, r, None, 1, 2, post_reverse=post_rev, pre_reverse=pre_rev)
     assert np.max(np.abs(z - Md @ r)) <= 1e-10 * np.max(np.abs(Md @ r))
 
 
