@@ -829,52 +829,42 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
       if (info.iters >= o.maxit) return finish(MGM_NOT_CONVERGED);
       if (info.iters > 0) info.restarts++;
       HIPCHECK(hipMemcpyAsync(rhat, r, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-      double rho_old = 1.0, alpha = 1.0, omega = 1.0;
-      bool first = true;
-      while (info.iters < o.maxit) {
-        mdot(c, n, rhat, ld, 1, r, c->dh, st, c->hpin);  // rho = rhat . r
-        host_wait(st);
-        double rho = c->hpin[0];
-        if (rho == 0.0) break;
-        if (first) {
-          HIPCHECK(hipMemcpyAsync(p, r, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-          first = false;
-        } else {
-          double beta = (rho / rho_old) * (alpha / omega);
-          // p = r + beta (p - omega v)
-          hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kBlock), 0, st, int(n), 1.0, p, -omega, v, p);
-          hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kBlock), 0, st, int(n), 1.0, r, beta, p, p);
-        }
+      // The step scalars stay on the device (k_bicg_*); the host waits twice
+      // per step, for |s| and for |r|, and sees rho and omega there.
+      double* sc = c->dh + 640;   // [parity][rho, rv, st, tt] (8 doubles per parity)
+      double* hsc = c->hpin + 640;
+      for (int k = 0; info.iters < o.maxit; ++k) {
+        const int q = k & 1;
+        mdot(c, n, rhat, ld, 1, r, sc + q * 8 + kBicgRho, st, hsc + q * 8 + kBicgRho);  // rho = rhat . r
+        if (k == 0) HIPCHECK(hipMemcpyAsync(p, r, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        else hipLaunchKernelGGL(k_bicg_p, dim3(g), dim3(kBlock), 0, st, int(n), r, v, p, sc, q);
         precond(c, p, phat, nullptr, st);
-        info.iters++;
         apply_A(c, phat, v, st);
-        mdot(c, n, rhat, ld, 1, v, c->dh, st, c->hpin);
+        mdot(c, n, rhat, ld, 1, v, sc + q * 8 + kBicgRv, st, hsc + q * 8 + kBicgRv);      // rhat . v
+        hipLaunchKernelGGL(k_bicg_s, dim3(g), dim3(kBlock), 0, st, int(n), r, v, s, sc, q);
+        mdot(c, n, s, ld, 1, s, c->dh + 512, st, c->hpin + 512);
         host_wait(st);
-        alpha = rho / c->hpin[0];
-        hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kBlock), 0, st, int(n), 1.0, r, -alpha, v, s);
-        mdot(c, n, s, ld, 1, s, c->dh, st, c->hpin);
-        host_wait(st);
-        double sn = std::sqrt(c->hpin[0]) / fnorm;
+        if (hsc[q * 8 + kBicgRho] == 0.0) break;  // the step just queued is discarded
+        info.iters++;
+        double sn = std::sqrt(c->hpin[512]) / fnorm;
         if (!std::isfinite(sn)) return finish(MGM_E_NONFINITE);
         if (hist && hist_n <= o.maxit) hist[hist_n++] = sn;
         info.rel_res_est = sn;
         if (sn <= tol) {
-          hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kBlock), 0, st, int(n), 1.0, x, alpha, phat, x);
+          hipLaunchKernelGGL(k_bicg_x, dim3(g), dim3(kBlock), 0, st, int(n), phat, (const double*)nullptr,
+                             (const double*)nullptr, (const double*)nullptr, x, (double*)nullptr, sc, q);
           break;
         }
         precond(c, s, shat, nullptr, st);
         info.iters++;
         apply_A(c, shat, t, st);
-        mdot(c, n, s, ld, 2, t, c->dh, st, c->hpin);  // [s.t, t.t] (s and t are adjacent)
+        // [s.t, t.t] (s and t are adjacent); the step's st and tt slots are adjacent too
+        mdot(c, n, s, ld, 2, t, sc + q * 8 + kBicgSt, st, hsc + q * 8 + kBicgSt);
+        hipLaunchKernelGGL(k_bicg_x, dim3(g), dim3(kBlock), 0, st, int(n), phat, shat, s, t, x, r, sc, q);
+        mdot(c, n, r, ld, 1, r, c->dh + 512, st, c->hpin + 512);
         host_wait(st);
-        omega = c->hpin[0] / c->hpin[1];
-        hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kBlock), 0, st, int(n), 1.0, x, alpha, phat, x);
-        hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kBlock), 0, st, int(n), 1.0, x, omega, shat, x);
-        hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kBlock), 0, st, int(n), 1.0, s, -omega, t, r);
-        rho_old = rho;
-        mdot(c, n, r, ld, 1, r, c->dh, st, c->hpin);
-        host_wait(st);
-        double rn2 = std::sqrt(c->hpin[0]) / fnorm;
+        const double omega = hsc[q * 8 + kBicgSt] / hsc[q * 8 + kBicgTt];
+        double rn2 = std::sqrt(c->hpin[512]) / fnorm;
         if (hist && hist_n <= o.maxit) hist[hist_n++] = rn2;
         info.rel_res_est = rn2;
         if (rn2 <= tol || omega == 0.0) break;

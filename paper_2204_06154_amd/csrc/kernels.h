@@ -309,6 +309,52 @@ __global__ __launch_bounds__(kBlock) void k_normalise_cast(int n, const double* 
   else if (rho && i == nf) *rho = v;
 }
 
+// BiCGSTAB updates with the scalars read from device memory (so the host
+// need not see them first). sc holds, for the current step k and the
+// previous one (slot parity), rho = rhat.r, rv = rhat.v, st = s.t, tt = t.t:
+// sc[q * 8 + 0..3] for parity q. alpha = rho / rv, omega = st / tt.
+constexpr int kBicgRho = 0, kBicgRv = 1, kBicgSt = 2, kBicgTt = 3;
+__device__ __forceinline__ double bicg(const double* sc, int q, int what) { return sc[q * 8 + what]; }
+
+// p = r + beta (p - omega_{k-1} v), beta = (rho_k / rho_{k-1}) (alpha_{k-1} / omega_{k-1})
+__global__ __launch_bounds__(kBlock) void k_bicg_p(int n, const double* __restrict__ r, const double* __restrict__ v,
+                                                   double* __restrict__ p, const double* __restrict__ sc, int q) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int qo = q ^ 1;
+  const double omega = bicg(sc, qo, kBicgSt) / bicg(sc, qo, kBicgTt);
+  const double alpha = bicg(sc, qo, kBicgRho) / bicg(sc, qo, kBicgRv);
+  const double beta = (bicg(sc, q, kBicgRho) / bicg(sc, qo, kBicgRho)) * (alpha / omega);
+  const double t = 1.0 * p[i] + (-omega) * v[i];
+  p[i] = 1.0 * r[i] + beta * t;
+}
+
+// s = r - alpha_k v
+__global__ __launch_bounds__(kBlock) void k_bicg_s(int n, const double* __restrict__ r, const double* __restrict__ v,
+                                                   double* __restrict__ s, const double* __restrict__ sc, int q) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double alpha = bicg(sc, q, kBicgRho) / bicg(sc, q, kBicgRv);
+  s[i] = 1.0 * r[i] + (-alpha) * v[i];
+}
+
+// x += alpha_k phat (+ omega_k shat when shat is given); r = s - omega_k t
+__global__ __launch_bounds__(kBlock) void k_bicg_x(int n, const double* __restrict__ phat,
+                                                   const double* __restrict__ shat, const double* __restrict__ s,
+                                                   const double* __restrict__ t, double* __restrict__ x,
+                                                   double* __restrict__ r, const double* __restrict__ sc, int q) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double alpha = bicg(sc, q, kBicgRho) / bicg(sc, q, kBicgRv);
+  double xi = 1.0 * x[i] + alpha * phat[i];
+  if (shat) {
+    const double omega = bicg(sc, q, kBicgSt) / bicg(sc, q, kBicgTt);
+    xi = 1.0 * xi + omega * shat[i];
+    r[i] = 1.0 * s[i] + (-omega) * t[i];
+  }
+  x[i] = xi;
+}
+
 // z = a*x + b*y (a, b host scalars)
 __global__ __launch_bounds__(kBlock) void k_axpby(int n, double a, const double* __restrict__ x, double b,
                                                   const double* __restrict__ y, double* __restrict__ z) {

@@ -145,23 +145,28 @@ def test_vcycle_fp64_matches_oracle(case):
         assert _rel(z, M(r)) < 1e-10
 
 
-def test_graph_replays_match_eager(case):
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
+def test_graph_replays_match_eager(case, prec):
     name, wl, H, m = case
-    m.set_precision("fp64")
-    r = _dev(_rhs(wl, H))
-    z_graph = []
-    for _ in range(3):
-        z_graph.append(_host(m.vcycle(r)))
-        _host(m.apply(r))          # eager work between graph replays
-    # a second handle without graphs gives the reference eager result
-    p = dict(wl.params)
-    p["use_graph"] = 0
-    m2 = mgm.Mgm(wl.xyz, wl.normals, p, device=0)
-    z_eager = _host(m2.vcycle(r))
-    for k, z in enumerate(z_graph):
-        torch.cuda.synchronize()
-        assert np.array_equal(z, z_eager), k
-    m2.close()
+    m.set_precision(prec)
+    try:
+        r = _dev(_rhs(wl, H))
+        z_graph = []
+        for _ in range(3):
+            z_graph.append(_host(m.vcycle(r)))
+            _host(m.apply(r))          # eager work between graph replays
+        # a second handle without graphs gives the reference eager result
+        p = dict(wl.params)
+        p["use_graph"] = 0
+        p["precision"] = prec
+        m2 = mgm.Mgm(wl.xyz, wl.normals, p, device=0)
+        z_eager = _host(m2.vcycle(r))
+        for k, z in enumerate(z_graph):
+            torch.cuda.synchronize()
+            assert np.array_equal(z, z_eager), k
+        m2.close()
+    finally:
+        m.set_precision("fp64")
 
 
 @pytest.mark.parametrize("method", ["fgmres", "bicgstab"])
