@@ -284,6 +284,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--weights-n", type=int, default=500_000)
     ap.add_argument("--gs-block", type=int, default=256)
+    ap.add_argument("--cycle", choices=["V", "W", "F"], default="V", help="multigrid cycle of the torus workload")
     ap.add_argument("--workload", choices=["torus", "learned", "sphere1m", "traffic", "sbdf2"], default="torus")
     ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--vcycle-precision", default="fp32", help="V-cycle precision of the learned and sbdf2 workloads")
@@ -318,7 +319,7 @@ def main():
     wl = synth.torus_workload(args.n)
     log(f"inputs N={args.n} generated in {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
-    m = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, gs_block=args.gs_block), device=0)
+    m = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, gs_block=args.gs_block, cycle=args.cycle), device=0)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     sizes = [int(s) for s in m.export("level_sizes")]
@@ -414,7 +415,7 @@ def main():
         "dtype": f"{main_prec} V-cycle, f64 Krylov",
         "data": "synthetic (seeded Poisson-disk torus points, random trigonometric rhs)",
         "config": {"workload": f"torus R=1 r=1/3, N={args.n} Poisson-disk points, RBF-FD r^5+deg3 k=50, "
-                               f"bordered surface Poisson, FGMRES(40)+MGM V(1,1) to 1e-10",
+                               f"bordered surface Poisson, FGMRES(40)+MGM {args.cycle}(1,1) to 1e-10",
                    "levels": sizes, "colours": ncol, "setup_s": round(setup_s, 2)},
         "solves": {p: {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in d.items()}
                    for p, d in results.items()},

@@ -56,6 +56,12 @@ enum { MGM_SCREENED = 0, MGM_POISSON = 1 };
 enum { MGM_FP64 = 0, MGM_FP32 = 1, MGM_FP16 = 2 };
 /* Smoother sweeps (Sec. 4.3: forward or backward Gauss-Seidel). */
 enum { MGM_GS_FWD = 0, MGM_GS_BWD = 1 };
+/* Cycle (Alg. 3 is the V-cycle; Sec. 4.5 names F- and W-cycles as options):
+ * the coarse problem of a level is solved by one V-cycle of the next level,
+ * by two W-cycles, or by an F-cycle followed by a V-cycle. A second visit
+ * continues from the first visit's iterate (pre-smoothing with the current
+ * multiplier, residual f - L e - b mu and constraint residual rho - b.e). */
+enum { MGM_CYCLE_V = 0, MGM_CYCLE_W = 1, MGM_CYCLE_F = 2 };
 /* Outer iteration (Sec. 4.6): right-preconditioned FGMRES(restart) or
  * BiCGSTAB, or the stationary V-cycle iteration u <- u + M(f - A u). */
 enum { MGM_FGMRES = 0, MGM_BICGSTAB = 1, MGM_STATIONARY = 2 };
@@ -84,11 +90,12 @@ typedef struct {
                              coordinate bisection, patch graph and in-patch graphs
                              coloured by DSATUR, one workgroup per patch; levels
                              with rows longer than 96 entries stay plain */
+  int32_t cycle;          /* MGM_CYCLE_V | MGM_CYCLE_W | MGM_CYCLE_F */
 } mgm_params;
 
 /* Paper defaults (Table 1): RBF-FD, k = l = 3, n = 20, forward GS, nu = 1,
  * m = 3, factor 4, N_min = 250, screened with mu = 1; FP64 V-cycle, graphs
- * on, device weights on, gs_block = 256. */
+ * on, device weights on, gs_block = 256, V-cycle. */
 void mgm_default_params(mgm_params *p);
 
 /* Preprocessing phase (Alg. 2): kNN stencils (Sec. 2), tangent-plane weights

@@ -1,4 +1,4 @@
-"""Gauss-Seidel smoothing and the MGM V(nu1,nu2)-cycle.
+"""Gauss-Seidel smoothing and the MGM V(nu1,nu2)-cycle (and W/F cycles).
 
 Smoother (Sec. 4.3, eq. smoother): u <- u + B^{-1}(f - L u), B the lower
 triangle of L in the update order (forward GS). For the bordered Poisson
@@ -102,8 +102,15 @@ def learned_sweep(ops, u, f):
     return u
 
 
-def vcycle(ops, r, rho=None, nu1=1, nu2=1, post_reverse=False, capture=None, pre_reverse=False):
+def vcycle(ops, r, rho=None, nu1=1, nu2=1, post_reverse=False, capture=None, pre_reverse=False, cycle="V"):
     """z = M r (Alg. 3 with zero initial guess). Bordered: returns (z, lambda).
+
+    cycle = "V" (Alg. 3), "W" or "F" (the options Sec. 4.5 names): the
+    coarse problem of level j is solved by one cycle of level j+1 (V), two W
+    cycles, or an F cycle followed by a V cycle. The second visit continues
+    from the first visit's iterate: it pre-smooths with the current
+    multiplier, restricts the residual f - L e - b mu and the constraint
+    residual rho - b . e, and adds the coarse correction to both e and mu.
 
     With `ops.learned` set (an N_1 x s array of step weights) the fine level
     is smoothed by `learned_sweep` instead of Gauss-Seidel. `capture`, if a
@@ -111,49 +118,59 @@ def vcycle(ops, r, rho=None, nu1=1, nu2=1, post_reverse=False, capture=None, pre
     correction (before post-smoothing)."""
     p = ops.nlevels()
     dt = ops.dtype
-    rhs = [None] * p
-    rhos = [None] * p
-    e = [None] * p
-    rhs[0] = np.asarray(r, dtype=dt)
-    rhos[0] = rho
     bordered = rho is not None
-    for j in range(p - 1):
-        e[j] = np.zeros(ops.size(j), dtype=dt)
+    first = {"V": "V", "W": "W", "F": "F"}
+    second = {"W": "W", "F": "V"}
+    if cycle not in first:
+        raise ValueError("cycle must be V, W or F")
+
+    def visit(j, f, rho_j, e, mu, kind, zero_start):
+        if j == p - 1:                       # exact: independent of the start
+            ec, muc = ops.coarse_solve(f, rho_j)
+            return np.asarray(ec, dtype=dt), muc
+        lam = mu if (bordered and not zero_start) else 0.0
         for _ in range(nu1):
             if j == 0 and getattr(ops, "learned", None) is not None:
-                learned_sweep(ops, e[j], rhs[j])
+                learned_sweep(ops, e, f)
             else:
-                gs_sweep(ops, j, e[j], rhs[j], 0.0, reverse=pre_reverse)
-        res = rhs[j] - ops.L(j, e[j])
-        rhs[j + 1] = ops.R(j, res)
-        if bordered:
-            rhos[j + 1] = rhos[j] - ops.dot_border(j, e[j])
-    e[p - 1], mu = ops.coarse_solve(rhs[p - 1], rhos[p - 1])
-    e[p - 1] = np.asarray(e[p - 1], dtype=dt)
-    for j in range(p - 2, -1, -1):
-        e[j] += ops.P(j, e[j + 1])
+                gs_sweep(ops, j, e, f, lam, reverse=pre_reverse)
+        res = f - ops.L(j, e)
+        if bordered and lam != 0.0:
+            res = res - ops.border(j) * dt(lam)
+        fc = ops.R(j, res)
+        rhoc = rho_j - ops.dot_border(j, e) if bordered else None
+        ec, muc = visit(j + 1, fc, rhoc, np.zeros(ops.size(j + 1), dtype=dt), 0.0, first[kind], True)
+        if kind != "V":
+            ec, muc = visit(j + 1, fc, rhoc, ec, muc, second[kind], False)
+        e += ops.P(j, ec)
+        mu = (0.0 if zero_start else mu) + (muc if bordered else 0.0)
         if j == 0 and capture is not None:
-            capture.append(np.array(e[0], dtype=np.float64))
+            capture.append(np.array(e, dtype=np.float64))
         for _ in range(nu2):
             if j == 0 and getattr(ops, "learned", None) is not None:
-                learned_sweep(ops, e[j], rhs[j])
+                learned_sweep(ops, e, f)
             else:
-                gs_sweep(ops, j, e[j], rhs[j], mu if bordered else 0.0, reverse=post_reverse)
+                gs_sweep(ops, j, e, f, mu if bordered else 0.0, reverse=post_reverse)
+        return e, mu
+
+    e0, mu0 = visit(0, np.asarray(r, dtype=dt), rho, np.zeros(ops.size(0), dtype=dt), 0.0, cycle, True)
     if bordered:
-        return e[0], mu
-    return e[0]
+        return e0, mu0
+    return e0
 
 
-def make_preconditioner(ops, problem, nu1=1, nu2=1, post_reverse=False, pre_reverse=False):
+def make_preconditioner(ops, problem, nu1=1, nu2=1, post_reverse=False, pre_reverse=False, cycle="V"):
     """Preconditioner on FP64 vectors of length N (screened) or N+1 (bordered).
-    pre_reverse / post_reverse select backward Gauss-Seidel sweeps (Sec. 4.3)."""
+    pre_reverse / post_reverse select backward Gauss-Seidel sweeps (Sec. 4.3);
+    cycle selects the V, W or F cycle."""
     if problem == "poisson":
         def M(v):
-            z, lam = vcycle(ops, v[:-1], float(v[-1]), nu1, nu2, post_reverse, pre_reverse=pre_reverse)
+            z, lam = vcycle(ops, v[:-1], float(v[-1]), nu1, nu2, post_reverse, pre_reverse=pre_reverse, cycle=cycle)
             return np.concatenate([np.asarray(z, dtype=np.float64), [lam]])
     else:
         def M(v):
-            return np.asarray(vcycle(ops, v, None, nu1, nu2, post_reverse, pre_reverse=pre_reverse), dtype=np.float64)
+            return np.asarray(vcycle(ops, v, None, nu1, nu2, post_reverse, pre_reverse=pre_reverse, cycle=cycle),
+                              dtype=np.float64)
     return M
 
 

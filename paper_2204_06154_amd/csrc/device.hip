@@ -276,13 +276,13 @@ static void upload(mgm_ctx* c) {
   c->cdim = H.coarse_dim;
   c->cinv = track(c, dupload(H.coarse_inv));
   c->rho = track(c, dalloc<double>(p + 1));
-  c->mu = track(c, dalloc<double>(1));
+  c->mu = track(c, dalloc<double>(p));  // multiplier correction of every level (mu[0]: the fine one)
   c->lam = track(c, dalloc<double>(1));
   int64_t maxblk = 1;
   for (auto& d : c->lv) maxblk = std::max<int64_t>(maxblk, nblk(int64_t(d.n) * 16) + 1);
   c->partial_len = maxblk;
   c->partial = track(c, dalloc<double>(maxblk));
-  HIPCHECK(hipMemset(c->mu, 0, sizeof(double)));
+  HIPCHECK(hipMemset(c->mu, 0, sizeof(double) * p));
   HIPCHECK(hipMemset(c->rho, 0, sizeof(double) * (p + 1)));
 }
 
@@ -418,7 +418,7 @@ static void gs_patch_launch(mgm_ctx* c, int j, int pc, bool reverse, bool border
 // patched level from its patch ELL: one workgroup per slot.
 template <typename V, typename S, bool SC, int MODE, bool BDOT, bool BORDER, typename X = S>
 static void rowop_patch_launch(const DevLevel& d, const V* val, const S* f, const X* x, S* out, const S* b,
-                               const S* lam, double* partial, hipStream_t st, const S* dinv = nullptr,
+                               const double* lam, double* partial, hipStream_t st, const S* dinv = nullptr,
                                const S* omega = nullptr, S* xcopy = nullptr) {
   const unsigned ns = unsigned(d.pstart_host_slots);
 #define ROWOP(WM)                                                                                           \
@@ -454,25 +454,29 @@ static void gs_sweep(mgm_ctx* c, int j, bool reverse, bool border, const double*
   }
 }
 
-// res_j = f_j - L_j e_j (bordered: partial sums of b_j . e_j) then
+// res_j = f_j - L_j e_j (bordered: partial sums of b_j . e_j; with_mu: a
+// level continuing from an earlier iterate also subtracts b_j mu_j) then
 // f_{j+1} = R_j res_j (bordered: rho_{j+1} = rho_j - b_j . e_j).
 template <typename V, typename S, bool SC>
-static void residual_restrict(mgm_ctx* c, int j, hipStream_t st) {
+static void residual_restrict(mgm_ctx* c, int j, hipStream_t st, bool with_mu = false) {
   using P = Prec<V, S, SC>;
   DevLevel& d = c->lv[j];
   DevLevel& nx = c->lv[j + 1];
   const bool bord = c->p.problem == MGM_POISSON;
+  const double* mu = c->mu + j;
   unsigned g;  // residual blocks = partial sums of b . e
   if (d.patched) {
     g = unsigned(d.pstart_host_slots);
-    if (bord) rowop_patch_launch<V, S, SC, kRowResidual, true, false>(d, P::pval(d), P::f(d), P::e(d), P::res(d), P::b(d), nullptr, c->partial, st);
+    if (bord && with_mu) rowop_patch_launch<V, S, SC, kRowResidual, true, true>(d, P::pval(d), P::f(d), P::e(d), P::res(d), P::b(d), mu, c->partial, st);
+    else if (bord) rowop_patch_launch<V, S, SC, kRowResidual, true, false>(d, P::pval(d), P::f(d), P::e(d), P::res(d), P::b(d), nullptr, c->partial, st);
     else rowop_patch_launch<V, S, SC, kRowResidual, false, false>(d, P::pval(d), P::f(d), P::e(d), P::res(d), P::b(d), nullptr, c->partial, st);
   } else {
     g = nblk(int64_t(d.n) * d.G);
+    const double* lam = (bord && with_mu) ? mu : nullptr;
     DISPATCH_G(d.G, if (bord) hipLaunchKernelGGL((k_residual<V, S, GG, SC, true>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr, d.col,
-                       P::val(d), d.s16, P::f(d), P::e(d), P::res(d), P::b(d), c->partial);
+                       P::val(d), d.s16, P::f(d), P::e(d), P::res(d), P::b(d), c->partial, lam);
                else hipLaunchKernelGGL((k_residual<V, S, GG, SC, false>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr, d.col,
-                       P::val(d), d.s16, P::f(d), P::e(d), P::res(d), P::b(d), c->partial));
+                       P::val(d), d.s16, P::f(d), P::e(d), P::res(d), P::b(d), c->partial, (const double*)nullptr));
   }
   unsigned gr = nblk(int64_t(nx.n) * kRestrictG);
   if (bord)
@@ -483,12 +487,16 @@ static void residual_restrict(mgm_ctx* c, int j, hipStream_t st) {
                        P::f(nx), c->partial, 0, c->rho + j, c->rho + j + 1);
 }
 
+// e_j += P_j e_{j+1}; bordered: mu_j = mu_{j+1}, or mu_j += mu_{j+1} when the
+// level continues from an earlier iterate (accumulate).
 template <typename V, typename S, bool SC>
-static void interp_add(mgm_ctx* c, int j, hipStream_t st) {
+static void interp_add(mgm_ctx* c, int j, hipStream_t st, bool accumulate = false) {
   using P = Prec<V, S, SC>;
   DevLevel& d = c->lv[j];
   DevLevel& nx = c->lv[j + 1];
-  hipLaunchKernelGGL((k_interp_add<S, S>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, d.m, d.pcol, P::pw(d), P::e(nx), P::e(d));
+  const bool bord = c->p.problem == MGM_POISSON;
+  hipLaunchKernelGGL((k_interp_add<S, S>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, d.m, d.pcol, P::pw(d), P::e(nx), P::e(d),
+                     bord ? c->mu + j + 1 : nullptr, bord ? c->mu + j : nullptr, accumulate ? 1 : 0);
 }
 
 // Fine-level learned smoother: s Richardson steps with per-node step weights
@@ -527,36 +535,50 @@ static void learned_sweep(mgm_ctx* c, hipStream_t st, bool zero_start = false) {
                                  (double*)nullptr);
 }
 
+// One visit of level j in a cycle of the given kind (MGM_CYCLE_V/W/F). With
+// zero_start the level starts from e_j = 0, mu_j = 0 (Alg. 3); otherwise it
+// continues from its current iterate (the second coarse visit of a W or F
+// cycle): pre-smoothing uses mu_j, the residual subtracts b_j mu_j and the
+// corrections are added to both e_j and mu_j. The coarsest solve is exact,
+// so it does not depend on the start.
 template <typename V, typename S, bool SC>
-static void vcycle_enqueue(mgm_ctx* c, hipStream_t st) {
+static void cycle_enqueue(mgm_ctx* c, int j, int kind, bool zero_start, hipStream_t st) {
   using P = Prec<V, S, SC>;
   const int p = int(c->lv.size());
   const bool bord = c->p.problem == MGM_POISSON;
-  for (int j = 0; j + 1 < p; ++j) {
-    DevLevel& d = c->lv[j];
-    // e_j starts at zero: a patch-blocked first sweep assumes it without reading e_j
-    const bool learned = j == 0 && c->ls_active;
-    const bool zg = (d.patched || learned) && c->p.nu1 > 0;
-    if (!zg) hipLaunchKernelGGL((k_fill<S>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, P::e(d), S(0));
-    for (int s = 0; s < c->p.nu1; ++s) {
-      if (learned) learned_sweep<V, S, SC>(c, st, s == 0);
-      else gs_sweep<V, S, SC>(c, j, c->p.pre_smoother == MGM_GS_BWD, false, c->mu, st, zg && s == 0);
-    }
-    residual_restrict<V, S, SC>(c, j, st);
+  if (j == p - 1) {
+    DevLevel& cl = c->lv[p - 1];
+    hipLaunchKernelGGL((k_coarse_gemv<S>), dim3(nblk(int64_t(c->cdim) * 64)), dim3(kBlock), 0, st, c->cdim, cl.n, c->cinv,
+                       P::f(cl), c->rho + (p - 1), P::e(cl), c->mu + (p - 1));
+    return;
   }
-  DevLevel& cl = c->lv[p - 1];
-  hipLaunchKernelGGL((k_coarse_gemv<S>), dim3(nblk(int64_t(c->cdim) * 64)), dim3(kBlock), 0, st, c->cdim, cl.n, c->cinv,
-                     P::f(cl), c->rho + (p - 1), P::e(cl), c->mu);
-  for (int j = p - 2; j >= 0; --j) {
-    interp_add<V, S, SC>(c, j, st);
-    if (j == 0 && c->capture)
-      hipLaunchKernelGGL((k_gather<S, double>), dim3(nblk(c->lv[0].n)), dim3(kBlock), 0, st,
-                         c->lv[0].n, (const int32_t*)nullptr, P::e(c->lv[0]), c->capture, (double*)nullptr);
-    for (int s = 0; s < c->p.nu2; ++s) {
-      if (j == 0 && c->ls_active) learned_sweep<V, S, SC>(c, st);
-      else gs_sweep<V, S, SC>(c, j, c->p.post_smoother == MGM_GS_BWD, bord, c->mu, st);
-    }
+  DevLevel& d = c->lv[j];
+  const double* mu = c->mu + j;
+  const bool learned = j == 0 && c->ls_active;
+  // e_j starts at zero: a patch-blocked first sweep assumes it without reading e_j
+  const bool zg = zero_start && (d.patched || learned) && c->p.nu1 > 0;
+  if (zero_start && !zg) hipLaunchKernelGGL((k_fill<S>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, P::e(d), S(0));
+  for (int s = 0; s < c->p.nu1; ++s) {
+    if (learned) learned_sweep<V, S, SC>(c, st, zero_start && s == 0);
+    else gs_sweep<V, S, SC>(c, j, c->p.pre_smoother == MGM_GS_BWD, bord && !zero_start, mu, st, zg && s == 0);
   }
+  residual_restrict<V, S, SC>(c, j, st, !zero_start);
+  const int first = kind;
+  cycle_enqueue<V, S, SC>(c, j + 1, first, true, st);
+  if (kind != MGM_CYCLE_V) cycle_enqueue<V, S, SC>(c, j + 1, kind == MGM_CYCLE_W ? MGM_CYCLE_W : MGM_CYCLE_V, false, st);
+  interp_add<V, S, SC>(c, j, st, !zero_start);
+  if (j == 0 && c->capture)
+    hipLaunchKernelGGL((k_gather<S, double>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, (const int32_t*)nullptr, P::e(d),
+                       c->capture, (double*)nullptr);
+  for (int s = 0; s < c->p.nu2; ++s) {
+    if (learned) learned_sweep<V, S, SC>(c, st);
+    else gs_sweep<V, S, SC>(c, j, c->p.post_smoother == MGM_GS_BWD, bord, mu, st);
+  }
+}
+
+template <typename V, typename S, bool SC>
+static void vcycle_enqueue(mgm_ctx* c, hipStream_t st) {
+  cycle_enqueue<V, S, SC>(c, 0, c->p.cycle, true, st);
 }
 
 void invalidate_graphs(mgm_ctx* c) {
@@ -1017,34 +1039,37 @@ static double residual_bytes(const mgm_ctx* c, int j, int prec) {
   return b;
 }
 
-static double vcycle_bytes(const mgm_ctx* c, int prec) {
+// Algorithmic bytes of one visit of level j (cf. cycle_enqueue), recursively.
+static double visit_bytes(const mgm_ctx* c, int prec, int j, int kind, bool zero_start) {
   const int p = int(c->lv.size());
+  if (j == p - 1) return 8.0 * double(c->cdim) * c->cdim + bvec(prec) * 2.0 * c->lv[p - 1].n;  // coarse
   const bool bord = c->p.problem == MGM_POISSON;
   const double bt = prec == MGM_FP64 ? 8.0 : 4.0;  // transfer value bytes
+  const DevLevel& d = c->lv[j];
+  const bool learned = j == 0 && c->ls_active;
   double tot = 0.0;
-  for (int j = 0; j + 1 < p; ++j) {
-    const DevLevel& d = c->lv[j];
-    const bool learned = j == 0 && c->ls_active;
-    if (!((d.patched || learned) && c->p.nu1 > 0)) tot += bvec(prec) * d.n;  // zero fill
-    if (learned) {
-      const double step = double(d.nnz) * (bval(prec) + 4.0) + double(d.n) * (5.0 * bvec(prec));
-      int steps = (c->p.nu1 + c->p.nu2) * c->ls_s;
-      if (c->p.nu1 > 0) {  // the first step from zero reads omega, dinv, f and writes e
-        --steps;
-        tot += 4.0 * bvec(prec) * d.n;
-      }
-      tot += steps * step;
-    } else {
-      tot += c->p.nu1 * gs_sweep_bytes(c, j, prec, false) + c->p.nu2 * gs_sweep_bytes(c, j, prec, bord);
+  if (zero_start && !((d.patched || learned) && c->p.nu1 > 0)) tot += bvec(prec) * d.n;  // zero fill
+  if (learned) {
+    const double step = double(d.nnz) * (bval(prec) + 4.0) + double(d.n) * (5.0 * bvec(prec));
+    int steps = (c->p.nu1 + c->p.nu2) * c->ls_s;
+    if (c->p.nu1 > 0 && zero_start) {  // the first step from zero reads omega, dinv, f and writes e
+      --steps;
+      tot += 4.0 * bvec(prec) * d.n;
     }
-    tot += residual_bytes(c, j, prec);
-    const int64_t nnzR = c->H.lv[j].R.nnz();
-    tot += double(nnzR) * (bt + 4.0) + 4.0 * (d.nnext + 1) + bvec(prec) * (d.n + d.nnext);      // restrict
-    tot += double(d.n) * d.m * (bt + 4.0) + bvec(prec) * (d.nnext + 2.0 * d.n);                  // interpolate
+    tot += steps * step;
+  } else {
+    tot += c->p.nu1 * gs_sweep_bytes(c, j, prec, bord && !zero_start) + c->p.nu2 * gs_sweep_bytes(c, j, prec, bord);
   }
-  tot += 8.0 * double(c->cdim) * c->cdim + bvec(prec) * 2.0 * c->lv[p - 1].n;                     // coarse
+  tot += residual_bytes(c, j, prec);
+  const int64_t nnzR = c->H.lv[j].R.nnz();
+  tot += double(nnzR) * (bt + 4.0) + 4.0 * (d.nnext + 1) + bvec(prec) * (d.n + d.nnext);      // restrict
+  tot += visit_bytes(c, prec, j + 1, kind, true);
+  if (kind != MGM_CYCLE_V) tot += visit_bytes(c, prec, j + 1, kind == MGM_CYCLE_W ? MGM_CYCLE_W : MGM_CYCLE_V, false);
+  tot += double(d.n) * d.m * (bt + 4.0) + bvec(prec) * (d.nnext + 2.0 * d.n);                  // interpolate
   return tot;
 }
+
+static double vcycle_bytes(const mgm_ctx* c, int prec) { return visit_bytes(c, prec, 0, c->p.cycle, true); }
 
 template <typename V, typename S, bool SC>
 static void gs_phase_launch(mgm_ctx* c, int j, int col, hipStream_t st) {
@@ -1219,6 +1244,7 @@ void mgm_default_params(mgm_params* p) {
   p->use_graph = 1;
   p->device_weights = 1;
   p->gs_block = 256;
+  p->cycle = MGM_CYCLE_V;
 }
 
 mgm_status mgm_setup(const double* h_xyz, const double* h_normals, int64_t n, const mgm_params* params, int32_t device,

@@ -36,6 +36,7 @@ void validate_params(const mgm_params& p, int64_t n) {
   if (p.nu1 < 0 || p.nu2 < 0 || p.nu1 > 8 || p.nu2 > 8) bad("nu1/nu2");
   if (p.precision < MGM_FP64 || p.precision > MGM_FP16) bad("precision");
   if (p.gs_block < 0 || p.gs_block > 256) bad("gs_block must be 0..256");
+  if (p.cycle < MGM_CYCLE_V || p.cycle > MGM_CYCLE_F) bad("cycle");
 }
 
 std::vector<int32_t> level_sizes(int64_t n1, const mgm_params& p) {

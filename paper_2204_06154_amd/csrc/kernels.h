@@ -75,14 +75,16 @@ __global__ __launch_bounds__(kBlock) void k_gs_colour(int r0, int r1, int W, con
 namespace mgm {
 namespace {
 
-// res = f - A u over all rows; with BDOT also per-block partial sums of b.u
+// res = f - A u (- b lambda when lam is given) over all rows; with BDOT also
+// per-block partial sums of b.u
 // (written to partial[blockIdx.x], fixed order, deterministic).
 template <typename V, typename S, int G, bool SCALED, bool BDOT>
 __global__ __launch_bounds__(kBlock) void k_residual(int n, int W, const int32_t* __restrict__ rowptr,
                                                      const int32_t* __restrict__ col, const V* __restrict__ val,
                                                      const float* __restrict__ scale, const S* __restrict__ f,
                                                      const S* __restrict__ u, S* __restrict__ res,
-                                                     const S* __restrict__ b, double* __restrict__ partial) {
+                                                     const S* __restrict__ b, double* __restrict__ partial,
+                                                     const double* __restrict__ lam = nullptr) {
   const int gid = blockIdx.x * kBlock + threadIdx.x;
   const int row = gid / G;
   const int lane = gid % G;
@@ -90,6 +92,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(int n, int W, const int32_t
   if (row < n) {
     S acc = row_dot<V, S, G, SCALED>(row, lane, W, rowptr, col, val, scale, u);
     if (lane == 0) {
+      if (lam) acc += b[row] * S(*lam);  // bordered, continuing iterate: f - L u - b lambda
       res[row] = f[row] - acc;
       if (BDOT) bu = double(b[row]) * double(u[row]);
     }
@@ -157,11 +160,15 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int32_t* __re
 }
 
 // Interpolation and correction e += P ec (P: fixed width m, row-major).
+// Bordered: the multiplier correction goes up with it, mu_j = mu_{j+1}, or
+// mu_j += mu_{j+1} when the level continues from an earlier iterate.
 template <typename V, typename S>
 __global__ __launch_bounds__(kBlock) void k_interp_add(int n, int m, const int32_t* __restrict__ pcol,
                                                        const V* __restrict__ pval, const S* __restrict__ ec,
-                                                       S* __restrict__ e) {
+                                                       S* __restrict__ e, const double* __restrict__ mu_in = nullptr,
+                                                       double* __restrict__ mu_out = nullptr, int accumulate = 0) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (mu_out && i == 0) *mu_out = (accumulate ? *mu_out : 0.0) + *mu_in;
   if (i >= n) return;
   S acc = S(0);
   for (int t = 0; t < m; ++t) acc += S(pval[i * m + t]) * ec[pcol[i * m + t]];

@@ -13,8 +13,9 @@
 namespace mgm {
 namespace {
 
-// MODE kRowResidual: out = f - A x (SCALED: A = diag(scale) H), and with BDOT
-//   partial[slot] = sum over the slot's rows of b_i x_i (fixed tree).
+// MODE kRowResidual: out = f - A x (SCALED: A = diag(scale) H), minus
+//   b_i * (*lam) when BORDER, and with BDOT partial[slot] = sum over the
+//   slot's rows of b_i x_i (fixed tree).
 // MODE kRowApply:   out = A x, plus b_i * (*lam) when BORDER (the bordered
 //   operator's multiplier column).
 // MODE kRowRichardson: out = x + omega_i dinv_i (f - A x), one step of the
@@ -30,7 +31,7 @@ template <typename V, typename S, typename X, int WL, bool SCALED, int MODE, boo
 __global__ __launch_bounds__(kPatch * kPatchG) void k_rowop_patch(
     int nw, int block, const int32_t* __restrict__ pstart, const V* __restrict__ pval,
     const int32_t* __restrict__ pcol, const float* __restrict__ scale, const S* __restrict__ f,
-    const X* __restrict__ x, S* __restrict__ out, const S* __restrict__ b, const S* __restrict__ lam,
+    const X* __restrict__ x, S* __restrict__ out, const S* __restrict__ b, const double* __restrict__ lam,
     double* __restrict__ partial, const S* __restrict__ dinv, const S* __restrict__ omega,
     S* __restrict__ xcopy, int tail) {
   const int slot = blockIdx.x;
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_rowop_patch(
     xl[t] = S(x[row]);
     if (xcopy) xcopy[row] = S(x[row]);
   }
-  if (BORDER && xcopy && slot == 0 && threadIdx.x == 0) xcopy[tail] = *lam;
+  if (BORDER && xcopy && slot == 0 && threadIdx.x == 0) xcopy[tail] = S(*lam);
   S a0 = S(0), a1 = S(0);
   if (act) {
 #pragma unroll
@@ -85,12 +86,13 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_rowop_patch(
   if (act && g == 0) {
     if (SCALED) acc *= S(scale[row]);
     if (MODE == kRowResidual) {
+      if (BORDER) acc += b[row] * S(*lam);  // continuing iterate: f - A x - b lambda
       out[row] = f[row] - acc;
       if (BDOT) bx = double(b[row]) * double(xl[t]);
     } else if (MODE == kRowRichardson) {
       out[row] = xl[t] + omega[row] * dinv[row] * (f[row] - acc);
     } else {
-      if (BORDER) acc += b[row] * (*lam);
+      if (BORDER) acc += b[row] * S(*lam);
       out[row] = acc;
     }
   }

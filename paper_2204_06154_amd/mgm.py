@@ -36,7 +36,7 @@ class Params(ctypes.Structure):
                 ("n_min", ctypes.c_int32), ("n_coarse_max", ctypes.c_int32), ("nu1", ctypes.c_int32),
                 ("nu2", ctypes.c_int32), ("pre_smoother", ctypes.c_int32), ("post_smoother", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("device_weights", ctypes.c_int32),
-                ("gs_block", ctypes.c_int32)]
+                ("gs_block", ctypes.c_int32), ("cycle", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -137,7 +137,7 @@ def make_params(d: dict) -> Params:
     lib.mgm_default_params(ctypes.byref(p))
     conv = {"disc": {"rbffd": RBFFD, "gfd": GFD}, "problem": {"screened": SCREENED, "poisson": POISSON},
             "precision": PRECISIONS, "pre_smoother": {"fwd": GS_FWD, "bwd": GS_BWD},
-            "post_smoother": {"fwd": GS_FWD, "bwd": GS_BWD}}
+            "post_smoother": {"fwd": GS_FWD, "bwd": GS_BWD}, "cycle": {"V": 0, "W": 1, "F": 2}}
     for k, v in d.items():
         if k in conv and isinstance(v, str):
             v = conv[k][v]

@@ -244,18 +244,19 @@ def test_reduced_precision_bicgstab(case, prec):
     assert abs(info["iters"] - info_ref.iters) <= 2, (info["iters"], info_ref.iters)
 
 
-@pytest.mark.parametrize("nu1,nu2,pre,post", [(2, 2, "fwd", "fwd"), (1, 1, "fwd", "bwd"), (0, 2, "fwd", "bwd"),
-                                               (2, 0, "bwd", "fwd")])
-def test_cycle_variants_match_oracle(case, nu1, nu2, pre, post):
-    """V(nu1, nu2) with forward or backward sweeps (Sec. 4.3; symmetric GS =
-    forward pre- and backward post-smoothing): V-cycle to 1e-10 and the FGMRES
-    iteration count of the oracle with the same cycle."""
+@pytest.mark.parametrize("cycle,nu1,nu2,pre,post", [("V", 2, 2, "fwd", "fwd"), ("V", 1, 1, "fwd", "bwd"),
+                                                     ("V", 0, 2, "fwd", "bwd"), ("V", 2, 0, "bwd", "fwd"),
+                                                     ("W", 1, 1, "fwd", "fwd"), ("F", 1, 1, "fwd", "bwd")])
+def test_cycle_variants_match_oracle(case, cycle, nu1, nu2, pre, post):
+    """V/W/F(nu1, nu2) cycles with forward or backward sweeps (Sec. 4.3;
+    symmetric GS = forward pre- and backward post-smoothing): the cycle to
+    1e-10 and the FGMRES iteration count of the oracle with the same cycle."""
     name, wl, H, m = case
-    p = dict(wl.params, nu1=nu1, nu2=nu2, pre_smoother=pre, post_smoother=post)
+    p = dict(wl.params, nu1=nu1, nu2=nu2, pre_smoother=pre, post_smoother=post, cycle=cycle)
     mv = mgm.Mgm(wl.xyz, wl.normals, p, device=0)
     try:
         M = vcycle.make_preconditioner(vcycle.Fp64Ops(H), H.problem, nu1, nu2, post_reverse=post == "bwd",
-                                       pre_reverse=pre == "bwd")
+                                       pre_reverse=pre == "bwd", cycle=cycle)
         f = _rhs(wl, H)
         assert _rel(_host(mv.vcycle(_dev(f))), M(f)) < 1e-10
         A = vcycle.make_operator(H)

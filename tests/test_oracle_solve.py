@@ -175,6 +175,77 @@ def test_bordered_two_level_matches_dense_definition():
     assert np.allclose(LH[:nc, nc], cl.b) and np.allclose(LH[nc, :nc], cl.b)
 
 
+def _dense_cycle(H, j, kind, nu1=1, nu2=1):
+    """Dense approximate inverse of the level-j cycle of the given kind, from
+    the definitions: M_j = (I - E_j) A_j^-1, E_j = S^nu2 (I - P Q P^T A_j) S^nu1,
+    Q the coarse approximate inverse: M_V of level j+1 (V); two W cycles as a
+    stationary iteration from zero, Q = M + M (I - A M) (W); an F cycle then a
+    V cycle, Q = M_F + M_V (I - A M_F) (F). Bordered levels use [L b; b 0],
+    P extended by the identity on the multiplier, and the smoother updating
+    only u."""
+    lv = H.levels[j]
+    bord = H.problem == "poisson"
+    L = lv.L.toarray()
+    n = lv.N
+    if bord:
+        A = np.block([[L, lv.b[:, None]], [lv.b[None, :], np.zeros((1, 1))]])
+    else:
+        A = L
+    if j == len(H.levels) - 1:
+        return np.linalg.inv(A)
+    P = lv.P.toarray()
+    if bord:
+        nc = H.levels[j + 1].N
+        Pt = np.zeros((n + 1, nc + 1))
+        Pt[:n, :nc] = P
+        Pt[n, nc] = 1.0
+        P = Pt
+    m = A.shape[0]
+    I = np.eye(m)
+    p = _perm(lv)
+    B = np.eye(m)
+    B[np.ix_(p, p)] = np.tril(L[np.ix_(p, p)])
+    S = np.eye(m)
+    S[:n, :] = I[:n, :] - np.linalg.solve(B, A)[:n, :]
+    Ac = P.T @ A @ P
+    if kind == "V":
+        Q = _dense_cycle(H, j + 1, "V", nu1, nu2)
+    elif kind == "W":
+        Mw = _dense_cycle(H, j + 1, "W", nu1, nu2)
+        Q = Mw + Mw @ (np.eye(Ac.shape[0]) - Ac @ Mw)
+    else:
+        Mf = _dense_cycle(H, j + 1, "F", nu1, nu2)
+        Mv = _dense_cycle(H, j + 1, "V", nu1, nu2)
+        Q = Mf + Mv @ (np.eye(Ac.shape[0]) - Ac @ Mf)
+    E = np.linalg.matrix_power(S, nu2) @ (I - P @ Q @ P.T @ A) @ np.linalg.matrix_power(S, nu1)
+    return (I - E) @ np.linalg.inv(A)
+
+
+@pytest.mark.parametrize("kind", ["V", "W", "F"])
+@pytest.mark.parametrize("problem", ["screened", "poisson"])
+def test_three_level_cycles_match_dense_definition(kind, problem):
+    if problem == "screened":
+        wl = synth.sphere_workload(1800)
+        wl.params["n_coarse_max"] = 120
+    else:
+        wl = synth.torus_workload(3200)
+        wl.params["n_min"] = 200
+    H = hierarchy.build(wl.xyz, wl.normals, wl.params)
+    assert len(H.levels) == 3
+    ops = vcycle.Fp64Ops(H)
+    Md = _dense_cycle(H, 0, kind)
+    rng = np.random.default_rng(9)
+    if problem == "screened":
+        r = rng.standard_normal(H.levels[0].N)
+        z = vcycle.vcycle(ops, r, None, cycle=kind)
+    else:
+        r = np.concatenate([rng.standard_normal(H.levels[0].N), [0.2]])
+        zz, lam = vcycle.vcycle(ops, r[:-1], r[-1], cycle=kind)
+        z = np.concatenate([zz, [lam]])
+    ref = Md @ r
+    assert np.max(np.abs(z - ref)) <= 1e-9 * np.max(np.abs(ref))
+
+
 def test_vcycle_is_linear(sphere_h, torus_h):
     for wl, H in (sphere_h, torus_h):
         ops = vcycle.Fp64Ops(H)
