@@ -49,7 +49,9 @@ typedef enum {
 enum { MGM_RBFFD = 0, MGM_GFD = 1 };
 /* Problem (Sec. 1.1, eq. discrete_system): POISSON: L_h = D_h, solved as the
  * bordered system [L b^T; b 0][u; lambda] = [f; 0] with b = 1^T (Sec. 4.4,
- * eq. saddle_point); SCREENED: L_h = I - mu D_h. */
+ * eq. saddle_point); SCREENED: L_h = I - mu D_h. With mu < 0 this is the
+ * shifted operator of shift-invert eigensolves (Sec. 6.1), L_h = -mu (D_h - sigma I)
+ * with sigma = 1/mu: mu = -1 gives D_h + I (sigma = -1), which is indefinite. */
 enum { MGM_SCREENED = 0, MGM_POISSON = 1 };
 /* V-cycle arithmetic: FP64; FP32 values and vectors; FP16 operator values with
  * one FP32 scale per row, FP32 vectors. Outer Krylov and coarsest LU: FP64. */
@@ -68,12 +70,12 @@ enum { MGM_FGMRES = 0, MGM_BICGSTAB = 1, MGM_STATIONARY = 2 };
 
 typedef struct {
   int32_t disc;           /* MGM_RBFFD | MGM_GFD */
-  int32_t phs_order;      /* k of the PHS kernel r^(2k+1) (RBF-FD only), 0..4 */
+  int32_t phs_order;      /* k of the PHS kernel r^(2k+1) (RBF-FD only), 0..6 */
   int32_t poly_degree;    /* l, degree of the bivariate polynomials, 0..6 */
   int32_t stencil_size;   /* n, stencil size, centre included, > L = (l+1)(l+2)/2 */
   double  gfd_alpha;      /* alpha of the GFD Gaussian weight (Sec. 2.3) */
   int32_t problem;        /* MGM_SCREENED | MGM_POISSON */
-  double  mu;             /* screened: L = I - mu D, mu > 0 */
+  double  mu;             /* screened: L = I - mu D, mu finite and non-zero */
   int32_t interp_size;    /* m, coarse stencil of the interpolation (Sec. 3); 3 */
   int32_t coarsen_factor; /* N_{j+1} = floor(N_j / factor) (Sec. 4.1); 4 */
   int32_t n_min;          /* > 0: p = floor(log(N_1/N_min)/log 4) + 1 (Alg. 2) */

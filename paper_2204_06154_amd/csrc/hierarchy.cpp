@@ -24,12 +24,13 @@ void validate_params(const mgm_params& p, int64_t n) {
   if (n < 16 || n > (int64_t(1) << 30)) bad("number of points out of range");
   if (p.disc != MGM_RBFFD && p.disc != MGM_GFD) bad("disc");
   if (p.poly_degree < 0 || p.poly_degree > 6) bad("poly_degree must be 0..6");
-  if (p.disc == MGM_RBFFD && (p.phs_order < 0 || p.phs_order > 4)) bad("phs_order must be 0..4");
+  if (p.disc == MGM_RBFFD && (p.phs_order < 0 || p.phs_order > 6)) bad("phs_order must be 0..6");
   int L = (p.poly_degree + 1) * (p.poly_degree + 2) / 2;
   if (p.stencil_size < L || p.stencil_size > 128 || p.stencil_size > n) bad("stencil_size");
   if (p.disc == MGM_GFD && !(p.gfd_alpha > 0)) bad("gfd_alpha must be > 0");
   if (p.problem != MGM_SCREENED && p.problem != MGM_POISSON) bad("problem");
-  if (p.problem == MGM_SCREENED && !(p.mu > 0)) bad("mu must be > 0 for the screened problem");
+  if (p.problem == MGM_SCREENED && !(std::isfinite(p.mu) && p.mu != 0.0))
+    bad("mu must be finite and non-zero for the screened problem");
   if (p.interp_size < 1 || p.interp_size > 16) bad("interp_size");
   if (p.coarsen_factor < 2) bad("coarsen_factor");
   if (p.n_min < 0 || p.n_coarse_max < 0 || (p.n_min == 0 && p.n_coarse_max == 0)) bad("n_min / n_coarse_max");

@@ -208,7 +208,7 @@ void batched_phs_weights_device(const double* d_xyz, const double* d_nrm, const 
                                 int phs_order, int deg, double* d_w, int* d_status, hipStream_t st) {
   const int L = (deg + 1) * (deg + 2) / 2;
   if (ns < 1 || ns + L > 64) throw Error(MGM_E_ARG, "device weights need stencil_size + L <= 64");
-  if (deg < 0 || deg > 6 || phs_order < 0 || phs_order > 4) throw Error(MGM_E_ARG, "phs_order/poly_degree out of range");
+  if (deg < 0 || deg > 6 || phs_order < 0 || phs_order > 6) throw Error(MGM_E_ARG, "phs_order/poly_degree out of range");
   if (nsys <= 0) return;
   const int m = 2 * phs_order + 1;
   const unsigned blocks = unsigned((nsys + kWaves - 1) / kWaves);

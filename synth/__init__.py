@@ -330,6 +330,20 @@ def sbdf2_workload(n: int = 300_000, dt: float = 0.05, jitter: float = 0.1, lmax
     return Workload(f"sbdf2_{n}", x, x.copy(), u0, params)
 
 
+def harmonics_workload(n: int = 436_605, jitter: float = 0.1, lmax: int = 8, config_id: int = 7) -> Workload:
+    """Shift-invert solves for surface harmonics on the unit sphere: systems
+    (D_h - sigma I) v = f with sigma = -1, i.e. the screened form I - mu D_h
+    with mu = -1. Jittered Fibonacci points, RBF-FD with l = 5, k = l (PHS
+    r^11) and n = (l+1)(l+2) = 42 as in the parameter table; `f` is a random
+    spherical-harmonic field (a start vector for the Arnoldi iteration)."""
+    rp, rf, _ = rng_streams(config_id)
+    x = jittered_fibonacci_sphere(n, rp, jitter)
+    f = sh_rhs(x, lmax, rf)
+    params = dict(disc="rbffd", phs_order=5, poly_degree=5, stencil_size=42, problem="screened",
+                  mu=-1.0, n_min=250, n_coarse_max=0)
+    return Workload(f"harmonics{n}", x, x.copy(), f, params)
+
+
 def torus_workload(n: int = 160_000, config_id: int = 2) -> Workload:
     """Torus, Poisson-disk points, Poisson (bordered) with zero-mean trig f (RBF-FD r^5 + deg 3, k=50)."""
     rp, rf, _ = rng_streams(config_id)

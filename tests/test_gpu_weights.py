@@ -37,7 +37,7 @@ def _poly_repro_error(xyz, nrm, sten, c, deg, centres=None):
 
 
 @pytest.mark.parametrize("surface,phs,deg,k", [("sphere", 1, 2, 30), ("torus", 2, 3, 50), ("star", 1, 3, 50),
-                                                ("star", 2, 2, 20), ("torus", 1, 0, 7)])
+                                                ("star", 2, 2, 20), ("torus", 1, 0, 7), ("sphere", 5, 5, 42)])
 def test_batched_weights_match_oracle(surface, phs, deg, k):
     if surface == "sphere":
         wl = synth.sphere_workload(3000)

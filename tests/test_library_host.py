@@ -43,6 +43,7 @@ CASES = [
     ("torus", lambda: synth.torus_workload(6000), {"n_min": 300}),
     ("gfd", lambda: synth.big_sphere_workload(9001), {"n_min": 200}),
     ("ragged", lambda: synth.sphere_workload(2053), {"n_coarse_max": 100}),
+    ("shifted", lambda: synth.harmonics_workload(3000), {}),
 ]
 
 
@@ -112,7 +113,7 @@ def test_host_only_handle_rejects_device_calls():
 
 
 @pytest.mark.parametrize("mutate,status", [
-    ("dup", -5), ("nan", -9), ("mu0", -1), ("tiny", -1), ("badstencil", -1), ("collinear", -4),
+    ("dup", -5), ("nan", -9), ("mu0", -1), ("muinf", -1), ("tiny", -1), ("badstencil", -1), ("collinear", -4),
 ])
 def test_failure_injection(mutate, status):
     wl = synth.sphere_workload(800)
@@ -124,6 +125,8 @@ def test_failure_injection(mutate, status):
         x[3, 1] = np.nan
     elif mutate == "mu0":
         p["mu"] = 0.0
+    elif mutate == "muinf":
+        p["mu"] = -np.inf
     elif mutate == "tiny":
         x, nrm = x[:10], nrm[:10]
     elif mutate == "badstencil":

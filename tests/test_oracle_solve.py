@@ -307,6 +307,37 @@ def test_screened_sphere_solution_approaches_continuous(sphere_h):
     assert err < 0.05
 
 
+def test_shift_invert_eigenvalues_on_sphere():
+    """Surface harmonics by shift-invert Arnoldi (Sec. 6.1, sigma = -1) with the
+    oracle's MGM-FGMRES solves of (D_h + I) v = x (screened form, mu = -1).
+    The eigenvalues of the Laplace-Beltrami operator on the unit sphere are
+    -l(l+1) with multiplicity 2l+1, so the 9 nearest -1 are 0, -2 (x3), -6
+    (x5); RBF-FD with l = 5 reproduces them to ~1e-7 at N = 4096. The same
+    eigenvalues from exact sparse-LU shift-invert pin the solves to 1e-9."""
+    import scipy.sparse.linalg as spla
+    wl = synth.harmonics_workload(4096)
+    H = hierarchy.build(wl.xyz, wl.normals, wl.params)
+    A = vcycle.make_operator(H)
+    M = vcycle.make_preconditioner(vcycle.Fp64Ops(H), H.problem)
+    n = len(wl.f)
+    iters = []
+
+    def opinv(x):
+        y, info = krylov.fgmres(A, M, np.asarray(x, dtype=np.float64).ravel(), tol=1e-10, restart=40, maxit=200)
+        assert info.converged
+        iters.append(info.iters)
+        return y                                  # (D + I)^{-1} x = L^{-1} x, since -mu = 1
+
+    D = (H.levels[0].L - sp.identity(n)).tocsc()  # L = I + D
+    ev = spla.eigs(D, k=9, sigma=-1.0, OPinv=spla.LinearOperator((n, n), matvec=opinv, dtype=np.float64),
+                   which="LM", v0=wl.f, tol=1e-10, return_eigenvectors=False)
+    ev = np.sort(ev.real)
+    exact = np.sort(spla.eigs(D, k=9, sigma=-1.0, which="LM", v0=wl.f, return_eigenvectors=False).real)
+    assert np.max(np.abs(ev - exact)) < 1e-9
+    assert np.max(np.abs(ev - np.array([-6.0] * 5 + [-2.0] * 3 + [0.0]))) < 1e-5
+    assert 30 <= len(iters) <= 80 and max(iters) <= 20
+
+
 # -------------------------------------------------- reduced-precision emulation
 def _fp16_rne_exact(x: float) -> float:
     """Round a double to the nearest binary16 value, ties to even, by exact rational arithmetic."""
