@@ -190,25 +190,44 @@ void build_interp(const HostLevel& fine, const std::vector<double>& cxyz, int m,
 
 Csr galerkin_product(const Csr& R, const Csr& A, const Csr& P) { return spgemm(R, spgemm(A, P)); }
 
-// Symmetrised adjacency of A without the diagonal (sorted rows).
+// Symmetrised adjacency of A without the diagonal (sorted rows): row i is the
+// union of row i of A and of A^T (both sorted), merged without duplicates.
 static void symmetric_adjacency(const Csr& A, std::vector<int32_t>& ptr, std::vector<int32_t>& adj) {
   const int32_t n = A.nrows;
-  Csr At = transpose(A);
-  std::vector<std::vector<int32_t>> rows(n);
+  // pattern of A^T (rows ascending, so each of its rows is sorted)
+  std::vector<int32_t> tptr(n + 1, 0), tcol(A.nnz());
+  for (int64_t k = 0; k < A.nnz(); ++k) tptr[A.col[k] + 1]++;
+  for (int32_t i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
+  {
+    std::vector<int32_t> fill(tptr.begin(), tptr.end() - 1);
+    for (int32_t i = 0; i < n; ++i)
+      for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) tcol[fill[A.col[k]]++] = i;
+  }
+  std::vector<int64_t> off(n + 1, 0);
+  for (int32_t i = 0; i < n; ++i) off[i + 1] = off[i] + (A.ptr[i + 1] - A.ptr[i]) + (tptr[i + 1] - tptr[i]);
+  std::vector<int32_t> buf(off[n]), len(n);
   parallel_for(n, [&](int64_t b, int64_t e) {
     for (int64_t i = b; i < e; ++i) {
-      auto& r = rows[i];
-      r.assign(A.col.begin() + A.ptr[i], A.col.begin() + A.ptr[i + 1]);
-      r.insert(r.end(), At.col.begin() + At.ptr[i], At.col.begin() + At.ptr[i + 1]);
-      std::sort(r.begin(), r.end());
-      r.erase(std::unique(r.begin(), r.end()), r.end());
-      r.erase(std::remove(r.begin(), r.end(), int32_t(i)), r.end());
+      int32_t ka = A.ptr[i], ea = A.ptr[i + 1], kt = tptr[i], et = tptr[i + 1];
+      int32_t* out = buf.data() + off[i];
+      int32_t cnt = 0, last = -1;
+      while (ka < ea || kt < et) {
+        int32_t c;
+        if (kt >= et || (ka < ea && A.col[ka] <= tcol[kt])) c = A.col[ka++];
+        else c = tcol[kt++];
+        if (c == last || c == int32_t(i)) continue;
+        out[cnt++] = c;
+        last = c;
+      }
+      len[i] = cnt;
     }
   });
   ptr.assign(n + 1, 0);
-  for (int32_t i = 0; i < n; ++i) ptr[i + 1] = ptr[i] + int32_t(rows[i].size());
+  for (int32_t i = 0; i < n; ++i) ptr[i + 1] = ptr[i] + len[i];
   adj.resize(ptr[n]);
-  for (int32_t i = 0; i < n; ++i) std::copy(rows[i].begin(), rows[i].end(), adj.begin() + ptr[i]);
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i) std::copy(buf.begin() + off[i], buf.begin() + off[i] + len[i], adj.begin() + ptr[i]);
+  });
 }
 
 // Jones-Plassmann colouring with largest-degree-first priorities: rank by
@@ -436,11 +455,12 @@ static int32_t rcb_patches(const double* xyz, int32_t n, int block, std::vector<
     int axis = 0;
     for (int a = 1; a < 3; ++a)
       if (hi[a] - lo[a] > hi[axis] - lo[axis]) axis = a;
-    std::sort(ids.begin() + b, ids.begin() + e, [&](int32_t i, int32_t j) {
+    const int32_t cut = ((e - b + block - 1) / block / 2) * block;
+    // only the set of the first `cut` points matters: select, do not sort
+    std::nth_element(ids.begin() + b, ids.begin() + b + cut, ids.begin() + e, [&](int32_t i, int32_t j) {
       const double xi = xyz[3 * size_t(i) + axis], xj = xyz[3 * size_t(j) + axis];
       return xi < xj || (xi == xj && i < j);
     });
-    const int32_t cut = ((e - b + block - 1) / block / 2) * block;
     stack.emplace_back(b + cut, e);
     stack.emplace_back(b, b + cut);
   }
@@ -507,7 +527,7 @@ void smoother_colouring(HostLevel& l, int block) {
   std::vector<int32_t> lc(n, -1), pnlc(l.npatch, 0);
   parallel_for(l.npatch, [&](int64_t b, int64_t e) {
     for (int64_t p = b; p < e; ++p) pnlc[p] = dsatur_range(lptr, ladj, pstart[p], pstart[p + 1], lc);
-  });
+  }, 2);
   l.lcolour.resize(n);
   for (int32_t t = 0; t < n; ++t) l.lcolour[byp[t]] = lc[t];
   int nlc = 0;
@@ -633,7 +653,7 @@ void build_hierarchy(const double* xyz, const double* nrm, int64_t n, const mgm_
       lu_solve(A.data(), dim, piv.data(), x.data());
       for (int r = 0; r < dim; ++r) H.coarse_inv[size_t(r) * dim + c] = x[r];
     }
-  });
+  }, 64);
 }
 
 }  // namespace mgm

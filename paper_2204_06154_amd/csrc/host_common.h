@@ -28,9 +28,11 @@ inline int num_threads() {
   return int(h);
 }
 
-inline void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& body) {
+// Runs on one thread when n < min_items (small loops of cheap items); loops
+// over few expensive items (patches, matrix columns) pass a smaller bound.
+inline void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& body, int64_t min_items = 2048) {
   int nt = num_threads();
-  if (n < 2048 || nt == 1) {
+  if (n < min_items || nt == 1) {
     body(0, n);
     return;
   }
