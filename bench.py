@@ -290,6 +290,35 @@ def bench_harmonics(args):
     m.close()
 
 
+def bench_setup(args):
+    """Preprocessing time (Alg. 2) of the torus workload: everything on the
+    host, with the batched device weight solve, and with the kNN searches and
+    Galerkin products on the device as well (median of 3 set-ups each)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2204_06154_amd import mgm
+
+    wl = synth.torus_workload(args.n)
+    out = {"workload": f"setup of the torus N={args.n}, RBF-FD r^5+deg3 k=50, bordered Poisson"}
+    for name, flags in (("host", dict(device_weights=0, device_setup=0)),
+                        ("device_weights", dict(device_weights=1, device_setup=0)),
+                        ("device_weights_knn_rap", dict(device_weights=1, device_setup=1))):
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            m = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, **flags), device=0)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            m.close()
+        out[name + "_s"] = round(float(np.median(ts)), 3)
+        log(f"setup {name}: {out[name + '_s']:.3f} s")
+    out["host_threads"] = len(os.sched_getaffinity(0))
+    print(json.dumps(out), flush=True)
+
+
 def bench_traffic(args):
     """Launch set for the HBM-traffic counters: FP32 patch-GS launches of the
     torus workload as the roofline times them (every smoother launch of a
@@ -329,7 +358,8 @@ def main():
     ap.add_argument("--weights-n", type=int, default=500_000)
     ap.add_argument("--gs-block", type=int, default=256)
     ap.add_argument("--cycle", choices=["V", "W", "F"], default="V", help="multigrid cycle of the torus workload")
-    ap.add_argument("--workload", choices=["torus", "learned", "sphere1m", "traffic", "sbdf2", "harmonics"],
+    ap.add_argument("--workload", choices=["torus", "learned", "sphere1m", "traffic", "sbdf2", "harmonics",
+                                                 "setup"],
                     default="torus")
     ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--vcycle-precision", default="fp32", help="V-cycle precision of the learned and sbdf2 workloads")
@@ -356,6 +386,8 @@ def main():
         if args.n == 160_000:
             args.n = 300_000
         return bench_sbdf2(args)
+    if args.workload == "setup":
+        return bench_setup(args)
     if args.workload == "harmonics":
         if args.n == 160_000:
             args.n = 436_605

@@ -89,15 +89,19 @@ typedef struct {
   int32_t gs_block;       /* smoother blocking: 0 = plain multicolour GS (Jones-
                              Plassmann colours); B in 1..256 = patch-blocked
                              multicolour GS: patches of B points by recursive
-                             coordinate bisection, patch graph and in-patch graphs
-                             coloured by DSATUR, one workgroup per patch; levels
+                             coordinate bisection, patch graph coloured by
+                             recursive largest first, in-patch graphs by DSATUR,
+                             one workgroup per patch; levels
                              with rows longer than 96 entries stay plain */
   int32_t cycle;          /* MGM_CYCLE_V | MGM_CYCLE_W | MGM_CYCLE_F */
+  int32_t device_setup;   /* 1: kNN searches (k <= 128) and the Galerkin sparse
+                             products on the device; results identical to the
+                             host path */
 } mgm_params;
 
 /* Paper defaults (Table 1): RBF-FD, k = l = 3, n = 20, forward GS, nu = 1,
  * m = 3, factor 4, N_min = 250, screened with mu = 1; FP64 V-cycle, graphs
- * on, device weights on, gs_block = 256, V-cycle. */
+ * on, device weights and device setup on, gs_block = 256, V-cycle. */
 void mgm_default_params(mgm_params *p);
 
 /* Preprocessing phase (Alg. 2): kNN stencils (Sec. 2), tangent-plane weights

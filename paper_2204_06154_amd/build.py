@@ -16,7 +16,8 @@ LIB = os.path.join(HERE, "libmgm.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SOURCES = ["knn.cpp", "weights.cpp", "wse.cpp", "hierarchy.cpp"]
-HIP_SOURCES = ["device.hip", "phs_batched.hip", "learned.hip"]
+HIP_SOURCES = ["device.hip", "phs_batched.hip", "learned.hip", "setup_device.hip"]
+EXACT_HIP_SOURCES = {"setup_device.hip"}
 
 
 def _run(cmd):
@@ -36,9 +37,11 @@ def build(verbose: bool = True) -> str:
         objs.append(obj)
     for src in HIP_SOURCES:
         obj = os.path.join(bdir, src + ".o")
+        # the device preprocessing must round exactly as the host path does
+        contract = "-ffp-contract=off" if src in EXACT_HIP_SOURCES else "-ffp-contract=fast"
         _run([hipcc, "-std=c++17", "-O3", "-fPIC", "--offload-arch=gfx950",
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-              "-ffp-contract=fast",
+              contract,
               "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     tmp = LIB + ".tmp"

@@ -1243,6 +1243,7 @@ void mgm_default_params(mgm_params* p) {
   p->precision = MGM_FP64;
   p->use_graph = 1;
   p->device_weights = 1;
+  p->device_setup = 1;
   p->gs_block = 256;
   p->cycle = MGM_CYCLE_V;
 }
@@ -1260,10 +1261,18 @@ mgm_status mgm_setup(const double* h_xyz, const double* h_normals, int64_t n, co
     c->p = *params;
     if (device < -1) throw Error(MGM_E_ARG, "device must be >= -1");
     if (device >= 0) HIPCHECK(hipSetDevice(device));
-    if (device >= 0 && params->device_weights)
-      build_hierarchy(h_xyz, h_normals, n, *params, device_weights_fn(static_cast<hipStream_t>(stream)), c->H);
-    else
-      build_hierarchy(h_xyz, h_normals, n, *params, stencil_weights_host, c->H);
+    SetupBackend be = host_backend();
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    if (device >= 0 && params->device_weights) be.weights = device_weights_fn(st);
+    if (device >= 0 && params->device_setup) {
+      be.knn = [st](const double* q, int64_t nq, const double* d, int64_t nd, int k, std::vector<int32_t>& idx,
+                    std::vector<double>& d2) {
+        if (k <= 128) knn_device(q, nq, d, nd, k, idx, d2, st);
+        else knn_search(q, nq, d, nd, k, idx, d2);
+      };
+      be.spgemm = [st](const Csr& A, const Csr& B) { return spgemm_device(A, B, st); };
+    }
+    build_hierarchy(h_xyz, h_normals, n, *params, be, c->H);
     if (device >= 0) {
       upload(c.get());
       HIPCHECK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));

@@ -76,10 +76,7 @@ Csr transpose(const Csr& A) {
   return T;  // rows ascending => columns sorted within each row
 }
 
-namespace {
-
-// C = A * B on the structural product pattern, columns sorted per row.
-Csr spgemm(const Csr& A, const Csr& B) {
+Csr spgemm_host(const Csr& A, const Csr& B) {
   Csr C;
   C.nrows = A.nrows;
   C.ncols = B.ncols;
@@ -121,6 +118,8 @@ Csr spgemm(const Csr& A, const Csr& B) {
   return C;
 }
 
+namespace {
+
 inline uint64_t splitmix64(uint64_t x) {
   uint64_t z = x + 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -128,11 +127,11 @@ inline uint64_t splitmix64(uint64_t x) {
   return z ^ (z >> 31);
 }
 
-void build_interp(const HostLevel& fine, const std::vector<double>& cxyz, int m, HostLevel& out) {
+void build_interp(const HostLevel& fine, const std::vector<double>& cxyz, int m, const KnnFn& knn, HostLevel& out) {
   const int64_t n = fine.n;
   const int64_t nc = int64_t(cxyz.size() / 3);
   std::vector<double> d2;
-  knn_search(fine.xyz.data(), n, cxyz.data(), nc, m, out.pidx, d2);
+  knn(fine.xyz.data(), n, cxyz.data(), nc, m, out.pidx, d2);
   out.pw.assign(size_t(n) * m, 0.0);
   out.injected.assign(n, 0);
   out.m = m;
@@ -188,7 +187,9 @@ void build_interp(const HostLevel& fine, const std::vector<double>& cxyz, int m,
 
 }  // namespace
 
-Csr galerkin_product(const Csr& R, const Csr& A, const Csr& P) { return spgemm(R, spgemm(A, P)); }
+Csr galerkin_product(const Csr& R, const Csr& A, const Csr& P) { return spgemm_host(R, spgemm_host(A, P)); }
+
+SetupBackend host_backend() { return SetupBackend{stencil_weights_host, knn_search, spgemm_host}; }
 
 // Symmetrised adjacency of A without the diagonal (sorted rows): row i is the
 // union of row i of A and of A^T (both sorted), merged without duplicates.
@@ -545,7 +546,7 @@ void smoother_colouring(HostLevel& l, int block) {
 }
 
 void build_hierarchy(const double* xyz, const double* nrm, int64_t n, const mgm_params& p,
-                     const WeightsFn& weights, HostHierarchy& H) {
+                     const SetupBackend& be, HostHierarchy& H) {
   validate_params(p, n);
   for (int64_t i = 0; i < 3 * n; ++i)
     if (!std::isfinite(xyz[i]) || !std::isfinite(nrm[i])) throw Error(MGM_E_NONFINITE, "non-finite point or normal");
@@ -556,12 +557,12 @@ void build_hierarchy(const double* xyz, const double* nrm, int64_t n, const mgm_
   const int ns = p.stencil_size;
   H.ns = ns;
   std::vector<double> d2;
-  knn_search(xyz, n, xyz, n, ns, H.stencils, d2);
+  be.knn(xyz, n, xyz, n, ns, H.stencils, d2);
   for (int64_t i = 0; i < n; ++i) {
     if (ns > 1 && d2[size_t(i) * ns + 1] == 0.0) throw Error(MGM_E_DUP_POINTS, "duplicate points in the point cloud");
     if (H.stencils[size_t(i) * ns] != i) throw Error(MGM_E_DUP_POINTS, "stencil centre is not first");
   }
-  weights(xyz, nrm, n, H.stencils.data(), ns, p, H.weights);
+  be.weights(xyz, nrm, n, H.stencils.data(), ns, p, H.weights);
   for (double w : H.weights)
     if (!std::isfinite(w)) throw Error(MGM_E_NONFINITE, "non-finite stencil weight");
 
@@ -604,8 +605,8 @@ void build_hierarchy(const double* xyz, const double* nrm, int64_t n, const mgm_
     c.xyz.resize(size_t(c.n) * 3);
     for (int32_t t = 0; t < c.n; ++t)
       for (int a = 0; a < 3; ++a) c.xyz[3 * size_t(t) + a] = f.xyz[3 * size_t(f.coarse_idx[t]) + a];
-    build_interp(f, c.xyz, std::min(p.interp_size, int(c.n)), f);
-    c.L = galerkin_product(f.R, f.L, f.P);
+    build_interp(f, c.xyz, std::min(p.interp_size, int(c.n)), be.knn, f);
+    c.L = be.spgemm(f.R, be.spgemm(f.L, f.P));
     if (!f.b.empty()) {
       c.b.assign(c.n, 0.0);
       for (int32_t i = 0; i < c.n; ++i) {

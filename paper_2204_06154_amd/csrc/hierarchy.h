@@ -48,9 +48,24 @@ struct HostHierarchy {
 
 constexpr int kMaxPatchWidth = 96;   // rows longer than this disable patch blocking on a level
 
+// k nearest neighbours of the queries among the data points (host or device).
+using KnnFn = std::function<void(const double* queries, int64_t nq, const double* data, int64_t nd, int k,
+                                 std::vector<int32_t>& idx, std::vector<double>& d2)>;
+// C = A * B on the structural product pattern (host or device).
+using SpgemmFn = std::function<Csr(const Csr& A, const Csr& B)>;
+
+// The preprocessing steps that have a host and a device implementation; both
+// give identical results.
+struct SetupBackend {
+  WeightsFn weights;
+  KnnFn knn;
+  SpgemmFn spgemm;
+};
+SetupBackend host_backend();
+
 void validate_params(const mgm_params& p, int64_t n);
 std::vector<int32_t> level_sizes(int64_t n1, const mgm_params& p);
 void build_hierarchy(const double* xyz, const double* nrm, int64_t n, const mgm_params& p,
-                     const WeightsFn& weights, HostHierarchy& H);
+                     const SetupBackend& be, HostHierarchy& H);
 
 }  // namespace mgm

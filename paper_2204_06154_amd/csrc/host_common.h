@@ -63,6 +63,19 @@ struct Csr {
   int64_t nnz() const { return ptr.empty() ? 0 : ptr.back(); }
 };
 
+// Dense grid of cubic cells over the bounding box of a point set, sized for
+// k-nearest-neighbour searches; points bucketed by cell, ascending index
+// within a cell.
+struct KnnGrid {
+  double lo[3], h;
+  int dim[3];
+  std::vector<int32_t> start;  // ncells + 1
+  std::vector<int32_t> pts;    // point indices sorted by cell, then index
+  int64_t cell_index(int cx, int cy, int cz) const;
+  int coord(double x, int a) const;  // clamped cell coordinate along axis a
+};
+KnnGrid knn_grid(const double* data, int64_t nd, int k);
+
 // kNN under the key (d2, index), d2 = ((dx*dx) + (dy*dy)) + dz*dz.
 // queries: nq x 3, data: nd x 3 (row-major). Outputs nq x k indices / d2.
 void knn_search(const double* queries, int64_t nq, const double* data, int64_t nd, int k,
@@ -81,6 +94,9 @@ std::vector<int32_t> wse_eliminate(const double* xyz, int64_t n, int factor);
 // Jones-Plassmann largest-degree-first colouring of the symmetrised graph of A.
 std::vector<int32_t> colour_graph(const Csr& A, int* ncolours);
 
+// C = A * B on the structural product pattern, columns sorted per row; entry
+// (i, j) is summed from 0.0 over the row of A in ascending column order.
+Csr spgemm_host(const Csr& A, const Csr& B);
 // C = R * A * P with the structural product pattern.
 Csr galerkin_product(const Csr& R, const Csr& A, const Csr& P);
 Csr transpose(const Csr& A);

@@ -18,27 +18,17 @@
 
 namespace mgm {
 
-namespace {
+int64_t KnnGrid::cell_index(int cx, int cy, int cz) const { return (int64_t(cz) * dim[1] + cy) * dim[0] + cx; }
 
-struct Grid {
-  double lo[3], h;
-  int dim[3];
-  std::vector<int32_t> start;  // ncells + 1
-  std::vector<int32_t> pts;    // point indices sorted by cell, then index
+int KnnGrid::coord(double x, int a) const {
+  double t = std::floor((x - lo[a]) / h);
+  if (!(t >= 0)) return 0;
+  if (t >= dim[a] - 1) return dim[a] - 1;
+  return int(t);
+}
 
-  int64_t cell_index(int cx, int cy, int cz) const {
-    return (int64_t(cz) * dim[1] + cy) * dim[0] + cx;
-  }
-  int coord(double x, int a) const {
-    double t = std::floor((x - lo[a]) / h);
-    if (!(t >= 0)) return 0;
-    if (t >= dim[a] - 1) return dim[a] - 1;
-    return int(t);
-  }
-};
-
-Grid build_grid(const double* data, int64_t nd, int k) {
-  Grid g;
+KnnGrid knn_grid(const double* data, int64_t nd, int k) {
+  KnnGrid g;
   double hi[3];
   for (int a = 0; a < 3; ++a) {
     g.lo[a] = std::numeric_limits<double>::infinity();
@@ -83,6 +73,8 @@ Grid build_grid(const double* data, int64_t nd, int k) {
   return g;
 }
 
+namespace {
+
 struct Cand {
   double d2;
   int32_t j;
@@ -96,7 +88,7 @@ inline bool key_less(const Cand& a, const Cand& b) {
 void knn_search(const double* queries, int64_t nq, const double* data, int64_t nd, int k,
                 std::vector<int32_t>& idx, std::vector<double>& d2out) {
   if (k < 1 || k > nd) throw Error(MGM_E_ARG, "knn: k out of range");
-  Grid g = build_grid(data, nd, k);
+  KnnGrid g = knn_grid(data, nd, k);
   idx.assign(size_t(nq) * k, 0);
   d2out.assign(size_t(nq) * k, 0.0);
   const double inf = std::numeric_limits<double>::infinity();

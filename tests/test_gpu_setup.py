@@ -1,0 +1,77 @@
+"""Preprocessing on the device (Alg. 2): kNN searches and Galerkin products.
+
+A handle set up with device_setup = 1 runs the stencil and interpolation
+neighbour searches and both sparse products of R L P on the GPU. The searches
+return the unique k smallest (d2, index) keys and every product entry is
+summed in the host's order, so the whole hierarchy must equal the host-only
+handle's bit for bit (integers and floating point), and its integer parts must
+equal the oracle's.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import hierarchy
+from paper_2204_06154_amd import mgm
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ("sphere", lambda: synth.sphere_workload(3000), {"n_coarse_max": 150}),
+    ("torus", lambda: synth.torus_workload(6000), {"n_min": 300}),
+    ("gfd", lambda: synth.big_sphere_workload(9001), {"n_min": 200}),
+    ("shifted", lambda: synth.harmonics_workload(3000), {}),
+    ("ragged", lambda: synth.sphere_workload(2053), {"n_coarse_max": 100}),
+]
+
+
+@pytest.mark.parametrize("name,make,extra", CASES, ids=[c[0] for c in CASES])
+def test_device_setup_equals_host_setup_bit_for_bit(name, make, extra):
+    wl = make()
+    wl.params.update(extra)
+    print(f"[setup] {name} N={len(wl.xyz)}", flush=True)
+    md = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, device_setup=1), device=0)
+    mh = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, device_weights=0), device=-1)
+    H = hierarchy.build(wl.xyz, wl.normals, wl.params)
+    try:
+        sizes = list(md.export("level_sizes"))
+        assert sizes == list(mh.export("level_sizes")) == [lv.N for lv in H.levels]
+        st = md.export("stencils")
+        assert np.array_equal(st, mh.export("stencils"))
+        assert np.array_equal(st.reshape(len(wl.xyz), -1), H.stencils)
+        for j in range(len(sizes) - 1):
+            for what in ("coarse_idx", "interp_idx", "colours", "patch"):
+                assert np.array_equal(md.export(what, j), mh.export(what, j)), (what, j)
+            assert np.array_equal(md.export("interp_idx", j).reshape(sizes[j], -1), H.levels[j].interp_idx), j
+            assert np.array_equal(md.export("coarse_idx", j), H.levels[j].coarse_idx), j
+        for j in range(len(sizes)):
+            for what in ("l_rowptr", "l_cols"):
+                assert np.array_equal(md.export(what, j), mh.export(what, j)), (what, j)
+            assert np.array_equal(md.export("l_rowptr", j), H.levels[j].pat.indptr), j
+            assert np.array_equal(md.export("l_cols", j), H.levels[j].pat.indices), j
+            if j > 0:   # level 1 holds the weights, which the device solves separately
+                a, b = md.export("l_vals", j), mh.export("l_vals", j)
+                if wl.params["disc"] == "gfd":
+                    assert np.array_equal(a.view(np.int64), b.view(np.int64)), j
+    finally:
+        md.close()
+        mh.close()
+
+
+def test_device_setup_products_bit_exact_with_host_weights():
+    """With the same (host) stencil weights on both sides, every coarse
+    operator from the device products equals the host's bit for bit."""
+    wl = synth.torus_workload(6000)
+    p = dict(wl.params, n_min=300, device_weights=0)
+    md = mgm.Mgm(wl.xyz, wl.normals, dict(p, device_setup=1), device=0)
+    mh = mgm.Mgm(wl.xyz, wl.normals, p, device=-1)
+    try:
+        for j in range(len(md.export("level_sizes"))):
+            a, b = md.export("l_vals", j), mh.export("l_vals", j)
+            assert np.array_equal(a.view(np.int64), b.view(np.int64)), j
+            if j > 0:
+                assert np.array_equal(md.export("border", j).view(np.int64), mh.export("border", j).view(np.int64))
+    finally:
+        md.close()
+        mh.close()
