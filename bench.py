@@ -319,6 +319,73 @@ def bench_setup(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_geodesic(args):
+    """Heat-method geodesic distance on the unit sphere (N points; LBO RBF-FD
+    l = 3, n = 20; surface gradient RBF-FD l = 2, n = 12): three backward-Euler
+    heat solves, the normalised gradient and its divergence, and the bordered
+    Poisson solve, all to 1e-8 with FGMRES + MGM, timed end to end; the
+    surface-operator kernels are also timed on their own (algorithmic bytes:
+    weights, columns, the input once and the output once per node)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2204_06154_amd import mgm
+    from paper_2204_06154_amd.geodesic import heat_distance
+
+    t0 = time.perf_counter()
+    wl = synth.geodesic_workload(args.n)
+    hp = wl.heat
+    log(f"inputs N={args.n} generated in {time.perf_counter() - t0:.1f} s")
+    prec = args.vcycle_precision
+    t0 = time.perf_counter()
+    m = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, precision=prec), device=0)
+    m.surface_ops_setup(hp["grad_phs_order"], hp["grad_degree"], hp["grad_stencil"])
+    mh = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, problem="screened", mu=hp["dt"], precision=prec), device=0)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    heat_distance(mh, m, hp["source"], steps=hp["steps"])          # graphs warmed up, not timed
+    times = []
+    for _ in range(max(args.steps, 1)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d, iters = heat_distance(mh, m, hp["source"], steps=hp["steps"])
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    x = wl.xyz
+    exact = np.arccos(np.clip(x @ x[hp["source"]], -1.0, 1.0))
+    err = np.abs(d.cpu().numpy() - exact)
+    n, ns = args.n, hp["grad_stencil"]
+    u = torch.rand(n, dtype=torch.float64, device="cuda")
+    g = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    dv = torch.empty(n, dtype=torch.float64, device="cuda")
+    kern = {}
+    for name, fn, nbytes in (("grad_normalise", lambda: m.surface_gradient(u, g, normalise=True),
+                              n * ns * 28 + n * 8 + n * 24),
+                             ("divergence", lambda: m.surface_divergence(g, dv), n * ns * 28 + n * 24 + n * 8)):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 50
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / reps
+        kern[name] = {"us": round(us, 2), "bytes": nbytes, "GB_s": round(nbytes / us / 1e3, 1)}
+        log(f"{name}: {us:.1f} us, {nbytes / 1e6:.1f} MB -> {nbytes / us / 1e3:.0f} GB/s")
+    out = {"workload": f"heat-method geodesics, unit sphere N={args.n}, LBO RBF-FD r^7+deg3 k=20, gradient "
+                       f"RBF-FD r^5+deg2 k=12, dt={hp['dt']} x{hp['steps']}, FGMRES(40)+MGM to 1e-8, V-cycle {prec}",
+           "levels": [int(v) for v in m.export("level_sizes")], "setup_s": round(setup_s, 2),
+           "ms_total": round(1e3 * float(np.median(times)), 3), "iters": iters,
+           "mean_err_vs_great_circle": float(err.mean()), "max_err_vs_great_circle": float(err.max()),
+           "kernels": kern}
+    log(f"distance in {out['ms_total']:.2f} ms, iterations {iters}, mean error {err.mean():.4f}")
+    print(json.dumps(out), flush=True)
+    m.close()
+    mh.close()
+
+
 def bench_traffic(args):
     """Launch set for the HBM-traffic counters: FP32 patch-GS launches of the
     torus workload as the roofline times them (every smoother launch of a
@@ -359,7 +426,7 @@ def main():
     ap.add_argument("--gs-block", type=int, default=256)
     ap.add_argument("--cycle", choices=["V", "W", "F"], default="V", help="multigrid cycle of the torus workload")
     ap.add_argument("--workload", choices=["torus", "learned", "sphere1m", "traffic", "sbdf2", "harmonics",
-                                                 "setup"],
+                                                 "setup", "geodesic"],
                     default="torus")
     ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--vcycle-precision", default="fp32", help="V-cycle precision of the learned and sbdf2 workloads")
@@ -386,6 +453,10 @@ def main():
         if args.n == 160_000:
             args.n = 300_000
         return bench_sbdf2(args)
+    if args.workload == "geodesic":
+        if args.n == 160_000:
+            args.n = 872_773
+        return bench_geodesic(args)
     if args.workload == "setup":
         return bench_setup(args)
     if args.workload == "harmonics":

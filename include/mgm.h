@@ -271,6 +271,30 @@ mgm_status mgm_batched_weights(const double *d_xyz, const double *d_normals, int
                                int32_t phs_order, int32_t poly_degree, double *d_weights,
                                void *stream);
 
+/* Surface gradient and divergence (Sec. 6.3: the heat method for geodesic
+ * distance uses them with MGM solves; the weights are the tangent-plane RBF-FD
+ * of Sec. 2.1-2.2 with first derivatives at the centre on the right-hand
+ * side). mgm_surface_ops_setup builds, on the handle's fine point cloud,
+ * stencils of stencil_size nearest points and PHS r^(2*phs_order+1) +
+ * degree-poly_degree weights: a vector W_ij per entry, W_ij = g1_ij t1_i +
+ * g2_ij t2_i with g1, g2 the weights of d/dxh, d/dyh in the tangent basis of
+ * x_i. Needs 1 <= poly_degree <= 6, 1 <= phs_order <= 6 and
+ * (l+1)(l+2)/2 <= stencil_size <= min(128, N); MGM_E_STENCIL_SINGULAR for a
+ * singular local system. The handle owns the operator (about 28 bytes per
+ * entry on the device). On a host-only handle the call builds the weights
+ * for mgm_export only. Calling it again replaces the operator.
+ *   mgm_surface_gradient: d_g (device FP64, N x 3 row-major, caller order) =
+ *     grad_M u for d_u (device FP64, length N); normalise = 1 gives instead
+ *     -grad u / |grad u| (the heat-method direction), 0 where grad u = 0.
+ *   mgm_surface_divergence: d_out (device FP64, length N) = div_M v for a
+ *     field d_v (device FP64, N x 3 row-major), taken in each node's tangent
+ *     plane: sum_j W_ij . v_j.
+ * Stream-ordered, no synchronisation; MGM_E_ARG before the setup call. */
+mgm_status mgm_surface_ops_setup(mgm_handle h, int32_t phs_order, int32_t poly_degree, int32_t stencil_size,
+                                 void *stream);
+mgm_status mgm_surface_gradient(mgm_handle h, const double *d_u, double *d_g, int32_t normalise, void *stream);
+mgm_status mgm_surface_divergence(mgm_handle h, const double *d_v, double *d_out, void *stream);
+
 /* Export of setup results for bit-exact comparison (host buffers).
  * Call with h_buf = NULL to query *len (element count); then with a buffer of
  * at least *len elements. Element types: I32 = int32_t, F64 = double.
@@ -288,13 +312,16 @@ mgm_status mgm_batched_weights(const double *d_xyz, const double *d_normals, int
  *   MGM_EX_NCOLOURS      I32  colours per smoothed level      (level ignored)
  *   MGM_EX_PATCH         I32  smoother patch of each row of level j (empty when
  *                             the level is not patch-blocked)
- *   MGM_EX_OMEGA         F64  N_1 x s learned step weights (caller order) */
+ *   MGM_EX_OMEGA         F64  N_1 x s learned step weights (caller order)
+ *   MGM_EX_GRAD_STENCILS I32  N_1 x n_g surface-operator stencils (after
+ *                             mgm_surface_ops_setup)
+ *   MGM_EX_GRAD_WEIGHTS  F64  N_1 x n_g x 3 surface-gradient weights W_ij */
 enum {
   MGM_EX_LEVEL_SIZES = 0, MGM_EX_STENCILS = 1, MGM_EX_WEIGHTS = 2,
   MGM_EX_COARSE_IDX = 3, MGM_EX_INTERP_IDX = 4, MGM_EX_INTERP_W = 5,
   MGM_EX_COLOURS = 6, MGM_EX_L_ROWPTR = 7, MGM_EX_L_COLS = 8,
   MGM_EX_L_VALS = 9, MGM_EX_BORDER = 10, MGM_EX_NCOLOURS = 11, MGM_EX_PATCH = 12,
-  MGM_EX_OMEGA = 13
+  MGM_EX_OMEGA = 13, MGM_EX_GRAD_STENCILS = 14, MGM_EX_GRAD_WEIGHTS = 15
 };
 mgm_status mgm_export(mgm_handle h, int32_t what, int32_t level, void *h_buf,
                       int64_t *len);

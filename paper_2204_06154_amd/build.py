@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libmgm.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SOURCES = ["knn.cpp", "weights.cpp", "wse.cpp", "hierarchy.cpp"]
-HIP_SOURCES = ["device.hip", "phs_batched.hip", "learned.hip", "setup_device.hip"]
+HIP_SOURCES = ["device.hip", "phs_batched.hip", "learned.hip", "setup_device.hip", "surface_ops.hip"]
 EXACT_HIP_SOURCES = {"setup_device.hip"}
 
 

@@ -152,6 +152,12 @@ struct mgm_ctx {
   double *ls_c = nullptr, *ls_loss = nullptr, *ls_scal = nullptr;
   float* ls_atb = nullptr;
   int ls_steps_cap = 0;
+  // surface gradient / divergence operator (heat-method geodesics)
+  int sg_ns = 0;
+  std::vector<int32_t> sg_sten;      // N_1 x ns stencils (caller order)
+  std::vector<double> sg_w;          // N_1 x ns x 3 weights W_ij
+  int32_t* sg_col = nullptr;         // ns x N_1, entry-major
+  double* sg_wd = nullptr;           // 3 planes of ns x N_1, entry-major
 };
 
 namespace mgm {

@@ -1463,6 +1463,8 @@ mgm_status mgm_export(mgm_handle h, int32_t what, int32_t level, void* h_buf, in
       case MGM_EX_L_VALS: need_level(p - 1); vd = H.lv[level].L.val; isint = false; break;
       case MGM_EX_BORDER: need_level(p - 1); vd = H.lv[level].b; isint = false; break;
       case MGM_EX_PATCH: need_level(p - 2); vi = H.lv[level].patch; break;
+      case MGM_EX_GRAD_STENCILS: vi = h->sg_sten; break;
+      case MGM_EX_GRAD_WEIGHTS: vd = h->sg_w; isint = false; break;
       case MGM_EX_OMEGA: {
         if (!h->ls_om64) throw Error(MGM_E_ARG, "learned smoother not trained");
         const int n = h->lv[0].n, s = h->ls_s;

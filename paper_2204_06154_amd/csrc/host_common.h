@@ -85,6 +85,11 @@ void knn_search(const double* queries, int64_t nq, const double* data, int64_t n
 void stencil_weights_host(const double* xyz, const double* nrm, int64_t n, const int32_t* sten,
                           int ns, const mgm_params& p, std::vector<double>& w);
 
+// Tangent-plane RBF-FD surface gradient weights, n x ns x 3 (W_ij, a vector
+// per entry): grad u(x_i) = sum_j W_ij u_j, div v(x_i) = sum_j W_ij . v_j.
+void surface_gradient_weights_host(const double* xyz, const double* nrm, int64_t n, const int32_t* sten, int ns,
+                                   int phs_order, int deg, std::vector<double>& W);
+
 // Tangent-plane coordinates (ns x 2) of the stencil st of node i (Sec. 2.1).
 void project_stencil(const double* xyz, const double* nrm, int64_t i, const int32_t* st, int ns, double* xh);
 

@@ -243,4 +243,61 @@ void stencil_weights_host(const double* xyz, const double* nrm, int64_t n, const
   }
 }
 
+// Tangent-plane RBF-FD surface gradient (Sec. 6.3 applies it in the heat
+// method; the construction is that of Sec. 2.2 with first derivatives): the
+// PHS r^m + degree-deg saddle system of the stencil, solved for the
+// right-hand sides d/dxh and d/dyh of the basis at the centre
+// (d/dx |x - x_j|^m at 0 = -m |x_j|^(m-2) x_j, and 1 for the monomial x),
+// then W_ij = (g1_ij t1_i + g2_ij t2_i) / s_i, three doubles per entry.
+void surface_gradient_weights_host(const double* xyz, const double* nrm, int64_t n, const int32_t* sten, int ns,
+                                   int phs_order, int deg, std::vector<double>& W) {
+  if (phs_order < 1) throw Error(MGM_E_ARG, "gradient weights need phs_order >= 1");
+  std::vector<int> ea, eb;
+  monomials(deg, ea, eb);
+  const int L = int(ea.size());
+  if (ns < L) throw Error(MGM_E_ARG, "gradient stencil smaller than the polynomial space");
+  const int m = 2 * phs_order + 1;
+  const int sz = ns + L;
+  W.assign(size_t(n) * ns * 3, 0.0);
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    std::vector<double> xh(2 * ns), M(size_t(sz) * sz), r1(sz), r2(sz);
+    std::vector<int> piv(sz);
+    for (int64_t i = b; i < e; ++i) {
+      const int32_t* st = sten + i * ns;
+      project_stencil(xyz, nrm, i, st, ns, xh.data());
+      double s = 0.0;
+      for (int j = 0; j < ns; ++j) s = std::max(s, std::sqrt(xh[2 * j] * xh[2 * j] + xh[2 * j + 1] * xh[2 * j + 1]));
+      for (int j = 0; j < 2 * ns; ++j) xh[j] /= s;
+      std::fill(M.begin(), M.end(), 0.0);
+      for (int j = 0; j < ns; ++j) {
+        for (int k = 0; k < ns; ++k) {
+          double dx = xh[2 * j] - xh[2 * k], dy = xh[2 * j + 1] - xh[2 * k + 1];
+          M[size_t(j) * sz + k] = ipow(std::sqrt(dx * dx + dy * dy), m);
+        }
+        for (int q = 0; q < L; ++q) {
+          double v = ipow(xh[2 * j], ea[q]) * ipow(xh[2 * j + 1], eb[q]);
+          M[size_t(j) * sz + ns + q] = v;
+          M[size_t(ns + q) * sz + j] = v;
+        }
+        double r = std::sqrt(xh[2 * j] * xh[2 * j] + xh[2 * j + 1] * xh[2 * j + 1]);
+        double c = -double(m) * ipow(r, m - 2);
+        r1[j] = c * xh[2 * j];
+        r2[j] = c * xh[2 * j + 1];
+      }
+      for (int q = 0; q < L; ++q) {
+        r1[ns + q] = (ea[q] == 1 && eb[q] == 0) ? 1.0 : 0.0;
+        r2[ns + q] = (ea[q] == 0 && eb[q] == 1) ? 1.0 : 0.0;
+      }
+      if (!lu_factor(M.data(), sz, piv.data()))
+        throw Error(MGM_E_STENCIL_SINGULAR, "gradient stencil system singular at node " + std::to_string(i));
+      lu_solve(M.data(), sz, piv.data(), r1.data());
+      lu_solve(M.data(), sz, piv.data(), r2.data());
+      double t1[3], t2[3];
+      tangent_basis(nrm + 3 * i, t1, t2);
+      for (int j = 0; j < ns; ++j)
+        for (int a = 0; a < 3; ++a) W[(size_t(i) * ns + j) * 3 + a] = (r1[j] * t1[a] + r2[j] * t2[a]) / s;
+    }
+  });
+}
+
 }  // namespace mgm

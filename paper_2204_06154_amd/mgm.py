@@ -22,8 +22,9 @@ GS_FWD, GS_BWD = 0, 1
 FGMRES, BICGSTAB, STATIONARY = 0, 1, 2
 OP_SMOOTH, OP_SPMV, OP_RESTRICT_RESIDUAL, OP_INTERP_ADD = 0, 1, 2, 3
 EX = dict(level_sizes=0, stencils=1, weights=2, coarse_idx=3, interp_idx=4, interp_w=5, colours=6,
-          l_rowptr=7, l_cols=8, l_vals=9, border=10, ncolours=11, patch=12, omega=13)
-EX_FLOAT = {"weights", "interp_w", "l_vals", "border", "omega"}
+          l_rowptr=7, l_cols=8, l_vals=9, border=10, ncolours=11, patch=12, omega=13, grad_stencils=14,
+          grad_weights=15)
+EX_FLOAT = {"weights", "interp_w", "l_vals", "border", "omega", "grad_weights"}
 
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16}
 KRYLOV = {"fgmres": FGMRES, "bicgstab": BICGSTAB, "stationary": STATIONARY}
@@ -71,7 +72,8 @@ _lib = None
 EXPORTED = ["mgm_default_params", "mgm_setup", "mgm_set_precision", "mgm_vcycle", "mgm_apply", "mgm_solve",
             "mgm_level_op", "mgm_time_kernel", "mgm_stencils", "mgm_batched_weights", "mgm_train_smoother",
             "mgm_smoother_params", "mgm_smoother_grad", "mgm_set_smoother", "mgm_export", "mgm_destroy",
-            "mgm_status_str", "mgm_last_error"]
+            "mgm_status_str", "mgm_last_error", "mgm_surface_ops_setup", "mgm_surface_gradient",
+            "mgm_surface_divergence"]
 TK = dict(spmv=0, gs=1, residual=2, vcycle=3)
 
 
@@ -112,6 +114,12 @@ def load():
     lib.mgm_smoother_grad.restype = i32
     lib.mgm_set_smoother.argtypes = [vp, i32]
     lib.mgm_set_smoother.restype = i32
+    lib.mgm_surface_ops_setup.argtypes = [vp, i32, i32, i32, vp]
+    lib.mgm_surface_ops_setup.restype = i32
+    lib.mgm_surface_gradient.argtypes = [vp, vp, vp, i32, vp]
+    lib.mgm_surface_gradient.restype = i32
+    lib.mgm_surface_divergence.argtypes = [vp, vp, vp, vp]
+    lib.mgm_surface_divergence.restype = i32
     lib.mgm_export.argtypes = [vp, i32, i32, vp, ctypes.POINTER(i64)]
     lib.mgm_export.restype = i32
     lib.mgm_destroy.argtypes = [vp]
@@ -149,6 +157,14 @@ def make_params(d: dict) -> Params:
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, shape):
+    """FP64, contiguous, on a GPU, of the given shape (the surface operators'
+    arguments; the library reads raw pointers)."""
+    if t.dtype.itemsize != 8 or not t.is_floating_point() or not t.is_contiguous() or not t.is_cuda \
+            or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected a contiguous float64 GPU tensor of shape {shape}")
 
 
 def _stream(stream):
@@ -277,6 +293,33 @@ class Mgm:
 
     def set_smoother(self, learned: bool):
         _check(self.lib.mgm_set_smoother(self.h, 1 if learned else 0))
+
+    def surface_ops_setup(self, phs_order: int, poly_degree: int, stencil_size: int, stream=None):
+        """Surface gradient / divergence operator on the fine point cloud."""
+        st = ctypes.c_void_p(0) if self.device < 0 else _stream(stream)
+        _check(self.lib.mgm_surface_ops_setup(self.h, phs_order, poly_degree, stencil_size, st))
+
+    def surface_gradient(self, u, g=None, normalise=False, stream=None):
+        """grad_M u (N x 3); normalise: -grad u / |grad u|."""
+        import torch
+        n = self.n
+        _need(u, (n,))
+        if g is None:
+            g = torch.empty((n, 3), dtype=torch.float64, device=u.device)
+        _need(g, (n, 3))
+        _check(self.lib.mgm_surface_gradient(self.h, _ptr(u), _ptr(g), 1 if normalise else 0, _stream(stream)))
+        return g
+
+    def surface_divergence(self, v, out=None, stream=None):
+        """div_M v for a field v given as N x 3."""
+        import torch
+        n = self.n
+        _need(v, (n, 3))
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=v.device)
+        _need(out, (n,))
+        _check(self.lib.mgm_surface_divergence(self.h, _ptr(v), _ptr(out), _stream(stream)))
+        return out
 
     def export(self, what: str, level: int = 0) -> np.ndarray:
         n = ctypes.c_int64(0)

@@ -344,6 +344,21 @@ def harmonics_workload(n: int = 436_605, jitter: float = 0.1, lmax: int = 8, con
     return Workload(f"harmonics{n}", x, x.copy(), f, params)
 
 
+def geodesic_workload(n: int = 872_773, jitter: float = 0.1, config_id: int = 8) -> Workload:
+    """Heat-method geodesics on the unit sphere (exact distance arccos(x . x*)):
+    jittered Fibonacci points, LBO by RBF-FD with l = 3, k = 3, n = 20 (the
+    parameter table), surface gradient by RBF-FD with l = 2, k = 2, n = 12;
+    heat steps dt = 0.01 (3 steps), source node 0. `params` is the Poisson
+    problem; the heat handle uses the screened form with mu = dt. `f` is None."""
+    rp, _, _ = rng_streams(config_id)
+    x = jittered_fibonacci_sphere(n, rp, jitter)
+    params = dict(disc="rbffd", phs_order=3, poly_degree=3, stencil_size=20, problem="poisson", mu=0.0,
+                  n_min=250, n_coarse_max=0)
+    wl = Workload(f"geodesic{n}", x, x.copy(), None, params)
+    wl.heat = dict(dt=0.01, steps=3, source=0, grad_phs_order=2, grad_degree=2, grad_stencil=12)
+    return wl
+
+
 def torus_workload(n: int = 160_000, config_id: int = 2) -> Workload:
     """Torus, Poisson-disk points, Poisson (bordered) with zero-mean trig f (RBF-FD r^5 + deg 3, k=50)."""
     rp, rf, _ = rng_streams(config_id)

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import hierarchy
+from oracle import hierarchy, knn
 from paper_2204_06154_amd import mgm
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -147,3 +147,24 @@ def test_library_stencils_bit_exact():
     x = synth.torus_workload(5000).xyz
     for k in (2, 3, 25, 50):
         assert np.array_equal(mgm.stencils(x, k), knn.stencils(x, k)), k
+
+
+def test_surface_gradient_weights_match_oracle():
+    """Library surface-gradient operator (host-only handle) against the
+    oracle's: stencils bit for bit, weights to the rounding of two LU solves."""
+    from oracle import geodesic
+    wl = synth.geodesic_workload(3000)
+    m = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, device_weights=0), device=-1)
+    try:
+        with pytest.raises(mgm.MgmError):
+            m.surface_ops_setup(0, 2, 12)          # needs r^3 or smoother
+        m.surface_ops_setup(2, 2, 12)
+        n = len(wl.xyz)
+        sten = m.export("grad_stencils").reshape(n, 12)
+        assert np.array_equal(sten, knn.stencils(wl.xyz, 12))
+        W = m.export("grad_weights").reshape(n, 12, 3)
+        ref = geodesic.surface_gradient_operator(wl.xyz, wl.normals, sten, 2, 2)
+        scale = np.abs(ref).max(axis=(1, 2), keepdims=True)
+        assert np.max(np.abs(W - ref) / scale) < 1e-10
+    finally:
+        m.close()
