@@ -27,6 +27,15 @@ g_{q-1} = g_q - L^T D^-1 (omega_q * g_q). Adam (Kingma & Ba 2015).
 
 Random numbers: the power-iteration start and the weight initialisation use
 SplitMix64 as a counter-based generator, u(k) = (splitmix64(k) >> 11) 2^-53.
+
+Per-level smoothing (also our reading): a coarse level j gets a smoother of
+the same form with its own MLP, lam_j and step weights. Coarse points are
+fine points, so they carry normals; the features of coarse node i are its n
+nearest level-j points (n capped at N_j; centre first) in the tangent plane,
+scaled by the stencil radius, and the entries of the Galerkin operator L_j
+at those points over |L_j(i,i)| (0 where L_j has no entry). Level j trains on
+level-j errors right after the coarse-grid correction of MGM iterations of
+the sub-hierarchy that starts at level j, on L_j e = 0.
 """
 from __future__ import annotations
 
@@ -191,24 +200,48 @@ def train(params, X, L, snaps, wcheb, steps, lr=1e-3):
     return params, hist
 
 
-def snapshots(H, starts: np.ndarray, iters: int) -> np.ndarray:
-    """Fine-level error snapshots for training (homogeneous problem L e = 0).
+def snapshots(H, starts: np.ndarray, iters: int, level: int = 0) -> np.ndarray:
+    """Error snapshots of level `level` for training (homogeneous L_j e = 0).
 
-    From each start e (rows of `starts`), `iters` MGM iterations
-    e <- e + M(-L e) with the Gauss-Seidel V-cycle; each iteration contributes
-    e + (fine-level vector right after the coarse correction)."""
+    From each start e (rows of `starts`, level-j vectors), `iters` MGM
+    iterations e <- e + M_j(-L_j e) with the Gauss-Seidel cycle of the
+    sub-hierarchy from level j; each iteration contributes e + (level-j vector
+    right after the coarse correction)."""
     from .vcycle import Fp64Ops, vcycle
     ops = Fp64Ops(H)
-    L = H.levels[0].L
+    L = H.levels[level].L
     out = []
     for e0 in starts:
         e = np.array(e0, dtype=np.float64)
         for _ in range(iters):
             cap = []
-            z = vcycle(ops, -(L @ e), None, capture=cap)
+            z = vcycle(ops, -(L @ e), None, capture=cap, level=level)
             out.append(e + cap[0])
             e = e + z
     return np.array(out)
+
+
+def level_fine_index(H, j: int) -> np.ndarray:
+    """Fine-level index of every level-j point (the coarse sets are nested)."""
+    idx = np.arange(H.levels[0].N)
+    for k in range(j):
+        idx = idx[H.levels[k].coarse_idx]
+    return idx
+
+
+def level_features(H, j: int) -> np.ndarray:
+    """Features of level j (j = 0: `stencil_features`)."""
+    if j == 0:
+        return stencil_features(H)
+    from .discretize import project_stencils
+    from .knn import stencils
+    lv = H.levels[j]
+    n = min(H.stencils.shape[1], lv.N)
+    sten = stencils(lv.xyz, n)
+    nrm = H.normals[level_fine_index(H, j)]
+    xh = project_stencils(lv.xyz, nrm, sten)
+    vals = np.asarray(lv.L[np.repeat(np.arange(lv.N), n), sten.ravel()]).reshape(lv.N, n)
+    return features(xh, vals)
 
 
 def stencil_features(H) -> np.ndarray:

@@ -55,8 +55,8 @@ class Fp32Ops(Fp64Ops):
     def gs_correction(self, j, rows, resid):
         return resid * self.dinv[j][rows]
 
-    def dinv_learned(self):
-        return self.dinv[0]
+    def dinv_learned(self, j=0):
+        return self.dinv[j]
 
     def P(self, j, e):
         return self.P32[j] @ e

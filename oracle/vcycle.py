@@ -60,8 +60,8 @@ class Fp64Ops:
 
     learned = None
 
-    def dinv_learned(self):
-        return 1.0 / self.diag[0]
+    def dinv_learned(self, j=0):
+        return 1.0 / self.diag[j]
 
     def P(self, j, e):
         return self.H.levels[j].P @ e
@@ -94,16 +94,31 @@ def gs_sweep(ops, j, u, f, lam=0.0, reverse=False):
     return u
 
 
-def learned_sweep(ops, u, f):
-    """Fine-level learned smoother: for q = 1..s, u <- u + omega_q D^-1 (f - L u)."""
-    omega = ops.learned
+def learned_weights(ops, j):
+    """Step weights of the learned smoother on level j, or None for Gauss-Seidel.
+    `ops.learned` is either an N_1 x s array (the fine level) or a dict
+    {level: N_j x s array}."""
+    lw = getattr(ops, "learned", None)
+    if lw is None:
+        return None
+    if isinstance(lw, dict):
+        return lw.get(j)
+    return lw if j == 0 else None
+
+
+def learned_sweep(ops, u, f, j=0):
+    """Learned smoother on level j: for q = 1..s, u <- u + omega_q D^-1 (f - L u)."""
+    omega = learned_weights(ops, j)
     for q in range(omega.shape[1]):
-        u += (omega[:, q] * ops.dinv_learned()) * (f - ops.L(0, u))
+        u += (omega[:, q] * ops.dinv_learned(j)) * (f - ops.L(j, u))
     return u
 
 
-def vcycle(ops, r, rho=None, nu1=1, nu2=1, post_reverse=False, capture=None, pre_reverse=False, cycle="V"):
+def vcycle(ops, r, rho=None, nu1=1, nu2=1, post_reverse=False, capture=None, pre_reverse=False, cycle="V", level=0):
     """z = M r (Alg. 3 with zero initial guess). Bordered: returns (z, lambda).
+
+    level > 0 runs the cycle of the sub-hierarchy that starts at that level
+    (r and z then live on level `level`); `capture` then records that level.
 
     cycle = "V" (Alg. 3), "W" or "F" (the options Sec. 4.5 names): the
     coarse problem of level j is solved by one cycle of level j+1 (V), two W
@@ -112,10 +127,11 @@ def vcycle(ops, r, rho=None, nu1=1, nu2=1, post_reverse=False, capture=None, pre
     multiplier, restricts the residual f - L e - b mu and the constraint
     residual rho - b . e, and adds the coarse correction to both e and mu.
 
-    With `ops.learned` set (an N_1 x s array of step weights) the fine level
-    is smoothed by `learned_sweep` instead of Gauss-Seidel. `capture`, if a
-    list, receives a copy of the fine-level vector right after the coarse-grid
-    correction (before post-smoothing)."""
+    With `ops.learned` set (an N_1 x s array of step weights, or a dict of
+    such arrays by level) those levels are smoothed by `learned_sweep` instead
+    of Gauss-Seidel. `capture`, if a list, receives a copy of the start
+    level's vector right after the coarse-grid correction (before
+    post-smoothing)."""
     p = ops.nlevels()
     dt = ops.dtype
     bordered = rho is not None
@@ -129,9 +145,10 @@ def vcycle(ops, r, rho=None, nu1=1, nu2=1, post_reverse=False, capture=None, pre
             ec, muc = ops.coarse_solve(f, rho_j)
             return np.asarray(ec, dtype=dt), muc
         lam = mu if (bordered and not zero_start) else 0.0
+        lw = learned_weights(ops, j)
         for _ in range(nu1):
-            if j == 0 and getattr(ops, "learned", None) is not None:
-                learned_sweep(ops, e, f)
+            if lw is not None:
+                learned_sweep(ops, e, f, j)
             else:
                 gs_sweep(ops, j, e, f, lam, reverse=pre_reverse)
         res = f - ops.L(j, e)
@@ -144,16 +161,18 @@ def vcycle(ops, r, rho=None, nu1=1, nu2=1, post_reverse=False, capture=None, pre
             ec, muc = visit(j + 1, fc, rhoc, ec, muc, second[kind], False)
         e += ops.P(j, ec)
         mu = (0.0 if zero_start else mu) + (muc if bordered else 0.0)
-        if j == 0 and capture is not None:
+        if j == level and capture is not None:
             capture.append(np.array(e, dtype=np.float64))
         for _ in range(nu2):
-            if j == 0 and getattr(ops, "learned", None) is not None:
-                learned_sweep(ops, e, f)
+            if lw is not None:
+                learned_sweep(ops, e, f, j)
             else:
                 gs_sweep(ops, j, e, f, mu if bordered else 0.0, reverse=post_reverse)
         return e, mu
 
-    e0, mu0 = visit(0, np.asarray(r, dtype=dt), rho, np.zeros(ops.size(0), dtype=dt), 0.0, cycle, True)
+    if not 0 <= level < p - 1:
+        raise ValueError("start level must be a smoothed level")
+    e0, mu0 = visit(level, np.asarray(r, dtype=dt), rho, np.zeros(ops.size(level), dtype=dt), 0.0, cycle, True)
     if bordered:
         return e0, mu0
     return e0

@@ -125,3 +125,47 @@ def test_training_reduces_the_loss(small):
     params = learned.init_params(X.shape[1], 3, seed=8)
     _, hist = learned.train(params, X, L, S, w, 30, lr=1e-3)
     assert hist[-1] < hist[0]
+
+
+def test_coarse_level_features_by_definition(small):
+    """Level-1 features: the n nearest level-1 points (brute force), their
+    tangent-plane offsets over the stencil radius, and L_1 entries over the
+    diagonal (0 off the pattern)."""
+    from oracle import discretize
+    H = small[0]
+    X1 = learned.level_features(H, 1)
+    lv = H.levels[1]
+    n = min(H.stencils.shape[1], lv.N)
+    assert X1.shape == (lv.N, 3 * n)
+    fidx = learned.level_fine_index(H, 1)
+    assert np.array_equal(H.levels[0].xyz[fidx], lv.xyz)
+    L1 = lv.L.toarray()
+    t1, t2 = discretize.tangent_frames(H.normals[fidx])
+    for i in (0, 7, lv.N - 1):
+        d = lv.xyz - lv.xyz[i]
+        d2 = ((d[:, 0] * d[:, 0]) + (d[:, 1] * d[:, 1])) + d[:, 2] * d[:, 2]
+        sten = np.lexsort((np.arange(lv.N), d2))[:n]
+        xh = np.stack([d[sten] @ t1[i], d[sten] @ t2[i]], axis=1)
+        rho = np.sqrt((xh ** 2).sum(axis=1)).max()
+        assert np.allclose(X1[i, :2 * n], (xh / rho).ravel(), atol=1e-12)
+        assert np.allclose(X1[i, 2 * n:], L1[i, sten] / abs(L1[i, i]), atol=1e-12)
+    assert np.allclose(learned.level_features(H, 0), learned.stencil_features(H))
+
+
+def test_coarse_level_snapshots_follow_sub_cycle(small):
+    """Level-1 snapshots: e + (level-1 vector right after the coarse
+    correction) of the level-1 sub-cycle; for a two-level sub-hierarchy (level
+    2 coarsest) that vector is e_pre + P_1 L_2^-1 R_1 (f - L_1 e_pre), with
+    e_pre the pre-smoothed iterate."""
+    H = small[0]
+    if len(H.levels) != 3:
+        pytest.skip("needs exactly three levels")
+    lv, cl = H.levels[1], H.levels[2]
+    rng = np.random.default_rng(5)
+    e0 = rng.standard_normal(lv.N)
+    snap = learned.snapshots(H, e0[None, :], 1, level=1)[0]
+    f = -(lv.L @ e0)
+    ops = vcycle.Fp64Ops(H)
+    u = vcycle.gs_sweep(ops, 1, np.zeros(lv.N), f)
+    cap = u + lv.P @ np.linalg.solve(cl.L.toarray(), lv.R @ (f - lv.L @ u))
+    assert np.allclose(snap, e0 + cap, rtol=0, atol=1e-10 * np.abs(e0 + cap).max())

@@ -175,7 +175,7 @@ def test_bordered_two_level_matches_dense_definition():
     assert np.allclose(LH[:nc, nc], cl.b) and np.allclose(LH[nc, :nc], cl.b)
 
 
-def _dense_cycle(H, j, kind, nu1=1, nu2=1):
+def _dense_cycle(H, j, kind, nu1=1, nu2=1, smoothers=None):
     """Dense approximate inverse of the level-j cycle of the given kind, from
     the definitions: M_j = (I - E_j) A_j^-1, E_j = S^nu2 (I - P Q P^T A_j) S^nu1,
     Q the coarse approximate inverse: M_V of level j+1 (V); two W cycles as a
@@ -207,9 +207,11 @@ def _dense_cycle(H, j, kind, nu1=1, nu2=1):
     B[np.ix_(p, p)] = np.tril(L[np.ix_(p, p)])
     S = np.eye(m)
     S[:n, :] = I[:n, :] - np.linalg.solve(B, A)[:n, :]
+    if smoothers is not None and j in smoothers:
+        S = smoothers[j]
     Ac = P.T @ A @ P
     if kind == "V":
-        Q = _dense_cycle(H, j + 1, "V", nu1, nu2)
+        Q = _dense_cycle(H, j + 1, "V", nu1, nu2, smoothers)
     elif kind == "W":
         Mw = _dense_cycle(H, j + 1, "W", nu1, nu2)
         Q = Mw + Mw @ (np.eye(Ac.shape[0]) - Ac @ Mw)
@@ -244,6 +246,45 @@ def test_three_level_cycles_match_dense_definition(kind, problem):
         z = np.concatenate([zz, [lam]])
     ref = Md @ r
     assert np.max(np.abs(z - ref)) <= 1e-9 * np.max(np.abs(ref))
+
+
+def test_per_level_learned_smoothing_and_sub_cycles_match_dense_definition():
+    """Learned (Richardson) smoothing on every smoothed level: the cycle equals
+    the dense definition with S_j = prod_q (I - diag(omega_q) D_j^-1 L_j) on
+    those levels; a cycle started at level 1 equals that level's dense cycle."""
+    wl = synth.sphere_workload(1800)
+    wl.params["n_coarse_max"] = 120
+    H = hierarchy.build(wl.xyz, wl.normals, wl.params)
+    assert len(H.levels) == 3
+    rng = np.random.default_rng(12)
+    om = {j: 0.3 + 0.5 * rng.random((H.levels[j].N, 3)) for j in (0, 1)}
+    S = {}
+    for j in (0, 1):
+        L = H.levels[j].L.toarray()
+        Dinv = np.diag(1.0 / np.diag(L))
+        Sj = np.eye(len(L))
+        for q in range(3):
+            Sj = (np.eye(len(L)) - np.diag(om[j][:, q]) @ Dinv @ L) @ Sj
+        S[j] = Sj
+    ops = vcycle.Fp64Ops(H)
+    ops.learned = om
+    r = rng.standard_normal(H.levels[0].N)
+    ref = _dense_cycle(H, 0, "V", smoothers=S) @ r
+    z = vcycle.vcycle(ops, r, None)
+    assert np.max(np.abs(z - ref)) <= 1e-9 * np.max(np.abs(ref))
+    # only level 1 learned
+    ops.learned = {1: om[1]}
+    ref = _dense_cycle(H, 0, "V", smoothers={1: S[1]}) @ r
+    assert np.max(np.abs(vcycle.vcycle(ops, r, None) - ref)) <= 1e-9 * np.max(np.abs(ref))
+    # the sub-hierarchy cycle from level 1 (Gauss-Seidel and learned)
+    r1 = rng.standard_normal(H.levels[1].N)
+    for learned_ops, sm in ((None, None), ({1: om[1]}, {1: S[1]})):
+        ops.learned = learned_ops
+        ref = _dense_cycle(H, 1, "V", smoothers=sm) @ r1
+        z1 = vcycle.vcycle(ops, r1, None, level=1)
+        assert np.max(np.abs(z1 - ref)) <= 1e-9 * np.max(np.abs(ref))
+    with pytest.raises(ValueError):
+        vcycle.vcycle(ops, np.zeros(H.levels[2].N), None, level=2)
 
 
 def test_vcycle_is_linear(sphere_h, torus_h):
