@@ -176,8 +176,8 @@ mgm_status mgm_level_op(mgm_handle h, int32_t op, int32_t level, double *d_x,
                         const double *d_b, double *d_y, double scalar,
                         int32_t reverse, void *stream);
 
-/* Learned per-node Chebyshev smoother for the fine level (an extension; the
- * paper smooths with Gauss-Seidel, Sec. 4.3). Screened problems only.
+/* Learned per-node Chebyshev smoother, one per smoothed level (an extension;
+ * the paper smooths with Gauss-Seidel, Sec. 4.3). Screened problems only.
  * Smoother: s Richardson steps e <- e + omega_{q,i} D^-1 (f - L e), with
  * omega_{q,i} = omega_q (1 + 0.5 tanh(o_{q,i})), omega_q = 1/theta_q the
  * reciprocal Chebyshev roots on [lam/4, 1.1 lam] (lam: 20-step power
@@ -186,7 +186,12 @@ mgm_status mgm_level_op(mgm_handle h, int32_t op, int32_t level, double *d_x,
  * (Sec. 2.1) over the stencil radius and its weights (Sec. 2.2-2.3) over
  * |c_ii|. Training snapshots: fine-level errors right after the coarse-grid
  * correction of MGM iterations (Gauss-Seidel V-cycle, FP64) on L e = 0;
- * loss mean_t |L S e_t|^2 / |L e_t|^2; adjoint-smoother backward; Adam. */
+ * loss mean_t |L S e_t|^2 / |L e_t|^2; adjoint-smoother backward; Adam.
+ * A coarse level j has its own smoother of the same form: its features use the
+ * level's own n nearest points (tangent-plane offsets with the points'
+ * normals) and the Galerkin operator's entries L_j(i, k) / |L_j(i, i)| at those
+ * points (0 off the pattern); its snapshots come from the cycle of the
+ * sub-hierarchy that starts at level j, on L_j e = 0. */
 typedef struct {
   int32_t  steps;           /* Adam steps (0: prepare snapshots/estimate only) */
   double   lr;              /* Adam learning rate, e.g. 1e-3 */
@@ -198,6 +203,8 @@ typedef struct {
   int32_t  activate;        /* 0: keep GS; 1: use the learned smoother when its
                                stationary convergence factor beats GS (measured
                                over 6 iterations from the first start); 2: always */
+  int32_t  level;           /* level whose smoother is trained (0 = fine; must
+                               be a smoothed level, not the coarsest) */
 } mgm_train_opts;
 
 typedef struct {
@@ -208,7 +215,9 @@ typedef struct {
 } mgm_train_info;
 
 /* Prepare and/or train the learned smoother.
- *   d_starts: device FP64, n_starts x n random start errors (caller order);
+ *   d_starts: device FP64, n_starts x N_j random start errors of the chosen
+ *   level (caller order on level 0; on a coarse level, the order of its points,
+ *   i.e. of MGM_EX_COARSE_IDX of the level above);
  *   h_loss_hist: nullable host array of steps+1 losses (entry k: before the
  *   (k+1)-th Adam step; the last: after training).
  * Errors: MGM_E_ARG (Poisson problem, bad options, layer too wide: stencil
@@ -216,18 +225,21 @@ typedef struct {
 mgm_status mgm_train_smoother(mgm_handle h, const mgm_train_opts *opts, const double *d_starts,
                               mgm_train_info *info, double *h_loss_hist, void *stream);
 
-/* Get (set = 0) or set (set = 1) the MLP parameters, FP32 row-major with each
+/* Get (set = 0) or set (set = 1) the MLP parameters of the smoother of
+ * `level`, FP32 row-major with each
  * layer's bias as its last row: W1 (3n+1) x 64 | W2 65 x 64 | W3 65 x s.
  * h_params = NULL queries *len. Setting resets the Adam state and recomputes
  * the step weights. */
-mgm_status mgm_smoother_params(mgm_handle h, int32_t set, float *h_params, int64_t *len);
+mgm_status mgm_smoother_params(mgm_handle h, int32_t level, int32_t set, float *h_params, int64_t *len);
 
 /* Loss and its gradient (same layout as the parameters, host FP32) at the
- * current parameters on the current snapshots, without an update. */
-mgm_status mgm_smoother_grad(mgm_handle h, float *h_grad, double *loss, void *stream);
+ * current parameters on the current snapshots of `level`, without an update. */
+mgm_status mgm_smoother_grad(mgm_handle h, int32_t level, float *h_grad, double *loss, void *stream);
 
-/* Select the fine-level smoother: 0 = Gauss-Seidel, 1 = learned (trained). */
-mgm_status mgm_set_smoother(mgm_handle h, int32_t learned);
+/* Select the smoothers: bit j of level_mask set = level j uses its learned
+ * smoother (which must be trained), clear = Gauss-Seidel. 0 = Gauss-Seidel
+ * everywhere, 1 = learned on the fine level only. */
+mgm_status mgm_set_smoother(mgm_handle h, int32_t level_mask);
 
 /* Profiling of one hot-path kernel: `reps` timed repetitions on the handle's
  * internal buffers (contents arbitrary), each bracketed by HIP events on
@@ -312,7 +324,8 @@ mgm_status mgm_surface_divergence(mgm_handle h, const double *d_v, double *d_out
  *   MGM_EX_NCOLOURS      I32  colours per smoothed level      (level ignored)
  *   MGM_EX_PATCH         I32  smoother patch of each row of level j (empty when
  *                             the level is not patch-blocked)
- *   MGM_EX_OMEGA         F64  N_1 x s learned step weights (caller order)
+ *   MGM_EX_OMEGA         F64  N_j x s learned step weights of level j (caller
+ *                             order)
  *   MGM_EX_GRAD_STENCILS I32  N_1 x n_g surface-operator stencils (after
  *                             mgm_surface_ops_setup)
  *   MGM_EX_GRAD_WEIGHTS  F64  N_1 x n_g x 3 surface-gradient weights W_ij */

@@ -111,6 +111,30 @@ struct DevLevel {
 
 }  // namespace mgm
 
+namespace mgm {
+
+// Learned smoother of one level: MLP parameters and Adam moments, features,
+// step weights, training snapshots and scratch.
+struct LearnedLevel {
+  bool active = false;
+  int s = 0, nin = 0, T = 0, adam_t = 0, steps_cap = 0;
+  double lam = 0.0;
+  std::vector<double> wcheb;
+  double* wcheb_d = nullptr;
+  float *params = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+  double* om64 = nullptr;
+  float* om32 = nullptr;
+  float *X = nullptr, *O = nullptr, *H1 = nullptr, *H2 = nullptr, *dO = nullptr, *dH1 = nullptr, *dH2 = nullptr,
+        *domega = nullptr, *omt = nullptr;
+  float *snap = nullptr, *z = nullptr, *e = nullptr, *y = nullptr, *g = nullptr, *t = nullptr;
+  int32_t *tptr = nullptr, *tcol = nullptr;
+  float* tval = nullptr;
+  double *c = nullptr, *loss = nullptr, *scal = nullptr;
+  float* atb = nullptr;
+};
+
+}  // namespace mgm
+
 struct mgm_ctx {
   int device = 0;
   mgm_params p{};
@@ -132,26 +156,12 @@ struct mgm_ctx {
   int64_t ld = 0;
   double *V = nullptr, *Z = nullptr, *vecs = nullptr, *kpart = nullptr, *dh = nullptr;
   double* hpin = nullptr;  // pinned host copies of dot results
-  double* capture = nullptr;         // when set: fine-level vector after the coarse correction (eager V-cycle)
-  // learned fine-level smoother
-  bool ls_active = false;
-  int ls_s = 0, ls_nin = 0, ls_T = 0, ls_adam_t = 0;
-  double ls_lam = 0.0;
-  std::vector<double> ls_wcheb;
-  double* ls_wcheb_d = nullptr;
-  float *ls_params = nullptr, *ls_m = nullptr, *ls_v = nullptr, *ls_grad = nullptr;
-  double* ls_om64 = nullptr;
-  float* ls_om32 = nullptr;
-  double* e_tmp64 = nullptr;
+  double* capture = nullptr;         // when set: the start level's vector after the coarse correction (eager cycle)
+  int capture_level = 0;
+  // learned smoothers, one state per smoothed level (see learned.hip)
+  std::vector<mgm::LearnedLevel> ls;
+  double* e_tmp64 = nullptr;         // ping-pong buffer of the Richardson steps (fine-level size)
   float* e_tmp32 = nullptr;
-  float *ls_X = nullptr, *ls_O = nullptr, *ls_H1 = nullptr, *ls_H2 = nullptr, *ls_dO = nullptr, *ls_dH1 = nullptr,
-        *ls_dH2 = nullptr, *ls_domega = nullptr, *ls_omt = nullptr;
-  float *ls_snap = nullptr, *ls_z = nullptr, *ls_e = nullptr, *ls_y = nullptr, *ls_g = nullptr, *ls_t = nullptr;
-  int32_t *ls_tptr = nullptr, *ls_tcol = nullptr;
-  float* ls_tval = nullptr;
-  double *ls_c = nullptr, *ls_loss = nullptr, *ls_scal = nullptr;
-  float* ls_atb = nullptr;
-  int ls_steps_cap = 0;
   // surface gradient / divergence operator (heat-method geodesics)
   int sg_ns = 0;
   std::vector<int32_t> sg_sten;      // N_1 x ns stencils (caller order)
@@ -180,6 +190,13 @@ void mdot(mgm_ctx* c, int64_t n, const double* V, int64_t ld, int k, const doubl
           double* host_out = nullptr);
 void host_wait(hipStream_t st);
 void to_host(mgm_ctx* c, const double* d, int k, hipStream_t st);
+// z = M_j v for FP64 vectors in level j's permuted order: the cycle of the
+// sub-hierarchy that starts at level j (j >= 1; screened problems), run
+// eagerly in the handle's precision.
+void precond_level(mgm_ctx* c, int j, const double* v, double* z, hipStream_t st);
+// y = L_j x, FP64, level j's permuted order (no border).
+void spmv_level64(mgm_ctx* c, int j, const double* x, double* y, hipStream_t st);
+inline bool learned_on(const mgm_ctx* c, int j) { return j < int(c->ls.size()) && c->ls[j].active; }
 void need_device(const mgm_ctx* c);
 mgm_status guard(const std::function<void()>& f);
 void invalidate_graphs(mgm_ctx* c);

@@ -502,13 +502,14 @@ static void interp_add(mgm_ctx* c, int j, hipStream_t st, bool accumulate = fals
 // Fine-level learned smoother: s Richardson steps with per-node step weights
 // (ping-pong between e and a scratch vector, the result left in e).
 template <typename V, typename S, bool SC>
-static void learned_sweep(mgm_ctx* c, hipStream_t st, bool zero_start = false) {
+static void learned_sweep(mgm_ctx* c, int j, hipStream_t st, bool zero_start = false) {
   using P = Prec<V, S, SC>;
-  DevLevel& d = c->lv[0];
+  DevLevel& d = c->lv[j];
+  const LearnedLevel& L = c->ls[j];
   S* e = P::e(d);
   S* tmp = reinterpret_cast<S*>(sizeof(S) == 8 ? static_cast<void*>(c->e_tmp64) : static_cast<void*>(c->e_tmp32));
-  const S* om = reinterpret_cast<const S*>(sizeof(S) == 8 ? static_cast<const void*>(c->ls_om64)
-                                                           : static_cast<const void*>(c->ls_om32));
+  const S* om = reinterpret_cast<const S*>(sizeof(S) == 8 ? static_cast<const void*>(L.om64)
+                                                           : static_cast<const void*>(L.om32));
   const unsigned g = nblk(int64_t(d.n) * d.G);
   auto step = [&](int q, const S* in, S* out) {
     if (d.patched)
@@ -527,7 +528,7 @@ static void learned_sweep(mgm_ctx* c, hipStream_t st, bool zero_start = false) {
     q = 1;
   }
   // the remaining steps ping-pong; with an odd count the result lands in tmp and is copied back
-  for (; q < c->ls_s; ++q) {
+  for (; q < L.s; ++q) {
     step(q, a, b);
     std::swap(a, b);
   }
@@ -554,12 +555,12 @@ static void cycle_enqueue(mgm_ctx* c, int j, int kind, bool zero_start, hipStrea
   }
   DevLevel& d = c->lv[j];
   const double* mu = c->mu + j;
-  const bool learned = j == 0 && c->ls_active;
+  const bool learned = learned_on(c, j);
   // e_j starts at zero: a patch-blocked first sweep assumes it without reading e_j
   const bool zg = zero_start && (d.patched || learned) && c->p.nu1 > 0;
   if (zero_start && !zg) hipLaunchKernelGGL((k_fill<S>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, P::e(d), S(0));
   for (int s = 0; s < c->p.nu1; ++s) {
-    if (learned) learned_sweep<V, S, SC>(c, st, zero_start && s == 0);
+    if (learned) learned_sweep<V, S, SC>(c, j, st, zero_start && s == 0);
     else gs_sweep<V, S, SC>(c, j, c->p.pre_smoother == MGM_GS_BWD, bord && !zero_start, mu, st, zg && s == 0);
   }
   residual_restrict<V, S, SC>(c, j, st, !zero_start);
@@ -567,11 +568,11 @@ static void cycle_enqueue(mgm_ctx* c, int j, int kind, bool zero_start, hipStrea
   cycle_enqueue<V, S, SC>(c, j + 1, first, true, st);
   if (kind != MGM_CYCLE_V) cycle_enqueue<V, S, SC>(c, j + 1, kind == MGM_CYCLE_W ? MGM_CYCLE_W : MGM_CYCLE_V, false, st);
   interp_add<V, S, SC>(c, j, st, !zero_start);
-  if (j == 0 && c->capture)
+  if (j == c->capture_level && c->capture)
     hipLaunchKernelGGL((k_gather<S, double>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, (const int32_t*)nullptr, P::e(d),
                        c->capture, (double*)nullptr);
   for (int s = 0; s < c->p.nu2; ++s) {
-    if (learned) learned_sweep<V, S, SC>(c, st);
+    if (learned) learned_sweep<V, S, SC>(c, j, st);
     else gs_sweep<V, S, SC>(c, j, c->p.post_smoother == MGM_GS_BWD, bord, mu, st);
   }
 }
@@ -674,6 +675,36 @@ void apply_A(mgm_ctx* c, const double* x, double* y, hipStream_t st) {
                        d.col, d.v64, nullptr, x, y, d.b64, x + d.n));
   }
   if (bord) mdot(c, d.n, d.b64, 0, 1, x, y + d.n, st);  // constraint row b . x
+}
+
+void spmv_level64(mgm_ctx* c, int j, const double* x, double* y, hipStream_t st) {
+  DevLevel& d = c->lv[j];
+  unsigned g = nblk(int64_t(d.n) * d.G);
+  DISPATCH_G(d.G, hipLaunchKernelGGL((k_spmv<double, double, GG, false, false>), dim3(g), dim3(kBlock), 0, st, d.n, d.W,
+                                     d.rowptr, d.col, d.v64, nullptr, x, y, nullptr, nullptr));
+}
+
+template <typename V, typename S, bool SC>
+static void precond_level_t(mgm_ctx* c, int j, const double* v, double* z, hipStream_t st) {
+  using P = Prec<V, S, SC>;
+  DevLevel& d = c->lv[j];
+  const unsigned g = nblk(d.n);
+  hipLaunchKernelGGL((k_gather<double, S>), dim3(g), dim3(kBlock), 0, st, d.n, (const int32_t*)nullptr, v, P::f(d),
+                     (double*)nullptr);
+  cycle_enqueue<V, S, SC>(c, j, MGM_CYCLE_V, true, st);
+  hipLaunchKernelGGL((k_scatter<S, double>), dim3(g), dim3(kBlock), 0, st, d.n, (const int32_t*)nullptr, P::e(d), z,
+                     (double*)nullptr);
+}
+
+void precond_level(mgm_ctx* c, int j, const double* v, double* z, hipStream_t st) {
+  if (j < 1 || j + 1 >= int(c->lv.size())) throw Error(MGM_E_ARG, "sub-cycle level out of range");
+  if (c->p.problem == MGM_POISSON) throw Error(MGM_E_ARG, "sub-cycles: screened problems only");
+  const int prec = c->p.precision;
+  build_precision(c, prec);
+  if (prec == MGM_FP64) precond_level_t<double, double, false>(c, j, v, z, st);
+  else if (prec == MGM_FP32) precond_level_t<float, float, false>(c, j, v, z, st);
+  else precond_level_t<_Float16, float, true>(c, j, v, z, st);
+  HIPCHECK(hipGetLastError());
 }
 
 // ------------------------------------------------------------------- solvers
@@ -1046,12 +1077,12 @@ static double visit_bytes(const mgm_ctx* c, int prec, int j, int kind, bool zero
   const bool bord = c->p.problem == MGM_POISSON;
   const double bt = prec == MGM_FP64 ? 8.0 : 4.0;  // transfer value bytes
   const DevLevel& d = c->lv[j];
-  const bool learned = j == 0 && c->ls_active;
+  const bool learned = learned_on(c, j);
   double tot = 0.0;
   if (zero_start && !((d.patched || learned) && c->p.nu1 > 0)) tot += bvec(prec) * d.n;  // zero fill
   if (learned) {
     const double step = double(d.nnz) * (bval(prec) + 4.0) + double(d.n) * (5.0 * bvec(prec));
-    int steps = (c->p.nu1 + c->p.nu2) * c->ls_s;
+    int steps = (c->p.nu1 + c->p.nu2) * c->ls[j].s;
     if (c->p.nu1 > 0 && zero_start) {  // the first step from zero reads omega, dinv, f and writes e
       --steps;
       tot += 4.0 * bvec(prec) * d.n;
@@ -1466,12 +1497,14 @@ mgm_status mgm_export(mgm_handle h, int32_t what, int32_t level, void* h_buf, in
       case MGM_EX_GRAD_STENCILS: vi = h->sg_sten; break;
       case MGM_EX_GRAD_WEIGHTS: vd = h->sg_w; isint = false; break;
       case MGM_EX_OMEGA: {
-        if (!h->ls_om64) throw Error(MGM_E_ARG, "learned smoother not trained");
-        const int n = h->lv[0].n, s = h->ls_s;
+        need_level(p - 2);
+        if (level >= int(h->ls.size()) || !h->ls[level].om64) throw Error(MGM_E_ARG, "learned smoother not trained");
+        const int n = h->lv[level].n, s = h->ls[level].s;
         std::vector<double> om(size_t(n) * s);
         std::vector<int32_t> perm(n);
-        HIPCHECK(hipMemcpy(om.data(), h->ls_om64, om.size() * sizeof(double), hipMemcpyDeviceToHost));
-        HIPCHECK(hipMemcpy(perm.data(), h->lv[0].perm, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(om.data(), h->ls[level].om64, om.size() * sizeof(double), hipMemcpyDeviceToHost));
+        if (h->lv[level].perm) HIPCHECK(hipMemcpy(perm.data(), h->lv[level].perm, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+        else std::iota(perm.begin(), perm.end(), 0);
         vd.assign(size_t(n) * s, 0.0);
         for (int q = 0; q < s; ++q)
           for (int pos = 0; pos < n; ++pos) vd[size_t(perm[pos]) * s + q] = om[size_t(q) * n + pos];

@@ -1,6 +1,7 @@
-// Learned per-node Chebyshev smoother on the fine level: features, spectral
-// estimate, training snapshots, training (MLP forward/backward, adjoint of the
-// smoother, Adam) and activation with Gauss-Seidel as the fallback.
+// Learned per-node Chebyshev smoother, one per smoothed level: features,
+// spectral estimate, training snapshots, training (MLP forward/backward,
+// adjoint of the smoother, Adam) and activation with Gauss-Seidel as the
+// fallback.
 //
 // The smoother (an extension; the paper smooths with Gauss-Seidel, Sec. 4.3):
 // s Richardson steps e <- e + omega_{q,i} D^-1 (f - L e) with
@@ -12,8 +13,14 @@
 // |c_ii|. Training snapshots: fine-level errors right after the coarse-grid
 // correction of MGM iterations on L e = 0 from caller-supplied random starts;
 // loss mean_t |L S e_t|^2 / |L e_t|^2.
+// A coarse level j has its own smoother of the same form: features from the
+// level's own n nearest points (the coarse points are fine points and keep
+// their normals) and the entries of the Galerkin operator L_j at those points
+// over |L_j(i,i)| (0 off its pattern); snapshots from the cycle of the
+// sub-hierarchy that starts at level j, on L_j e = 0.
 #include <algorithm>
 #include <cmath>
+#include <numeric>
 
 #include "ctx.h"
 #include "kernels_learned.h"
@@ -24,76 +31,116 @@ namespace {
 
 constexpr int kPowerSteps = 20;
 
-void ensure_learned_buffers(mgm_ctx* c, int s, int T) {
-  DevLevel& d = c->lv[0];
+void ensure_learned_buffers(mgm_ctx* c, int j, int s, int T) {
+  DevLevel& d = c->lv[j];
+  LearnedLevel& L = c->ls[j];
   const int n = d.n;
-  const int nin = c->ls_nin;
+  const int nin = L.nin;
   const int np = mlp_param_count(nin, s);
-  if (!c->ls_params || c->ls_s != s) {
-    c->ls_params = track(c, dalloc<float>(np));
-    c->ls_m = track(c, dalloc<float>(np));
-    c->ls_v = track(c, dalloc<float>(np));
-    c->ls_grad = track(c, dalloc<float>(np));
-    c->ls_om64 = track(c, dalloc<double>(size_t(s) * n));
-    c->ls_om32 = track(c, dalloc<float>(size_t(s) * n));
-    c->ls_O = track(c, dalloc<float>(size_t(n) * s));
-    c->ls_dO = track(c, dalloc<float>(size_t(n) * s));
-    c->ls_domega = track(c, dalloc<float>(size_t(n) * s));
-    c->ls_omt = track(c, dalloc<float>(size_t(n) * s));
-    c->ls_wcheb_d = track(c, dalloc<double>(s));
-    c->ls_s = s;
+  if (!L.params || L.s != s) {
+    L.params = track(c, dalloc<float>(np));
+    L.m = track(c, dalloc<float>(np));
+    L.v = track(c, dalloc<float>(np));
+    L.grad = track(c, dalloc<float>(np));
+    L.om64 = track(c, dalloc<double>(size_t(s) * n));
+    L.om32 = track(c, dalloc<float>(size_t(s) * n));
+    L.O = track(c, dalloc<float>(size_t(n) * s));
+    L.dO = track(c, dalloc<float>(size_t(n) * s));
+    L.domega = track(c, dalloc<float>(size_t(n) * s));
+    L.omt = track(c, dalloc<float>(size_t(n) * s));
+    L.wcheb_d = track(c, dalloc<double>(s));
+    L.s = s;
   }
-  if (!c->ls_H1) {
-    c->ls_H1 = track(c, dalloc<float>(size_t(n) * (kHid + 1)));
-    c->ls_H2 = track(c, dalloc<float>(size_t(n) * (kHid + 1)));
-    c->ls_dH1 = track(c, dalloc<float>(size_t(n) * kHid));
-    c->ls_dH2 = track(c, dalloc<float>(size_t(n) * kHid));
-    c->ls_e = track(c, dalloc<float>(size_t(2) * n));
-    c->ls_y = track(c, dalloc<float>(n));
-    c->ls_g = track(c, dalloc<float>(size_t(2) * n));
-    c->ls_t = track(c, dalloc<float>(n));
-    c->e_tmp64 = track(c, dalloc<double>(n + 1));
-    c->e_tmp32 = track(c, dalloc<float>(n + 1));
-    c->ls_scal = track(c, dalloc<double>(16));
+  if (!L.H1) {
+    L.H1 = track(c, dalloc<float>(size_t(n) * (kHid + 1)));
+    L.H2 = track(c, dalloc<float>(size_t(n) * (kHid + 1)));
+    L.dH1 = track(c, dalloc<float>(size_t(n) * kHid));
+    L.dH2 = track(c, dalloc<float>(size_t(n) * kHid));
+    L.e = track(c, dalloc<float>(size_t(2) * n));
+    L.y = track(c, dalloc<float>(n));
+    L.g = track(c, dalloc<float>(size_t(2) * n));
+    L.t = track(c, dalloc<float>(n));
+    L.scal = track(c, dalloc<double>(16));
     const int nb = (n + kAtbChunk - 1) / kAtbChunk;
-    c->ls_atb = track(c, dalloc<float>(size_t(nb) * (nin + 1) * kHid));
+    L.atb = track(c, dalloc<float>(size_t(nb) * (nin + 1) * kHid));
   }
-  if (T > c->ls_T) {
-    c->ls_snap = track(c, dalloc<float>(size_t(T) * n));
-    c->ls_z = track(c, dalloc<float>(size_t(T) * s * n));
-    c->ls_c = track(c, dalloc<double>(T));
-    c->ls_T = T;
+  if (!c->e_tmp64) {  // shared by all levels: sized for the fine level
+    c->e_tmp64 = track(c, dalloc<double>(c->lv[0].n + 1));
+    c->e_tmp32 = track(c, dalloc<float>(c->lv[0].n + 1));
+  }
+  if (T > L.T) {
+    L.snap = track(c, dalloc<float>(size_t(T) * n));
+    L.z = track(c, dalloc<float>(size_t(T) * s * n));
+    L.c = track(c, dalloc<double>(T));
+    L.T = T;
   }
 }
 
 // features (permuted rows, FP32, with a trailing 1 for the bias)
-void build_features(mgm_ctx* c, const std::vector<int32_t>& perm) {
+void build_features(mgm_ctx* c, int j, const std::vector<int32_t>& perm) {
   const HostHierarchy& H = c->H;
-  const int n = H.lv[0].n, ns = H.ns;
+  const HostLevel& lv = H.lv[j];
+  const int n = lv.n;
+  const int ns = std::min(H.ns, n);
   const int nin = 3 * ns;
   std::vector<float> X(size_t(n) * (nin + 1));
   std::vector<int32_t> iperm(n);
   for (int t = 0; t < n; ++t) iperm[perm[t]] = t;
+  // stencils, normals and normalised operator entries of level j
+  const int32_t* sten = H.stencils.data();
+  std::vector<int32_t> csten;
+  std::vector<double> cnrm, cval;
+  const double* nrm = H.normals.data();
+  if (j > 0) {
+    std::vector<double> d2;
+    knn_search(lv.xyz.data(), n, lv.xyz.data(), n, ns, csten, d2);
+    std::vector<int64_t> fidx(H.lv[0].n);  // fine index of each level-k point, k = 0..j
+    std::iota(fidx.begin(), fidx.end(), 0);
+    for (int k = 0; k < j; ++k) {
+      const std::vector<int32_t>& ci = H.lv[k].coarse_idx;
+      std::vector<int64_t> nx(ci.size());
+      for (size_t t = 0; t < ci.size(); ++t) nx[t] = fidx[ci[t]];
+      fidx.swap(nx);
+    }
+    cnrm.resize(size_t(n) * 3);
+    for (int i = 0; i < n; ++i)
+      for (int a = 0; a < 3; ++a) cnrm[size_t(i) * 3 + a] = H.normals[size_t(fidx[i]) * 3 + a];
+    cval.assign(size_t(n) * ns, 0.0);
+    parallel_for(n, [&](int64_t b, int64_t e) {
+      for (int64_t i = b; i < e; ++i) {
+        const int32_t* cb = lv.L.col.data() + lv.L.ptr[i];
+        const int32_t* ce = lv.L.col.data() + lv.L.ptr[i + 1];
+        for (int k = 0; k < ns; ++k) {
+          const int32_t* it = std::lower_bound(cb, ce, csten[size_t(i) * ns + k]);
+          if (it != ce && *it == csten[size_t(i) * ns + k]) cval[size_t(i) * ns + k] = lv.L.val[lv.L.ptr[i] + (it - cb)];
+        }
+      }
+    });
+    sten = csten.data();
+    nrm = cnrm.data();
+  }
+  const double* wts = j == 0 ? H.weights.data() : cval.data();
   parallel_for(n, [&](int64_t b, int64_t e) {
     std::vector<double> xh(2 * ns);
     for (int64_t i = b; i < e; ++i) {
-      project_stencil(H.lv[0].xyz.data(), H.normals.data(), i, &H.stencils[size_t(i) * ns], ns, xh.data());
+      project_stencil(lv.xyz.data(), nrm, i, &sten[size_t(i) * ns], ns, xh.data());
       double rho = 0.0;
-      for (int j = 0; j < ns; ++j) rho = std::max(rho, std::sqrt(xh[2 * j] * xh[2 * j] + xh[2 * j + 1] * xh[2 * j + 1]));
+      for (int k = 0; k < ns; ++k) rho = std::max(rho, std::sqrt(xh[2 * k] * xh[2 * k] + xh[2 * k + 1] * xh[2 * k + 1]));
       float* row = &X[size_t(iperm[i]) * (nin + 1)];
-      for (int j = 0; j < 2 * ns; ++j) row[j] = float(xh[j] / rho);
-      const double c0 = std::fabs(H.weights[size_t(i) * ns]);
-      for (int j = 0; j < ns; ++j) row[2 * ns + j] = float(H.weights[size_t(i) * ns + j] / c0);
+      for (int k = 0; k < 2 * ns; ++k) row[k] = float(xh[k] / rho);
+      const double c0 = std::fabs(wts[size_t(i) * ns]);
+      for (int k = 0; k < ns; ++k) row[2 * ns + k] = float(wts[size_t(i) * ns + k] / c0);
       row[nin] = 1.0f;
     }
   });
-  c->ls_nin = nin;
-  c->ls_X = track(c, dupload(X));
+  c->ls[j].nin = nin;
+  c->ls[j].X = track(c, dupload(X));
 }
 
 // transposed fine operator (permuted numbering), FP32 values
-void build_transpose(mgm_ctx* c) {
-  DevLevel& d = c->lv[0];
+void build_transpose(mgm_ctx* c, int j) {
+  DevLevel& d = c->lv[j];
+  LearnedLevel& L = c->ls[j];
   const int n = d.n;
   std::vector<int32_t> col(d.nnz);
   HIPCHECK(hipMemcpy(col.data(), d.col, sizeof(int32_t) * d.nnz, hipMemcpyDeviceToHost));
@@ -104,13 +151,13 @@ void build_transpose(mgm_ctx* c) {
   A.val = d.hv;
   Csr T = transpose(A);
   std::vector<float> tv(T.val.begin(), T.val.end());
-  c->ls_tptr = track(c, dupload(T.ptr));
-  c->ls_tcol = track(c, dupload(T.col));
-  c->ls_tval = track(c, dupload(tv));
+  L.tptr = track(c, dupload(T.ptr));
+  L.tcol = track(c, dupload(T.col));
+  L.tval = track(c, dupload(tv));
 }
 
-double power_estimate(mgm_ctx* c, hipStream_t st) {
-  DevLevel& d = c->lv[0];
+double power_estimate(mgm_ctx* c, int j, hipStream_t st) {
+  DevLevel& d = c->lv[j];
   const int n = d.n;
   double* v = c->vecs + 2 * c->ld;
   double* w = c->vecs + 3 * c->ld;
@@ -145,33 +192,34 @@ void fdot(mgm_ctx* c, int n, const float* x, const float* y, double* out, hipStr
   hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, 1, nb, c->kpart, out);
 }
 
-void atb(mgm_ctx* c, int n, int ka, int kb, const float* A, const float* B, float* out, hipStream_t st) {
+void atb(mgm_ctx* c, LearnedLevel& L, int n, int ka, int kb, const float* A, const float* B, float* out, hipStream_t st) {
   if (ka > kAtbMaxK || kb > kAtbMaxK || ka * kb > 24 * kBlock) throw Error(MGM_E_ARG, "learned smoother: layer too wide");
   const int nb = (n + kAtbChunk - 1) / kAtbChunk;
-  hipLaunchKernelGGL(k_atb_partial, dim3(nb), dim3(kBlock), 0, st, n, ka, kb, A, B, c->ls_atb);
-  hipLaunchKernelGGL(k_reduce_cols, dim3(nblk(ka * kb)), dim3(kBlock), 0, st, nb, ka * kb, c->ls_atb, out);
+  hipLaunchKernelGGL(k_atb_partial, dim3(nb), dim3(kBlock), 0, st, n, ka, kb, A, B, L.atb);
+  hipLaunchKernelGGL(k_reduce_cols, dim3(nblk(ka * kb)), dim3(kBlock), 0, st, nb, ka * kb, L.atb, out);
 }
 
 // one loss/gradient evaluation (and an Adam step when `update`); the loss of
 // this evaluation is accumulated into loss_slot (device)
-void train_step(mgm_ctx* c, bool update, double* loss_slot, float lr, hipStream_t st) {
-  DevLevel& d = c->lv[0];
-  const int n = d.n, s = c->ls_s, nin = c->ls_nin, T = c->ls_T;
+void train_step(mgm_ctx* c, int j, bool update, double* loss_slot, float lr, hipStream_t st) {
+  DevLevel& d = c->lv[j];
+  LearnedLevel& L = c->ls[j];
+  const int n = d.n, s = L.s, nin = L.nin, T = L.T;
   const int np = mlp_param_count(nin, s);
   const size_t lds = size_t(np) * sizeof(float);
-  hipLaunchKernelGGL(k_mlp_forward, dim3(nblk(n)), dim3(kBlock), lds, st, n, nin, s, c->ls_X, c->ls_params, c->ls_O,
-                     c->ls_H1, c->ls_H2);
-  hipLaunchKernelGGL((k_omega<float>), dim3(nblk(n)), dim3(kBlock), 0, st, n, s, c->ls_O, c->ls_wcheb_d, c->ls_omt);
-  hipLaunchKernelGGL((k_fill<float>), dim3(nblk(int64_t(n) * s)), dim3(kBlock), 0, st, n * s, c->ls_domega, 0.0f);
+  hipLaunchKernelGGL(k_mlp_forward, dim3(nblk(n)), dim3(kBlock), lds, st, n, nin, s, L.X, L.params, L.O,
+                     L.H1, L.H2);
+  hipLaunchKernelGGL((k_omega<float>), dim3(nblk(n)), dim3(kBlock), 0, st, n, s, L.O, L.wcheb_d, L.omt);
+  hipLaunchKernelGGL((k_fill<float>), dim3(nblk(int64_t(n) * s)), dim3(kBlock), 0, st, n * s, L.domega, 0.0f);
   hipLaunchKernelGGL((k_fill<double>), dim3(1), dim3(kBlock), 0, st, 1, loss_slot, 0.0);
   const unsigned g = nblk(int64_t(n) * d.G);
   for (int t = 0; t < T; ++t) {
-    const float* ein = c->ls_snap + size_t(t) * n;
-    float* bufs[2] = {c->ls_e, c->ls_e + n};
+    const float* ein = L.snap + size_t(t) * n;
+    float* bufs[2] = {L.e, L.e + n};
     for (int q = 0; q < s; ++q) {
       float* eout = bufs[q & 1];
-      float* z = c->ls_z + (size_t(t) * s + q) * n;
-      const float* om = c->ls_omt + size_t(q) * n;
+      float* z = L.z + (size_t(t) * s + q) * n;
+      const float* om = L.omt + size_t(q) * n;
       switch (d.G) {
         case 2: hipLaunchKernelGGL((k_train_step<2>), dim3(g), dim3(kBlock), 0, st, n, d.W, d.rowptr, d.col, d.v32, d.dinv32, om, ein, eout, z); break;
         case 4: hipLaunchKernelGGL((k_train_step<4>), dim3(g), dim3(kBlock), 0, st, n, d.W, d.rowptr, d.col, d.v32, d.dinv32, om, ein, eout, z); break;
@@ -180,58 +228,72 @@ void train_step(mgm_ctx* c, bool update, double* loss_slot, float lr, hipStream_
       }
       ein = eout;
     }
-    SPMV_F32(d.G, n, d.W, d.rowptr, d.col, d.v32, ein, c->ls_y);
-    fdot(c, n, c->ls_y, c->ls_y, c->ls_scal, st);
-    hipLaunchKernelGGL(k_loss_acc, dim3(1), dim3(64), 0, st, c->ls_scal, c->ls_c + t, 1.0 / T, loss_slot);
+    SPMV_F32(d.G, n, d.W, d.rowptr, d.col, d.v32, ein, L.y);
+    fdot(c, n, L.y, L.y, L.scal, st);
+    hipLaunchKernelGGL(k_loss_acc, dim3(1), dim3(64), 0, st, L.scal, L.c + t, 1.0 / T, loss_slot);
     // g = 2 L^T y / (c_t T)
-    float* gb[2] = {c->ls_g, c->ls_g + n};
-    SPMV_F32(d.G, n, 0, c->ls_tptr, c->ls_tcol, c->ls_tval, c->ls_y, gb[0]);
-    hipLaunchKernelGGL(k_scale_ct, dim3(nblk(n)), dim3(kBlock), 0, st, n, c->ls_c + t, 2.0 / T, gb[0]);
+    float* gb[2] = {L.g, L.g + n};
+    SPMV_F32(d.G, n, 0, L.tptr, L.tcol, L.tval, L.y, gb[0]);
+    hipLaunchKernelGGL(k_scale_ct, dim3(nblk(n)), dim3(kBlock), 0, st, n, L.c + t, 2.0 / T, gb[0]);
     int cur = 0;
     for (int q = s - 1; q >= 0; --q) {
-      const float* z = c->ls_z + (size_t(t) * s + q) * n;
-      hipLaunchKernelGGL(k_adj_accum, dim3(nblk(n)), dim3(kBlock), 0, st, n, gb[cur], z, d.dinv32, c->ls_omt + size_t(q) * n,
-                         c->ls_domega + size_t(q) * n, c->ls_t);
+      const float* z = L.z + (size_t(t) * s + q) * n;
+      hipLaunchKernelGGL(k_adj_accum, dim3(nblk(n)), dim3(kBlock), 0, st, n, gb[cur], z, d.dinv32, L.omt + size_t(q) * n,
+                         L.domega + size_t(q) * n, L.t);
       if (q > 0) {
         switch (d.G) {
-          case 2: hipLaunchKernelGGL((k_xmAt<2>), dim3(g), dim3(kBlock), 0, st, n, 0, c->ls_tptr, c->ls_tcol, c->ls_tval, gb[cur], c->ls_t, gb[1 - cur]); break;
-          case 4: hipLaunchKernelGGL((k_xmAt<4>), dim3(g), dim3(kBlock), 0, st, n, 0, c->ls_tptr, c->ls_tcol, c->ls_tval, gb[cur], c->ls_t, gb[1 - cur]); break;
-          case 8: hipLaunchKernelGGL((k_xmAt<8>), dim3(g), dim3(kBlock), 0, st, n, 0, c->ls_tptr, c->ls_tcol, c->ls_tval, gb[cur], c->ls_t, gb[1 - cur]); break;
-          default: hipLaunchKernelGGL((k_xmAt<16>), dim3(g), dim3(kBlock), 0, st, n, 0, c->ls_tptr, c->ls_tcol, c->ls_tval, gb[cur], c->ls_t, gb[1 - cur]); break;
+          case 2: hipLaunchKernelGGL((k_xmAt<2>), dim3(g), dim3(kBlock), 0, st, n, 0, L.tptr, L.tcol, L.tval, gb[cur], L.t, gb[1 - cur]); break;
+          case 4: hipLaunchKernelGGL((k_xmAt<4>), dim3(g), dim3(kBlock), 0, st, n, 0, L.tptr, L.tcol, L.tval, gb[cur], L.t, gb[1 - cur]); break;
+          case 8: hipLaunchKernelGGL((k_xmAt<8>), dim3(g), dim3(kBlock), 0, st, n, 0, L.tptr, L.tcol, L.tval, gb[cur], L.t, gb[1 - cur]); break;
+          default: hipLaunchKernelGGL((k_xmAt<16>), dim3(g), dim3(kBlock), 0, st, n, 0, L.tptr, L.tcol, L.tval, gb[cur], L.t, gb[1 - cur]); break;
         }
         cur = 1 - cur;
       }
     }
   }
-  hipLaunchKernelGGL(k_mlp_backward, dim3(nblk(n)), dim3(kBlock), lds, st, n, nin, s, c->ls_params, c->ls_O, c->ls_domega,
-                     c->ls_wcheb_d, c->ls_H1, c->ls_H2, c->ls_dO, c->ls_dH1, c->ls_dH2);
-  atb(c, n, nin + 1, kHid, c->ls_X, c->ls_dH1, c->ls_grad, st);
-  atb(c, n, kHid + 1, kHid, c->ls_H1, c->ls_dH2, c->ls_grad + (nin + 1) * kHid, st);
-  atb(c, n, kHid + 1, s, c->ls_H2, c->ls_dO, c->ls_grad + (nin + 1) * kHid + (kHid + 1) * kHid, st);
+  hipLaunchKernelGGL(k_mlp_backward, dim3(nblk(n)), dim3(kBlock), lds, st, n, nin, s, L.params, L.O, L.domega,
+                     L.wcheb_d, L.H1, L.H2, L.dO, L.dH1, L.dH2);
+  atb(c, L, n, nin + 1, kHid, L.X, L.dH1, L.grad, st);
+  atb(c, L, n, kHid + 1, kHid, L.H1, L.dH2, L.grad + (nin + 1) * kHid, st);
+  atb(c, L, n, kHid + 1, s, L.H2, L.dO, L.grad + (nin + 1) * kHid + (kHid + 1) * kHid, st);
   if (update) {
-    c->ls_adam_t++;
+    L.adam_t++;
     const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.0f - std::pow(b1, float(c->ls_adam_t)), c2 = 1.0f - std::pow(b2, float(c->ls_adam_t));
-    hipLaunchKernelGGL(k_adam, dim3(nblk(np)), dim3(kBlock), 0, st, np, c->ls_params, c->ls_grad, c->ls_m, c->ls_v, lr, b1,
+    const float c1 = 1.0f - std::pow(b1, float(L.adam_t)), c2 = 1.0f - std::pow(b2, float(L.adam_t));
+    hipLaunchKernelGGL(k_adam, dim3(nblk(np)), dim3(kBlock), 0, st, np, L.params, L.grad, L.m, L.v, lr, b1,
                        b2, 1e-8f, c1, c2);
   }
 }
 
 // inference step weights from the current parameters
-void compute_omega(mgm_ctx* c, hipStream_t st) {
-  DevLevel& d = c->lv[0];
-  const int n = d.n, s = c->ls_s, nin = c->ls_nin;
+void compute_omega(mgm_ctx* c, int j, hipStream_t st) {
+  DevLevel& d = c->lv[j];
+  LearnedLevel& L = c->ls[j];
+  const int n = d.n, s = L.s, nin = L.nin;
   const size_t lds = size_t(mlp_param_count(nin, s)) * sizeof(float);
-  hipLaunchKernelGGL(k_mlp_forward, dim3(nblk(n)), dim3(kBlock), lds, st, n, nin, s, c->ls_X, c->ls_params, c->ls_O,
+  hipLaunchKernelGGL(k_mlp_forward, dim3(nblk(n)), dim3(kBlock), lds, st, n, nin, s, L.X, L.params, L.O,
                      (float*)nullptr, (float*)nullptr);
-  hipLaunchKernelGGL((k_omega<double>), dim3(nblk(n)), dim3(kBlock), 0, st, n, s, c->ls_O, c->ls_wcheb_d, c->ls_om64);
-  hipLaunchKernelGGL((k_omega<float>), dim3(nblk(n)), dim3(kBlock), 0, st, n, s, c->ls_O, c->ls_wcheb_d, c->ls_om32);
+  hipLaunchKernelGGL((k_omega<double>), dim3(nblk(n)), dim3(kBlock), 0, st, n, s, L.O, L.wcheb_d, L.om64);
+  hipLaunchKernelGGL((k_omega<float>), dim3(nblk(n)), dim3(kBlock), 0, st, n, s, L.O, L.wcheb_d, L.om32);
 }
 
-// convergence factor of the stationary MGM iteration on L e = 0 from `e0`
-// (permuted FP64): (|L e_k| / |L e_0|)^(1/k)
-double stationary_rate(mgm_ctx* c, const double* e0, int k, hipStream_t st) {
-  DevLevel& d = c->lv[0];
+// y = L_j x (FP64, permuted order; the fine level through the outer operator)
+void apply_level(mgm_ctx* c, int j, const double* x, double* y, hipStream_t st) {
+  if (j == 0) apply_A(c, x, y, st);
+  else spmv_level64(c, j, x, y, st);
+}
+
+// z = M_j v (FP64, permuted order): the full cycle on the fine level, the
+// sub-hierarchy's cycle on a coarse level
+void precond_at(mgm_ctx* c, int j, const double* v, double* z, hipStream_t st) {
+  if (j == 0) precond(c, v, z, nullptr, st);
+  else precond_level(c, j, v, z, st);
+}
+
+// convergence factor of the stationary MGM iteration on L_j e = 0 from `e0`
+// (permuted FP64): (|L_j e_k| / |L_j e_0|)^(1/k)
+double stationary_rate(mgm_ctx* c, int j, const double* e0, int k, hipStream_t st) {
+  DevLevel& d = c->lv[j];
   const int n = d.n;
   double* e = c->vecs + 4 * c->ld;
   double* r = c->vecs + 5 * c->ld;
@@ -239,7 +301,7 @@ double stationary_rate(mgm_ctx* c, const double* e0, int k, hipStream_t st) {
   HIPCHECK(hipMemcpyAsync(e, e0, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
   double n0 = 0.0, nk = 0.0;
   for (int it = 0; it <= k; ++it) {
-    apply_A(c, e, r, st);
+    apply_level(c, j, e, r, st);
     mdot(c, n, r, c->ld, 1, r, c->dh, st);
     to_host(c, c->dh, 1, st);
     if (it == 0) n0 = std::sqrt(c->hpin[0]);
@@ -248,14 +310,15 @@ double stationary_rate(mgm_ctx* c, const double* e0, int k, hipStream_t st) {
       break;
     }
     hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(kBlock), 0, st, n, -1.0, r, 0.0, r, r);
-    precond(c, r, z, nullptr, st);
+    precond_at(c, j, r, z, st);
     hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(kBlock), 0, st, n, 1.0, e, 1.0, z, e);
   }
   return n0 > 0.0 ? std::pow(nk / n0, 1.0 / k) : 0.0;
 }
 
-void init_params_counter(mgm_ctx* c, uint64_t seed, hipStream_t st) {
-  const int nin = c->ls_nin, s = c->ls_s;
+void init_params_counter(mgm_ctx* c, int j, uint64_t seed, hipStream_t st) {
+  LearnedLevel& L = c->ls[j];
+  const int nin = L.nin, s = L.s;
   std::vector<float> p(mlp_param_count(nin, s), 0.0f);
   auto u = [](uint64_t k) {
     uint64_t z = k + 0x9E3779B97F4A7C15ull;
@@ -274,17 +337,23 @@ void init_params_counter(mgm_ctx* c, uint64_t seed, hipStream_t st) {
       p[off + idx] = float((u(seed * (uint64_t(1) << 32) + (uint64_t(l) << 24) + uint64_t(idx)) * 2.0 - 1.0) * lim);
     off += size_t(fin[l] + 1) * kHid;
   }
-  HIPCHECK(hipMemcpyAsync(c->ls_params, p.data(), p.size() * sizeof(float), hipMemcpyHostToDevice, st));
-  HIPCHECK(hipMemsetAsync(c->ls_m, 0, p.size() * sizeof(float), st));
-  HIPCHECK(hipMemsetAsync(c->ls_v, 0, p.size() * sizeof(float), st));
-  c->ls_adam_t = 0;
+  HIPCHECK(hipMemcpyAsync(L.params, p.data(), p.size() * sizeof(float), hipMemcpyHostToDevice, st));
+  HIPCHECK(hipMemsetAsync(L.m, 0, p.size() * sizeof(float), st));
+  HIPCHECK(hipMemsetAsync(L.v, 0, p.size() * sizeof(float), st));
+  L.adam_t = 0;
 }
 
-void set_active(mgm_ctx* c, bool on) {
-  if (c->ls_active != on) {
-    c->ls_active = on;
+void set_active(mgm_ctx* c, int j, bool on) {
+  LearnedLevel& L = c->ls[j];
+  if (L.active != on) {
+    L.active = on;
     invalidate_graphs(c);
   }
+}
+
+void ensure_levels(mgm_ctx* c) {
+  const size_t nl = c->lv.size() - 1;  // smoothed levels
+  if (c->ls.size() < nl) c->ls.resize(nl);
 }
 
 }  // namespace
@@ -307,33 +376,41 @@ mgm_status mgm_train_smoother(mgm_handle h, const mgm_train_opts* o, const doubl
     HIPCHECK(hipSetDevice(h->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (h->p.problem != MGM_SCREENED) throw Error(MGM_E_ARG, "learned smoother: screened problems only");
-    DevLevel& d = h->lv[0];
+    const int j = o->level;
+    if (j < 0 || j + 1 >= int(h->lv.size())) throw Error(MGM_E_ARG, "learned smoother: level out of range");
+    ensure_levels(h);
+    LearnedLevel& L = h->ls[j];
+    DevLevel& d = h->lv[j];
     const int n = d.n;
     ensure_ws(h, 1);
     build_precision(h, MGM_FP32);
+    build_precision(h, MGM_FP64);
     std::vector<int32_t> perm(n);
-    HIPCHECK(hipMemcpy(perm.data(), d.perm, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
-    if (!h->ls_X) {
-      build_features(h, perm);
-      build_transpose(h);
+    if (d.perm) HIPCHECK(hipMemcpy(perm.data(), d.perm, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    else std::iota(perm.begin(), perm.end(), 0);
+    if (!L.X) {
+      build_features(h, j, perm);
+      build_transpose(h, j);
     }
-    const bool was_active = h->ls_active;
-    const bool fresh = !h->ls_params || h->ls_s != o->s;
+    const bool was_active = L.active;
+    const bool fresh = !L.params || L.s != o->s;
     const int T = o->n_starts * o->iters_per_start;
-    ensure_learned_buffers(h, o->s, std::max(T, 1));
+    ensure_learned_buffers(h, j, o->s, std::max(T, 1));
     *info = mgm_train_info{};
     // spectral estimate and Chebyshev step weights
-    h->ls_lam = power_estimate(h, st);
-    const double a = h->ls_lam / 4.0, b = 1.1 * h->ls_lam;
-    h->ls_wcheb.resize(o->s);
+    L.lam = power_estimate(h, j, st);
+    const double a = L.lam / 4.0, b = 1.1 * L.lam;
+    L.wcheb.resize(o->s);
     for (int q = 1; q <= o->s; ++q)
-      h->ls_wcheb[q - 1] = 1.0 / ((b + a) / 2.0 + (b - a) / 2.0 * std::cos((2.0 * q - 1.0) * M_PI / (2.0 * o->s)));
-    HIPCHECK(hipMemcpyAsync(h->ls_wcheb_d, h->ls_wcheb.data(), sizeof(double) * o->s, hipMemcpyHostToDevice, st));
-    info->lam = h->ls_lam;
-    if (o->init || fresh) init_params_counter(h, o->seed, st);
-    // snapshots with the Gauss-Seidel V-cycle in FP64
+      L.wcheb[q - 1] = 1.0 / ((b + a) / 2.0 + (b - a) / 2.0 * std::cos((2.0 * q - 1.0) * M_PI / (2.0 * o->s)));
+    HIPCHECK(hipMemcpyAsync(L.wcheb_d, L.wcheb.data(), sizeof(double) * o->s, hipMemcpyHostToDevice, st));
+    info->lam = L.lam;
+    if (o->init || fresh) init_params_counter(h, j, o->seed, st);
+    // snapshots with the Gauss-Seidel cycle (every level) in FP64
+    std::vector<char> mask(h->ls.size());
+    for (size_t k = 0; k < h->ls.size(); ++k) mask[k] = h->ls[k].active;
     if (T > 0) {
-      set_active(h, false);
+      for (size_t k = 0; k < h->ls.size(); ++k) set_active(h, int(k), false);
       const int prec = h->p.precision;
       h->p.precision = MGM_FP64;
       double* e = h->vecs + 4 * h->ld;
@@ -345,59 +422,63 @@ mgm_status mgm_train_smoother(mgm_handle h, const mgm_train_opts* o, const doubl
         hipLaunchKernelGGL((k_gather<double, double>), dim3(nblk(n)), dim3(kBlock), 0, st, n, d.perm, d_starts + size_t(s0) * n,
                            e, (double*)nullptr);
         for (int it = 0; it < o->iters_per_start; ++it, ++t) {
-          apply_A(h, e, r, st);
+          apply_level(h, j, e, r, st);
           hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(kBlock), 0, st, n, -1.0, r, 0.0, r, r);
           h->capture = cap;
-          precond(h, r, z, nullptr, st);
+          h->capture_level = j;
+          precond_at(h, j, r, z, st);
           h->capture = nullptr;
-          hipLaunchKernelGGL(k_add_cast, dim3(nblk(n)), dim3(kBlock), 0, st, n, e, cap, h->ls_snap + size_t(t) * n);
+          h->capture_level = 0;
+          hipLaunchKernelGGL(k_add_cast, dim3(nblk(n)), dim3(kBlock), 0, st, n, e, cap, L.snap + size_t(t) * n);
           hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(kBlock), 0, st, n, 1.0, e, 1.0, z, e);
           // c_t = |L e_t|^2 in the training precision
-          SPMV_F32(d.G, n, d.W, d.rowptr, d.col, d.v32, h->ls_snap + size_t(t) * n, h->ls_y);
-          fdot(h, n, h->ls_y, h->ls_y, h->ls_c + t, st);
+          SPMV_F32(d.G, n, d.W, d.rowptr, d.col, d.v32, L.snap + size_t(t) * n, L.y);
+          fdot(h, n, L.y, L.y, L.c + t, st);
         }
       }
       h->p.precision = prec;
-      h->ls_T = T;
+      L.T = T;
+      for (size_t k = 0; k < h->ls.size(); ++k) set_active(h, int(k), mask[k] != 0);
     }
-    if (h->ls_T < 1 && o->steps > 0) throw Error(MGM_E_ARG, "learned smoother: no snapshots");
+    if (L.T < 1 && o->steps > 0) throw Error(MGM_E_ARG, "learned smoother: no snapshots");
     // training
     if (o->steps > 0) {
-      if (!h->ls_loss || o->steps + 1 > h->ls_steps_cap) {
-        h->ls_loss = track(h, dalloc<double>(o->steps + 1));
-        h->ls_steps_cap = o->steps + 1;
+      if (!L.loss || o->steps + 1 > L.steps_cap) {
+        L.loss = track(h, dalloc<double>(o->steps + 1));
+        L.steps_cap = o->steps + 1;
       }
-      for (int it = 0; it < o->steps; ++it) train_step(h, true, h->ls_loss + it, float(o->lr), st);
-      train_step(h, false, h->ls_loss + o->steps, float(o->lr), st);
+      for (int it = 0; it < o->steps; ++it) train_step(h, j, true, L.loss + it, float(o->lr), st);
+      train_step(h, j, false, L.loss + o->steps, float(o->lr), st);
       std::vector<double> hist(o->steps + 1);
-      HIPCHECK(hipMemcpyAsync(hist.data(), h->ls_loss, sizeof(double) * hist.size(), hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipMemcpyAsync(hist.data(), L.loss, sizeof(double) * hist.size(), hipMemcpyDeviceToHost, st));
       HIPCHECK(hipStreamSynchronize(st));
       info->loss_first = hist.front();
       info->loss_last = hist.back();
       if (h_loss_hist) std::copy(hist.begin(), hist.end(), h_loss_hist);
     }
-    compute_omega(h, st);
+    compute_omega(h, j, st);
     // activation: compare stationary convergence factors from the first start
+    // (the other levels keep their smoothers)
     if (o->activate == 2) {
-      set_active(h, true);
+      set_active(h, j, true);
     } else if (o->activate == 1 && o->n_starts > 0) {
       double* e0 = h->vecs + 8 * h->ld;
       hipLaunchKernelGGL((k_gather<double, double>), dim3(nblk(n)), dim3(kBlock), 0, st, n, d.perm, d_starts, e0,
                          (double*)nullptr);
-      set_active(h, false);
-      info->rate_gs = stationary_rate(h, e0, 6, st);
-      set_active(h, true);
-      info->rate_learned = stationary_rate(h, e0, 6, st);
-      set_active(h, info->rate_learned < info->rate_gs);
+      set_active(h, j, false);
+      info->rate_gs = stationary_rate(h, j, e0, 6, st);
+      set_active(h, j, true);
+      info->rate_learned = stationary_rate(h, j, e0, 6, st);
+      set_active(h, j, info->rate_learned < info->rate_gs);
     } else {
-      set_active(h, o->activate == 0 ? false : was_active);
+      set_active(h, j, o->activate == 0 ? false : was_active);
     }
-    info->active = h->ls_active ? 1 : 0;
+    info->active = L.active ? 1 : 0;
     HIPCHECK(hipStreamSynchronize(st));
   });
 }
 
-mgm_status mgm_smoother_params(mgm_handle h, int32_t set, float* h_params, int64_t* len) {
+mgm_status mgm_smoother_params(mgm_handle h, int32_t level, int32_t set, float* h_params, int64_t* len) {
   if (!h || !len) {
     g_last_error = "bad arguments";
     return MGM_E_ARG;
@@ -405,28 +486,30 @@ mgm_status mgm_smoother_params(mgm_handle h, int32_t set, float* h_params, int64
   return guard([&] {
     need_device(h);
     HIPCHECK(hipSetDevice(h->device));
-    if (!h->ls_params) throw Error(MGM_E_ARG, "learned smoother not prepared (call mgm_train_smoother first)");
-    const int64_t np = mlp_param_count(h->ls_nin, h->ls_s);
+    if (level < 0 || level >= int(h->ls.size()) || !h->ls[level].params)
+      throw Error(MGM_E_ARG, "learned smoother not prepared on this level (call mgm_train_smoother first)");
+    LearnedLevel& L = h->ls[level];
+    const int64_t np = mlp_param_count(L.nin, L.s);
     if (!h_params) {
       *len = np;
       return;
     }
     if (*len < np) throw Error(MGM_E_ARG, "parameter buffer too small");
     if (set) {
-      HIPCHECK(hipMemcpy(h->ls_params, h_params, np * sizeof(float), hipMemcpyHostToDevice));
-      HIPCHECK(hipMemset(h->ls_m, 0, np * sizeof(float)));
-      HIPCHECK(hipMemset(h->ls_v, 0, np * sizeof(float)));
-      h->ls_adam_t = 0;
-      compute_omega(h, nullptr);
+      HIPCHECK(hipMemcpy(L.params, h_params, np * sizeof(float), hipMemcpyHostToDevice));
+      HIPCHECK(hipMemset(L.m, 0, np * sizeof(float)));
+      HIPCHECK(hipMemset(L.v, 0, np * sizeof(float)));
+      L.adam_t = 0;
+      compute_omega(h, level, nullptr);
       HIPCHECK(hipDeviceSynchronize());
     } else {
-      HIPCHECK(hipMemcpy(h_params, h->ls_params, np * sizeof(float), hipMemcpyDeviceToHost));
+      HIPCHECK(hipMemcpy(h_params, L.params, np * sizeof(float), hipMemcpyDeviceToHost));
     }
     *len = np;
   });
 }
 
-mgm_status mgm_smoother_grad(mgm_handle h, float* h_grad, double* loss, void* stream) {
+mgm_status mgm_smoother_grad(mgm_handle h, int32_t level, float* h_grad, double* loss, void* stream) {
   if (!h || !loss) {
     g_last_error = "bad arguments";
     return MGM_E_ARG;
@@ -435,29 +518,35 @@ mgm_status mgm_smoother_grad(mgm_handle h, float* h_grad, double* loss, void* st
     need_device(h);
     HIPCHECK(hipSetDevice(h->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (!h->ls_params || h->ls_T < 1) throw Error(MGM_E_ARG, "learned smoother has no snapshots");
+    if (level < 0 || level >= int(h->ls.size()) || !h->ls[level].params || h->ls[level].T < 1)
+      throw Error(MGM_E_ARG, "learned smoother has no snapshots on this level");
+    LearnedLevel& L = h->ls[level];
     ensure_ws(h, 1);
-    if (!h->ls_loss) {
-      h->ls_loss = track(h, dalloc<double>(2));
-      h->ls_steps_cap = 2;
+    if (!L.loss) {
+      L.loss = track(h, dalloc<double>(2));
+      L.steps_cap = 2;
     }
-    train_step(h, false, h->ls_loss, 0.0f, st);
-    const int64_t np = mlp_param_count(h->ls_nin, h->ls_s);
-    if (h_grad) HIPCHECK(hipMemcpyAsync(h_grad, h->ls_grad, np * sizeof(float), hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipMemcpyAsync(loss, h->ls_loss, sizeof(double), hipMemcpyDeviceToHost, st));
+    train_step(h, level, false, L.loss, 0.0f, st);
+    const int64_t np = mlp_param_count(L.nin, L.s);
+    if (h_grad) HIPCHECK(hipMemcpyAsync(h_grad, L.grad, np * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(loss, L.loss, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
   });
 }
 
-mgm_status mgm_set_smoother(mgm_handle h, int32_t learned) {
+mgm_status mgm_set_smoother(mgm_handle h, int32_t level_mask) {
   if (!h) {
     g_last_error = "bad arguments";
     return MGM_E_ARG;
   }
   return guard([&] {
     need_device(h);
-    if (learned && !h->ls_om64) throw Error(MGM_E_ARG, "learned smoother not trained");
-    set_active(h, learned != 0);
+    const int nl = int(h->lv.size()) - 1;
+    if (level_mask < 0 || (nl < 31 && (level_mask >> nl) != 0)) throw Error(MGM_E_ARG, "level mask names a level without a smoother");
+    ensure_levels(h);
+    for (int j = 0; j < nl; ++j)
+      if (((level_mask >> j) & 1) && !h->ls[j].om64) throw Error(MGM_E_ARG, "learned smoother not trained on a level of the mask");
+    for (int j = 0; j < nl; ++j) set_active(h, j, ((level_mask >> j) & 1) != 0);
   });
 }
 

@@ -53,7 +53,7 @@ class SolveInfo(ctypes.Structure):
 class TrainOpts(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int32), ("lr", ctypes.c_double), ("s", ctypes.c_int32),
                 ("n_starts", ctypes.c_int32), ("iters_per_start", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("init", ctypes.c_int32), ("activate", ctypes.c_int32)]
+                ("init", ctypes.c_int32), ("activate", ctypes.c_int32), ("level", ctypes.c_int32)]
 
 
 class TrainInfo(ctypes.Structure):
@@ -108,9 +108,9 @@ def load():
     lib.mgm_batched_weights.restype = i32
     lib.mgm_train_smoother.argtypes = [vp, ctypes.POINTER(TrainOpts), vp, ctypes.POINTER(TrainInfo), vp, vp]
     lib.mgm_train_smoother.restype = i32
-    lib.mgm_smoother_params.argtypes = [vp, i32, vp, ctypes.POINTER(i64)]
+    lib.mgm_smoother_params.argtypes = [vp, i32, i32, vp, ctypes.POINTER(i64)]
     lib.mgm_smoother_params.restype = i32
-    lib.mgm_smoother_grad.argtypes = [vp, vp, ctypes.POINTER(dbl), vp]
+    lib.mgm_smoother_grad.argtypes = [vp, i32, vp, ctypes.POINTER(dbl), vp]
     lib.mgm_smoother_grad.restype = i32
     lib.mgm_set_smoother.argtypes = [vp, i32]
     lib.mgm_set_smoother.restype = i32
@@ -256,10 +256,11 @@ class Mgm:
         return ms.value, nbytes.value
 
     def train_smoother(self, starts=None, steps=200, lr=1e-3, s=3, iters_per_start=2, seed=1, init=True,
-                       activate=1, history=False, stream=None):
-        """Prepare/train the learned fine-level smoother. `starts`: torch (n_starts x n) float64 on the device."""
+                       activate=1, history=False, level=0, stream=None):
+        """Prepare/train the learned smoother of `level` (0 = fine). `starts`:
+        torch (n_starts x N_level) float64 on the device."""
         n_starts = 0 if starts is None else int(starts.shape[0])
-        opts = TrainOpts(steps, lr, s, n_starts, iters_per_start, seed, 1 if init else 0, activate)
+        opts = TrainOpts(steps, lr, s, n_starts, iters_per_start, seed, 1 if init else 0, activate, level)
         info = TrainInfo()
         hist = np.zeros(steps + 1) if history else None
         hp = hist.ctypes.data_as(ctypes.c_void_p) if history else ctypes.c_void_p(0)
@@ -271,28 +272,33 @@ class Mgm:
             out["history"] = hist
         return out
 
-    def smoother_params(self, new=None):
+    def smoother_params(self, new=None, level=0):
         n = ctypes.c_int64(0)
-        _check(self.lib.mgm_smoother_params(self.h, 0, None, ctypes.byref(n)))
+        _check(self.lib.mgm_smoother_params(self.h, level, 0, None, ctypes.byref(n)))
         if new is None:
             buf = np.empty(n.value, dtype=np.float32)
-            _check(self.lib.mgm_smoother_params(self.h, 0, buf.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
+            _check(self.lib.mgm_smoother_params(self.h, level, 0, buf.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
             return buf
         buf = np.ascontiguousarray(new, dtype=np.float32)
-        assert buf.size == n.value
-        _check(self.lib.mgm_smoother_params(self.h, 1, buf.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
+        if buf.size != n.value:
+            raise ValueError(f"expected {n.value} parameters")
+        _check(self.lib.mgm_smoother_params(self.h, level, 1, buf.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
         return buf
 
-    def smoother_grad(self, stream=None):
+    def smoother_grad(self, level=0, stream=None):
         n = ctypes.c_int64(0)
-        _check(self.lib.mgm_smoother_params(self.h, 0, None, ctypes.byref(n)))
+        _check(self.lib.mgm_smoother_params(self.h, level, 0, None, ctypes.byref(n)))
         g = np.empty(n.value, dtype=np.float32)
         loss = ctypes.c_double()
-        _check(self.lib.mgm_smoother_grad(self.h, g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss), _stream(stream)))
+        _check(self.lib.mgm_smoother_grad(self.h, level, g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss),
+                                          _stream(stream)))
         return loss.value, g
 
-    def set_smoother(self, learned: bool):
-        _check(self.lib.mgm_set_smoother(self.h, 1 if learned else 0))
+    def set_smoother(self, learned):
+        """True / False: learned smoother on the fine level only / nowhere; an
+        int: bit mask of the levels that use their learned smoother."""
+        mask = int(learned) if not isinstance(learned, bool) else (1 if learned else 0)
+        _check(self.lib.mgm_set_smoother(self.h, mask))
 
     def surface_ops_setup(self, phs_order: int, poly_degree: int, stencil_size: int, stream=None):
         """Surface gradient / divergence operator on the fine point cloud."""

@@ -117,3 +117,57 @@ def test_activation_with_fallback_rule(setup):
     assert res["rate_gs"] > 0 and res["rate_learned"] > 0
     assert res["active"] == (res["rate_learned"] < res["rate_gs"])
     m.set_smoother(False)
+
+
+def test_coarse_level_smoother_matches_oracle(setup):
+    """Learned smoother on level 1 (its own features, spectral estimate,
+    snapshots from the level-1 sub-cycle, loss and gradient), then the cycle
+    with learned smoothing on levels 0 and 1 against the oracle."""
+    wl, H, m, info, L0, X0, S0, _ = setup
+    lv = H.levels[1]
+    rng = np.random.default_rng(31)
+    starts1 = rng.standard_normal((2, lv.N))
+    info1 = m.train_smoother(torch.tensor(starts1, device="cuda"), steps=0, s=3, iters_per_start=2, seed=11,
+                             init=True, activate=0, level=1)
+    L1 = lv.L
+    assert abs(info1["lam"] - learned.power_estimate(L1)) <= 1e-10 * info1["lam"]
+    X1 = learned.level_features(H, 1)
+    p1 = learned.init_params(X1.shape[1], 3, seed=11)
+    assert np.array_equal(m.smoother_params(level=1), _flat(p1).astype(np.float32))
+    w1 = learned.cheb_omegas(info1["lam"], 3)
+    p1[4] = 0.2 * rng.standard_normal(p1[4].shape)
+    p1[5] = 0.1 * rng.standard_normal(p1[5].shape)
+    m.smoother_params(_flat(p1), level=1)
+    o, _ = learned.mlp_forward(p1, X1)
+    om1_ref = learned.omegas_from_output(o, w1)
+    om1 = m.export("omega", 1).reshape(om1_ref.shape)
+    assert np.max(np.abs(om1 - om1_ref)) <= 1e-5 * np.abs(om1_ref).max()
+    S1 = learned.snapshots(H, starts1, 2, level=1)
+    loss, g = m.smoother_grad(level=1)
+    loss_ref, grads = learned.total_loss_and_grads(p1, X1, L1, S1, w1)
+    assert abs(loss - loss_ref) <= 1e-5 * loss_ref
+    assert np.linalg.norm(g - _flat(grads)) <= 1e-4 * np.linalg.norm(_flat(grads))
+    # the cycle with learned smoothing on levels 0 and 1
+    m.set_smoother(3)
+    try:
+        om0 = m.export("omega", 0).reshape(-1, 3)
+        ops = vcycle.Fp64Ops(H)
+        ops.learned = {0: om0, 1: om1}
+        M = vcycle.make_preconditioner(ops, H.problem)
+        z = m.vcycle(torch.tensor(wl.f, device="cuda")).cpu().numpy()
+        zr = M(wl.f)
+        assert np.max(np.abs(z - zr)) <= 1e-10 * np.abs(zr).max()
+        A = vcycle.make_operator(H)
+        _, info_ref = krylov.fgmres(A, M, wl.f, tol=1e-10, maxit=200)
+        u, inf = m.solve(torch.tensor(wl.f, device="cuda"), rtol=1e-10, maxit=200)
+        assert inf["status"] == 0 and inf["iters"] == info_ref.iters
+        # only level 1
+        m.set_smoother(2)
+        ops.learned = {1: om1}
+        z = m.vcycle(torch.tensor(wl.f, device="cuda")).cpu().numpy()
+        zr = vcycle.make_preconditioner(ops, H.problem)(wl.f)
+        assert np.max(np.abs(z - zr)) <= 1e-10 * np.abs(zr).max()
+    finally:
+        m.set_smoother(0)
+    with pytest.raises(mgm.MgmError):
+        m.set_smoother(4)   # level 2 has no trained smoother
