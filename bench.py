@@ -162,6 +162,29 @@ def bench_learned(args):
                       "vcycle_us": round(vc_ms * 1e3, 1)}
     log(f"learned: {ms:.2f} ms, {info['iters']} iters, V-cycle {vc_ms * 1e3:.0f} us")
     out["speedup_learned_vs_gs"] = round(out["gs"]["ms"] / out["learned"]["ms"], 3)
+    # per-level learned smoothing: train every coarse smoothed level on its own
+    # sub-hierarchy (same recipe), keep those whose factor beats Gauss-Seidel
+    sizes = out["levels"]
+    mask = 1 if tr["active"] else 0
+    levels = []
+    t0 = time.perf_counter()
+    for j in range(1, len(sizes) - 1):
+        sj = torch.randn((4, sizes[j]), generator=gen, device="cuda", dtype=torch.float64)
+        tj = m.train_smoother(sj, steps=args.train_steps, lr=1e-3, s=3, iters_per_start=2, seed=5 + j, init=True,
+                              activate=1, level=j)
+        levels.append({"level": j, "rate_gs": tj["rate_gs"], "rate_learned": tj["rate_learned"],
+                       "active": tj["active"]})
+        if tj["active"]:
+            mask |= 1 << j
+    train_levels_s = time.perf_counter() - t0
+    m.set_smoother(mask)
+    ms, info = timed_solves(m, f, u, "fgmres", args.steps, args.warmup, restart=40, maxit=400, rtol=1e-10)
+    vc_ms, _ = m.time_kernel("vcycle", 0, reps=10)
+    out["learned_all_levels"] = {"ms": round(ms, 3), "iters": info["iters"], "rel_res": info["rel_res_true"],
+                                 "vcycle_us": round(vc_ms * 1e3, 1), "level_mask": mask, "levels": levels,
+                                 "training_s": round(train_levels_s, 2)}
+    log(f"learned on levels (mask {mask:#x}): {ms:.2f} ms, {info['iters']} iters, V-cycle {vc_ms * 1e3:.0f} us; "
+        f"coarse rates {[(l['rate_gs'], l['rate_learned']) for l in levels]}")
     print(json.dumps(out), flush=True)
     m.close()
 
