@@ -23,6 +23,8 @@ CASES = [
     ("gfd", lambda: synth.big_sphere_workload(9001), {"n_min": 200}),
     ("shifted", lambda: synth.harmonics_workload(3000), {}),
     ("ragged", lambda: synth.sphere_workload(2053), {"n_coarse_max": 100}),
+    # 80-point stencils: the device search's wide variant (k > 64)
+    ("wide", lambda: synth.sphere_workload(3000), {"n_coarse_max": 150, "stencil_size": 80}),
 ]
 
 
