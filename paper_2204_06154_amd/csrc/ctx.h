@@ -18,6 +18,9 @@ namespace mgm {
 void knn_device(const double* queries, int64_t nq, const double* data, int64_t nd, int k, std::vector<int32_t>& idx,
                 std::vector<double>& d2, hipStream_t st);
 Csr spgemm_device(const Csr& A, const Csr& B, hipStream_t st);
+void dsatur_patches_device(const std::vector<int32_t>& lptr, const std::vector<int32_t>& ladj,
+                           const std::vector<int32_t>& pstart, std::vector<int32_t>& lc, std::vector<int32_t>& pnlc,
+                           hipStream_t st);
 void batched_phs_weights_device(const double* d_xyz, const double* d_nrm, const int32_t* d_sten, int64_t nsys, int ns,
                                 int phs_order, int deg, double* d_w, int* d_status, hipStream_t st);
 

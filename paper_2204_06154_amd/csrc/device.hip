@@ -1302,6 +1302,10 @@ mgm_status mgm_setup(const double* h_xyz, const double* h_normals, int64_t n, co
         else knn_search(q, nq, d, nd, k, idx, d2);
       };
       be.spgemm = [st](const Csr& A, const Csr& B) { return spgemm_device(A, B, st); };
+      be.dsatur = [st](const std::vector<int32_t>& lptr, const std::vector<int32_t>& ladj,
+                       const std::vector<int32_t>& pstart, std::vector<int32_t>& lc, std::vector<int32_t>& pnlc) {
+        dsatur_patches_device(lptr, ladj, pstart, lc, pnlc, st);
+      };
     }
     build_hierarchy(h_xyz, h_normals, n, *params, be, c->H);
     if (device >= 0) {

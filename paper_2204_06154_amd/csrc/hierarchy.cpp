@@ -189,7 +189,7 @@ void build_interp(const HostLevel& fine, const std::vector<double>& cxyz, int m,
 
 Csr galerkin_product(const Csr& R, const Csr& A, const Csr& P) { return spgemm_host(R, spgemm_host(A, P)); }
 
-SetupBackend host_backend() { return SetupBackend{stencil_weights_host, knn_search, spgemm_host}; }
+SetupBackend host_backend() { return SetupBackend{stencil_weights_host, knn_search, spgemm_host, dsatur_patches_host}; }
 
 // Symmetrised adjacency of A without the diagonal (sorted rows): row i is the
 // union of row i of A and of A^T (both sorted), merged without duplicates.
@@ -470,7 +470,17 @@ static int32_t rcb_patches(const double* xyz, int32_t n, int block, std::vector<
 
 // Smoother colouring of one level: patch-blocked (block > 0 and every row at
 // most kMaxPatchWidth entries) or plain multicolour.
-void smoother_colouring(HostLevel& l, int block) {
+void dsatur_patches_host(const std::vector<int32_t>& lptr, const std::vector<int32_t>& ladj,
+                         const std::vector<int32_t>& pstart, std::vector<int32_t>& lc, std::vector<int32_t>& pnlc) {
+  const int32_t np = int32_t(pstart.size()) - 1;
+  lc.assign(pstart.back(), -1);
+  pnlc.assign(np, 0);
+  parallel_for(np, [&](int64_t b, int64_t e) {
+    for (int64_t p = b; p < e; ++p) pnlc[p] = dsatur_range(lptr, ladj, pstart[p], pstart[p + 1], lc);
+  }, 2);
+}
+
+void smoother_colouring(HostLevel& l, int block, const DsaturFn& dsatur) {
   int32_t maxw = 0;
   for (int32_t i = 0; i < l.n; ++i) maxw = std::max(maxw, l.L.ptr[i + 1] - l.L.ptr[i]);
   std::vector<int32_t> ptr, adj;
@@ -525,10 +535,8 @@ void smoother_colouring(HostLevel& l, int block) {
       for (int32_t k = iptr[i]; k < iptr[i + 1]; ++k) ladj[o++] = pos[iadj[k]];
     }
   });
-  std::vector<int32_t> lc(n, -1), pnlc(l.npatch, 0);
-  parallel_for(l.npatch, [&](int64_t b, int64_t e) {
-    for (int64_t p = b; p < e; ++p) pnlc[p] = dsatur_range(lptr, ladj, pstart[p], pstart[p + 1], lc);
-  }, 2);
+  std::vector<int32_t> lc, pnlc;
+  dsatur(lptr, ladj, pstart, lc, pnlc);
   l.lcolour.resize(n);
   for (int32_t t = 0; t < n; ++t) l.lcolour[byp[t]] = lc[t];
   int nlc = 0;
@@ -627,7 +635,7 @@ void build_hierarchy(const double* xyz, const double* nrm, int64_t n, const mgm_
       if (d == 0.0 && j + 1 < H.lv.size())
         throw Error(MGM_E_ZERO_DIAG, "zero diagonal on level " + std::to_string(j) + " row " + std::to_string(i));
     }
-    if (j + 1 < H.lv.size()) smoother_colouring(l, p.gs_block);
+    if (j + 1 < H.lv.size()) smoother_colouring(l, p.gs_block, be.dsatur);
   }
   // dense inverse of the coarsest (bordered) operator
   HostLevel& cl = H.lv.back();

@@ -53,6 +53,14 @@ using KnnFn = std::function<void(const double* queries, int64_t nq, const double
                                  std::vector<int32_t>& idx, std::vector<double>& d2)>;
 // C = A * B on the structural product pattern (host or device).
 using SpgemmFn = std::function<Csr(const Csr& A, const Csr& B)>;
+// DSATUR colouring of every patch's graph: rows numbered so that patch p holds
+// [pstart[p], pstart[p+1]) and no edge (lptr, ladj) leaves its patch; writes
+// each row's colour to lc and each patch's colour count to pnlc (host or device).
+using DsaturFn = std::function<void(const std::vector<int32_t>& lptr, const std::vector<int32_t>& ladj,
+                                    const std::vector<int32_t>& pstart, std::vector<int32_t>& lc,
+                                    std::vector<int32_t>& pnlc)>;
+void dsatur_patches_host(const std::vector<int32_t>& lptr, const std::vector<int32_t>& ladj,
+                         const std::vector<int32_t>& pstart, std::vector<int32_t>& lc, std::vector<int32_t>& pnlc);
 
 // The preprocessing steps that have a host and a device implementation; both
 // give identical results.
@@ -60,6 +68,7 @@ struct SetupBackend {
   WeightsFn weights;
   KnnFn knn;
   SpgemmFn spgemm;
+  DsaturFn dsatur;
 };
 SetupBackend host_backend();
 

@@ -1,7 +1,8 @@
 // Preprocessing steps on the device (Alg. 2): exact k-nearest-neighbour
-// searches (stencils, Sec. 2; interpolation neighbours, Sec. 3) and the sparse
-// products of the Galerkin operator R L P (eq. galerkin). Both give the host
-// path's results bit for bit: the searches return the unique k smallest keys
+// searches (stencils, Sec. 2; interpolation neighbours, Sec. 3), the sparse
+// products of the Galerkin operator R L P (eq. galerkin) and the DSATUR
+// colouring of the smoother's patch graphs. All give the host path's results
+// bit for bit: the searches return the unique k smallest keys
 // (d2, index) with d2 = ((dx*dx) + (dy*dy)) + dz*dz rounded the same way, and
 // every product entry is summed from 0.0 in the host's order (row of the left
 // factor ascending, then row of the right factor ascending), one rounding per
@@ -171,6 +172,62 @@ __global__ void k_heads(int64_t m, const int32_t* __restrict__ flag, const int32
   if (flag[t]) heads[incl[t] - 1] = t;
 }
 
+// DSATUR of one patch graph per 64-lane workgroup (Brelaz 1979; the host's
+// dsatur_range): each step colours the uncoloured row with the largest
+// (saturation, degree, -index), found as a wave maximum of the packed key
+// saturation << 20 | degree << 10 | (1023 - local index), with the smallest
+// colour absent from its neighbours (a 256-bit mask per row in LDS), then
+// marks that colour in its uncoloured neighbours. Patches hold at most
+// kDsaturRows rows, so no row needs more than 256 colours.
+constexpr int kDsaturRows = 256;
+__global__ __launch_bounds__(64) void k_dsatur(const int32_t* __restrict__ pstart, const int32_t* __restrict__ lptr,
+                                               const int32_t* __restrict__ ladj, int32_t* __restrict__ lc,
+                                               int32_t* __restrict__ pnlc) {
+  __shared__ int16_t col[kDsaturRows], sat[kDsaturRows], deg[kDsaturRows];
+  __shared__ uint64_t mask[kDsaturRows][4];
+  const int p = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int v0 = pstart[p];
+  const int n = pstart[p + 1] - v0;  // <= kDsaturRows (checked on the host)
+  for (int v = lane; v < n; v += 64) {
+    col[v] = -1;
+    sat[v] = 0;
+    deg[v] = int16_t(lptr[v0 + v + 1] - lptr[v0 + v]);
+    for (int w = 0; w < 4; ++w) mask[v][w] = 0;
+  }
+  __syncthreads();
+  int maxc = 0;
+  for (int step = 0; step < n; ++step) {
+    uint32_t best = 0;
+    for (int v = lane; v < n; v += 64)
+      if (col[v] < 0) best = max(best, (uint32_t(sat[v]) << 20) | (uint32_t(deg[v]) << 10) | uint32_t(1023 - v));
+    for (int o = 32; o > 0; o >>= 1) best = max(best, uint32_t(__shfl_xor(int(best), o)));
+    const int v = 1023 - int(best & 1023u);
+    int c = 0;
+    for (int w = 0; w < 4; ++w) {
+      const uint64_t free_bits = ~mask[v][w];
+      if (free_bits) {
+        c = w * 64 + __builtin_ctzll(free_bits);
+        break;
+      }
+    }
+    maxc = max(maxc, c + 1);
+    __syncthreads();  // every lane has read this step's state
+    if (lane == 0) col[v] = int16_t(c);
+    const uint64_t bit = uint64_t(1) << (c & 63);
+    for (int k = lptr[v0 + v] + lane; k < lptr[v0 + v + 1]; k += 64) {
+      const int u = ladj[k] - v0;  // distinct neighbours: no two lanes share a row
+      if (col[u] < 0 && !(mask[u][c >> 6] & bit)) {
+        mask[u][c >> 6] |= bit;
+        sat[u] = int16_t(sat[u] + 1);
+      }
+    }
+    __syncthreads();
+  }
+  for (int v = lane; v < n; v += 64) lc[v0 + v] = col[v];
+  if (lane == 0) pnlc[p] = maxc;
+}
+
 // Device buffers freed on scope exit (setup-time allocations only).
 struct Scratch {
   std::vector<void*> p;
@@ -237,6 +294,29 @@ void knn_device(const double* queries, int64_t nq, const double* data, int64_t n
   d2.resize(size_t(nq) * k);
   HIPCHECK(hipMemcpyAsync(idx.data(), d_idx, idx.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipMemcpyAsync(d2.data(), d_d2, d2.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+}
+
+void dsatur_patches_device(const std::vector<int32_t>& lptr, const std::vector<int32_t>& ladj,
+                           const std::vector<int32_t>& pstart, std::vector<int32_t>& lc, std::vector<int32_t>& pnlc,
+                           hipStream_t st) {
+  const int32_t np = int32_t(pstart.size()) - 1;
+  for (int32_t p = 0; p < np; ++p)
+    if (pstart[p + 1] - pstart[p] > kDsaturRows) throw Error(MGM_E_ARG, "device DSATUR: patch larger than 256 rows");
+  const int32_t n = pstart.back();
+  lc.assign(n, -1);
+  pnlc.assign(np, 0);
+  if (np == 0) return;
+  Scratch s;
+  const int32_t* d_ps = s.up(pstart.data(), pstart.size(), st);
+  const int32_t* d_lptr = s.up(lptr.data(), lptr.size(), st);
+  const int32_t* d_ladj = s.up(ladj.data(), ladj.size(), st);
+  int32_t* d_lc = s.get<int32_t>(n);
+  int32_t* d_pn = s.get<int32_t>(np);
+  hipLaunchKernelGGL(k_dsatur, dim3(np), dim3(64), 0, st, d_ps, d_lptr, d_ladj, d_lc, d_pn);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipMemcpyAsync(lc.data(), d_lc, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipMemcpyAsync(pnlc.data(), d_pn, sizeof(int32_t) * np, hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
 }
 
