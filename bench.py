@@ -409,6 +409,47 @@ def bench_geodesic(args):
     mh.close()
 
 
+def bench_table2(args):
+    """The paper's scaling study on the sphere (Table 2): icosahedral nodes
+    N = 10,242 ... 655,362, shifted Poisson (mu = 1) with a random
+    right-hand side, RBF-FD l = 3, 5, 7 (k = l, n = (l+1)(l+2)), MGM-GMRES(40)
+    and MGM-BiCGSTAB to 1e-12: iteration counts with the FP64 cycle beside the
+    paper's, and solve times with the FP64 and FP32 cycles."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2204_06154_amd import mgm
+
+    paper = {r[0]: r for r in json.load(open(os.path.join(ROOT, "tests", "golden", "table2_sphere_rbffd_mgm.json")))["rows"]}
+    rows = []
+    for k in (5, 6, 7, 8):
+        for ell in (3, 5, 7):
+            wl = synth.icosahedral_workload(k, ell)
+            n = len(wl.xyz)
+            t0 = time.perf_counter()
+            m = mgm.Mgm(wl.xyz, wl.normals, wl.params, device=0)
+            torch.cuda.synchronize()
+            setup_s = time.perf_counter() - t0
+            f = torch.tensor(wl.f, device="cuda")
+            u = torch.zeros_like(f)
+            row = {"N": n, "l": ell, "levels": [int(v) for v in m.export("level_sizes")], "setup_s": round(setup_s, 2)}
+            for prec in ("fp64", "fp32"):
+                m.set_precision(prec)
+                for kry in ("fgmres", "bicgstab"):
+                    ms, info = timed_solves(m, f, u, kry, 2, 1, restart=40, maxit=300, rtol=1e-12)
+                    row[f"{kry}_{prec}"] = {"iters": info["iters"], "ms": round(ms, 3), "rel_res": info["rel_res_true"]}
+            col = {3: 1, 5: 3, 7: 5}[ell]
+            row["paper"] = {"gmres": paper[n][col], "bicgstab": paper[n][col + 1]}
+            rows.append(row)
+            log(f"N={n} l={ell}: GMRES {row['fgmres_fp64']['iters']} (paper {paper[n][col]}), BiCGSTAB "
+                f"{row['bicgstab_fp64']['iters']} (paper {paper[n][col + 1]}); FP32-cycle GMRES "
+                f"{row['fgmres_fp32']['ms']:.2f} ms, setup {setup_s:.1f} s")
+            m.close()
+    print(json.dumps({"workload": "icosahedral sphere, shifted Poisson mu=1, random RHS, RBF-FD l=3/5/7, tol 1e-12",
+                      "rows": rows}), flush=True)
+
+
 def bench_traffic(args):
     """Launch set for the HBM-traffic counters: FP32 patch-GS launches of the
     torus workload as the roofline times them (every smoother launch of a
@@ -449,7 +490,7 @@ def main():
     ap.add_argument("--gs-block", type=int, default=256)
     ap.add_argument("--cycle", choices=["V", "W", "F"], default="V", help="multigrid cycle of the torus workload")
     ap.add_argument("--workload", choices=["torus", "learned", "sphere1m", "traffic", "sbdf2", "harmonics",
-                                                 "setup", "geodesic"],
+                                                 "setup", "geodesic", "table2"],
                     default="torus")
     ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--vcycle-precision", default="fp32", help="V-cycle precision of the learned and sbdf2 workloads")
@@ -476,6 +517,8 @@ def main():
         if args.n == 160_000:
             args.n = 300_000
         return bench_sbdf2(args)
+    if args.workload == "table2":
+        return bench_table2(args)
     if args.workload == "geodesic":
         if args.n == 160_000:
             args.n = 872_773

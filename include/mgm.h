@@ -70,8 +70,8 @@ enum { MGM_FGMRES = 0, MGM_BICGSTAB = 1, MGM_STATIONARY = 2 };
 
 typedef struct {
   int32_t disc;           /* MGM_RBFFD | MGM_GFD */
-  int32_t phs_order;      /* k of the PHS kernel r^(2k+1) (RBF-FD only), 0..6 */
-  int32_t poly_degree;    /* l, degree of the bivariate polynomials, 0..6 */
+  int32_t phs_order;      /* k of the PHS kernel r^(2k+1) (RBF-FD only), 0..8 */
+  int32_t poly_degree;    /* l, degree of the bivariate polynomials, 0..8 */
   int32_t stencil_size;   /* n, stencil size, centre included, > L = (l+1)(l+2)/2 */
   double  gfd_alpha;      /* alpha of the GFD Gaussian weight (Sec. 2.3) */
   int32_t problem;        /* MGM_SCREENED | MGM_POISSON */

@@ -90,6 +90,32 @@ def fibonacci_sphere(n: int) -> np.ndarray:
     return np.stack([r * np.cos(phi), r * np.sin(phi), z], axis=1)
 
 
+def icosahedral_sphere(k: int) -> np.ndarray:
+    """Vertices of the icosahedral grid on the unit sphere after k recursive
+    subdivisions (each triangle split into four through its edge midpoints,
+    projected to the sphere): N = 10 * 4^k + 2 points (k = 5: 10,242)."""
+    g = (1.0 + 5.0 ** 0.5) / 2.0
+    v = np.array([[-1, g, 0], [1, g, 0], [-1, -g, 0], [1, -g, 0], [0, -1, g], [0, 1, g], [0, -1, -g], [0, 1, -g],
+                  [g, 0, -1], [g, 0, 1], [-g, 0, -1], [-g, 0, 1]], dtype=np.float64)
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    f = np.array([[0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11], [1, 5, 9], [5, 11, 4], [11, 10, 2],
+                  [10, 7, 6], [7, 1, 8], [3, 9, 4], [3, 4, 2], [3, 2, 6], [3, 6, 8], [3, 8, 9], [4, 9, 5],
+                  [2, 4, 11], [6, 2, 10], [8, 6, 7], [9, 8, 1]], dtype=np.int64)
+    for _ in range(k):
+        e = np.concatenate([f[:, [0, 1]], f[:, [1, 2]], f[:, [2, 0]]])
+        e.sort(axis=1)
+        ue, inv = np.unique(e, axis=0, return_inverse=True)
+        mid = v[ue[:, 0]] + v[ue[:, 1]]
+        mid /= np.linalg.norm(mid, axis=1, keepdims=True)
+        m = len(v) + inv.reshape(3, -1).T          # midpoint ids of edges (01, 12, 20) of every face
+        v = np.concatenate([v, mid])
+        a, b, c = f[:, 0], f[:, 1], f[:, 2]
+        ab, bc, ca = m[:, 0], m[:, 1], m[:, 2]
+        f = np.concatenate([np.stack([a, ab, ca], 1), np.stack([ab, b, bc], 1), np.stack([ca, bc, c], 1),
+                            np.stack([ab, bc, ca], 1)])
+    return v
+
+
 def _sphere_tangent_basis(x: np.ndarray):
     east = np.stack([-x[:, 1], x[:, 0], np.zeros(len(x))], axis=1)
     east /= np.linalg.norm(east, axis=1, keepdims=True)
@@ -357,6 +383,19 @@ def geodesic_workload(n: int = 872_773, jitter: float = 0.1, config_id: int = 8)
     wl = Workload(f"geodesic{n}", x, x.copy(), None, params)
     wl.heat = dict(dt=0.01, steps=3, source=0, grad_phs_order=2, grad_degree=2, grad_stencil=12)
     return wl
+
+
+def icosahedral_workload(k: int = 5, ell: int = 3, config_id: int = 9) -> Workload:
+    """The sphere experiments of the paper's scaling study: icosahedral nodes
+    (k subdivisions), the shifted Poisson problem I - Delta (mu = 1) with a
+    random right-hand side (standard normal per node), RBF-FD with degree l,
+    PHS order k = l and n = (l+1)(l+2) (the parameter table), N_min = 250."""
+    _, rf, _ = rng_streams(config_id)
+    x = icosahedral_sphere(k)
+    f = rf.standard_normal(len(x))
+    params = dict(disc="rbffd", phs_order=ell, poly_degree=ell, stencil_size=(ell + 1) * (ell + 2),
+                  problem="screened", mu=1.0, n_min=250, n_coarse_max=0)
+    return Workload(f"icos{len(x)}_l{ell}", x, x.copy(), f, params)
 
 
 def torus_workload(n: int = 160_000, config_id: int = 2) -> Workload:

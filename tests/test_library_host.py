@@ -45,6 +45,7 @@ CASES = [
     ("gfd", lambda: synth.big_sphere_workload(9001), {"n_min": 200}),
     ("ragged", lambda: synth.sphere_workload(2053), {"n_coarse_max": 100}),
     ("shifted", lambda: synth.harmonics_workload(3000), {}),
+    ("icos_l7", lambda: synth.icosahedral_workload(4, 7), {}),
 ]
 
 
@@ -77,20 +78,27 @@ def test_integer_setup_bit_exact(pair):
         assert np.array_equal(m.export("l_cols", j), lv.pat.indices)
 
 
-def test_float_setup_within_rounding(pair):
+# Degree 7 with PHS r^15: the scaled saddle systems reach cond ~2.5e11
+# (degree 3: ~6e4, degree 5: ~9e7), so two LU solves may differ by up to
+# cond * eps ~ 6e-5 relative; 1e-8 holds with margin (8e-10 measured).
+WEIGHT_TOL = {"icos_l7": 1e-8}
+
+
+def test_float_setup_within_rounding(pair, request):
     """Weights: two pivoted-LU / QR solves of the same local systems differ by
-    about cond * eps; the scaled saddle systems have cond up to ~1e4-1e6, so
-    1e-10 relative to each row's weight magnitude."""
+    about cond * eps; the scaled saddle systems have cond up to ~1e4-1e6
+    (degree <= 3), so 1e-10 relative to each row's weight magnitude."""
     wl, H, m = pair
+    tol = WEIGHT_TOL.get(request.node.callspec.id, 1e-10)
     w = m.export("weights").reshape(H.weights.shape)
     scale = np.abs(H.weights).max(axis=1, keepdims=True)
-    assert np.max(np.abs(w - H.weights) / scale) < 1e-10
+    assert np.max(np.abs(w - H.weights) / scale) < tol
     for j, lv in enumerate(H.levels):
         v = m.export("l_vals", j)
         L = lv.L
         rows = np.repeat(np.arange(L.shape[0]), np.diff(L.indptr))
         rs = np.maximum.reduceat(np.abs(L.data), L.indptr[:-1])[rows]
-        assert np.max(np.abs(v - L.data) / rs) < 1e-9, j
+        assert np.max(np.abs(v - L.data) / rs) < 10 * tol, j
         if lv.b is not None:
             assert np.max(np.abs(m.export("border", j) - lv.b)) < 1e-10 * np.abs(lv.b).max()
     for j in range(len(H.levels) - 1):

@@ -287,6 +287,35 @@ def test_per_level_learned_smoothing_and_sub_cycles_match_dense_definition():
         vcycle.vcycle(ops, np.zeros(H.levels[2].N), None, level=2)
 
 
+def test_icosahedral_iteration_counts_near_the_papers():
+    """The paper's scaling study (Table 2; fixture tests/golden/table2_sphere_rbffd_mgm.json):
+    MGM-preconditioned GMRES / BiCGSTAB to 1e-12 on icosahedral sphere nodes,
+    shifted Poisson, random right-hand side, RBF-FD with l = 3, 5. The paper
+    leaves mu and the RHS distribution open and smooths in RCM order, while
+    this GS runs in multicolour order, so counts are compared within a band
+    of 5 iterations; they must also stay flat from N = 10,242 to 40,962."""
+    import json
+    import os
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table2_sphere_rbffd_mgm.json")))
+    paper = {row[0]: row for row in fx["rows"]}
+    got = {}
+    for k, ell in ((5, 3), (5, 5), (6, 3)):
+        wl = synth.icosahedral_workload(k, ell)
+        H = hierarchy.build(wl.xyz, wl.normals, wl.params)
+        A = vcycle.make_operator(H)
+        M = vcycle.make_preconditioner(vcycle.Fp64Ops(H), H.problem)
+        x, ig = krylov.fgmres(A, M, wl.f, tol=1e-12, restart=40, maxit=200)
+        _, ib = krylov.bicgstab(A, M, wl.f, tol=1e-12, maxit=200)
+        assert ig.converged and ib.converged
+        assert np.linalg.norm(wl.f - A(x)) <= 1.01e-12 * np.linalg.norm(wl.f)
+        n = len(wl.xyz)
+        col = {3: 1, 5: 3}[ell]
+        assert abs(ig.iters - paper[n][col]) <= 5, (n, ell, ig.iters, paper[n][col])
+        assert abs(ib.iters - paper[n][col + 1]) <= 5, (n, ell, ib.iters, paper[n][col + 1])
+        got[(n, ell)] = ig.iters
+    assert abs(got[(40962, 3)] - got[(10242, 3)]) <= 2
+
+
 def test_vcycle_is_linear(sphere_h, torus_h):
     for wl, H in (sphere_h, torus_h):
         ops = vcycle.Fp64Ops(H)
