@@ -412,9 +412,10 @@ def bench_geodesic(args):
 def bench_table2(args):
     """The paper's scaling study on the sphere (Table 2): icosahedral nodes
     N = 10,242 ... 655,362, shifted Poisson (mu = 1) with a random
-    right-hand side, RBF-FD l = 3, 5, 7 (k = l, n = (l+1)(l+2)), MGM-GMRES(40)
-    and MGM-BiCGSTAB to 1e-12: iteration counts with the FP64 cycle beside the
-    paper's, and solve times with the FP64 and FP32 cycles."""
+    right-hand side, RBF-FD l = 3, 5, 7 (k = l, n = (l+1)(l+2)), MGM-GMRES(40),
+    MGM-BiCGSTAB and standalone MGM (the stationary iteration) to 1e-12:
+    iteration counts with the FP64 cycle beside the paper's, and solve times
+    with the FP64 and FP32 cycles."""
     import numpy as np
     import torch
 
@@ -436,14 +437,15 @@ def bench_table2(args):
             row = {"N": n, "l": ell, "levels": [int(v) for v in m.export("level_sizes")], "setup_s": round(setup_s, 2)}
             for prec in ("fp64", "fp32"):
                 m.set_precision(prec)
-                for kry in ("fgmres", "bicgstab"):
+                for kry in ("fgmres", "bicgstab") + (("stationary",) if prec == "fp64" else ()):
                     ms, info = timed_solves(m, f, u, kry, 2, 1, restart=40, maxit=300, rtol=1e-12)
                     row[f"{kry}_{prec}"] = {"iters": info["iters"], "ms": round(ms, 3), "rel_res": info["rel_res_true"]}
             col = {3: 1, 5: 3, 7: 5}[ell]
             row["paper"] = {"gmres": paper[n][col], "bicgstab": paper[n][col + 1]}
             rows.append(row)
             log(f"N={n} l={ell}: GMRES {row['fgmres_fp64']['iters']} (paper {paper[n][col]}), BiCGSTAB "
-                f"{row['bicgstab_fp64']['iters']} (paper {paper[n][col + 1]}); FP32-cycle GMRES "
+                f"{row['bicgstab_fp64']['iters']} (paper {paper[n][col + 1]}), standalone MGM "
+                f"{row['stationary_fp64']['iters']}; FP32-cycle GMRES "
                 f"{row['fgmres_fp32']['ms']:.2f} ms, setup {setup_s:.1f} s")
             m.close()
     print(json.dumps({"workload": "icosahedral sphere, shifted Poisson mu=1, random RHS, RBF-FD l=3/5/7, tol 1e-12",
@@ -496,8 +498,8 @@ def main():
     ap.add_argument("--vcycle-precision", default="fp32", help="V-cycle precision of the learned and sbdf2 workloads")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the MGM solve is not sharded across GPUs in this build "
-              "(see DESIGN.md for how it would shard).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the MGM solve is not sharded across GPUs (a single-GPU "
+              "implementation; multi-GPU runs are not supported).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

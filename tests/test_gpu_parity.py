@@ -22,11 +22,11 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 CASES = {
-    # configs[0]: jittered Fibonacci sphere N=4096, RBF-FD r^3 + deg 2, k=30, screened mu=1
+    # jittered Fibonacci sphere N=4096, RBF-FD r^3 + deg 2, k=30, screened mu=1
     "sphere4096": (lambda: synth.sphere_workload(4096), {}),
-    # torus Poisson (bordered), RBF-FD r^5 + deg 3, k=50: the config-2 family at small N
+    # torus Poisson (bordered), RBF-FD r^5 + deg 3, k=50: the benchmark's torus family at small N
     "torus8000": (lambda: synth.torus_workload(8000), {"n_min": 250}),
-    # GFD deg 2, k=25 on a ragged-size plain Fibonacci sphere (config-3 family)
+    # GFD deg 2, k=25 on a ragged-size plain Fibonacci sphere (the 2^20-point sphere's family)
     "gfd9001": (lambda: synth.big_sphere_workload(9001), {"n_min": 150}),
     # plain multicolour GS (no patch blocking), bordered Poisson
     "torus6000plain": (lambda: synth.torus_workload(6000), {"n_min": 300, "gs_block": 0}),
