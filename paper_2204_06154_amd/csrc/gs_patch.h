@@ -98,15 +98,14 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
   for (int step = 0; step < ncl; ++step) {
     const int c = reverse ? ncl - 1 - step : step;
     if (myc == c) {  // all lanes of a row agree
-      S a0 = S(0), a1 = S(0), a2 = S(0), a3 = S(0);
+      S a[4] = {S(0), S(0), S(0), S(0)};
 #pragma unroll
-      for (int i = 0; i < WL; i += 4) {
-        a0 += iv[i] * ul[ic[i]];
-        a1 += iv[i + 1] * ul[ic[i + 1]];
-        a2 += iv[i + 2] * ul[ic[i + 2]];
-        a3 += iv[i + 3] * ul[ic[i + 3]];
-      }
-      const S acc = group_sum<kPatchG>((a0 + a1) + (a2 + a3));
+      for (int i = 0; i < WL; ++i) a[i & 3] += iv[i] * ul[ic[i]];
+      // issue every LDS gather of the step before the first multiply-add (one
+      // LDS latency per step instead of one per batch of eight)
+      __builtin_amdgcn_sched_group_barrier(0x100, WL, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 4 * WL, 0);
+      const S acc = group_sum<kPatchG>((a[0] + a[1]) + (a[2] + a[3]));
       uown = uown + (rhs - sc * acc) * di;
       if (g == 0) ul[t] = uown;
     }
