@@ -65,20 +65,33 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_rowop_patch(
     if (xcopy) xcopy[row] = S(x[row]);
   }
   if (BORDER && xcopy && slot == 0 && threadIdx.x == 0) xcopy[tail] = S(*lam);
+  // Halo gathers are issued unconditionally, so that no branch makes a load
+  // wait for the one before it; in-patch and padding entries read the row's
+  // own value instead (one cache line) and are masked out of the sums. Each
+  // sum adds the same terms in the same order as a masked loop would.
   S a0 = S(0), a1 = S(0);
   if (act) {
+    X xv[WL];
+#pragma unroll
+    for (int i = 0; i < WL; ++i) {
+      const bool halo = i < nw && unsigned(cc[i] - r0) >= unsigned(nr);
+      xv[i] = x[halo ? cc[i] : row];
+    }
 #pragma unroll
     for (int i = 0; i < WL; i += 2) {
-      if (i < nw && unsigned(cc[i] - r0) >= unsigned(nr)) a0 += iv[i] * S(x[cc[i]]);
-      if (i + 1 < nw && unsigned(cc[i + 1] - r0) >= unsigned(nr)) a1 += iv[i + 1] * S(x[cc[i + 1]]);
+      if (i < nw && unsigned(cc[i] - r0) >= unsigned(nr)) a0 += iv[i] * S(xv[i]);
+      if (i + 1 < nw && unsigned(cc[i + 1] - r0) >= unsigned(nr)) a1 += iv[i + 1] * S(xv[i + 1]);
     }
   }
   __syncthreads();
   if (act) {
+    S lv[WL];
+#pragma unroll
+    for (int i = 0; i < WL; ++i) lv[i] = xl[unsigned(cc[i] - r0) < unsigned(nr) ? cc[i] - r0 : 0];
 #pragma unroll
     for (int i = 0; i < WL; i += 2) {
-      if (i < nw && unsigned(cc[i] - r0) < unsigned(nr)) a0 += iv[i] * xl[cc[i] - r0];
-      if (i + 1 < nw && unsigned(cc[i + 1] - r0) < unsigned(nr)) a1 += iv[i + 1] * xl[cc[i + 1] - r0];
+      if (i < nw && unsigned(cc[i] - r0) < unsigned(nr)) a0 += iv[i] * lv[i];
+      if (i + 1 < nw && unsigned(cc[i + 1] - r0) < unsigned(nr)) a1 += iv[i + 1] * lv[i + 1];
     }
   }
   S acc = group_sum<kPatchG>(a0 + a1);
