@@ -50,7 +50,7 @@ HBM_PEAK_GBS = 8000.0
 # `bench.py --workload traffic` (summary and commands in
 # profiles/gs_patch_torus160k_traffic.md): bytes per launch, valid only for
 # the kernel source it was measured on (SHA-256 over lane_ops.h + gs_patch.h).
-GS_TRAFFIC = {"source_sha256": "c8931d11cd0e9109e853f706235d2d453b1e6b4b04aeaced6e9aa4dba94e61ac", "bytes_per_launch": 5314544,
+GS_TRAFFIC = {"source_sha256": "24e083d04b661247d25a2dbd078faf017ed22bc3d4ffd8600abb19924c88e963", "bytes_per_launch": 23430355,
               "summary": "profiles/gs_patch_torus160k_traffic.md"}
 
 
@@ -464,7 +464,8 @@ def bench_traffic(args):
     from paper_2204_06154_amd import mgm
 
     wl = synth.torus_workload(args.n)
-    m = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, gs_block=args.gs_block, precision=mgm.FP32), device=0)
+    m = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, gs_block=args.gs_block, gs_flow=args.gs_flow,
+                                         precision=mgm.FP32), device=0)
     f = torch.tensor(__import__("numpy").concatenate([wl.f, [0.0]]), device="cuda")
     m.vcycle(f)
     ms, nbytes = m.time_kernel("gs", -1, reps=args.steps)
@@ -490,6 +491,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--weights-n", type=int, default=500_000)
     ap.add_argument("--gs-block", type=int, default=256)
+    ap.add_argument("--gs-flow", type=int, choices=[0, 1], default=1,
+                    help="1: one launch per patch-blocked sweep (dataflow order between patches); "
+                         "0: one launch per patch colour")
     ap.add_argument("--cycle", choices=["V", "W", "F"], default="V", help="multigrid cycle of the torus workload")
     ap.add_argument("--workload", choices=["torus", "learned", "sphere1m", "traffic", "sbdf2", "harmonics",
                                                  "setup", "geodesic", "table2"],
@@ -539,7 +543,8 @@ def main():
     wl = synth.torus_workload(args.n)
     log(f"inputs N={args.n} generated in {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
-    m = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, gs_block=args.gs_block, cycle=args.cycle), device=0)
+    m = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, gs_block=args.gs_block, gs_flow=args.gs_flow, cycle=args.cycle),
+                device=0)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     sizes = [int(s) for s in m.export("level_sizes")]

@@ -42,7 +42,10 @@ typedef enum {
   MGM_E_ZERO_DIAG = -6,        /* a level operator has a zero diagonal entry */
   MGM_E_COARSE_SINGULAR = -7,  /* coarsest-level LU hit a zero pivot */
   MGM_E_BREAKDOWN = -8,        /* Krylov breakdown */
-  MGM_E_NONFINITE = -9         /* NaN/Inf in an input or an iterate */
+  MGM_E_NONFINITE = -9,        /* NaN/Inf in an input or an iterate */
+  MGM_E_SYNC = -10             /* a one-launch smoother sweep (gs_flow) gave up
+                                  waiting for a coupled patch: the results of
+                                  the calls since the last solve are invalid */
 } mgm_status;
 
 /* Discretisation of the Laplace-Beltrami operator (Sec. 2). */
@@ -97,11 +100,19 @@ typedef struct {
   int32_t device_setup;   /* 1: kNN searches (k <= 128) and the Galerkin sparse
                              products on the device; results identical to the
                              host path */
+  int32_t gs_flow;        /* 1 (default): each patch-blocked sweep is one
+                             launch in which a patch starts once the coupled
+                             patches before it in the sweep order are done
+                             (the same GS order and bit-identical results as
+                             0: one launch per patch colour). A wait is
+                             bounded; if one gives up, the next mgm_solve
+                             returns MGM_E_SYNC */
 } mgm_params;
 
 /* Paper defaults (Table 1): RBF-FD, k = l = 3, n = 20, forward GS, nu = 1,
  * m = 3, factor 4, N_min = 250, screened with mu = 1; FP64 V-cycle, graphs
- * on, device weights and device setup on, gs_block = 256, V-cycle. */
+ * on, device weights and device setup on, gs_block = 256, V-cycle,
+ * one-launch sweeps (gs_flow = 1). */
 void mgm_default_params(mgm_params *p);
 
 /* Preprocessing phase (Alg. 2): kNN stencils (Sec. 2), tangent-plane weights

@@ -110,6 +110,11 @@ struct DevLevel {
   _Float16* pv16 = nullptr;
   std::vector<double> hpv;           // host copy of the patch values (FP64)
   std::vector<int32_t> hprow;        // permuted row of each patch entry (host)
+  // one-launch sweeps (see GsFlow): coupled slots, colour row ranges, sweep state
+  bool flow_ok = false;
+  int32_t *fl_nbptr = nullptr, *fl_nb = nullptr, *fl_crow = nullptr;
+  unsigned long long* fl_ticket = nullptr;
+  unsigned* fl_flag = nullptr;
 };
 
 }  // namespace mgm
@@ -159,6 +164,8 @@ struct mgm_ctx {
   int64_t ld = 0;
   double *V = nullptr, *Z = nullptr, *vecs = nullptr, *kpart = nullptr, *dh = nullptr;
   double* hpin = nullptr;  // pinned host copies of dot results
+  int* flow_err = nullptr;   // device: a one-launch sweep gave up waiting
+  int* hflow_err = nullptr;  // pinned host copy
   double* capture = nullptr;         // when set: the start level's vector after the coarse correction (eager cycle)
   int capture_level = 0;
   // learned smoothers, one state per smoothed level (see learned.hip)

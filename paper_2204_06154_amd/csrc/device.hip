@@ -225,6 +225,48 @@ static void upload(mgm_ctx* c) {
           d.pc_rows[pc] += ps[s + 1] - ps[s];
         }
       d.pstart_host_slots = int(ps.size()) - 1;
+      {
+        // one-launch sweeps: the coupled slots of every slot (both directions:
+        // a slot that reads another must also be waited for by it) and the
+        // row range of each slot's patch colour
+        const int nsl = d.pstart_host_slots;
+        std::vector<int32_t> slot_of(n), scol(nsl);
+        for (int sl = 0; sl < nsl; ++sl)
+          for (int r = ps[sl]; r < ps[sl + 1]; ++r) slot_of[r] = sl;
+        for (int pc = 0; pc < h.npcolours; ++pc)
+          for (int sl = d.pc_start[pc]; sl < d.pc_start[pc + 1]; ++sl) scol[sl] = pc;
+        std::vector<std::vector<int32_t>> nbl(nsl);
+        for (int sl = 0; sl < nsl; ++sl)
+          for (int r = ps[sl]; r < ps[sl + 1]; ++r)
+            for (int k = rp[r]; k < rp[r + 1]; ++k) {
+              const int q = slot_of[cl[k]];
+              if (q != sl) {
+                nbl[sl].push_back(q);
+                nbl[q].push_back(sl);
+              }
+            }
+        bool ok = true;
+        std::vector<int32_t> nbptr(nsl + 1, 0), nb, crow(2 * size_t(nsl));
+        for (int sl = 0; sl < nsl; ++sl) {
+          auto& v = nbl[sl];
+          std::sort(v.begin(), v.end());
+          v.erase(std::unique(v.begin(), v.end()), v.end());
+          for (int q : v) ok = ok && scol[q] != scol[sl];
+          nb.insert(nb.end(), v.begin(), v.end());
+          nbptr[sl + 1] = int32_t(nb.size());
+          crow[2 * size_t(sl)] = ps[d.pc_start[scol[sl]]];
+          crow[2 * size_t(sl) + 1] = ps[d.pc_start[scol[sl] + 1]];
+        }
+        if (nb.empty()) nb.push_back(0);
+        d.flow_ok = ok && nsl > 0;
+        d.fl_nbptr = track(c, dupload(nbptr));
+        d.fl_nb = track(c, dupload(nb));
+        d.fl_crow = track(c, dupload(crow));
+        d.fl_ticket = track(c, dalloc<unsigned long long>(1));
+        d.fl_flag = track(c, dalloc<unsigned>(nsl));
+        HIPCHECK(hipMemset(d.fl_ticket, 0, sizeof(unsigned long long)));
+        HIPCHECK(hipMemset(d.fl_flag, 0, sizeof(unsigned) * nsl));
+      }
       d.pstart = track(c, dupload(ps));
       d.pncl = track(c, dupload(pn));
       d.lcol = track(c, dupload(lc));
@@ -282,6 +324,8 @@ static void upload(mgm_ctx* c) {
   for (auto& d : c->lv) maxblk = std::max<int64_t>(maxblk, nblk(int64_t(d.n) * 16) + 1);
   c->partial_len = maxblk;
   c->partial = track(c, dalloc<double>(maxblk));
+  c->flow_err = track(c, dalloc<int>(1));
+  HIPCHECK(hipMemset(c->flow_err, 0, sizeof(int)));
   HIPCHECK(hipMemset(c->mu, 0, sizeof(double) * p));
   HIPCHECK(hipMemset(c->rho, 0, sizeof(double) * (p + 1)));
 }
@@ -392,25 +436,37 @@ struct Prec<_Float16, float, true> {
     default: { constexpr int GG = 16; __VA_ARGS__; } break; \
   }
 
+// One patch colour (pc >= 0, one workgroup per patch of that colour) or, with
+// pc < 0, the whole sweep in one dataflow launch (one workgroup per patch).
 template <typename V, typename S, bool SC>
 static void gs_patch_launch(mgm_ctx* c, int j, int pc, bool reverse, bool border, const double* lam, hipStream_t st,
                             bool zero_guess = false) {
   using P = Prec<V, S, SC>;
   DevLevel& d = c->lv[j];
-  const int s0 = d.pc_start[pc], ns = d.pc_start[pc + 1] - s0;
+  const bool flow = pc < 0;
+  const int s0 = flow ? 0 : d.pc_start[pc];
+  const int ns = flow ? d.pstart_host_slots : d.pc_start[pc + 1] - s0;
   if (ns <= 0) return;
-#define GS_PATCH(WM, BD)                                                                                 \
-  hipLaunchKernelGGL((k_gs_patch<V, S, WM / kPatchG, SC, BD>), dim3(ns), dim3(kPatch * kPatchG), 0, st, s0, \
+  GsFlow fl{};
+  if (flow) fl = GsFlow{d.fl_ticket, d.fl_flag, d.fl_nbptr, d.fl_nb, d.fl_crow, c->flow_err, ns};
+#define GS_PATCH(WM, BD, FL)                                                                                 \
+  hipLaunchKernelGGL((k_gs_patch<V, S, WM / kPatchG, SC, BD, FL>), dim3(ns), dim3(kPatch * kPatchG), 0, st, s0, \
                      reverse ? 1 : 0, zero_guess ? 1 : 0, d.pw, d.pblock, d.pstart, \
                      d.pncl, d.lcol, P::pval(d), d.pcolidx, d.s16, P::dinv(d), P::f(d), P::e(d),  \
-                     P::b(d), lam)
+                     P::b(d), lam, fl)
+#define GS_PATCH_W(WM, FL) \
+  if (border) GS_PATCH(WM, true, FL); else GS_PATCH(WM, false, FL);
+#define GS_PATCH_F(WM) \
+  if (flow) { GS_PATCH_W(WM, true) } else { GS_PATCH_W(WM, false) }
   if (d.wmax == 32) {
-    if (border) GS_PATCH(32, true); else GS_PATCH(32, false);
+    GS_PATCH_F(32)
   } else if (d.wmax == 64) {
-    if (border) GS_PATCH(64, true); else GS_PATCH(64, false);
+    GS_PATCH_F(64)
   } else {
-    if (border) GS_PATCH(96, true); else GS_PATCH(96, false);
+    GS_PATCH_F(96)
   }
+#undef GS_PATCH_F
+#undef GS_PATCH_W
 #undef GS_PATCH
 }
 
@@ -437,6 +493,10 @@ static void gs_sweep(mgm_ctx* c, int j, bool reverse, bool border, const double*
   using P = Prec<V, S, SC>;
   DevLevel& d = c->lv[j];
   if (d.patched) {
+    if (c->p.gs_flow && d.flow_ok) {
+      gs_patch_launch<V, S, SC>(c, j, -1, reverse, border, lam, st, zero_guess);
+      return;
+    }
     const int npc = int(d.pc_start.size()) - 1;
     for (int t = 0; t < npc; ++t)
       gs_patch_launch<V, S, SC>(c, j, reverse ? npc - 1 - t : t, reverse, border, lam, st, zero_guess);
@@ -717,6 +777,8 @@ void ensure_ws(mgm_ctx* c, int restart) {
     c->kpart = track(c, dalloc<double>(kp));
     c->dh = track(c, dalloc<double>(1024));
     HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&c->hpin), 1024 * sizeof(double), hipHostMallocDefault));
+    HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&c->hflow_err), sizeof(int), hipHostMallocDefault));
+    *c->hflow_err = 0;
   }
   if (restart > c->ws_restart) {
     c->V = track(c, dalloc<double>(size_t(c->ld) * (restart + 1)));
@@ -784,8 +846,14 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
       HIPCHECK(hipMemcpyAsync(d_u + d0.n, x + d0.n, sizeof(double), hipMemcpyDeviceToDevice, st));
       HIPCHECK(hipMemcpyAsync(c->hpin, x + d0.n, sizeof(double), hipMemcpyDeviceToHost, st));
     }
+    HIPCHECK(hipMemcpyAsync(c->hflow_err, c->flow_err, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
     info.lambda = bord ? c->hpin[0] : 0.0;
+    if (*c->hflow_err) {
+      HIPCHECK(hipMemsetAsync(c->flow_err, 0, sizeof(int), st));
+      HIPCHECK(hipStreamSynchronize(st));
+      throw Error(MGM_E_SYNC, "a one-launch smoother sweep gave up waiting for a coupled patch");
+    }
     return s;
   };
   if (fnorm == 0.0) {
@@ -1172,7 +1240,7 @@ static void time_kernel_impl(mgm_ctx* c, int which, int level, int reps, hipStre
       double b = 0.0;
       for (int j = 0; j + 1 < p; ++j) {
         const DevLevel& d = c->lv[j];
-        const int per = d.patched ? int(d.pc_start.size()) - 1 : d.ncol;
+        const int per = d.patched ? (c->p.gs_flow && d.flow_ok ? 1 : int(d.pc_start.size()) - 1) : d.ncol;
         launches += int64_t(c->p.nu1 + c->p.nu2) * per;
         b += c->p.nu1 * gs_sweep_bytes(c, j, prec, false) + c->p.nu2 * gs_sweep_bytes(c, j, prec, bord);
       }
@@ -1193,6 +1261,12 @@ static void time_kernel_impl(mgm_ctx* c, int which, int level, int reps, hipStre
       };
       timed(sweeps, b);
       count += launches - 1;  // timed() counted the batch once
+    } else if (which == MGM_TK_GS && c->lv[level].patched && c->p.gs_flow && c->lv[level].flow_ok) {
+      timed([&] {
+        if (prec == MGM_FP64) gs_patch_launch<double, double, false>(c, level, -1, false, false, c->mu, st);
+        else if (prec == MGM_FP32) gs_patch_launch<float, float, false>(c, level, -1, false, false, c->mu, st);
+        else gs_patch_launch<_Float16, float, true>(c, level, -1, false, false, c->mu, st);
+      }, gs_sweep_bytes(c, level, prec, false));
     } else if (which == MGM_TK_GS && c->lv[level].patched) {
       DevLevel& d = c->lv[level];
       for (int pc = 0; pc + 1 < int(d.pc_start.size()); ++pc) {
@@ -1277,6 +1351,7 @@ void mgm_default_params(mgm_params* p) {
   p->device_setup = 1;
   p->gs_block = 256;
   p->cycle = MGM_CYCLE_V;
+  p->gs_flow = 1;
 }
 
 mgm_status mgm_setup(const double* h_xyz, const double* h_normals, int64_t n, const mgm_params* params, int32_t device,
@@ -1540,6 +1615,7 @@ void mgm_destroy(mgm_handle h) {
     if (h->cap) (void)hipStreamDestroy(h->cap);
     for (void* p : h->allocs) (void)hipFree(p);
     if (h->hpin) (void)hipHostFree(h->hpin);
+    if (h->hflow_err) (void)hipHostFree(h->hflow_err);
   }
   delete h;
 }
@@ -1557,6 +1633,7 @@ const char* mgm_status_str(mgm_status s) {
     case MGM_E_COARSE_SINGULAR: return "singular coarse operator";
     case MGM_E_BREAKDOWN: return "Krylov breakdown";
     case MGM_E_NONFINITE: return "non-finite value";
+    case MGM_E_SYNC: return "smoother sweep synchronisation failed";
   }
   return "unknown status";
 }

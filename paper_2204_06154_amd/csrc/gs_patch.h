@@ -28,17 +28,65 @@ namespace {
 // (slot * block * nw + i * block + t) * kPatchG + g, so the lanes of a
 // workgroup read consecutive addresses and the entry loads depend on no other
 // load; padding entries have value zero and a valid column.
+//
+// Dataflow variant (FLOW): one launch sweeps every patch colour of the level.
+// A patch may start once every coupled patch that precedes it in the sweep
+// order has finished (it reads their new values, and they must have read its
+// old ones), so the sweep is the same sequential GS order without a launch
+// boundary per colour. Workgroups take their position in the sweep order from
+// a ticket counter, so a workgroup only waits for workgroups that are already
+// running or done (no deadlock whatever the dispatch order); the counter is
+// never reset, and ticket / slots - 1 numbers the sweep, which is what each
+// patch's flag records when it finishes. Values that pass between workgroups
+// of the launch (the final stores of u, the halo loads, the flags) are
+// agent-scope atomic accesses, which the hardware keeps coherent across the
+// chip's L2 caches (stores written through, loads not served from a stale
+// line); a wave waits for its stores to complete before the barrier that
+// precedes the flag store, and the halo loads are issued after the barrier
+// that follows the wait, so no cache write-back or invalidation is needed.
+// A wait gives up after kFlowWaitTicks
+// ticks of the constant-rate real-time counter (2^24 ticks: ~0.17 s at its
+// usual 100 MHz, against waits of tens of microseconds) and raises the error
+// flag, so every workgroup ends.
 constexpr int kPatch = 256;
 constexpr int kPatchG = 4;
-template <typename V, typename S, int WL, bool SCALED, bool BORDER>
+constexpr unsigned long long kFlowWaitTicks = 1ull << 24;
+// s_waitcnt operand (gfx9 encoding) for vmcnt(0) with expcnt and lgkmcnt left
+// at their maxima: wait for this wave's outstanding vector memory operations
+constexpr int kWaitVmcnt0 = 0x0F70;
+
+struct GsFlow {
+  unsigned long long* ticket;    // sweeps * slots workgroups started so far
+  unsigned* flag;                // per slot: number of the last sweep it finished
+  const int32_t* nbptr;          // coupled slots of slot s: nb[nbptr[s] .. nbptr[s+1])
+  const int32_t* nb;
+  const int32_t* crow;           // slot s: rows [crow[2s], crow[2s+1]) of its patch colour
+  int* err;                      // set when a wait gave up
+  int nslot;
+};
+
+template <typename V, typename S, int WL, bool SCALED, bool BORDER, bool FLOW = false>
 __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
     int slot0, int reverse, int zero_guess, int nw, int block, const int32_t* __restrict__ pstart,
     const int32_t* __restrict__ pncl, const int32_t* __restrict__ lcol,
     const V* __restrict__ pval, const int32_t* __restrict__ pcol, const float* __restrict__ scale,
     const S* __restrict__ dinv, const S* __restrict__ f, S* u, const S* __restrict__ b,
-    const double* __restrict__ lam) {
+    const double* __restrict__ lam, GsFlow fl) {
   __shared__ S ul[kPatch];
-  const int slot = slot0 + blockIdx.x;
+  __shared__ unsigned s_ticket[2];
+  int slot = slot0 + blockIdx.x;
+  unsigned sweep = 0;
+  if (FLOW) {
+    if (threadIdx.x == 0) {
+      const unsigned long long tk =
+          __hip_atomic_fetch_add(fl.ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_ticket[0] = unsigned(tk % unsigned(fl.nslot));
+      s_ticket[1] = unsigned(tk / unsigned(fl.nslot)) + 1u;
+    }
+    __syncthreads();
+    slot = reverse ? fl.nslot - 1 - int(s_ticket[0]) : int(s_ticket[0]);
+    sweep = s_ticket[1];
+  }
   const int t = threadIdx.x / kPatchG;
   const int g = threadIdx.x % kPatchG;
   const bool slot_row = t < block;
@@ -63,8 +111,13 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
   // rows [upd_lo, upd_hi) hold current values (all rows unless zero_guess)
   int upd_lo = 0, upd_hi = INT_MAX;
   if (zero_guess) {
-    if (reverse) upd_lo = pstart[slot0 + gridDim.x];
-    else upd_hi = pstart[slot0];
+    if (FLOW) {
+      if (reverse) upd_lo = fl.crow[2 * slot + 1];
+      else upd_hi = fl.crow[2 * slot];
+    } else {
+      if (reverse) upd_lo = pstart[slot0 + gridDim.x];
+      else upd_hi = pstart[slot0];
+    }
   }
   const bool act = t < nr;
   const int row = r0 + t;
@@ -78,13 +131,41 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
     rhs = f[row];
     if (SCALED) sc = S(scale[row]);
     if (BORDER) rhs -= b[row] * S(*lam);
+  }
+  if (FLOW) {
+    // the first wave waits for the coupled slots that precede this one
+    if (threadIdx.x < 64) {
+      const int k1 = fl.nbptr[slot + 1];
+      for (int k = fl.nbptr[slot] + int(threadIdx.x); k < k1; k += 64) {
+        const int q = fl.nb[k];
+        if (reverse ? q > slot : q < slot) {
+          const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+          while (int(__hip_atomic_load(fl.flag + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - sweep) < 0) {
+            if (__builtin_amdgcn_s_memrealtime() - t0 > kFlowWaitTicks) {
+              __hip_atomic_store(fl.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (act) {
     S halo = S(0);
 #pragma unroll
     for (int i = 0; i < WL; ++i) {
       const bool live = i < nw;
       const bool in = live && unsigned(cc[i] - r0) < unsigned(nr);
       const bool cur = cc[i] >= upd_lo && cc[i] < upd_hi;
-      const S uv = (live && !in && cur) ? u[cc[i]] : S(0);
+      S uv = S(0);
+      if (FLOW) {
+        // agent-coherent load: the value another workgroup wrote through in this launch
+        if (live && !in && cur) uv = __hip_atomic_load(u + cc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        uv = (live && !in && cur) ? u[cc[i]] : S(0);
+      }
       halo += iv[i] * uv;
       ic[i] = in ? cc[i] - r0 : t;
       iv[i] = in ? iv[i] : S(0);
@@ -111,7 +192,16 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
     }
     __syncthreads();
   }
-  if (act && g == 0) u[row] = uown;
+  if (FLOW) {
+    // agent-coherent (write-through) stores; each wave waits for its own to
+    // complete before the barrier, after which the flag is raised
+    if (act && g == 0) __hip_atomic_store(u + row, uown, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(fl.flag + slot, sweep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else if (act && g == 0) {
+    u[row] = uown;
+  }
 }
 
 }  // namespace

@@ -1,0 +1,94 @@
+"""One-launch patch-blocked sweeps (gs_flow = 1) against one launch per patch
+colour (gs_flow = 0).
+
+Both run the same arithmetic in the same Gauss-Seidel order (patch colour,
+patch, local colour); only the synchronisation between patches differs, so
+every output must agree bit for bit. Repeated calls advance the sweep counter
+that the waits compare against, and both the forward and the backward sweep
+(and the zero-guess first sweep of a cycle) are covered, in every precision.
+"""
+import numpy as np
+import pytest
+
+import synth
+from paper_2204_06154_amd import mgm
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # screened sphere, forward pre-smoothing and backward post-smoothing
+    "sphere4096_fwd_bwd": (lambda: synth.sphere_workload(4096), {"post_smoother": "bwd"}),
+    # bordered torus Poisson (the benchmark's family at small N)
+    "torus8000": (lambda: synth.torus_workload(8000), {"n_min": 250}),
+    # GFD on a ragged-size sphere, W-cycle, two sweeps per side
+    "gfd9001_w": (lambda: synth.big_sphere_workload(9001), {"n_min": 150, "cycle": "W", "nu1": 2, "nu2": 2}),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES), ids=list(CASES))
+def pair(request):
+    make, extra = CASES[request.param]
+    wl = make()
+    wl.params.update(extra)
+    print(f"[gpu-gs-flow] setting up {request.param}", flush=True)
+    m0 = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, gs_flow=0), device=0)
+    m1 = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, gs_flow=1), device=0)
+    yield request.param, wl, m0, m1
+    m0.close()
+    m1.close()
+
+
+def _rhs(wl, m):
+    f = np.concatenate([wl.f, [0.0]]) if m.bordered else wl.f.copy()
+    return torch.tensor(f, device="cuda")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
+def test_cycles_identical(pair, prec):
+    name, wl, m0, m1 = pair
+    m0.set_precision(prec)
+    m1.set_precision(prec)
+    f = _rhs(wl, m0)
+    rng = np.random.default_rng(5)
+    for k in range(6):
+        r = f if k == 0 else torch.tensor(rng.standard_normal(m0.vec_len), device="cuda")
+        z0 = m0.vcycle(r)
+        z1 = m1.vcycle(r)
+        torch.cuda.synchronize()
+        assert torch.equal(z0, z1), (name, prec, k)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_solves_identical(pair, prec):
+    name, wl, m0, m1 = pair
+    m0.set_precision(prec)
+    m1.set_precision(prec)
+    f = _rhs(wl, m0)
+    u0, i0 = m0.solve(f, rtol=1e-10, maxit=200, history=True)
+    u1, i1 = m1.solve(f, rtol=1e-10, maxit=200, history=True)
+    assert i0["status"] == 0 and i1["status"] == 0
+    assert i0["iters"] == i1["iters"]
+    assert np.array_equal(i0["history"], i1["history"])
+    assert torch.equal(u0, u1)
+
+
+def test_single_sweeps_identical(pair):
+    """One smoothing sweep of every smoothed level, forward and backward, from
+    the same start vector and right-hand side."""
+    name, wl, m0, m1 = pair
+    m0.set_precision("fp64")
+    m1.set_precision("fp64")
+    sizes = [int(s) for s in m0.export("level_sizes")]
+    rng = np.random.default_rng(7)
+    for j, n in enumerate(sizes[:-1]):
+        x = rng.standard_normal(n)
+        b = rng.standard_normal(n)
+        for reverse in (False, True):
+            y0 = torch.tensor(x, device="cuda")
+            y1 = torch.tensor(x, device="cuda")
+            bt = torch.tensor(b, device="cuda")
+            m0.level_op(mgm.OP_SMOOTH, j, y0, b=bt, scalar=0.3, reverse=reverse)
+            m1.level_op(mgm.OP_SMOOTH, j, y1, b=bt, scalar=0.3, reverse=reverse)
+            torch.cuda.synchronize()
+            assert torch.equal(y0, y1), (name, j, reverse)

@@ -36,7 +36,7 @@ def test_params_struct_layout_matches_defaults():
     assert (p.disc, p.phs_order, p.poly_degree, p.stencil_size) == (mgm.RBFFD, 3, 3, 20)
     assert (p.interp_size, p.coarsen_factor, p.n_min, p.nu1, p.nu2) == (3, 4, 250, 1, 1)
     assert p.gfd_alpha == 4.0 and p.mu == 1.0 and p.use_graph == 1
-    assert p.device_weights == 1 and p.device_setup == 1 and p.cycle == 0
+    assert p.device_weights == 1 and p.device_setup == 1 and p.cycle == 0 and p.gs_flow == 1
 
 
 CASES = [
