@@ -81,7 +81,9 @@ typedef struct {
   double  mu;             /* screened: L = I - mu D, mu finite and non-zero */
   int32_t interp_size;    /* m, coarse stencil of the interpolation (Sec. 3); 3 */
   int32_t coarsen_factor; /* N_{j+1} = floor(N_j / factor) (Sec. 4.1); 4 */
-  int32_t n_min;          /* > 0: p = floor(log(N_1/N_min)/log 4) + 1 (Alg. 2) */
+  int32_t n_min;          /* > 0: p = floor(log(N_1/N_min)/log 4) + 1 (Alg. 2);
+                             setup rejects p < 2 (MGM_E_ARG): the cycle needs
+                             one smoothed level above the coarsest */
   int32_t n_coarse_max;   /* used when n_min == 0: coarsen while N_j > this */
   int32_t nu1, nu2;       /* pre/post smoothing sweeps (Alg. 3) */
   int32_t pre_smoother;   /* MGM_GS_FWD | MGM_GS_BWD */

@@ -122,7 +122,8 @@ def test_host_only_handle_rejects_device_calls():
 
 
 @pytest.mark.parametrize("mutate,status", [
-    ("dup", -5), ("nan", -9), ("mu0", -1), ("muinf", -1), ("tiny", -1), ("badstencil", -1), ("collinear", -4),
+    ("dup", -5), ("nan", -9), ("mu0", -1), ("muinf", -1), ("tiny", -1), ("onelevel", -1), ("badstencil", -1),
+    ("collinear", -4),
 ])
 def test_failure_injection(mutate, status):
     wl = synth.sphere_workload(800)
@@ -138,6 +139,11 @@ def test_failure_injection(mutate, status):
         p["mu"] = -np.inf
     elif mutate == "tiny":
         x, nrm = x[:10], nrm[:10]
+    elif mutate == "onelevel":
+        # N < 4 N_min: the level count of Alg. 2 is 1, no level to smooth
+        p.pop("n_coarse_max")
+        p["n_min"] = 250
+        x, nrm = x[:600], nrm[:600]
     elif mutate == "badstencil":
         p["stencil_size"] = 3   # fewer than the 6 degree-2 monomials
     elif mutate == "collinear":
