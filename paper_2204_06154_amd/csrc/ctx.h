@@ -166,6 +166,7 @@ struct mgm_ctx {
   double* hpin = nullptr;  // pinned host copies of dot results
   int* flow_err = nullptr;   // device: a one-launch sweep gave up waiting
   int* hflow_err = nullptr;  // pinned host copy
+  hipEvent_t step_done = nullptr;  // FGMRES: end of an Arnoldi step's kernels
   double* capture = nullptr;         // when set: the start level's vector after the coarse correction (eager cycle)
   int capture_level = 0;
   // learned smoothers, one state per smoothed level (see learned.hip)

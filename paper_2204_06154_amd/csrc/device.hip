@@ -779,6 +779,7 @@ void ensure_ws(mgm_ctx* c, int restart) {
     HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&c->hpin), 1024 * sizeof(double), hipHostMallocDefault));
     HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&c->hflow_err), sizeof(int), hipHostMallocDefault));
     *c->hflow_err = 0;
+    HIPCHECK(hipEventCreateWithFlags(&c->step_done, hipEventDisableTiming));
   }
   if (restart > c->ws_restart) {
     c->V = track(c, dalloc<double>(size_t(c->ld) * (restart + 1)));
@@ -803,6 +804,11 @@ void to_host(mgm_ctx* c, const double* d, int k, hipStream_t st) {
   HIPCHECK(hipMemcpyAsync(c->hpin, d, sizeof(double) * k, hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
 }
+
+// FGMRES queues the next step's preconditioner before reading this step's
+// dots unless the last residual reduction, repeated once more, would bring the
+// estimate within this factor of the tolerance.
+constexpr double kLookaheadMargin = 10.0;
 
 static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const mgm_solve_opts& o, mgm_solve_info& info,
                              double* hist, hipStream_t st) {
@@ -883,14 +889,26 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
       std::fill(gv.begin(), gv.end(), 0.0);
       gv[0] = beta;
       int k = 0;
-      for (int j = 0; j < m; ++j) {
+      // Preconditioner and operator of step j (they need only V_j, which the
+      // device writes itself). Step j + 1's are queued before the host waits
+      // for step j's dot products, so the device does not idle during the
+      // host's Hessenberg update; the stream order, and so every result, is
+      // the same. Not done when the residual trend says step j will converge
+      // (the queued work would then delay the solution update).
+      auto precond_apply = [&](int jj) {
         if (fused) {
           vcycle_core(c, st);
-          apply_from_vcycle(c, Z + j * ld, w, st);
+          apply_from_vcycle(c, Z + jj * ld, w, st);
         } else {
-          precond(c, V + j * ld, Z + j * ld, nullptr, st);
-          apply_A(c, Z + j * ld, w, st);
+          precond(c, V + jj * ld, Z + jj * ld, nullptr, st);
+          apply_A(c, Z + jj * ld, w, st);
         }
+      };
+      bool queued = false;
+      double last_est = beta / fnorm, rate = 1.0;
+      for (int j = 0; j < m; ++j) {
+        if (!queued) precond_apply(j);
+        queued = false;
         info.iters++;
         // CGS2: two projections, then the norm; the dots land on the host directly
         const double* hp = c->hpin;
@@ -901,7 +919,14 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
         mdot(c, n, w, ld, 1, w, c->dh + 512, st, c->hpin + 512);
         if (fused) normalise_to_vcycle(c, n, w, c->dh + 512, V + (j + 1) * ld, st);
         else hipLaunchKernelGGL(k_normalise, dim3(g), dim3(kBlock), 0, st, int(n), w, c->dh + 512, V + (j + 1) * ld);
-        host_wait(st);
+        if (j + 1 < m && info.iters < o.maxit && last_est * rate > kLookaheadMargin * tol) {
+          HIPCHECK(hipEventRecord(c->step_done, st));
+          precond_apply(j + 1);
+          queued = true;
+          HIPCHECK(hipEventSynchronize(c->step_done));
+        } else {
+          host_wait(st);
+        }
         for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = hp[i] + hp[256 + i];
         const double hn = std::sqrt(hp[512]);
         if (!std::isfinite(hn)) return finish(MGM_E_NONFINITE);
@@ -923,6 +948,8 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
         const double est = std::fabs(gv[j + 1]) / fnorm;
         info.rel_res_est = est;
         if (hist && hist_n <= o.maxit) hist[hist_n++] = est;
+        rate = last_est > 0.0 ? est / last_est : 1.0;
+        last_est = est;
         if (est <= tol || info.iters >= o.maxit || hn == 0.0) break;
       }
       for (int i = k - 1; i >= 0; --i) {
@@ -1616,6 +1643,7 @@ void mgm_destroy(mgm_handle h) {
     for (void* p : h->allocs) (void)hipFree(p);
     if (h->hpin) (void)hipHostFree(h->hpin);
     if (h->hflow_err) (void)hipHostFree(h->hflow_err);
+    if (h->step_done) (void)hipEventDestroy(h->step_done);
   }
   delete h;
 }
