@@ -98,7 +98,7 @@ struct DevLevel {
   std::vector<int64_t> rowlen_prefix;  // host copy of the permuted row pointer
   // patch-blocked smoother (see k_gs_patch)
   bool patched = false;
-  int wmax = 0;                      // register width class of the patch kernel (32/64/96)
+  int wmax = 0;                      // register width class of the patch kernels (24, 32, .., 96)
   std::vector<int> pc_start;         // slot range of each patch colour (host)
   std::vector<int64_t> pc_nnz;       // stored entries (incl. padding) per patch colour (host)
   std::vector<int32_t> pc_rows;      // rows per patch colour (host)

@@ -216,7 +216,9 @@ static void upload(mgm_ctx* c) {
       d.pc_start.resize(h.npcolours + 1);
       ps.push_back(n);
       for (int pos = 0; pos < n; ++pos) lc[pos] = h.lcolour[order[pos]];
-      d.wmax = maxw <= 32 ? 32 : (maxw <= 64 ? 64 : 96);
+      // width class of the patch kernels: entries per row rounded up to a
+      // multiple of 8 (24 .. 96), so a row carries few padding entries
+      d.wmax = std::max(24, (maxw + 7) / 8 * 8);
       d.pc_nnz.assign(h.npcolours, 0);
       d.pc_rows.assign(h.npcolours, 0);
       for (int pc = 0; pc < h.npcolours; ++pc)
@@ -458,12 +460,17 @@ static void gs_patch_launch(mgm_ctx* c, int j, int pc, bool reverse, bool border
   if (border) GS_PATCH(WM, true, FL); else GS_PATCH(WM, false, FL);
 #define GS_PATCH_F(WM) \
   if (flow) { GS_PATCH_W(WM, true) } else { GS_PATCH_W(WM, false) }
-  if (d.wmax == 32) {
-    GS_PATCH_F(32)
-  } else if (d.wmax == 64) {
-    GS_PATCH_F(64)
-  } else {
-    GS_PATCH_F(96)
+  switch (d.wmax) {
+    case 24: GS_PATCH_F(24) break;
+    case 32: GS_PATCH_F(32) break;
+    case 40: GS_PATCH_F(40) break;
+    case 48: GS_PATCH_F(48) break;
+    case 56: GS_PATCH_F(56) break;
+    case 64: GS_PATCH_F(64) break;
+    case 72: GS_PATCH_F(72) break;
+    case 80: GS_PATCH_F(80) break;
+    case 88: GS_PATCH_F(88) break;
+    default: GS_PATCH_F(96) break;
   }
 #undef GS_PATCH_F
 #undef GS_PATCH_W
@@ -481,9 +488,18 @@ static void rowop_patch_launch(const DevLevel& d, const V* val, const S* f, cons
   hipLaunchKernelGGL((k_rowop_patch<V, S, X, WM / kPatchG, SC, MODE, BDOT, BORDER>), dim3(ns), dim3(kPatch * kPatchG), \
                      0, st, d.pw, d.pblock, d.pstart, val, d.pcolidx, d.s16, f, x, out, b, lam, partial, dinv, omega, \
                      xcopy, d.n)
-  if (d.wmax == 32) ROWOP(32);
-  else if (d.wmax == 64) ROWOP(64);
-  else ROWOP(96);
+  switch (d.wmax) {
+    case 24: ROWOP(24); break;
+    case 32: ROWOP(32); break;
+    case 40: ROWOP(40); break;
+    case 48: ROWOP(48); break;
+    case 56: ROWOP(56); break;
+    case 64: ROWOP(64); break;
+    case 72: ROWOP(72); break;
+    case 80: ROWOP(80); break;
+    case 88: ROWOP(88); break;
+    default: ROWOP(96); break;
+  }
 #undef ROWOP
 }
 
