@@ -36,7 +36,7 @@ namespace {
 // boundary per colour. Workgroups take their position in the sweep order from
 // a ticket counter, so a workgroup only waits for workgroups that are already
 // running or done (no deadlock whatever the dispatch order); the counter is
-// never reset, and ticket / slots - 1 numbers the sweep, which is what each
+// never reset, and ticket / slots + 1 numbers the sweep, which is what each
 // patch's flag records when it finishes. Values that pass between workgroups
 // of the launch (the final stores of u, the halo loads, the flags) are
 // agent-scope atomic accesses, which the hardware keeps coherent across the
