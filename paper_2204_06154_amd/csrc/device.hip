@@ -163,6 +163,7 @@ static void upload(mgm_ctx* c) {
       // width w (a multiple of kPatchG) and a fixed stride of block rows, so
       // an entry's address follows from (slot, entry, row) alone.
       const int block = c->p.gs_block;
+      if (block < 1 || block > kPatch) throw Error(MGM_E_ARG, "gs_block exceeds the patch kernels' rows per workgroup");
       std::vector<int32_t> ps, pn, lc(n), pci;
       std::vector<double> pv;
       std::vector<int32_t> prow;
@@ -485,7 +486,7 @@ static void rowop_patch_launch(const DevLevel& d, const V* val, const S* f, cons
                                const S* omega = nullptr, S* xcopy = nullptr) {
   const unsigned ns = unsigned(d.pstart_host_slots);
 #define ROWOP(WM)                                                                                           \
-  hipLaunchKernelGGL((k_rowop_patch<V, S, X, WM / kPatchG, SC, MODE, BDOT, BORDER>), dim3(ns), dim3(kPatch * kPatchG), \
+  hipLaunchKernelGGL((k_rowop_patch<V, S, X, WM / kPatchG, SC, MODE, BDOT, BORDER>), dim3(2 * ns), dim3(kRowHalf * kPatchG), \
                      0, st, d.pw, d.pblock, d.pstart, val, d.pcolidx, d.s16, f, x, out, b, lam, partial, dinv, omega, \
                      xcopy, d.n)
   switch (d.wmax) {
@@ -542,7 +543,7 @@ static void residual_restrict(mgm_ctx* c, int j, hipStream_t st, bool with_mu = 
   const double* mu = c->mu + j;
   unsigned g;  // residual blocks = partial sums of b . e
   if (d.patched) {
-    g = unsigned(d.pstart_host_slots);
+    g = 2u * unsigned(d.pstart_host_slots);  // one partial per half slot
     if (bord && with_mu) rowop_patch_launch<V, S, SC, kRowResidual, true, true>(d, P::pval(d), P::f(d), P::e(d), P::res(d), P::b(d), mu, c->partial, st);
     else if (bord) rowop_patch_launch<V, S, SC, kRowResidual, true, false>(d, P::pval(d), P::f(d), P::e(d), P::res(d), P::b(d), nullptr, c->partial, st);
     else rowop_patch_launch<V, S, SC, kRowResidual, false, false>(d, P::pval(d), P::f(d), P::e(d), P::res(d), P::b(d), nullptr, c->partial, st);

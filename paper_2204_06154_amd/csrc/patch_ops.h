@@ -1,7 +1,10 @@
 // Whole-level row operators that read the operator from the patch ELL of a
-// patch-blocked level (the smoother's storage): one workgroup per patch slot,
-// kPatchG lanes per row, so every entry load of a workgroup covers 1024
-// consecutive elements and the operator streams at full width.
+// patch-blocked level (the smoother's storage): one workgroup per half patch
+// slot (kRowHalf rows), kPatchG lanes per row, so every entry load of a
+// workgroup covers 512 consecutive elements and the operator streams at full
+// width. Half slots give twice as many workgroups as slots, so the last round
+// of workgroups on the chip is short (with one per slot, 625 slots of the
+// fine torus level ran as three rounds of 256 for 2.4 rounds of work).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,15 +30,16 @@ constexpr int kRowRichardson = 2;
 // given, every row also writes S(x_i) there (and, bordered, xcopy[tail] =
 // *lam): the FGMRES step uses this to widen the preconditioner's FP32 output
 // while applying the operator to it.
+constexpr int kRowHalf = kPatch / 2;
 template <typename V, typename S, typename X, int WL, bool SCALED, int MODE, bool BDOT, bool BORDER>
-__global__ __launch_bounds__(kPatch * kPatchG) void k_rowop_patch(
+__global__ __launch_bounds__(kRowHalf * kPatchG) void k_rowop_patch(
     int nw, int block, const int32_t* __restrict__ pstart, const V* __restrict__ pval,
     const int32_t* __restrict__ pcol, const float* __restrict__ scale, const S* __restrict__ f,
     const X* __restrict__ x, S* __restrict__ out, const S* __restrict__ b, const double* __restrict__ lam,
     double* __restrict__ partial, const S* __restrict__ dinv, const S* __restrict__ omega,
     S* __restrict__ xcopy, int tail) {
-  const int slot = blockIdx.x;
-  const int t = threadIdx.x / kPatchG;
+  const int slot = blockIdx.x >> 1;
+  const int t = (blockIdx.x & 1) * kRowHalf + int(threadIdx.x) / kPatchG;
   const int g = threadIdx.x % kPatchG;
   const bool slot_row = t < block;
   const int tt = slot_row ? t : 0;  // lanes past the slot's rows read row 0's entries (in bounds, unused)
@@ -56,15 +60,14 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_rowop_patch(
   const int nr = pstart[slot + 1] - r0;
   const bool act = t < nr;
   const int row = r0 + t;
-  // The slot's own rows are a contiguous range of x: stage it in LDS and take
-  // the in-patch columns (most of them) from there; only the halo columns go
-  // to the cache hierarchy, and those loads are issued before the barrier.
+  // The slot's own rows are a contiguous range of x: stage it (both halves'
+  // rows) in LDS and take the in-patch columns (most of them) from there; only
+  // the halo columns go to the cache hierarchy, and those loads are issued
+  // before the barrier.
   __shared__ S xl[kPatch];
-  if (act && g == 0) {
-    xl[t] = S(x[row]);
-    if (xcopy) xcopy[row] = S(x[row]);
-  }
-  if (BORDER && xcopy && slot == 0 && threadIdx.x == 0) xcopy[tail] = S(*lam);
+  for (int q = int(threadIdx.x); q < nr; q += int(blockDim.x)) xl[q] = S(x[r0 + q]);
+  if (xcopy && act && g == 0) xcopy[row] = S(x[row]);
+  if (BORDER && xcopy && blockIdx.x == 0 && threadIdx.x == 0) xcopy[tail] = S(*lam);
   // Halo gathers are issued unconditionally, so that no branch makes a load
   // wait for the one before it; in-patch and padding entries read the row's
   // own value instead (one cache line) and are masked out of the sums. Each
@@ -80,7 +83,7 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_rowop_patch(
 #pragma unroll
     for (int i = 0; i < WL; i += 2) {
       if (i < nw && unsigned(cc[i] - r0) >= unsigned(nr)) a0 += iv[i] * S(xv[i]);
-      if (i + 1 < nw && unsigned(cc[i + 1] - r0) >= unsigned(nr)) a1 += iv[i + 1] * S(xv[i + 1]);
+      if (i + 1 < WL && i + 1 < nw && unsigned(cc[i + 1] - r0) >= unsigned(nr)) a1 += iv[i + 1] * S(xv[i + 1]);
     }
   }
   __syncthreads();
@@ -91,7 +94,7 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_rowop_patch(
 #pragma unroll
     for (int i = 0; i < WL; i += 2) {
       if (i < nw && unsigned(cc[i] - r0) < unsigned(nr)) a0 += iv[i] * lv[i];
-      if (i + 1 < nw && unsigned(cc[i + 1] - r0) < unsigned(nr)) a1 += iv[i + 1] * lv[i + 1];
+      if (i + 1 < WL && i + 1 < nw && unsigned(cc[i + 1] - r0) < unsigned(nr)) a1 += iv[i + 1] * lv[i + 1];
     }
   }
   S acc = group_sum<kPatchG>(a0 + a1);
@@ -109,15 +112,15 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_rowop_patch(
       out[row] = acc;
     }
   }
-  if (BDOT) {
-    __shared__ double sh[kPatch * kPatchG];
+  if (BDOT) {  // one partial per workgroup (two per slot)
+    __shared__ double sh[kRowHalf * kPatchG];
     sh[threadIdx.x] = bx;
     __syncthreads();
-    for (int s = kPatch * kPatchG / 2; s > 0; s >>= 1) {
+    for (int s = kRowHalf * kPatchG / 2; s > 0; s >>= 1) {
       if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
       __syncthreads();
     }
-    if (threadIdx.x == 0) partial[slot] = sh[0];
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
   }
 }
 
