@@ -912,13 +912,14 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
       // host's Hessenberg update; the stream order, and so every result, is
       // the same. Not done when the residual trend says step j will converge
       // (the queued work would then delay the solution update).
+      // The new vector A z_j is built in place in V's column j + 1.
       auto precond_apply = [&](int jj) {
         if (fused) {
           vcycle_core(c, st);
-          apply_from_vcycle(c, Z + jj * ld, w, st);
+          apply_from_vcycle(c, Z + jj * ld, V + (jj + 1) * ld, st);
         } else {
           precond(c, V + jj * ld, Z + jj * ld, nullptr, st);
-          apply_A(c, Z + jj * ld, w, st);
+          apply_A(c, Z + jj * ld, V + (jj + 1) * ld, st);
         }
       };
       bool queued = false;
@@ -927,15 +928,28 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
         if (!queued) precond_apply(j);
         queued = false;
         info.iters++;
-        // CGS2: two projections, then the norm; the dots land on the host directly
+        // CGS2: two projections; the second one's dots include |w|^2 (w is
+        // column j + 1), from which the norm of the projected vector follows,
+        // and the second update is fused with the normalisation. The dots
+        // land on the host directly.
         const double* hp = c->hpin;
-        mdot(c, n, V, ld, j + 1, w, c->dh, st, c->hpin);
-        hipLaunchKernelGGL(k_mupdate, dim3(g), dim3(kBlock), 0, st, int(n), V, ld, j + 1, c->dh, w);
-        mdot(c, n, V, ld, j + 1, w, c->dh + 256, st, c->hpin + 256);
-        hipLaunchKernelGGL(k_mupdate, dim3(g), dim3(kBlock), 0, st, int(n), V, ld, j + 1, c->dh + 256, w);
-        mdot(c, n, w, ld, 1, w, c->dh + 512, st, c->hpin + 512);
-        if (fused) normalise_to_vcycle(c, n, w, c->dh + 512, V + (j + 1) * ld, st);
-        else hipLaunchKernelGGL(k_normalise, dim3(g), dim3(kBlock), 0, st, int(n), w, c->dh + 512, V + (j + 1) * ld);
+        double* wj = V + (j + 1) * ld;
+        mdot(c, n, V, ld, j + 1, wj, c->dh, st, c->hpin);
+        hipLaunchKernelGGL(k_mupdate, dim3(g), dim3(kBlock), 0, st, int(n), V, ld, j + 1, c->dh, wj);
+        mdot(c, n, V, ld, j + 2, wj, c->dh + 256, st, c->hpin + 256);
+        if (fused) {
+          DevLevel& dl = c->lv[0];
+          double* rho = c->p.problem == MGM_POISSON ? c->rho : nullptr;
+          if (c->p.precision == MGM_FP64)
+            hipLaunchKernelGGL((k_mupdate_normalise<double>), dim3(g), dim3(kBlock), 0, st, int(n), V, ld, j + 1,
+                               c->dh + 256, wj, dl.f64, dl.n, rho);
+          else
+            hipLaunchKernelGGL((k_mupdate_normalise<float>), dim3(g), dim3(kBlock), 0, st, int(n), V, ld, j + 1,
+                               c->dh + 256, wj, dl.f32, dl.n, rho);
+        } else {
+          hipLaunchKernelGGL((k_mupdate_normalise<double>), dim3(g), dim3(kBlock), 0, st, int(n), V, ld, j + 1,
+                             c->dh + 256, wj, (double*)nullptr, 0, (double*)nullptr);
+        }
         if (j + 1 < m && info.iters < o.maxit && last_est * rate > kLookaheadMargin * tol) {
           HIPCHECK(hipEventRecord(c->step_done, st));
           precond_apply(j + 1);
@@ -944,8 +958,13 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
         } else {
           host_wait(st);
         }
-        for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = hp[i] + hp[256 + i];
-        const double hn = std::sqrt(hp[512]);
+        double hh = 0.0;
+        for (int i = 0; i <= j; ++i) {
+          H[size_t(i) * m + j] = hp[i] + hp[256 + i];
+          hh += hp[256 + i] * hp[256 + i];
+        }
+        const double hn2 = hp[256 + j + 1] - hh;
+        const double hn = hn2 > 0.0 ? std::sqrt(hn2) : (std::isfinite(hn2) ? 0.0 : hn2);
         if (!std::isfinite(hn)) return finish(MGM_E_NONFINITE);
         H[size_t(j + 1) * m + j] = hn;
         for (int i = 0; i < j; ++i) {

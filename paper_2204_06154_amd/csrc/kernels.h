@@ -316,6 +316,34 @@ __global__ __launch_bounds__(kBlock) void k_normalise_cast(int n, const double* 
   else if (rho && i == nf) *rho = v;
 }
 
+// Second Gram-Schmidt update fused with the normalisation: w -= sum_{t<k}
+// V[t] h[t], then w /= s with s^2 = h[k] - sum_{t<k} h[t]^2, where h[k] = |w|^2
+// before this update (the updated w is orthogonal to V[0..k), so its squared
+// norm is that difference; after the first projection the h[t] are small, so
+// it does not cancel). s <= 0 gives w = 0. With f0 given, the result is also
+// handed to the V-cycle as in k_normalise_cast. w is updated in place.
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_mupdate_normalise(int n, const double* __restrict__ V, int64_t ld, int k,
+                                                              const double* __restrict__ h, double* __restrict__ w,
+                                                              S* __restrict__ f0, int nf, double* __restrict__ rho) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double acc = w[i];
+  double hh = 0.0;
+  for (int t = 0; t < k; ++t) {
+    acc -= V[t * ld + i] * h[t];
+    hh += h[t] * h[t];
+  }
+  const double s2 = h[k] - hh;
+  const double s = s2 > 0.0 ? sqrt(s2) : 0.0;
+  const double v = s > 0.0 ? acc / s : 0.0;
+  w[i] = v;
+  if (f0) {
+    if (i < nf) f0[i] = S(v);
+    else if (rho && i == nf) *rho = v;
+  }
+}
+
 // BiCGSTAB updates with the scalars read from device memory (so the host
 // need not see them first). sc holds, for the current step k and the
 // previous one (slot parity), rho = rhat.r, rv = rhat.v, st = s.t, tt = t.t:
