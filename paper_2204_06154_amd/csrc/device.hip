@@ -728,13 +728,16 @@ static void apply_from_vcycle(mgm_ctx* c, double* z, double* y, hipStream_t st) 
   DevLevel& d = c->lv[0];
   const bool bord = c->p.problem == MGM_POISSON;
   if (c->p.precision == MGM_FP64) {
-    if (bord) rowop_patch_launch<double, double, false, kRowApply, false, true, double>(d, d.pv64, nullptr, d.e64, y, d.b64, c->mu, nullptr, st, nullptr, nullptr, z);
+    if (bord) rowop_patch_launch<double, double, false, kRowApply, true, true, double>(d, d.pv64, nullptr, d.e64, y, d.b64, c->mu, c->partial, st, nullptr, nullptr, z);
     else rowop_patch_launch<double, double, false, kRowApply, false, false, double>(d, d.pv64, nullptr, d.e64, y, d.b64, c->mu, nullptr, st, nullptr, nullptr, z);
   } else {
-    if (bord) rowop_patch_launch<double, double, false, kRowApply, false, true, float>(d, d.pv64, nullptr, d.e32, y, d.b64, c->mu, nullptr, st, nullptr, nullptr, z);
+    if (bord) rowop_patch_launch<double, double, false, kRowApply, true, true, float>(d, d.pv64, nullptr, d.e32, y, d.b64, c->mu, c->partial, st, nullptr, nullptr, z);
     else rowop_patch_launch<double, double, false, kRowApply, false, false, float>(d, d.pv64, nullptr, d.e32, y, d.b64, c->mu, nullptr, st, nullptr, nullptr, z);
   }
-  if (bord) mdot(c, d.n, d.b64, 0, 1, z, y + d.n, st);  // constraint row b . z
+  // constraint row b . z from the operator pass's partial sums (two per slot)
+  if (bord)
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, 1, 2 * d.pstart_host_slots, c->partial, y + d.n,
+                       (double*)nullptr);
 }
 
 // y = A x (FP64 fine operator, permuted order; bordered tail at index n).

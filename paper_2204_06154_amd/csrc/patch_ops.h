@@ -20,7 +20,8 @@ namespace {
 //   b_i * (*lam) when BORDER, and with BDOT partial[slot] = sum over the
 //   slot's rows of b_i x_i (fixed tree).
 // MODE kRowApply:   out = A x, plus b_i * (*lam) when BORDER (the bordered
-//   operator's multiplier column).
+//   operator's multiplier column); with BDOT the partial sums of b_i x_i as
+//   above (its constraint row).
 // MODE kRowRichardson: out = x + omega_i dinv_i (f - A x), one step of the
 //   learned per-node smoother (out and x distinct).
 constexpr int kRowResidual = 0;
@@ -110,6 +111,7 @@ __global__ __launch_bounds__(kRowHalf * kPatchG) void k_rowop_patch(
     } else {
       if (BORDER) acc += b[row] * S(*lam);
       out[row] = acc;
+      if (BDOT) bx = double(b[row]) * double(xl[t]);  // the bordered constraint row b . x
     }
   }
   if (BDOT) {  // one partial per workgroup (two per slot)
