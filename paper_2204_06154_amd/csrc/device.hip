@@ -723,8 +723,10 @@ static void normalise_to_vcycle(mgm_ctx* c, int64_t n, const double* x, const do
 }
 
 // z = widened V-cycle output and y = A z in one pass over the operator
-// (patch-blocked fine level); the bordered constraint row follows as a dot.
-static void apply_from_vcycle(mgm_ctx* c, double* z, double* y, hipStream_t st) {
+// (patch-blocked fine level); the bordered constraint row y[n] = b . z is left
+// as partial sums in c->partial (two per slot) when defer_border, else summed
+// by a reduction launch.
+static void apply_from_vcycle(mgm_ctx* c, double* z, double* y, hipStream_t st, bool defer_border = false) {
   DevLevel& d = c->lv[0];
   const bool bord = c->p.problem == MGM_POISSON;
   if (c->p.precision == MGM_FP64) {
@@ -735,7 +737,7 @@ static void apply_from_vcycle(mgm_ctx* c, double* z, double* y, hipStream_t st) 
     else rowop_patch_launch<double, double, false, kRowApply, false, false, float>(d, d.pv64, nullptr, d.e32, y, d.b64, c->mu, nullptr, st, nullptr, nullptr, z);
   }
   // constraint row b . z from the operator pass's partial sums (two per slot)
-  if (bord)
+  if (bord && !defer_border)
     hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, 1, 2 * d.pstart_host_slots, c->partial, y + d.n,
                        (double*)nullptr);
 }
@@ -916,10 +918,13 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
       // the same. Not done when the residual trend says step j will converge
       // (the queued work would then delay the solution update).
       // The new vector A z_j is built in place in V's column j + 1.
+      // Bordered: the new vector's constraint entry stays as partial sums
+      // until the first projection's reduction (k_reduce_partials_border).
+      const bool defer = fused && bord;
       auto precond_apply = [&](int jj) {
         if (fused) {
           vcycle_core(c, st);
-          apply_from_vcycle(c, Z + jj * ld, V + (jj + 1) * ld, st);
+          apply_from_vcycle(c, Z + jj * ld, V + (jj + 1) * ld, st, defer);
         } else {
           precond(c, V + jj * ld, Z + jj * ld, nullptr, st);
           apply_A(c, Z + jj * ld, V + (jj + 1) * ld, st);
@@ -937,7 +942,15 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
         // land on the host directly.
         const double* hp = c->hpin;
         double* wj = V + (j + 1) * ld;
-        mdot(c, n, V, ld, j + 1, wj, c->dh, st, c->hpin);
+        if (defer) {
+          const int64_t ni = d0.n;  // interior rows; the border entry comes from the partial sums
+          const int nb = int(std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (ni + 2047) / 2048)));
+          hipLaunchKernelGGL(k_mdot_partial, dim3(nb, j + 1), dim3(kBlock), 0, st, int(ni), V, ld, wj, c->kpart);
+          hipLaunchKernelGGL(k_reduce_partials_border, dim3(j + 1), dim3(kBlock), 0, st, j + 1, nb, c->kpart, c->dh,
+                             c->hpin, c->partial, 2 * d0.pstart_host_slots, V, ld, int(ni), wj);
+        } else {
+          mdot(c, n, V, ld, j + 1, wj, c->dh, st, c->hpin);
+        }
         hipLaunchKernelGGL(k_mupdate, dim3(g), dim3(kBlock), 0, st, int(n), V, ld, j + 1, c->dh, wj);
         mdot(c, n, V, ld, j + 2, wj, c->dh + 256, st, c->hpin + 256);
         if (fused) {

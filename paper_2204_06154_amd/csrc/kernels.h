@@ -271,6 +271,34 @@ __global__ __launch_bounds__(kBlock) void k_reduce_partials(int k, int nb, const
 }
 
 
+// k_reduce_partials for dots over the interior rows [0, nrow) of a bordered
+// vector y whose last entry y[nrow] is still held as nc partial sums cpart
+// (the operator pass's constraint row): every block sums them in the same
+// order (block 0 stores y[nrow]) and adds the border term V[t][nrow] y[nrow]
+// to its dot.
+__global__ __launch_bounds__(kBlock) void k_reduce_partials_border(int k, int nb, const double* __restrict__ partial,
+                                                                   double* __restrict__ out, double* __restrict__ host_out,
+                                                                   const double* __restrict__ cpart, int nc,
+                                                                   const double* __restrict__ V, int64_t ld, int nrow,
+                                                                   double* __restrict__ y) {
+  const int t = blockIdx.x;
+  if (t >= k) return;
+  __shared__ double sh[kBlock];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kBlock) acc += partial[t * nb + i];
+  const double r = block_sum(acc, sh);
+  __syncthreads();
+  double cacc = 0.0;
+  for (int i = threadIdx.x; i < nc; i += kBlock) cacc += cpart[i];
+  const double cy = block_sum(cacc, sh);
+  if (threadIdx.x == 0) {
+    if (t == 0) y[nrow] = cy;
+    const double v = r + V[t * ld + nrow] * cy;
+    out[t] = v;
+    if (host_out) host_out[t] = v;
+  }
+}
+
 // w[i] -= sum_{t<k} V[t][i] * h[t]
 __global__ __launch_bounds__(kBlock) void k_mupdate(int n, const double* __restrict__ V, int64_t ld, int k,
                                                     const double* __restrict__ h, double* __restrict__ w) {
