@@ -50,7 +50,7 @@ HBM_PEAK_GBS = 8000.0
 # `bench.py --workload traffic` (summary and commands in
 # profiles/gs_patch_torus160k_traffic.md): bytes per launch, valid only for
 # the kernel source it was measured on (SHA-256 over lane_ops.h + gs_patch.h).
-GS_TRAFFIC = {"source_sha256": "3b9def0c998ff9e09a5ca3a668b8293e548cd3cc9747ea6b2773183f06ca592e", "bytes_per_launch": 23423986,
+GS_TRAFFIC = {"source_sha256": "3b9def0c998ff9e09a5ca3a668b8293e548cd3cc9747ea6b2773183f06ca592e", "bytes_per_launch": 23420857,
               "summary": "profiles/gs_patch_torus160k_traffic.md"}
 
 
