@@ -843,7 +843,6 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
   double* f = c->vecs;
   double* x = c->vecs + ld;
   double* r = c->vecs + 2 * ld;
-  double* w = c->vecs + 3 * ld;
   const unsigned g = nblk(n);
   // permute inputs
   hipLaunchKernelGGL((k_gather<double, double>), dim3(nblk(d0.n)), dim3(kBlock), 0, st, d0.n, d0.perm, d_f, f, nullptr);
