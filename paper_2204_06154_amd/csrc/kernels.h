@@ -224,7 +224,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int n, const int32_t* __rest
 // Deterministic two-stage reductions: stage 1 writes one partial per block
 // (grid.y selects the vector), stage 2 sums the partials in block order.
 constexpr int kRedBlocks = 512;
-constexpr int kMaxDots = 200;  // vectors of one dot launch (the FGMRES restart limit)
+// vectors of one dot launch: the FGMRES restart limit (200) plus one, since the
+// second projection of the last step also takes |w|^2
+constexpr int kMaxDots = 201;
 
 // Fixed-tree sum over the kBlock threads of a block (result in thread 0).
 __device__ __forceinline__ double block_sum(double v, double* sh) {

@@ -324,6 +324,11 @@ def test_solver_error_paths(case):
     assert info["status"] == 1 and info["iters"] == 1
     u, info = m.solve(_dev(np.zeros_like(f)))
     assert info["status"] == 0 and float(torch.abs(u).max()) == 0.0
+    # the longest restart runs to its end (its last step's second projection
+    # takes 201 dots) and reports "not converged" against an unreachable tolerance
+    u, info = m.solve(_dev(f), restart=200, maxit=200, rtol=1e-30)
+    assert info["status"] == 1 and info["iters"] == 200
+    assert np.isfinite(_host(u)).all()
 
 
 def test_time_kernel_modes(case):
