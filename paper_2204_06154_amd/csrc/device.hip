@@ -323,8 +323,13 @@ static void upload(mgm_ctx* c) {
   c->rho = track(c, dalloc<double>(p + 1));
   c->mu = track(c, dalloc<double>(p));  // multiplier correction of every level (mu[0]: the fine one)
   c->lam = track(c, dalloc<double>(1));
+  // partial sums: one per block of a plain-level residual (at most 16 lanes a
+  // row), or one per half slot of a patch-blocked level's row operators
   int64_t maxblk = 1;
-  for (auto& d : c->lv) maxblk = std::max<int64_t>(maxblk, nblk(int64_t(d.n) * 16) + 1);
+  for (auto& d : c->lv) {
+    maxblk = std::max<int64_t>(maxblk, nblk(int64_t(d.n) * 16) + 1);
+    if (d.patched) maxblk = std::max<int64_t>(maxblk, 2 * int64_t(d.pstart_host_slots) + 1);
+  }
   c->partial_len = maxblk;
   c->partial = track(c, dalloc<double>(maxblk));
   c->flow_err = track(c, dalloc<int>(1));
@@ -531,6 +536,12 @@ static void gs_sweep(mgm_ctx* c, int j, bool reverse, bool border, const double*
   }
 }
 
+// The row operators of level j write one partial sum per block into
+// c->partial; its length is fixed at setup from every level's grid.
+static void check_partials(const mgm_ctx* c, int64_t blocks) {
+  if (blocks > c->partial_len) throw Error(MGM_E_ARG, "row-operator grid exceeds the partial-sum buffer");
+}
+
 // res_j = f_j - L_j e_j (bordered: partial sums of b_j . e_j; with_mu: a
 // level continuing from an earlier iterate also subtracts b_j mu_j) then
 // f_{j+1} = R_j res_j (bordered: rho_{j+1} = rho_j - b_j . e_j).
@@ -544,11 +555,13 @@ static void residual_restrict(mgm_ctx* c, int j, hipStream_t st, bool with_mu = 
   unsigned g;  // residual blocks = partial sums of b . e
   if (d.patched) {
     g = 2u * unsigned(d.pstart_host_slots);  // one partial per half slot
+    check_partials(c, g);
     if (bord && with_mu) rowop_patch_launch<V, S, SC, kRowResidual, true, true>(d, P::pval(d), P::f(d), P::e(d), P::res(d), P::b(d), mu, c->partial, st);
     else if (bord) rowop_patch_launch<V, S, SC, kRowResidual, true, false>(d, P::pval(d), P::f(d), P::e(d), P::res(d), P::b(d), nullptr, c->partial, st);
     else rowop_patch_launch<V, S, SC, kRowResidual, false, false>(d, P::pval(d), P::f(d), P::e(d), P::res(d), P::b(d), nullptr, c->partial, st);
   } else {
     g = nblk(int64_t(d.n) * d.G);
+    check_partials(c, g);
     const double* lam = (bord && with_mu) ? mu : nullptr;
     DISPATCH_G(d.G, if (bord) hipLaunchKernelGGL((k_residual<V, S, GG, SC, true>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr, d.col,
                        P::val(d), d.s16, P::f(d), P::e(d), P::res(d), P::b(d), c->partial, lam);
@@ -729,6 +742,7 @@ static void normalise_to_vcycle(mgm_ctx* c, int64_t n, const double* x, const do
 static void apply_from_vcycle(mgm_ctx* c, double* z, double* y, hipStream_t st, bool defer_border = false) {
   DevLevel& d = c->lv[0];
   const bool bord = c->p.problem == MGM_POISSON;
+  if (bord) check_partials(c, 2 * int64_t(d.pstart_host_slots));
   if (c->p.precision == MGM_FP64) {
     if (bord) rowop_patch_launch<double, double, false, kRowApply, true, true, double>(d, d.pv64, nullptr, d.e64, y, d.b64, c->mu, c->partial, st, nullptr, nullptr, z);
     else rowop_patch_launch<double, double, false, kRowApply, false, false, double>(d, d.pv64, nullptr, d.e64, y, d.b64, c->mu, nullptr, st, nullptr, nullptr, z);
