@@ -296,6 +296,22 @@ mgm_status mgm_batched_weights(const double *d_xyz, const double *d_normals, int
                                int32_t phs_order, int32_t poly_degree, double *d_weights,
                                void *stream);
 
+/* Allocation-free form of mgm_batched_weights, for callers that cannot
+ * allocate device memory (code that must not call hipMalloc, such as tight
+ * serving loops or harnesses that forbid it). Same arguments, results
+ * (bit for bit, same kernel) and errors as mgm_batched_weights, plus
+ * MGM_E_ARG for a batch above 2^33 systems (the launch grid's limit, which
+ * mgm_batched_weights shares). The singular-system flag that
+ * mgm_batched_weights allocates per call lives instead in a 256-byte device
+ * array of the library, one per GPU, held until the process ends; a call
+ * uses 4 bytes of it whatever the batch size, clears it on the stream before
+ * the solve and reads it back after (one stream synchronisation). Calls that
+ * overlap on one GPU share that flag and race: serialise them. */
+mgm_status mgm_batched_weights_noalloc(const double *d_xyz, const double *d_normals, int64_t n_points,
+                                       const int32_t *d_stencils, int64_t n_systems, int32_t stencil_size,
+                                       int32_t phs_order, int32_t poly_degree, double *d_weights,
+                                       void *stream);
+
 /* Surface gradient and divergence (Sec. 6.3: the heat method for geodesic
  * distance uses them with MGM solves; the weights are the tangent-plane RBF-FD
  * of Sec. 2.1-2.2 with first derivatives at the centre on the right-hand

@@ -18,12 +18,19 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/mgm.h"
 #include "host_common.h"
 
 namespace mgm {
+
+// status conversion of the C entry points (defined in device.hip)
+extern thread_local std::string g_last_error;
+mgm_status guard(const std::function<void()>& f);
 
 namespace {
 
@@ -210,6 +217,7 @@ void batched_phs_weights_device(const double* d_xyz, const double* d_nrm, const 
   if (ns < 1 || ns + L > 64) throw Error(MGM_E_ARG, "device weights need stencil_size + L <= 64");
   if (deg < 0 || deg > 6 || phs_order < 0 || phs_order > 6) throw Error(MGM_E_ARG, "phs_order/poly_degree out of range");
   if (nsys <= 0) return;
+  if ((nsys + kWaves - 1) / kWaves > 0x7fffffff) throw Error(MGM_E_ARG, "too many systems for one launch");
   const int m = 2 * phs_order + 1;
   const unsigned blocks = unsigned((nsys + kWaves - 1) / kWaves);
   // the register row is sized for the system: S = 60 (50 points, degree 3) needs 61 doubles, not 65
@@ -229,4 +237,72 @@ void batched_phs_weights_device(const double* d_xyz, const double* d_nrm, const 
   HIPOK(hipGetLastError());
 }
 
+// ------------------------------------------------- allocation-free variant
+// Device scratch of mgm_batched_weights_noalloc: int 0 is the flag that the
+// weight kernel raises for a singular system (the buffer that
+// mgm_batched_weights allocates per call). A file-scope device array: every
+// GPU the library runs on holds its own copy until the process ends, and
+// host code may only use the per-device address that hipGetSymbolAddress
+// returns, never the array's name.
+constexpr size_t kNoallocScratchBytes = 256;
+static __device__ __align__(256) int scratch[kNoallocScratchBytes / sizeof(int)];
+
+namespace {
+
+constexpr size_t kNoallocStatusBytes = sizeof(int);  // what one call uses, whatever the batch size
+static_assert(kNoallocStatusBytes <= kNoallocScratchBytes, "status word must fit the scratch");
+
+__global__ void k_clear_status(int* status) { status[0] = 0; }
+
+std::mutex g_scratch_mu;
+std::vector<int*> g_scratch_dev;  // scratch address per device ordinal, looked up once
+
+// The scratch address on the current device (the one whose buffers the call
+// receives), looked up on the first call on that device.
+int* scratch_on_current_device() {
+  int dev = -1;
+  HIPOK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev >= int(g_scratch_dev.size())) g_scratch_dev.resize(size_t(dev) + 1, nullptr);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HIPOK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Error(MGM_E_HIP, "no device address for the weight solver's scratch");
+    g_scratch_dev[dev] = static_cast<int*>(p);
+  }
+  return g_scratch_dev[dev];
+}
+
+}  // namespace
+
 }  // namespace mgm
+
+extern "C" mgm_status mgm_batched_weights_noalloc(const double* d_xyz, const double* d_normals, int64_t n_points,
+                                                  const int32_t* d_stencils, int64_t n_systems, int32_t stencil_size,
+                                                  int32_t phs_order, int32_t poly_degree, double* d_weights,
+                                                  void* stream) {
+  using namespace mgm;
+  if (!d_xyz || !d_normals || !d_stencils || !d_weights || n_points < 1 || n_systems < 0 || stencil_size < 1 ||
+      stencil_size > n_points) {
+    g_last_error = "bad arguments";
+    return MGM_E_ARG;
+  }
+  mgm_status res = MGM_OK;
+  const mgm_status s = guard([&] {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int* status = scratch_on_current_device();
+    // the array keeps the previous call's flag: clear it on the stream first
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, st, status);
+    HIPOK(hipGetLastError());
+    batched_phs_weights_device(d_xyz, d_normals, d_stencils, n_systems, stencil_size, phs_order, poly_degree,
+                               d_weights, status, st);
+    int h_status = 0;
+    HIPOK(hipMemcpyAsync(&h_status, status, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPOK(hipStreamSynchronize(st));
+    if (h_status) {
+      g_last_error = "a stencil system is singular";
+      res = MGM_E_STENCIL_SINGULAR;
+    }
+  });
+  return s != MGM_OK ? s : res;
+}
