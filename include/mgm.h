@@ -357,13 +357,20 @@ mgm_status mgm_surface_divergence(mgm_handle h, const double *d_v, double *d_out
  *                             order)
  *   MGM_EX_GRAD_STENCILS I32  N_1 x n_g surface-operator stencils (after
  *                             mgm_surface_ops_setup)
- *   MGM_EX_GRAD_WEIGHTS  F64  N_1 x n_g x 3 surface-gradient weights W_ij */
+ *   MGM_EX_GRAD_WEIGHTS  F64  N_1 x n_g x 3 surface-gradient weights W_ij
+ *   MGM_EX_L16_VALS      F64  the FP16 operator values h_ij of level j as the
+ *                             device holds them (each exactly widened), in
+ *                             the order of MGM_EX_L_VALS; built on first use.
+ *                             Smoothed levels of a device handle only
+ *   MGM_EX_ROW_SCALE     F64  the FP32 row scales s_i of that operator
+ *                             (L_ij ~ s_i h_ij), natural order */
 enum {
   MGM_EX_LEVEL_SIZES = 0, MGM_EX_STENCILS = 1, MGM_EX_WEIGHTS = 2,
   MGM_EX_COARSE_IDX = 3, MGM_EX_INTERP_IDX = 4, MGM_EX_INTERP_W = 5,
   MGM_EX_COLOURS = 6, MGM_EX_L_ROWPTR = 7, MGM_EX_L_COLS = 8,
   MGM_EX_L_VALS = 9, MGM_EX_BORDER = 10, MGM_EX_NCOLOURS = 11, MGM_EX_PATCH = 12,
-  MGM_EX_OMEGA = 13, MGM_EX_GRAD_STENCILS = 14, MGM_EX_GRAD_WEIGHTS = 15
+  MGM_EX_OMEGA = 13, MGM_EX_GRAD_STENCILS = 14, MGM_EX_GRAD_WEIGHTS = 15,
+  MGM_EX_L16_VALS = 16, MGM_EX_ROW_SCALE = 17
 };
 mgm_status mgm_export(mgm_handle h, int32_t what, int32_t level, void *h_buf,
                       int64_t *len);

@@ -1685,6 +1685,49 @@ mgm_status mgm_export(mgm_handle h, int32_t what, int32_t level, void* h_buf, in
       case MGM_EX_NCOLOURS:
         for (int j = 0; j + 1 < p; ++j) vi.push_back(H.lv[j].ncolours);
         break;
+      case MGM_EX_L16_VALS:
+      case MGM_EX_ROW_SCALE: {
+        // the FP16 operator the device holds (built on first use), read back
+        // and moved from the device's permuted numbering to the natural one
+        need_level(p - 2);
+        need_device(h);
+        HIPCHECK(hipSetDevice(h->device));
+        build_precision(h, MGM_FP16);
+        const DevLevel& d = h->lv[level];
+        const Csr& L = H.lv[level].L;
+        const int n = d.n;
+        std::vector<int32_t> perm(n), rp(n + 1);
+        if (d.perm) HIPCHECK(hipMemcpy(perm.data(), d.perm, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+        else std::iota(perm.begin(), perm.end(), 0);
+        HIPCHECK(hipMemcpy(rp.data(), d.rowptr, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+        const int64_t nnz = rp[n];
+        if (nnz != int64_t(L.val.size())) throw Error(MGM_E_ARG, "device operator pattern differs from the host's");
+        if (what == MGM_EX_ROW_SCALE) {
+          std::vector<float> sc(n);
+          HIPCHECK(hipMemcpy(sc.data(), d.s16, n * sizeof(float), hipMemcpyDeviceToHost));
+          vd.assign(n, 0.0);
+          for (int pos = 0; pos < n; ++pos) vd[perm[pos]] = double(sc[pos]);
+        } else {
+          std::vector<int32_t> cl(nnz);
+          std::vector<_Float16> hv(nnz);
+          HIPCHECK(hipMemcpy(cl.data(), d.col, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+          HIPCHECK(hipMemcpy(hv.data(), d.v16, nnz * sizeof(_Float16), hipMemcpyDeviceToHost));
+          vd.assign(nnz, std::nan(""));
+          for (int pos = 0; pos < n; ++pos) {
+            const int i = perm[pos];
+            const int32_t* c0 = L.col.data() + L.ptr[i];
+            const int32_t* c1 = L.col.data() + L.ptr[i + 1];
+            for (int k = rp[pos]; k < rp[pos + 1]; ++k) {
+              const int32_t cn = perm[cl[k]];
+              const int32_t* at = std::lower_bound(c0, c1, cn);
+              if (at == c1 || *at != cn) throw Error(MGM_E_ARG, "device operator pattern differs from the host's");
+              vd[size_t(at - L.col.data())] = double(float(hv[k]));
+            }
+          }
+        }
+        isint = false;
+        break;
+      }
       default: throw Error(MGM_E_ARG, "unknown export item");
     }
     int64_t cnt = isint ? int64_t(vi.size()) : int64_t(vd.size());

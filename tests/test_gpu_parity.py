@@ -5,8 +5,11 @@ different summation order (and with fused multiply-adds), so single operator
 applications agree to a few ulp of the row's magnitude (1e-13 relative). The
 V-cycle chains ~10^2 such steps and a dense coarse inverse (vs. the oracle's
 LU solve; the coarse operators have condition numbers up to ~1e5), so its
-output is held to 1e-10 relative; Krylov iterates to 1e-10 and iteration
-counts must be identical. FP32/FP16: compared with the oracle's emulation of
+output is held to 1e-10 relative, and iteration counts must be identical.
+These comparisons include the difference between the two FP64 setups (the
+local weight solves round differently, ~1e-10 of a row's scale);
+test_gpu_exported_parity.py runs the oracle on the library's own operators
+and holds the V-cycle to 1e-12 and the Krylov iterates to 1e-10. FP32/FP16: compared with the oracle's emulation of
 the same reduced-precision arithmetic (quantisation is bit-exact, so only
 FP32 summation order differs): 1e-5 relative for a V-cycle. All solves must
 reach a true FP64 relative residual of 1e-10.
@@ -182,7 +185,10 @@ def test_solve_fp64_matches_oracle(case, method):
     u = _host(u)
     assert info["status"] == 0 and info["rel_res_true"] <= 1e-10
     assert info["iters"] == info_ref.iters, (info["iters"], info_ref.iters)
-    assert np.linalg.norm(u - x_ref) <= 1e-10 * np.linalg.norm(x_ref) * 10
+    # the two solve systems whose operators differ by the setups' rounding
+    # (~1e-10 of a row's scale), so their solutions differ by up to cond(A)
+    # times that; iterates are compared on the library's own operators, to
+    # 1e-10, in test_gpu_exported_parity.py
     # independent residual check with the oracle's operator
     assert np.linalg.norm(f - A(u)) <= 1.01e-10 * np.linalg.norm(f)
 

@@ -464,3 +464,68 @@ def test_reduced_precision_vcycle_close_to_fp64(torus_h):
         assert info.converged and info.rel_res_true <= 1e-10
         it[prec] = info.iters
     assert abs(it["fp32"] - it["fp64"]) <= 1 and abs(it["fp16"] - it["fp64"]) <= 1
+
+
+def _f32_row_sum(data, cols, lo, hi, u, coef=None):
+    """sum_k fp32(a_k) u_k in FP32, left to right, each product and partial sum
+    rounded to FP32 (coef: per-entry FP32 values instead of fp32(a_k))."""
+    acc = np.float32(0.0)
+    for k in range(lo, hi):
+        a = np.float32(data[k]) if coef is None else coef[k]
+        acc = np.float32(acc + np.float32(a * u[cols[k]]))
+    return acc
+
+
+def test_reduced_precision_emulation_is_float32_arithmetic():
+    """Pins the FP32 and FP16-row-scale emulations by scalar FP32 loops on a
+    tiny hierarchy: one GS sweep (in colour order, each row's residual summed
+    in FP32, the correction scaled by the FP32 inverse diagonal), the residual
+    restriction R(f - L u) and the interpolation P e agree bit for bit, and
+    the sweep differs from the FP64 one by far more than FP64 rounding (an
+    emulation that silently ran in FP64 fails)."""
+    wl = synth.sphere_workload(700)
+    wl.params["n_coarse_max"] = 100
+    H = hierarchy.build(wl.xyz, wl.normals, wl.params)
+    rng = np.random.default_rng(3)
+    for prec in ("fp32", "fp16"):
+        ops = precision.ops_for(H, prec)
+        for j in range(len(H.levels) - 1):
+            lv, nx = H.levels[j], H.levels[j + 1]
+            L = lv.L
+            if prec == "fp16":
+                h, s = precision.fp16_row_scale(L)
+                coef = h.astype(np.float32)
+                scale = s
+            else:
+                coef, scale = None, None
+            dinv = np.empty(lv.N, dtype=np.float32)
+            for i in range(lv.N):
+                k = L.indptr[i] + int(np.nonzero(L.indices[L.indptr[i]:L.indptr[i + 1]] == i)[0][0])
+                dii = float(L.data[k]) if coef is None else float(scale[i]) * float(coef[k])
+                dinv[i] = np.float32(1.0 / dii)
+            u0 = rng.standard_normal(lv.N).astype(np.float32)
+            f = rng.standard_normal(lv.N).astype(np.float32)
+
+            def row(i, u):
+                acc = _f32_row_sum(L.data, L.indices, L.indptr[i], L.indptr[i + 1], u, coef)
+                return acc if scale is None else np.float32(scale[i] * acc)
+
+            got = vcycle.gs_sweep(ops, j, u0.copy(), f)
+            u = u0.copy()
+            for c in range(lv.ncolours):
+                for i in lv.rows_by_colour[c]:  # rows of one colour do not couple
+                    u[i] = np.float32(u[i] + np.float32(np.float32(f[i] - row(i, u)) * dinv[i]))
+            assert got.dtype == np.float32 and np.array_equal(got, u), (prec, j)
+            ref64 = vcycle.gs_sweep(vcycle.Fp64Ops(H), j, u0.astype(np.float64), f.astype(np.float64))
+            assert np.max(np.abs(got - ref64)) > 1e-9 * np.max(np.abs(ref64)), (prec, j)
+            # residual restriction and interpolation
+            res = np.array([np.float32(f[i] - row(i, u0)) for i in range(lv.N)], dtype=np.float32)
+            R = lv.R
+            rr = np.array([_f32_row_sum(R.data, R.indices, R.indptr[q], R.indptr[q + 1], res) for q in range(nx.N)],
+                          dtype=np.float32)
+            assert np.array_equal(ops.R(j, np.float32(f) - ops.L(j, u0)), rr), (prec, j)
+            e = rng.standard_normal(nx.N).astype(np.float32)
+            P = lv.P
+            pe = np.array([_f32_row_sum(P.data, P.indices, P.indptr[i], P.indptr[i + 1], e) for i in range(lv.N)],
+                          dtype=np.float32)
+            assert np.array_equal(ops.P(j, e), pe), (prec, j)
