@@ -616,7 +616,8 @@ def main():
               "systems_per_s": round(args.weights_n / (wms * 1e-3)),
               "TFLOPs_lu_model": round(flops / (wms * 1e-3) / 1e12, 2),
               "frac_fp64_peak": round(flops / (wms * 1e-3) / 1e12 / 78.6, 4),
-              "note": "FP64 Gauss-Jordan with partial pivoting, one wavefront per system; flops = (2/3)S^3 + 2S^2"}
+              "note": "FP64 Gauss-Jordan with partial pivoting, one wavefront per system, in panels of 4 columns "
+                      "whose updates run on the FP64 matrix cores (MFMA); flops = (2/3)S^3 + 2S^2"}
         log(f"batched weights: {wms:.2f} ms for {args.weights_n} systems ({bw['TFLOPs_lu_model']} TFLOP/s LU model)")
 
     cpu = None

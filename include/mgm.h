@@ -288,7 +288,10 @@ mgm_status mgm_stencils(const double *h_xyz, int64_t n, int32_t k, int32_t *h_id
  * saddle system in the tangent plane of the centre and write the stencil_size
  * weights of row i to d_weights (device FP64, n_systems x stencil_size).
  * One wavefront per system, FP64 Gauss-Jordan with partial pivoting; needs
- * stencil_size + (poly_degree+1)(poly_degree+2)/2 <= 64. Synchronises the
+ * stencil_size + (poly_degree+1)(poly_degree+2)/2 <= 64. Systems of more
+ * than 32 unknowns with poly_degree <= 4 are eliminated in panels of four
+ * columns whose updates run on the FP64 matrix cores (MFMA); the others
+ * one column at a time on the vector units. Synchronises the
  * stream once to report MGM_E_STENCIL_SINGULAR (some system had a pivot below
  * 1e-13 of its largest entry; the other rows are still written). */
 mgm_status mgm_batched_weights(const double *d_xyz, const double *d_normals, int64_t n_points,

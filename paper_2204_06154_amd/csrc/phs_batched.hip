@@ -202,6 +202,260 @@ __global__ __launch_bounds__(64 * kWaves) void k_phs_weights(int64_t nsys, int n
   }
 }
 
+// ------------------------------------------------------ MFMA blocked variant
+// The same Gauss-Jordan elimination with partial pivoting, blocked by panels
+// of 4 columns so that the update of the remaining columns is a 64 x 4 by
+// 4 x 64 product on the FP64 matrix cores (v_mfma_f64_16x16x4f64). One
+// wavefront per system; the 64 x 64 matrix (the system padded with identity
+// rows and columns) stays in the MFMA accumulator layout for the whole solve:
+// tile (bi, bj) = rows 16bi.., columns 16bj..; lane 16g + c holds, in its
+// register v of that tile, row 16bi + 4v + g, column 16bj + c. The right-hand
+// side stays in rows (lane r holds row r).
+// Per panel p (columns 4p .. 4p+3):
+//  1. its 64 x 4 columns go through LDS into rows (lane r: row r);
+//  2. four pivot steps on them (unused row with the largest |entry|, ties to
+//     the lower row): multipliers M[r][k], pivot rows b_k;
+//  3. the pivot rows' current entries B (4 x 64, through LDS) become
+//     U = Lambda^-1 B, Lambda the unit lower triangle of the multipliers the
+//     panel applied to its own pivot rows (U[k] is pivot row b_k as it stood
+//     at step k); columns of this and earlier panels are set to zero in U;
+//  4. every row r: A[r][:] -= sum_k M[r][k] U[k][:], as MFMA tiles.
+// This is the unblocked elimination's arithmetic reassociated per panel.
+// After the last panel each pivot row holds one nonzero and x = rhs / pivot.
+// The 64 x 64 FP64 matrix takes 128 registers of every lane; the register
+// bound of three wavefronts per SIMD (168) spills a few values of the
+// assembly phase, which costs less than the latency two wavefronts leave
+// exposed (measured: 12.2 against 15.5 ms for 500,000 systems of 60).
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int kMWaves = 4;    // systems (wavefronts) per block
+constexpr int kMonoMax = 16;  // monomials per point in the table: degree <= 4
+
+// Order the LDS accesses of the lanes of one wavefront (no hardware wait).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(64 * kMWaves, 3) void k_phs_weights_mfma(int64_t nsys, int ns, int deg, int L, int m,
+                                                                 const double* __restrict__ xyz,
+                                                                 const double* __restrict__ nrm,
+                                                                 const int32_t* __restrict__ sten,
+                                                                 double* __restrict__ w, int* __restrict__ status) {
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  const int64_t sys = int64_t(blockIdx.x) * kMWaves + wv;
+  const bool active = sys < nsys;  // uniform per wavefront
+  const int S = ns + L;
+  __shared__ double xs[kMWaves][64][2];
+  // per wavefront: the monomial table, then per panel the panel rows / the A
+  // operand (-M, 64 x 4) and the pivot rows B / U (4 x 64)
+  __shared__ double scr[kMWaves][64 * kMonoMax];
+
+  // tangent frame of the centre (Sec. 2.1) and this lane's projected point
+  double px = 0.0, py = 0.0;
+  if (active) {
+    const int32_t* st = sten + sys * ns;
+    const int ci = st[0];
+    double n0 = nrm[3 * ci], n1 = nrm[3 * ci + 1], n2 = nrm[3 * ci + 2];
+    double nn = sqrt(fma(n0, n0, fma(n1, n1, n2 * n2)));
+    n0 /= nn;
+    n1 /= nn;
+    n2 /= nn;
+    int ax = 0;
+    if (fabs(n1) < fabs(n0)) ax = 1;
+    if (fabs(n2) < fabs(ax == 0 ? n0 : n1)) ax = 2;
+    double nax = ax == 0 ? n0 : (ax == 1 ? n1 : n2);
+    double t1x = (ax == 0 ? 1.0 : 0.0) - nax * n0;
+    double t1y = (ax == 1 ? 1.0 : 0.0) - nax * n1;
+    double t1z = (ax == 2 ? 1.0 : 0.0) - nax * n2;
+    double l1 = sqrt(t1x * t1x + t1y * t1y + t1z * t1z);
+    t1x /= l1;
+    t1y /= l1;
+    t1z /= l1;
+    double t2x = n1 * t1z - n2 * t1y, t2y = n2 * t1x - n0 * t1z, t2z = n0 * t1y - n1 * t1x;
+    if (lane < ns) {
+      const int j = st[lane];
+      double dx = xyz[3 * j] - xyz[3 * ci], dy = xyz[3 * j + 1] - xyz[3 * ci + 1], dz = xyz[3 * j + 2] - xyz[3 * ci + 2];
+      px = t1x * dx + t1y * dy + t1z * dz;
+      py = t2x * dx + t2y * dy + t2z * dz;
+    }
+  }
+  double r = sqrt(px * px + py * py);
+  double s = r;
+  for (int off = 32; off > 0; off >>= 1) s = fmax(s, __shfl_xor(s, off, 64));
+  if (!(s > 0.0)) s = 1.0;
+  px /= s;
+  py /= s;
+  r /= s;
+  xs[wv][lane][0] = px;
+  xs[wv][lane][1] = py;
+  wave_sync();
+
+  // the monomials of this lane's point (total degree, then descending power
+  // of x), so that the polynomial entries are table reads
+  double* mono = scr[wv];  // kMonoMax per point
+  {
+    int q = 0;  // (deg + 1)(deg + 2) / 2 = L <= kMonoMax monomials (checked on the host)
+    for (int d = 0; d <= deg; ++d)
+      for (int b = 0; b <= d; ++b, ++q) mono[lane * kMonoMax + q] = ipow_d(px, d - b) * ipow_d(py, b);
+  }
+  wave_sync();
+  // the padded system in the accumulator layout
+  dbl4 acc[4][4];
+  double amax = 0.0;
+#pragma unroll
+  for (int bj = 0; bj < 4; ++bj) {
+    const int col = 16 * bj + c;
+    const double xc = xs[wv][col][0], yc = xs[wv][col][1];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * bi + 4 * v + g;
+        const double dx = xs[wv][row][0] - xc, dy = xs[wv][row][1] - yc;
+        const double phs = ipow_d(sqrt(dx * dx + dy * dy), m);
+        // P (row a point, col a monomial) or P^T (row a monomial, col a point)
+        const bool rp = row < ns;
+        const int pt = rp ? row : col, mq = (rp ? col : row) - ns;
+        const double pq = mono[pt * kMonoMax + min(max(mq, 0), kMonoMax - 1)];
+        double val;
+        if (row < S && col < S) {
+          val = (row < ns && col < ns) ? phs : ((row < ns) != (col < ns) ? pq : 0.0);
+          amax = fmax(amax, fabs(val));
+        } else {
+          val = row == col ? 1.0 : 0.0;  // padding: identity
+        }
+        acc[bi][bj][v] = val;
+      }
+    }
+  }
+  wave_sync();  // the monomial table's space is reused below
+  for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+  const double tiny = amax * 1e-13;
+  // right-hand side (eq. rbf_fd_lap), row `lane`
+  double rhs = 0.0;
+  if (lane < ns) {
+    rhs = double(m) * double(m) * ipow_d(r, m - 2);
+  } else if (lane < S) {
+    int qa, qb;
+    mono_exp(lane - ns, qa, qb);
+    rhs = ((qa == 2 && qb == 0) || (qa == 0 && qb == 2)) ? 2.0 : 0.0;
+  }
+
+  bool used = false;
+  int kpos = -1;
+  double diag = 1.0;
+  bool singular = false;
+  double(*pan)[4] = reinterpret_cast<double(*)[4]>(scr[wv]);          // 64 x 4
+  double(*ub)[64] = reinterpret_cast<double(*)[64]>(scr[wv] + 64 * 4);  // 4 x 64
+  const int np = (S + 3) / 4;
+  for (int p = 0; p < np; ++p) {
+    const int bjp = p >> 2, co = (p & 3) * 4;
+    // 1. the panel's columns into rows
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+      if (bj == bjp && c >= co && c < co + 4) {
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) pan[16 * bi + 4 * v + g][c - co] = acc[bi][bj][v];
+      }
+    wave_sync();
+    double pr[4], mk[4];
+    int bk[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) pr[j] = pan[lane][j];
+    // 2. pivot steps on the panel
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double v = pr[k];
+      // pivot: the unused row whose |v|, rounded to FP32, is largest (a
+      // non-negative float orders like its bit pattern; +1 so that used
+      // rows, keyed 0, never win), ties to the lowest row: one wave-wide
+      // maximum instead of an exact FP64 comparison in two passes
+      const uint32_t key = used ? 0u : __builtin_bit_cast(uint32_t, float(fabs(v))) + 1u;
+      const uint32_t kmax = wave_max_u32(key);
+      const int bl = int(__builtin_ctzll(__ballot(key == kmax)));
+      const double piv = readlane_d(v, bl);
+      if (4 * p + k < S && !(fabs(piv) > tiny)) singular = true;
+      const double rpiv = 1.0 / piv;
+      const double mlt = lane == bl ? 0.0 : v * rpiv;
+#pragma unroll
+      for (int j = k + 1; j < 4; ++j) pr[j] = fma(-mlt, readlane_d(pr[j], bl), pr[j]);
+      mk[k] = mlt;
+      bk[k] = bl;
+      if (lane == bl) {
+        used = true;
+        kpos = 4 * p + k;
+        diag = piv;
+      }
+    }
+    // 3. pivot rows B (current entries) into LDS, then U = Lambda^-1 B
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int rb = bk[k];
+      const int bib = rb >> 4, vb = (rb >> 2) & 3;
+      if (g == (rb & 3)) {
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (bi == bib && v == vb) {
+#pragma unroll
+              for (int bj = 0; bj < 4; ++bj) ub[k][16 * bj + c] = acc[bi][bj][v];
+            }
+      }
+    }
+    double lam[4][4];  // lam[k][q] = multiplier of pivot row b_k at step q < k
+#pragma unroll
+    for (int k = 1; k < 4; ++k)
+#pragma unroll
+      for (int q = 0; q < k; ++q) lam[k][q] = readlane_d(mk[q], bk[k]);
+    wave_sync();
+    double u[4], urhs[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      u[k] = ub[k][lane];
+      urhs[k] = readlane_d(rhs, bk[k]);
+#pragma unroll
+      for (int q = 0; q < k; ++q) {
+        u[k] = fma(-lam[k][q], u[q], u[k]);
+        urhs[k] = fma(-lam[k][q], urhs[q], urhs[k]);
+      }
+    }
+    const bool done_col = lane < 4 * p + 4;  // this lane's column is eliminated already
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      ub[k][lane] = done_col ? 0.0 : u[k];
+      rhs = fma(-mk[k], urhs[k], rhs);
+      pan[lane][k] = -mk[k];
+    }
+    wave_sync();
+    // 4. the update on the matrix cores: A operand lane 16k + i = -M[16bi + i][k],
+    //    B operand lane 16k + j = U[k][16bj + j]
+    double aop[4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) aop[bi] = pan[16 * bi + c][g];
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+      if (bj >= bjp) {
+        const double bop = ub[g][16 * bj + c];
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi) acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[bi], bop, acc[bi][bj], 0, 0, 0);
+      }
+    wave_sync();  // the next panel reuses pan and ub
+  }
+  if (active) {
+    if (singular) {
+      if (lane == 0) atomicMax(status, 1);
+    } else if (kpos >= 0 && kpos < ns) {
+      w[sys * ns + kpos] = (rhs / diag) / (s * s);
+    }
+  }
+}
+
 #define HIPOK(x)                                                                                   \
   do {                                                                                             \
     hipError_t e_ = (x);                                                                           \
@@ -222,7 +476,12 @@ void batched_phs_weights_device(const double* d_xyz, const double* d_nrm, const 
   const unsigned blocks = unsigned((nsys + kWaves - 1) / kWaves);
   // the register row is sized for the system: S = 60 (50 points, degree 3) needs 61 doubles, not 65
   const int S = ns + L;
-  if (S <= 32)
+  if (S > 32 && L <= kMonoMax) {
+    // larger systems: blocked elimination with the update on the matrix cores
+    const unsigned mblocks = unsigned((nsys + kMWaves - 1) / kMWaves);
+    hipLaunchKernelGGL(k_phs_weights_mfma, dim3(mblocks), dim3(64 * kMWaves), 0, st, nsys, ns, deg, L, m, d_xyz, d_nrm,
+                       d_sten, d_w, d_status);
+  } else if (S <= 32)
     hipLaunchKernelGGL(k_phs_weights<32>, dim3(blocks), dim3(64 * kWaves), 0, st, nsys, ns, L, m, d_xyz, d_nrm, d_sten,
                        d_w, d_status);
   else if (S <= 48)
