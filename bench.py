@@ -69,7 +69,7 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n_sample: int, n_full: int, reps: int = 1):
+def cpu_baseline(n_sample: int, n_full: int, reps: int = 3):
     import numpy as np
     from threadpoolctl import threadpool_limits
 
