@@ -45,7 +45,8 @@ typedef enum {
   MGM_E_NONFINITE = -9,        /* NaN/Inf in an input or an iterate */
   MGM_E_SYNC = -10             /* a one-launch smoother sweep (gs_flow) gave up
                                   waiting for a coupled patch: the results of
-                                  the calls since the last solve are invalid */
+                                  the calls since the last check are invalid;
+                                  the sweeps are resynchronised (mgm_check) */
 } mgm_status;
 
 /* Discretisation of the Laplace-Beltrami operator (Sec. 2). */
@@ -107,8 +108,8 @@ typedef struct {
                              patches before it in the sweep order are done
                              (the same GS order and bit-identical results as
                              0: one launch per patch colour). A wait is
-                             bounded; if one gives up, the next mgm_solve
-                             returns MGM_E_SYNC */
+                             bounded; if one gives up, the next mgm_solve,
+                             mgm_level_op or mgm_check returns MGM_E_SYNC */
 } mgm_params;
 
 /* Paper defaults (Table 1): RBF-FD, k = l = 3, n = 20, forward GS, nu = 1,
@@ -174,6 +175,22 @@ typedef struct {
 mgm_status mgm_solve(mgm_handle h, const double *d_f, double *d_u,
                      const mgm_solve_opts *opts, mgm_solve_info *info,
                      double *h_res_hist, void *stream);
+
+/* Synchronises the stream and reports whether a one-launch smoother sweep
+ * (gs_flow = 1) gave up waiting for a coupled patch since the last check:
+ * MGM_E_SYNC if so (the results of the calls since then are invalid; the
+ * sweeps' ticket counters and flags have been reset, so later calls are
+ * valid again), else MGM_OK. mgm_solve and mgm_level_op make the same check
+ * before returning; mgm_vcycle does not synchronise and leaves it to them or
+ * to this call. */
+mgm_status mgm_check(mgm_handle h, void *stream);
+
+/* For tests of the give-up path: bound of each wait of the one-launch
+ * sweeps, in ticks of the GPU's constant-rate real-time counter (100 MHz on
+ * MI355X); ticks < 0 restores the default 2^24 (~0.17 s). With a bound too
+ * small for the waits to succeed, sweeps give up (every kernel still ends)
+ * and the next check returns MGM_E_SYNC. Waits for the device first. */
+mgm_status mgm_set_flow_wait(mgm_handle h, int64_t ticks);
 
 /* Per-level operations for testing and profiling; vectors are device FP64 in
  * the level's natural numbering (level 1: caller order; level j+1: the WSE

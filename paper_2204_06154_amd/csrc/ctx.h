@@ -166,6 +166,7 @@ struct mgm_ctx {
   double* hpin = nullptr;  // pinned host copies of dot results
   int* flow_err = nullptr;   // device: a one-launch sweep gave up waiting
   int* hflow_err = nullptr;  // pinned host copy
+  unsigned long long flow_wait_ticks = 0;  // bound of the one-launch sweeps' waits (set at setup)
   hipEvent_t step_done = nullptr;  // FGMRES: end of an Arnoldi step's kernels
   double* capture = nullptr;         // when set: the start level's vector after the coarse correction (eager cycle)
   int capture_level = 0;
@@ -211,5 +212,9 @@ inline bool learned_on(const mgm_ctx* c, int j) { return j < int(c->ls.size()) &
 void need_device(const mgm_ctx* c);
 mgm_status guard(const std::function<void()>& f);
 void invalidate_graphs(mgm_ctx* c);
+// Waits for the stream; if a one-launch sweep gave up waiting since the last
+// check, clears the error, resets every level's ticket counter and flags (so
+// the next sweeps number from 1 again) and throws MGM_E_SYNC.
+void flow_check(mgm_ctx* c, hipStream_t st);
 
 }  // namespace mgm

@@ -334,6 +334,9 @@ static void upload(mgm_ctx* c) {
   c->partial = track(c, dalloc<double>(maxblk));
   c->flow_err = track(c, dalloc<int>(1));
   HIPCHECK(hipMemset(c->flow_err, 0, sizeof(int)));
+  HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&c->hflow_err), sizeof(int), hipHostMallocDefault));
+  *c->hflow_err = 0;
+  c->flow_wait_ticks = kFlowWaitTicks;
   HIPCHECK(hipMemset(c->mu, 0, sizeof(double) * p));
   HIPCHECK(hipMemset(c->rho, 0, sizeof(double) * (p + 1)));
 }
@@ -456,7 +459,7 @@ static void gs_patch_launch(mgm_ctx* c, int j, int pc, bool reverse, bool border
   const int ns = flow ? d.pstart_host_slots : d.pc_start[pc + 1] - s0;
   if (ns <= 0) return;
   GsFlow fl{};
-  if (flow) fl = GsFlow{d.fl_ticket, d.fl_flag, d.fl_nbptr, d.fl_nb, d.fl_crow, c->flow_err, ns};
+  if (flow) fl = GsFlow{d.fl_ticket, d.fl_flag, d.fl_nbptr, d.fl_nb, d.fl_crow, c->flow_err, ns, c->flow_wait_ticks};
 #define GS_PATCH(WM, BD, FL)                                                                                 \
   hipLaunchKernelGGL((k_gs_patch<V, S, WM / kPatchG, SC, BD, FL>), dim3(ns), dim3(kPatch * kPatchG), 0, st, s0, \
                      reverse ? 1 : 0, zero_guess ? 1 : 0, d.pw, d.pblock, d.pstart, \
@@ -672,6 +675,23 @@ static void vcycle_enqueue(mgm_ctx* c, hipStream_t st) {
   cycle_enqueue<V, S, SC>(c, 0, c->p.cycle, true, st);
 }
 
+void flow_check(mgm_ctx* c, hipStream_t st) {
+  HIPCHECK(hipMemcpyAsync(c->hflow_err, c->flow_err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  if (!*c->hflow_err) return;
+  // every launch has ended (each wait is bounded): start the numbering of
+  // the sweeps afresh on every patch-blocked level
+  HIPCHECK(hipMemsetAsync(c->flow_err, 0, sizeof(int), st));
+  for (auto& d : c->lv)
+    if (d.fl_ticket) {
+      HIPCHECK(hipMemsetAsync(d.fl_ticket, 0, sizeof(unsigned long long), st));
+      HIPCHECK(hipMemsetAsync(d.fl_flag, 0, sizeof(unsigned) * size_t(d.pstart_host_slots), st));
+    }
+  HIPCHECK(hipStreamSynchronize(st));
+  *c->hflow_err = 0;
+  throw Error(MGM_E_SYNC, "a one-launch smoother sweep gave up waiting for a coupled patch; sweeps resynchronised");
+}
+
 void invalidate_graphs(mgm_ctx* c) {
   for (int k = 0; k < 3; ++k)
     if (c->graph[k]) {
@@ -813,8 +833,6 @@ void ensure_ws(mgm_ctx* c, int restart) {
     c->kpart = track(c, dalloc<double>(kp));
     c->dh = track(c, dalloc<double>(1024));
     HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&c->hpin), 1024 * sizeof(double), hipHostMallocDefault));
-    HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&c->hflow_err), sizeof(int), hipHostMallocDefault));
-    *c->hflow_err = 0;
     HIPCHECK(hipEventCreateWithFlags(&c->step_done, hipEventDisableTiming));
   }
   if (restart > c->ws_restart) {
@@ -887,14 +905,9 @@ static mgm_status solve_impl(mgm_ctx* c, const double* d_f, double* d_u, const m
       HIPCHECK(hipMemcpyAsync(d_u + d0.n, x + d0.n, sizeof(double), hipMemcpyDeviceToDevice, st));
       HIPCHECK(hipMemcpyAsync(c->hpin, x + d0.n, sizeof(double), hipMemcpyDeviceToHost, st));
     }
-    HIPCHECK(hipMemcpyAsync(c->hflow_err, c->flow_err, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
     info.lambda = bord ? c->hpin[0] : 0.0;
-    if (*c->hflow_err) {
-      HIPCHECK(hipMemsetAsync(c->flow_err, 0, sizeof(int), st));
-      HIPCHECK(hipStreamSynchronize(st));
-      throw Error(MGM_E_SYNC, "a one-launch smoother sweep gave up waiting for a coupled patch");
-    }
+    flow_check(c, st);
     return s;
   };
   if (fnorm == 0.0) {
@@ -1571,7 +1584,33 @@ mgm_status mgm_level_op(mgm_handle h, int32_t op, int32_t level, double* d_x, co
     if (h->p.precision == MGM_FP64) level_op_t<double, double, false>(h, op, level, d_x, d_b, d_y, reverse != 0, st);
     else if (h->p.precision == MGM_FP32) level_op_t<float, float, false>(h, op, level, d_x, d_b, d_y, reverse != 0, st);
     else level_op_t<_Float16, float, true>(h, op, level, d_x, d_b, d_y, reverse != 0, st);
-    HIPCHECK(hipStreamSynchronize(st));
+    flow_check(h, st);
+  });
+}
+
+mgm_status mgm_check(mgm_handle h, void* stream) {
+  if (!h) {
+    g_last_error = "bad arguments";
+    return MGM_E_ARG;
+  }
+  return guard([&] {
+    need_device(h);
+    HIPCHECK(hipSetDevice(h->device));
+    flow_check(h, static_cast<hipStream_t>(stream));
+  });
+}
+
+mgm_status mgm_set_flow_wait(mgm_handle h, int64_t ticks) {
+  if (!h) {
+    g_last_error = "bad arguments";
+    return MGM_E_ARG;
+  }
+  return guard([&] {
+    need_device(h);
+    HIPCHECK(hipSetDevice(h->device));
+    HIPCHECK(hipDeviceSynchronize());
+    h->flow_wait_ticks = ticks < 0 ? kFlowWaitTicks : (unsigned long long)ticks;
+    invalidate_graphs(h);  // the bound is a launch argument captured in the graphs
   });
 }
 

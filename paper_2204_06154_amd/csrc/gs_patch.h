@@ -44,10 +44,10 @@ namespace {
 // line); a wave waits for its stores to complete before the barrier that
 // precedes the flag store, and the halo loads are issued after the barrier
 // that follows the wait, so no cache write-back or invalidation is needed.
-// A wait gives up after kFlowWaitTicks
-// ticks of the constant-rate real-time counter (2^24 ticks: ~0.17 s at its
-// usual 100 MHz, against waits of tens of microseconds) and raises the error
-// flag, so every workgroup ends.
+// A wait gives up after fl.wait_ticks ticks of the constant-rate real-time
+// counter (by default kFlowWaitTicks = 2^24: ~0.17 s at its usual 100 MHz,
+// against waits of tens of microseconds) and raises the error flag, so every
+// workgroup ends; the host then resets the level's ticket counter and flags.
 constexpr int kPatch = 256;
 constexpr int kPatchG = 4;
 constexpr unsigned long long kFlowWaitTicks = 1ull << 24;
@@ -63,6 +63,7 @@ struct GsFlow {
   const int32_t* crow;           // slot s: rows [crow[2s], crow[2s+1]) of its patch colour
   int* err;                      // set when a wait gave up
   int nslot;
+  unsigned long long wait_ticks;  // bound of each wait (real-time counter ticks)
 };
 
 template <typename V, typename S, int WL, bool SCALED, bool BORDER, bool FLOW = false>
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
         if (reverse ? q > slot : q < slot) {
           const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
           while (int(__hip_atomic_load(fl.flag + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - sweep) < 0) {
-            if (__builtin_amdgcn_s_memrealtime() - t0 > kFlowWaitTicks) {
+            if (__builtin_amdgcn_s_memrealtime() - t0 > fl.wait_ticks) {
               __hip_atomic_store(fl.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
               break;
             }

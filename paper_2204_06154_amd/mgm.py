@@ -75,7 +75,7 @@ EXPORTED = ["mgm_default_params", "mgm_setup", "mgm_set_precision", "mgm_vcycle"
             "mgm_level_op", "mgm_time_kernel", "mgm_stencils", "mgm_batched_weights", "mgm_batched_weights_noalloc", "mgm_train_smoother",
             "mgm_smoother_params", "mgm_smoother_grad", "mgm_set_smoother", "mgm_export", "mgm_destroy",
             "mgm_status_str", "mgm_last_error", "mgm_surface_ops_setup", "mgm_surface_gradient",
-            "mgm_surface_divergence"]
+            "mgm_surface_divergence", "mgm_check", "mgm_set_flow_wait"]
 TK = dict(spmv=0, gs=1, residual=2, vcycle=3)
 
 
@@ -124,6 +124,10 @@ def load():
     lib.mgm_surface_gradient.restype = i32
     lib.mgm_surface_divergence.argtypes = [vp, vp, vp, vp]
     lib.mgm_surface_divergence.restype = i32
+    lib.mgm_check.argtypes = [vp, vp]
+    lib.mgm_check.restype = i32
+    lib.mgm_set_flow_wait.argtypes = [vp, i64]
+    lib.mgm_set_flow_wait.restype = i32
     lib.mgm_export.argtypes = [vp, i32, i32, vp, ctypes.POINTER(i64)]
     lib.mgm_export.restype = i32
     lib.mgm_destroy.argtypes = [vp]
@@ -251,6 +255,16 @@ class Mgm:
         _check(self.lib.mgm_level_op(self.h, op, level, _ptr(x), _ptr(b) if b is not None else None,
                                      _ptr(y) if y is not None else None, float(scalar), 1 if reverse else 0,
                                      _stream(stream)))
+
+    def check(self, stream=None):
+        """Synchronise; raise MgmError(MGM_E_SYNC) if a one-launch sweep gave up
+        since the last check (the sweeps are resynchronised by then)."""
+        _check(self.lib.mgm_check(self.h, _stream(stream)))
+
+    def set_flow_wait(self, ticks: int):
+        """Bound of the one-launch sweeps' waits in real-time counter ticks
+        (< 0: the default); for tests of the give-up path."""
+        _check(self.lib.mgm_set_flow_wait(self.h, int(ticks)))
 
     def time_kernel(self, which: str, level: int = 0, reps: int = 20, stream=None):
         """(mean ms per launch, algorithmic bytes per launch) of one hot-path kernel."""

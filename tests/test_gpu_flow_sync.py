@@ -1,0 +1,53 @@
+"""The give-up path of the one-launch smoother sweeps, forced from the host.
+
+With the wait bound set to zero ticks, a patch whose coupled predecessors
+have not finished when it first looks gives up at once, raises the error
+flag and carries on, so every kernel ends normally. The solve must then
+report MGM_E_SYNC, and after the bound is restored the next solves must be
+exactly those of a handle that never gave up: the library reset the
+sweeps' ticket counters and flags when it reported the error.
+"""
+import numpy as np
+import pytest
+
+import synth
+from paper_2204_06154_amd import mgm
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+E_SYNC = -10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_give_up_is_reported_and_the_next_solves_are_clean(prec):
+    wl = synth.torus_workload(20000)
+    p = dict(wl.params, precision=prec)
+    print(f"[gpu-flow-sync] torus N=20000 {prec}", flush=True)
+    m = mgm.Mgm(wl.xyz, wl.normals, p, device=0)
+    ref = mgm.Mgm(wl.xyz, wl.normals, p, device=0)
+    f = torch.tensor(np.concatenate([wl.f, [0.0]]), device="cuda")
+    u_ref, info_ref = ref.solve(f, rtol=1e-10, maxit=200)
+    u_ref2, _ = ref.solve(f, rtol=1e-10, maxit=200)
+    m.set_flow_wait(0)
+    with pytest.raises(mgm.MgmError) as ei:
+        m.solve(f, rtol=1e-10, maxit=5)
+    assert ei.value.status == E_SYNC
+    m.check()  # the report cleared the flag
+    m.set_flow_wait(-1)
+    for want in (u_ref, u_ref2):  # two clean solves in a row, as on the reference handle
+        u, info = m.solve(f, rtol=1e-10, maxit=200)
+        assert info["status"] == 0 and info["iters"] == info_ref["iters"]
+        assert torch.equal(u, want)
+    # the stand-alone V-cycle's give-up is reported by the check that follows it
+    m.set_flow_wait(0)
+    m.vcycle(f)
+    with pytest.raises(mgm.MgmError) as ei:
+        m.check()
+    assert ei.value.status == E_SYNC
+    m.set_flow_wait(-1)
+    z = m.vcycle(f)
+    m.check()
+    assert torch.equal(z, ref.vcycle(f))
+    m.close()
+    ref.close()
