@@ -223,6 +223,37 @@ def bench_sphere1m(args):
                      "err_vs_fp64_solution": err}
         log(f"{prec}: {ms:.2f} ms, {info['iters']} applications, V-cycle {vc_ms * 1e3:.0f} us, err {err:.1e}")
     out["speedup_fp16_vs_fp64"] = round(out["fp64"]["ms"] / out["fp16"]["ms"], 3)
+    # bandwidth of the operator and smoother kernels on an operator larger than
+    # the 256 MB Infinity Cache, next to what a plain device copy reaches
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 2 * src.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    out["copy_GBps"] = round(copy_gbps, 1)
+
+    def rl(ms, nbytes, kernel):
+        gbps = nbytes / (ms * 1e-3) / 1e9
+        return {"kernel": kernel, "bound": "hbm", "us_per_launch": round(ms * 1e3, 2), "bytes_per_launch": nbytes,
+                "achieved": round(gbps, 1), "peak": 8000.0, "unit": "GB/s", "frac": round(gbps / 8000.0, 4),
+                "frac_of_copy": round(gbps / copy_gbps, 4)}
+
+    m.set_precision("fp64")
+    sp_ms, sp_b = m.time_kernel("spmv", 0, reps=20)
+    out["spmv_roofline"] = rl(sp_ms, sp_b, "outer FP64 operator, fine level")
+    out["gs_roofline"] = {}
+    for prec in ("fp64", "fp32", "fp16"):
+        m.set_precision(prec)
+        g_ms, g_b = m.time_kernel("gs", 0, reps=10)
+        out["gs_roofline"][prec] = rl(g_ms, g_b, f"k_gs_patch {prec}: one fine-level sweep")
+    log(f"copy {copy_gbps:.0f} GB/s; SpMV {out['spmv_roofline']['achieved']:.0f} GB/s; fine GS sweep "
+        + ", ".join(f"{k} {v['achieved']:.0f} GB/s" for k, v in out["gs_roofline"].items()))
     print(json.dumps(out), flush=True)
     m.close()
 
