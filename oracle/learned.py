@@ -36,6 +36,12 @@ scaled by the stencil radius, and the entries of the Galerkin operator L_j
 at those points over |L_j(i,i)| (0 where L_j has no entry). Level j trains on
 level-j errors right after the coarse-grid correction of MGM iterations of
 the sub-hierarchy that starts at level j, on L_j e = 0.
+
+Bordered Poisson system (Sec. 4.4; our reading): the Richardson steps hold
+the multiplier fixed, like the Gauss-Seidel smoother, so a step is
+e <- e + omega_q D^-1 (r - L e - b lam); the snapshots come from the
+homogeneous bordered iteration (see `snapshots`) and the loss and its
+gradient are unchanged.
 """
 from __future__ import annotations
 
@@ -206,16 +212,28 @@ def snapshots(H, starts: np.ndarray, iters: int, level: int = 0) -> np.ndarray:
     From each start e (rows of `starts`, level-j vectors), `iters` MGM
     iterations e <- e + M_j(-L_j e) with the Gauss-Seidel cycle of the
     sub-hierarchy from level j; each iteration contributes e + (level-j vector
-    right after the coarse correction)."""
+    right after the coarse correction).
+
+    Bordered Poisson system (Sec. 4.4; our reading): the iteration runs on the
+    homogeneous bordered system of level j, [L_j b_j; b_j^T 0] (e, mu) = 0,
+    from (start, 0): (e, mu) <- (e, mu) + M_j(-(L_j e + b_j mu), -b_j . e).
+    The snapshots are the e parts; the smoother holds mu fixed, so the loss
+    is the same function of L_j as for the screened problem."""
     from .vcycle import Fp64Ops, vcycle
     ops = Fp64Ops(H)
     L = H.levels[level].L
+    b = H.levels[level].b if H.problem == "poisson" else None
     out = []
     for e0 in starts:
         e = np.array(e0, dtype=np.float64)
+        mu = 0.0
         for _ in range(iters):
             cap = []
-            z = vcycle(ops, -(L @ e), None, capture=cap, level=level)
+            if b is None:
+                z = vcycle(ops, -(L @ e), None, capture=cap, level=level)
+            else:
+                z, dmu = vcycle(ops, -(L @ e + b * mu), -float(b @ e), capture=cap, level=level)
+                mu += dmu
             out.append(e + cap[0])
             e = e + z
     return np.array(out)

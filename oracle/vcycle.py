@@ -106,11 +106,18 @@ def learned_weights(ops, j):
     return lw if j == 0 else None
 
 
-def learned_sweep(ops, u, f, j=0):
-    """Learned smoother on level j: for q = 1..s, u <- u + omega_q D^-1 (f - L u)."""
+def learned_sweep(ops, u, f, j=0, lam=0.0):
+    """Learned smoother on level j: for q = 1..s, u <- u + omega_q D^-1 (f - L u).
+    Bordered system: the multiplier is held fixed at lam, as in the
+    Gauss-Seidel smoother (the inexact-Uzawa form of Sec. 4.4), so each step
+    uses the residual f - L u - b lam."""
     omega = learned_weights(ops, j)
+    b = ops.border(j)
     for q in range(omega.shape[1]):
-        u += (omega[:, q] * ops.dinv_learned(j)) * (f - ops.L(j, u))
+        res = f - ops.L(j, u)
+        if b is not None and lam != 0.0:
+            res = res - b * ops.dtype(lam)
+        u += (omega[:, q] * ops.dinv_learned(j)) * res
     return u
 
 
@@ -148,7 +155,7 @@ def vcycle(ops, r, rho=None, nu1=1, nu2=1, post_reverse=False, capture=None, pre
         lw = learned_weights(ops, j)
         for _ in range(nu1):
             if lw is not None:
-                learned_sweep(ops, e, f, j)
+                learned_sweep(ops, e, f, j, lam)
             else:
                 gs_sweep(ops, j, e, f, lam, reverse=pre_reverse)
         res = f - ops.L(j, e)
@@ -165,7 +172,7 @@ def vcycle(ops, r, rho=None, nu1=1, nu2=1, post_reverse=False, capture=None, pre
             capture.append(np.array(e, dtype=np.float64))
         for _ in range(nu2):
             if lw is not None:
-                learned_sweep(ops, e, f, j)
+                learned_sweep(ops, e, f, j, mu if bordered else 0.0)
             else:
                 gs_sweep(ops, j, e, f, mu if bordered else 0.0, reverse=post_reverse)
         return e, mu

@@ -169,3 +169,148 @@ def test_coarse_level_snapshots_follow_sub_cycle(small):
     u = vcycle.gs_sweep(ops, 1, np.zeros(lv.N), f)
     cap = u + lv.P @ np.linalg.solve(cl.L.toarray(), lv.R @ (f - lv.L @ u))
     assert np.allclose(snap, e0 + cap, rtol=0, atol=1e-10 * np.abs(e0 + cap).max())
+
+
+# ------------------------------------------- bordered Poisson system (Sec. 4.4)
+@pytest.fixture(scope="module")
+def torus_small():
+    wl = synth.torus_workload(1500)
+    wl.params["n_min"] = 60
+    H = hierarchy.build(wl.xyz, wl.normals, wl.params)
+    assert H.problem == "poisson" and len(H.levels) >= 3
+    return wl, H
+
+
+def _weights(N, s, seed):
+    rng = np.random.default_rng(seed)
+    return 0.4 + 0.6 * rng.random((N, s))
+
+
+def _step_product(L, omega, left):
+    """prod_q (I - W_q L) (left=False) or prod_q (I - L W_q) (left=True),
+    W_q = diag(omega_q / L_ii), later steps on the left."""
+    N = L.shape[0]
+    E = np.eye(N)
+    for q in range(omega.shape[1]):
+        W = np.diag(omega[:, q] / np.diag(L))
+        E = ((np.eye(N) - L @ W) if left else (np.eye(N) - W @ L)) @ E
+    return E
+
+
+@pytest.mark.parametrize("j", [0, 1])
+def test_bordered_learned_sweep_holds_the_multiplier(torus_small, j):
+    """With the multiplier fixed at lam, every v with L_j v + b_j lam = f is a
+    fixed point and the error propagates by the dense product
+    prod_q (I - W_q L_j): u_s - v = E (u_0 - v)."""
+    _, H = torus_small
+    lv = H.levels[j]
+    L = lv.L.toarray()
+    rng = np.random.default_rng(40 + j)
+    v = rng.standard_normal(lv.N)
+    lam = 0.7
+    f = L @ v + lv.b * lam
+    omega = _weights(lv.N, 3, 41 + j)
+    ops = vcycle.Fp64Ops(H)
+    ops.learned = {j: omega}
+    u0 = rng.standard_normal(lv.N)
+    u = vcycle.learned_sweep(ops, u0.copy(), f, j, lam)
+    ref = v + _step_product(L, omega, False) @ (u0 - v)
+    assert np.allclose(u, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
+def test_bordered_cycle_post_smoothing_uses_the_coarse_multiplier(torus_small):
+    """Bordered V-cycle with learned smoothing on levels 0 and 1: with e_c the
+    level-0 vector right after the coarse correction and mu the multiplier
+    correction the cycle returns, the post-smoothed residual is
+    prod_q (I - L W_q) (r - L e_c - b mu) (the smoother holds mu fixed)."""
+    _, H = torus_small
+    lv = H.levels[0]
+    L = lv.L.toarray()
+    ops = vcycle.Fp64Ops(H)
+    ops.learned = {0: _weights(lv.N, 3, 50), 1: _weights(H.levels[1].N, 2, 51)}
+    rng = np.random.default_rng(52)
+    r, rho = rng.standard_normal(lv.N), 0.3
+    cap = []
+    z, mu = vcycle.vcycle(ops, r, rho, capture=cap)
+    assert abs(mu) > 1e-3
+    r_mid = r - L @ cap[0] - lv.b * mu
+    ref = _step_product(L, ops.learned[0], True) @ r_mid
+    out = r - L @ z - lv.b * mu
+    assert np.allclose(out, ref, rtol=0, atol=1e-10 * np.abs(ref).max())
+
+
+def test_bordered_two_level_cycle_by_definition():
+    """Two levels, learned smoothing on level 0, V(1,1): z = e_1 + P e_c + post,
+    with e_1 the s steps from zero (no multiplier), (e_c, mu) the exact solution
+    of the coarse bordered system [L_c b_c; b_c^T 0] for (R(r - L e_1),
+    rho - b . e_1), and the post-smoother's s steps with mu fixed; every step
+    written as a dense affine map."""
+    wl = synth.torus_workload(700)
+    wl.params["n_min"] = 100
+    H = hierarchy.build(wl.xyz, wl.normals, wl.params)
+    assert len(H.levels) == 2
+    lv, cl = H.levels
+    L, P, R = lv.L.toarray(), lv.P.toarray(), lv.R.toarray()
+    Lc, bc, b = cl.L.toarray(), cl.b, lv.b
+    N = lv.N
+    omega = _weights(N, 3, 60)
+    rng = np.random.default_rng(61)
+    r, rho = rng.standard_normal(N), -0.4
+    # s steps from zero: u_s = G r, G = sum_q (prod_{p>q} (I - W_p L)) W_q
+    Ws = [np.diag(omega[:, q] / np.diag(L)) for q in range(3)]
+    G = np.zeros((N, N))
+    for q in range(3):
+        G = (np.eye(N) - Ws[q] @ L) @ G + Ws[q]
+    e1 = G @ r
+    K = np.block([[Lc, bc[:, None]], [bc[None, :], np.zeros((1, 1))]])
+    sol = np.linalg.solve(K, np.concatenate([R @ (r - L @ e1), [rho - b @ e1]]))
+    e2, mu = e1 + P @ sol[:-1], sol[-1]
+    z_ref = e2 + G @ (r - L @ e2 - b * mu)
+    ops = vcycle.Fp64Ops(H)
+    ops.learned = omega
+    z, mu_o = vcycle.vcycle(ops, r, rho)
+    assert abs(mu_o - mu) <= 1e-10 * abs(mu)
+    assert np.allclose(z, z_ref, rtol=0, atol=1e-10 * np.abs(z_ref).max())
+
+
+def test_bordered_snapshots_follow_the_bordered_iteration(torus_small):
+    """Bordered snapshots: the iterate x = (e, mu) follows x <- x + M(-A x)
+    with the bordered operator and preconditioner (from (start, 0)); each
+    snapshot is e + the level-0 vector captured right after the coarse
+    correction of the cycle applied to -A x."""
+    _, H = torus_small
+    lv = H.levels[0]
+    rng = np.random.default_rng(70)
+    e0 = rng.standard_normal(lv.N)
+    S = learned.snapshots(H, e0[None, :], 3)
+    ops = vcycle.Fp64Ops(H)
+    A = vcycle.make_operator(H)
+    M = vcycle.make_preconditioner(ops, H.problem)
+    x = np.concatenate([e0, [0.0]])
+    for t in range(3):
+        ax = A(x)
+        cap = []
+        vcycle.vcycle(ops, -ax[:-1], -ax[-1], capture=cap)
+        assert np.allclose(S[t], x[:-1] + cap[0], rtol=0, atol=1e-10 * np.abs(S[t]).max())
+        x = x + M(-ax)
+        if t == 0:
+            assert abs(x[-1]) > 1e-6          # later iterations carry a multiplier
+
+
+def test_bordered_omega_gradient_matches_finite_differences(torus_small):
+    """The loss on bordered snapshots (the torus Laplacian, singular) and its
+    adjoint gradient against central differences."""
+    _, H = torus_small
+    L = H.levels[0].L
+    S = learned.snapshots(H, np.random.default_rng(80).standard_normal((2, L.shape[0])), 2)
+    rng = np.random.default_rng(81)
+    omega = 0.5 + 0.3 * rng.random((L.shape[0], 3))
+    loss, g = learned.loss_and_grad_omega(L, omega, S)
+    for _ in range(10):
+        i, q = rng.integers(L.shape[0]), rng.integers(3)
+        h = 1e-4                          # loss ~1e-2: smaller steps drown in rounding
+        op, om = omega.copy(), omega.copy()
+        op[i, q] += h
+        om[i, q] -= h
+        fd = (learned.loss_and_grad_omega(L, op, S)[0] - learned.loss_and_grad_omega(L, om, S)[0]) / (2 * h)
+        assert abs(fd - g[i, q]) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(g).max())
