@@ -207,7 +207,7 @@ mgm_status mgm_level_op(mgm_handle h, int32_t op, int32_t level, double *d_x,
                         int32_t reverse, void *stream);
 
 /* Learned per-node Chebyshev smoother, one per smoothed level (an extension;
- * the paper smooths with Gauss-Seidel, Sec. 4.3). Screened problems only.
+ * the paper smooths with Gauss-Seidel, Sec. 4.3).
  * Smoother: s Richardson steps e <- e + omega_{q,i} D^-1 (f - L e), with
  * omega_{q,i} = omega_q (1 + 0.5 tanh(o_{q,i})), omega_q = 1/theta_q the
  * reciprocal Chebyshev roots on [lam/4, 1.1 lam] (lam: 20-step power
@@ -221,7 +221,13 @@ mgm_status mgm_level_op(mgm_handle h, int32_t op, int32_t level, double *d_x,
  * level's own n nearest points (tangent-plane offsets with the points'
  * normals) and the Galerkin operator's entries L_j(i, k) / |L_j(i, i)| at those
  * points (0 off the pattern); its snapshots come from the cycle of the
- * sub-hierarchy that starts at level j, on L_j e = 0. */
+ * sub-hierarchy that starts at level j, on L_j e = 0.
+ * Bordered Poisson problem (Sec. 4.4): each Richardson step holds the
+ * multiplier fixed, like the Gauss-Seidel sweep (f - L e - b_j mu_j with the
+ * visit's mu_j; zero on a pre-smoothing from e = 0); snapshots and the
+ * measured factors come from MGM iterations on the level's homogeneous
+ * bordered system [L_j b_j; b_j^T 0](e, mu) = 0 started from (start, 0), the
+ * snapshots being the e parts; the loss is unchanged. */
 typedef struct {
   int32_t  steps;           /* Adam steps (0: prepare snapshots/estimate only) */
   double   lr;              /* Adam learning rate, e.g. 1e-3 */
@@ -250,8 +256,9 @@ typedef struct {
  *   i.e. of MGM_EX_COARSE_IDX of the level above);
  *   h_loss_hist: nullable host array of steps+1 losses (entry k: before the
  *   (k+1)-th Adam step; the last: after training).
- * Errors: MGM_E_ARG (Poisson problem, bad options, layer too wide: stencil
- * size above 31). Synchronises the stream. */
+ * Errors: MGM_E_ARG (bad options, layer too wide: the MLP's parameters above
+ * 64 KiB, i.e. a stencil above 59 points with s = 8, above 61 with s = 3).
+ * Synchronises the stream. */
 mgm_status mgm_train_smoother(mgm_handle h, const mgm_train_opts *opts, const double *d_starts,
                               mgm_train_info *info, double *h_loss_hist, void *stream);
 

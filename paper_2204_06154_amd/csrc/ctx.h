@@ -203,10 +203,12 @@ void mdot(mgm_ctx* c, int64_t n, const double* V, int64_t ld, int k, const doubl
 void host_wait(hipStream_t st);
 void to_host(mgm_ctx* c, const double* d, int k, hipStream_t st);
 // z = M_j v for FP64 vectors in level j's permuted order: the cycle of the
-// sub-hierarchy that starts at level j (j >= 1; screened problems), run
-// eagerly in the handle's precision.
+// sub-hierarchy that starts at level j (j >= 1), run eagerly in the handle's
+// precision; bordered problems: n_j + 1 entries, the multiplier (constraint
+// residual in v, multiplier correction in z) at index n_j.
 void precond_level(mgm_ctx* c, int j, const double* v, double* z, hipStream_t st);
-// y = L_j x, FP64, level j's permuted order (no border).
+// y = A_j x, FP64, level j's permuted order: L_j, or bordered the level's
+// [L_j b_j; b_j^T 0] on n_j + 1 entries.
 void spmv_level64(mgm_ctx* c, int j, const double* x, double* y, hipStream_t st);
 inline bool learned_on(const mgm_ctx* c, int j) { return j < int(c->ls.size()) && c->ls[j].active; }
 void need_device(const mgm_ctx* c);

@@ -592,10 +592,12 @@ static void interp_add(mgm_ctx* c, int j, hipStream_t st, bool accumulate = fals
                      bord ? c->mu + j + 1 : nullptr, bord ? c->mu + j : nullptr, accumulate ? 1 : 0);
 }
 
-// Fine-level learned smoother: s Richardson steps with per-node step weights
-// (ping-pong between e and a scratch vector, the result left in e).
+// Learned smoother of level j: s Richardson steps with per-node step weights
+// (ping-pong between e and a scratch vector, the result left in e). With
+// border (bordered system) the multiplier is held fixed at *lam, as in the
+// Gauss-Seidel sweep.
 template <typename V, typename S, bool SC>
-static void learned_sweep(mgm_ctx* c, int j, hipStream_t st, bool zero_start = false) {
+static void learned_sweep(mgm_ctx* c, int j, hipStream_t st, bool border, const double* lam, bool zero_start = false) {
   using P = Prec<V, S, SC>;
   DevLevel& d = c->lv[j];
   const LearnedLevel& L = c->ls[j];
@@ -605,12 +607,23 @@ static void learned_sweep(mgm_ctx* c, int j, hipStream_t st, bool zero_start = f
                                                            : static_cast<const void*>(L.om32));
   const unsigned g = nblk(int64_t(d.n) * d.G);
   auto step = [&](int q, const S* in, S* out) {
-    if (d.patched)
-      rowop_patch_launch<V, S, SC, kRowRichardson, false, false>(d, P::pval(d), P::f(d), in, out, nullptr, nullptr,
-                                                                 nullptr, st, P::dinv(d), om + size_t(q) * d.n);
-    else
-      DISPATCH_G(d.G, hipLaunchKernelGGL((k_richardson<V, S, GG, SC>), dim3(g), dim3(kBlock), 0, st, d.n, d.W, d.rowptr,
-                                         d.col, P::val(d), d.s16, P::dinv(d), om + size_t(q) * d.n, P::f(d), in, out));
+    const S* omq = om + size_t(q) * d.n;
+    if (d.patched) {
+      if (border)
+        rowop_patch_launch<V, S, SC, kRowRichardson, false, true>(d, P::pval(d), P::f(d), in, out, P::b(d), lam, nullptr,
+                                                                  st, P::dinv(d), omq);
+      else
+        rowop_patch_launch<V, S, SC, kRowRichardson, false, false>(d, P::pval(d), P::f(d), in, out, nullptr, nullptr,
+                                                                   nullptr, st, P::dinv(d), omq);
+    } else if (border) {
+      DISPATCH_G(d.G, hipLaunchKernelGGL((k_richardson<V, S, GG, SC, true>), dim3(g), dim3(kBlock), 0, st, d.n, d.W,
+                                         d.rowptr, d.col, P::val(d), d.s16, P::dinv(d), omq, P::f(d), in, out, P::b(d),
+                                         lam));
+    } else {
+      DISPATCH_G(d.G, hipLaunchKernelGGL((k_richardson<V, S, GG, SC, false>), dim3(g), dim3(kBlock), 0, st, d.n, d.W,
+                                         d.rowptr, d.col, P::val(d), d.s16, P::dinv(d), omq, P::f(d), in, out,
+                                         (const S*)nullptr, (const double*)nullptr));
+    }
   };
   int q = 0;
   S* a = e;
@@ -653,7 +666,7 @@ static void cycle_enqueue(mgm_ctx* c, int j, int kind, bool zero_start, hipStrea
   const bool zg = zero_start && (d.patched || learned) && c->p.nu1 > 0;
   if (zero_start && !zg) hipLaunchKernelGGL((k_fill<S>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, P::e(d), S(0));
   for (int s = 0; s < c->p.nu1; ++s) {
-    if (learned) learned_sweep<V, S, SC>(c, j, st, zero_start && s == 0);
+    if (learned) learned_sweep<V, S, SC>(c, j, st, bord && !zero_start, mu, zero_start && s == 0);
     else gs_sweep<V, S, SC>(c, j, c->p.pre_smoother == MGM_GS_BWD, bord && !zero_start, mu, st, zg && s == 0);
   }
   residual_restrict<V, S, SC>(c, j, st, !zero_start);
@@ -665,7 +678,7 @@ static void cycle_enqueue(mgm_ctx* c, int j, int kind, bool zero_start, hipStrea
     hipLaunchKernelGGL((k_gather<S, double>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, (const int32_t*)nullptr, P::e(d),
                        c->capture, (double*)nullptr);
   for (int s = 0; s < c->p.nu2; ++s) {
-    if (learned) learned_sweep<V, S, SC>(c, j, st);
+    if (learned) learned_sweep<V, S, SC>(c, j, st, bord, mu);
     else gs_sweep<V, S, SC>(c, j, c->p.post_smoother == MGM_GS_BWD, bord, mu, st);
   }
 }
@@ -793,28 +806,34 @@ void apply_A(mgm_ctx* c, const double* x, double* y, hipStream_t st) {
   if (bord) mdot(c, d.n, d.b64, 0, 1, x, y + d.n, st);  // constraint row b . x
 }
 
+// y = A_j x on a level's CSR (FP64, permuted order); bordered: the level's
+// bordered operator [L_j b_j; b_j^T 0], the multiplier at index n_j.
 void spmv_level64(mgm_ctx* c, int j, const double* x, double* y, hipStream_t st) {
   DevLevel& d = c->lv[j];
+  const bool bord = c->p.problem == MGM_POISSON;
   unsigned g = nblk(int64_t(d.n) * d.G);
-  DISPATCH_G(d.G, hipLaunchKernelGGL((k_spmv<double, double, GG, false, false>), dim3(g), dim3(kBlock), 0, st, d.n, d.W,
+  DISPATCH_G(d.G, if (bord) hipLaunchKernelGGL((k_spmv<double, double, GG, false, true>), dim3(g), dim3(kBlock), 0, st, d.n,
+                                               d.W, d.rowptr, d.col, d.v64, nullptr, x, y, d.b64, x + d.n);
+             else hipLaunchKernelGGL((k_spmv<double, double, GG, false, false>), dim3(g), dim3(kBlock), 0, st, d.n, d.W,
                                      d.rowptr, d.col, d.v64, nullptr, x, y, nullptr, nullptr));
+  if (bord) mdot(c, d.n, d.b64, 0, 1, x, y + d.n, st);  // constraint row b_j . x
 }
 
 template <typename V, typename S, bool SC>
 static void precond_level_t(mgm_ctx* c, int j, const double* v, double* z, hipStream_t st) {
   using P = Prec<V, S, SC>;
   DevLevel& d = c->lv[j];
+  const bool bord = c->p.problem == MGM_POISSON;
   const unsigned g = nblk(d.n);
   hipLaunchKernelGGL((k_gather<double, S>), dim3(g), dim3(kBlock), 0, st, d.n, (const int32_t*)nullptr, v, P::f(d),
-                     (double*)nullptr);
+                     bord ? c->rho + j : nullptr);
   cycle_enqueue<V, S, SC>(c, j, MGM_CYCLE_V, true, st);
   hipLaunchKernelGGL((k_scatter<S, double>), dim3(g), dim3(kBlock), 0, st, d.n, (const int32_t*)nullptr, P::e(d), z,
-                     (double*)nullptr);
+                     bord ? c->mu + j : nullptr);
 }
 
 void precond_level(mgm_ctx* c, int j, const double* v, double* z, hipStream_t st) {
   if (j < 1 || j + 1 >= int(c->lv.size())) throw Error(MGM_E_ARG, "sub-cycle level out of range");
-  if (c->p.problem == MGM_POISSON) throw Error(MGM_E_ARG, "sub-cycles: screened problems only");
   const int prec = c->p.precision;
   build_precision(c, prec);
   if (prec == MGM_FP64) precond_level_t<double, double, false>(c, j, v, z, st);

@@ -21,19 +21,23 @@ constexpr int kHid = 64;
 
 __host__ __device__ inline int mlp_param_count(int nin, int s) { return (nin + 1) * kHid + (kHid + 1) * kHid + (kHid + 1) * s; }
 
-// e_out = e_in + omega * dinv * (f - A e_in)   (one Richardson step)
-template <typename V, typename S, int G, bool SCALED>
+// e_out = e_in + omega * dinv * (f - A e_in)   (one Richardson step); with
+// BORDER the bordered system's multiplier is held fixed at *lam:
+// e_out = e_in + omega * dinv * (f - (A e_in + b *lam))
+template <typename V, typename S, int G, bool SCALED, bool BORDER>
 __global__ __launch_bounds__(kBlock) void k_richardson(int n, int W, const int32_t* __restrict__ rowptr,
                                                        const int32_t* __restrict__ col, const V* __restrict__ val,
                                                        const float* __restrict__ scale, const S* __restrict__ dinv,
                                                        const S* __restrict__ omega, const S* __restrict__ f,
-                                                       const S* __restrict__ ein, S* __restrict__ eout) {
+                                                       const S* __restrict__ ein, S* __restrict__ eout,
+                                                       const S* __restrict__ b, const double* __restrict__ lam) {
   const int gid = blockIdx.x * kBlock + threadIdx.x;
   const int row = gid / G;
   const int lane = gid % G;
   if (row >= n) return;
   const S fr = f[row], di = dinv[row], om = omega[row], er = ein[row];
   S acc = row_dot<V, S, G, SCALED>(row, lane, W, rowptr, col, val, scale, ein);
+  if (BORDER) acc += b[row] * S(*lam);
   if (lane == 0) eout[row] = er + om * di * (fr - acc);
 }
 
@@ -244,13 +248,15 @@ __global__ __launch_bounds__(kBlock) void k_mlp_backward(int n, int nin, int s, 
 }
 
 // C_partial[blk] = sum over the block's node chunk of A[n]^T B[n]
-// (A: N x ka, B: N x kb, row-major FP32, ka*kb <= kAtbMaxC; C: ka x kb).
-// Tiles of kAtbTile nodes of A and B are staged in LDS (coalesced loads);
-// each thread owns a fixed set of C entries and sums over the nodes in order,
-// so the result is deterministic.
+// (A: N x ka, B: N x kb, row-major FP32, ka, kb <= kAtbMaxK; C: ka x kb).
+// blockIdx.x picks the node chunk, blockIdx.y a group of kAtbPer * kBlock
+// entries of C. Tiles of kAtbTile nodes of A and B are staged in LDS
+// (coalesced loads); each thread owns a fixed set of C entries and sums over
+// the nodes in order, so the result is deterministic.
 constexpr int kAtbChunk = 2048;
 constexpr int kAtbTile = 32;
 constexpr int kAtbMaxK = 200;
+constexpr int kAtbPer = 24;  // C entries per thread
 __global__ __launch_bounds__(kBlock) void k_atb_partial(int n, int ka, int kb, const float* __restrict__ A,
                                                         const float* __restrict__ B, float* __restrict__ partial) {
   __shared__ float sa[kAtbTile * kAtbMaxK];
@@ -258,7 +264,8 @@ __global__ __launch_bounds__(kBlock) void k_atb_partial(int n, int ka, int kb, c
   const int n0 = blockIdx.x * kAtbChunk;
   const int n1 = min(n, n0 + kAtbChunk);
   const int nc = ka * kb;
-  constexpr int kPer = 24;  // C entries per thread (ka*kb <= 256*24)
+  constexpr int kPer = kAtbPer;
+  const int e0 = int(blockIdx.y) * kPer * kBlock + int(threadIdx.x);
   float acc[kPer];
 #pragma unroll
   for (int r = 0; r < kPer; ++r) acc[r] = 0.0f;
@@ -269,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_atb_partial(int n, int ka, int kb, c
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kPer; ++r) {
-      const int e = threadIdx.x + r * kBlock;
+      const int e = e0 + r * kBlock;
       if (e < nc) {
         const int a = e / kb, b = e % kb;
         float s = acc[r];
@@ -282,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_atb_partial(int n, int ka, int kb, c
   float* out = partial + size_t(blockIdx.x) * nc;
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
-    const int e = threadIdx.x + r * kBlock;
+    const int e = e0 + r * kBlock;
     if (e < nc) out[e] = acc[r];
   }
 }

@@ -62,7 +62,9 @@ void ensure_learned_buffers(mgm_ctx* c, int j, int s, int T) {
     L.t = track(c, dalloc<float>(n));
     L.scal = track(c, dalloc<double>(16));
     const int nb = (n + kAtbChunk - 1) / kAtbChunk;
-    L.atb = track(c, dalloc<float>(size_t(nb) * (nin + 1) * kHid));
+    // partials of the widest product: the first layer's (nin + 1) x 64 or the
+    // second's 65 x 64 (the last layer's 65 x s is smaller)
+    L.atb = track(c, dalloc<float>(size_t(nb) * std::max(nin + 1, kHid + 1) * kHid));
   }
   if (!c->e_tmp64) {  // shared by all levels: sized for the fine level
     c->e_tmp64 = track(c, dalloc<double>(c->lv[0].n + 1));
@@ -193,9 +195,10 @@ void fdot(mgm_ctx* c, int n, const float* x, const float* y, double* out, hipStr
 }
 
 void atb(mgm_ctx* c, LearnedLevel& L, int n, int ka, int kb, const float* A, const float* B, float* out, hipStream_t st) {
-  if (ka > kAtbMaxK || kb > kAtbMaxK || ka * kb > 24 * kBlock) throw Error(MGM_E_ARG, "learned smoother: layer too wide");
+  if (ka > kAtbMaxK || kb > kAtbMaxK) throw Error(MGM_E_ARG, "learned smoother: layer too wide");
   const int nb = (n + kAtbChunk - 1) / kAtbChunk;
-  hipLaunchKernelGGL(k_atb_partial, dim3(nb), dim3(kBlock), 0, st, n, ka, kb, A, B, L.atb);
+  const int ng = (ka * kb + kAtbPer * kBlock - 1) / (kAtbPer * kBlock);
+  hipLaunchKernelGGL(k_atb_partial, dim3(nb, ng), dim3(kBlock), 0, st, n, ka, kb, A, B, L.atb);
   hipLaunchKernelGGL(k_reduce_cols, dim3(nblk(ka * kb)), dim3(kBlock), 0, st, nb, ka * kb, L.atb, out);
 }
 
@@ -277,7 +280,8 @@ void compute_omega(mgm_ctx* c, int j, hipStream_t st) {
   hipLaunchKernelGGL((k_omega<float>), dim3(nblk(n)), dim3(kBlock), 0, st, n, s, L.O, L.wcheb_d, L.om32);
 }
 
-// y = L_j x (FP64, permuted order; the fine level through the outer operator)
+// y = A_j x (FP64, permuted order; the fine level through the outer operator;
+// bordered: n_j + 1 entries, the multiplier at index n_j)
 void apply_level(mgm_ctx* c, int j, const double* x, double* y, hipStream_t st) {
   if (j == 0) apply_A(c, x, y, st);
   else spmv_level64(c, j, x, y, st);
@@ -290,11 +294,12 @@ void precond_at(mgm_ctx* c, int j, const double* v, double* z, hipStream_t st) {
   else precond_level(c, j, v, z, st);
 }
 
-// convergence factor of the stationary MGM iteration on L_j e = 0 from `e0`
-// (permuted FP64): (|L_j e_k| / |L_j e_0|)^(1/k)
+// convergence factor of the stationary MGM iteration on A_j e = 0 from `e0`
+// (permuted FP64; bordered: n_j + 1 entries, the multiplier last):
+// (|A_j e_k| / |A_j e_0|)^(1/k)
 double stationary_rate(mgm_ctx* c, int j, const double* e0, int k, hipStream_t st) {
   DevLevel& d = c->lv[j];
-  const int n = d.n;
+  const int n = d.n + (c->p.problem == MGM_POISSON ? 1 : 0);
   double* e = c->vecs + 4 * c->ld;
   double* r = c->vecs + 5 * c->ld;
   double* z = c->vecs + 6 * c->ld;
@@ -375,13 +380,16 @@ mgm_status mgm_train_smoother(mgm_handle h, const mgm_train_opts* o, const doubl
     need_device(h);
     HIPCHECK(hipSetDevice(h->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (h->p.problem != MGM_SCREENED) throw Error(MGM_E_ARG, "learned smoother: screened problems only");
     const int j = o->level;
     if (j < 0 || j + 1 >= int(h->lv.size())) throw Error(MGM_E_ARG, "learned smoother: level out of range");
     ensure_levels(h);
     LearnedLevel& L = h->ls[j];
     DevLevel& d = h->lv[j];
     const int n = d.n;
+    // bordered problems iterate on the level's bordered system: the
+    // multiplier rides at index n (zero in every start)
+    const bool bord = h->p.problem == MGM_POISSON;
+    const int nv = n + (bord ? 1 : 0);
     ensure_ws(h, 1);
     build_precision(h, MGM_FP32);
     build_precision(h, MGM_FP64);
@@ -392,6 +400,10 @@ mgm_status mgm_train_smoother(mgm_handle h, const mgm_train_opts* o, const doubl
       build_features(h, j, perm);
       build_transpose(h, j);
     }
+    // the MLP kernels stage every parameter in LDS (64 KiB per workgroup) and
+    // the gradient products take at most kAtbMaxK columns a side
+    if (size_t(mlp_param_count(L.nin, o->s)) * sizeof(float) > 65536 || L.nin + 1 > kAtbMaxK)
+      throw Error(MGM_E_ARG, "learned smoother: layer too wide (MLP parameters above 64 KiB of LDS)");
     const bool was_active = L.active;
     const bool fresh = !L.params || L.s != o->s;
     const int T = o->n_starts * o->iters_per_start;
@@ -421,16 +433,17 @@ mgm_status mgm_train_smoother(mgm_handle h, const mgm_train_opts* o, const doubl
       for (int s0 = 0; s0 < o->n_starts; ++s0) {
         hipLaunchKernelGGL((k_gather<double, double>), dim3(nblk(n)), dim3(kBlock), 0, st, n, d.perm, d_starts + size_t(s0) * n,
                            e, (double*)nullptr);
+        if (bord) hipLaunchKernelGGL((k_fill<double>), dim3(1), dim3(kBlock), 0, st, 1, e + n, 0.0);
         for (int it = 0; it < o->iters_per_start; ++it, ++t) {
           apply_level(h, j, e, r, st);
-          hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(kBlock), 0, st, n, -1.0, r, 0.0, r, r);
+          hipLaunchKernelGGL(k_axpby, dim3(nblk(nv)), dim3(kBlock), 0, st, nv, -1.0, r, 0.0, r, r);
           h->capture = cap;
           h->capture_level = j;
           precond_at(h, j, r, z, st);
           h->capture = nullptr;
           h->capture_level = 0;
           hipLaunchKernelGGL(k_add_cast, dim3(nblk(n)), dim3(kBlock), 0, st, n, e, cap, L.snap + size_t(t) * n);
-          hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(kBlock), 0, st, n, 1.0, e, 1.0, z, e);
+          hipLaunchKernelGGL(k_axpby, dim3(nblk(nv)), dim3(kBlock), 0, st, nv, 1.0, e, 1.0, z, e);
           // c_t = |L e_t|^2 in the training precision
           SPMV_F32(d.G, n, d.W, d.rowptr, d.col, d.v32, L.snap + size_t(t) * n, L.y);
           fdot(h, n, L.y, L.y, L.c + t, st);
@@ -465,6 +478,7 @@ mgm_status mgm_train_smoother(mgm_handle h, const mgm_train_opts* o, const doubl
       double* e0 = h->vecs + 8 * h->ld;
       hipLaunchKernelGGL((k_gather<double, double>), dim3(nblk(n)), dim3(kBlock), 0, st, n, d.perm, d_starts, e0,
                          (double*)nullptr);
+      if (bord) hipLaunchKernelGGL((k_fill<double>), dim3(1), dim3(kBlock), 0, st, 1, e0 + n, 0.0);
       set_active(h, j, false);
       info->rate_gs = stationary_rate(h, j, e0, 6, st);
       set_active(h, j, true);

@@ -23,7 +23,8 @@ namespace {
 //   operator's multiplier column); with BDOT the partial sums of b_i x_i as
 //   above (its constraint row).
 // MODE kRowRichardson: out = x + omega_i dinv_i (f - A x), one step of the
-//   learned per-node smoother (out and x distinct).
+//   learned per-node smoother (out and x distinct); with BORDER the
+//   multiplier is held fixed, f - A x - b_i * (*lam).
 constexpr int kRowResidual = 0;
 constexpr int kRowApply = 1;
 constexpr int kRowRichardson = 2;
@@ -107,6 +108,7 @@ __global__ __launch_bounds__(kRowHalf * kPatchG) void k_rowop_patch(
       out[row] = f[row] - acc;
       if (BDOT) bx = double(b[row]) * double(xl[t]);
     } else if (MODE == kRowRichardson) {
+      if (BORDER) acc += b[row] * S(*lam);  // multiplier held fixed: f - A x - b lambda
       out[row] = xl[t] + omega[row] * dinv[row] * (f[row] - acc);
     } else {
       if (BORDER) acc += b[row] * S(*lam);

@@ -1,0 +1,150 @@
+"""GPU learned smoother on the bordered Poisson system against the oracle.
+
+Workload: the torus family (Poisson-disk points, RBF-FD r^5 + degree 3,
+k = 50, bordered Poisson system of Sec. 4.4) at N = 6000, patch-blocked and
+with plain multicolour levels (gs_block = 0, CSR Richardson kernels). Every
+Richardson step holds the visit's multiplier fixed, as Gauss-Seidel does.
+
+Tolerances as for the screened smoother: the spectral estimate is FP64 on
+both sides (1e-10); loss and gradient come from FP32 training kernels
+against the oracle's FP64 maths on the same bordered snapshots (1e-5 and
+1e-4 relative); with the step weights fixed the cycle is FP64 on both sides
+(1e-10, identical FGMRES iteration counts).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import hierarchy, krylov, learned, vcycle
+from paper_2204_06154_amd import mgm
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _flat(params):
+    W1, b1, W2, b2, W3, b3 = params
+    return np.concatenate([np.vstack([W1, b1[None]]).ravel(), np.vstack([W2, b2[None]]).ravel(),
+                           np.vstack([W3, b3[None]]).ravel()])
+
+
+CASES = {
+    "torus6000": {},
+    "torus6000plain": {"gs_block": 0},
+}
+
+
+def _perturbed(params, seed):
+    """A non-zero last layer, so the step weights vary per node."""
+    rng = np.random.default_rng(seed)
+    params[4] = 0.2 * rng.standard_normal(params[4].shape)
+    params[5] = 0.1 * rng.standard_normal(params[5].shape)
+    return params
+
+
+@pytest.fixture(scope="module", params=list(CASES), ids=list(CASES))
+def setup(request):
+    wl = synth.torus_workload(6000)
+    wl.params.update(CASES[request.param])
+    print(f"[gpu-learned-bordered] setting up {request.param}", flush=True)
+    H = hierarchy.build(wl.xyz, wl.normals, wl.params)
+    assert H.problem == "poisson" and len(H.levels) >= 3
+    m = mgm.Mgm(wl.xyz, wl.normals, wl.params, device=0)
+    rng = np.random.default_rng(23)
+    starts = rng.standard_normal((2, H.levels[0].N))
+    d_starts = torch.tensor(starts, device="cuda")
+    info = m.train_smoother(d_starts, steps=0, s=3, iters_per_start=2, seed=9, init=True, activate=0)
+    X = learned.stencil_features(H)
+    p0 = _perturbed(learned.init_params(X.shape[1], 3, seed=9), 24)
+    m.smoother_params(_flat(p0))
+    starts1 = rng.standard_normal((2, H.levels[1].N))
+    info1 = m.train_smoother(torch.tensor(starts1, device="cuda"), steps=0, s=2, iters_per_start=2, seed=11,
+                             init=True, activate=0, level=1)
+    X1 = learned.level_features(H, 1)
+    p1 = _perturbed(learned.init_params(X1.shape[1], 2, seed=11), 25)
+    m.smoother_params(_flat(p1), level=1)
+    f = np.concatenate([wl.f, [0.0]])
+    yield dict(wl=wl, H=H, m=m, f=f, info=(info, info1), X=(X, X1), p=(p0, p1), starts=(starts, starts1),
+               d_starts=d_starts)
+    m.close()
+
+
+@pytest.mark.parametrize("j", [0, 1])
+def test_bordered_loss_and_gradient(setup, j):
+    """Spectral estimate, then loss and gradient on the bordered snapshots
+    (the homogeneous bordered iteration of level j) against the oracle."""
+    H, m = setup["H"], setup["m"]
+    L = H.levels[j].L
+    s = 3 if j == 0 else 2
+    info = setup["info"][j]
+    assert abs(info["lam"] - learned.power_estimate(L)) <= 1e-10 * info["lam"]
+    S = learned.snapshots(H, setup["starts"][j], 2, level=j)
+    w = learned.cheb_omegas(info["lam"], s)
+    loss, g = m.smoother_grad(level=j)
+    loss_ref, grads = learned.total_loss_and_grads(setup["p"][j], setup["X"][j], L, S, w)
+    print(f"[gpu-learned-bordered] level {j}: loss {loss:.6f} (oracle {loss_ref:.6f})", flush=True)
+    assert abs(loss - loss_ref) <= 1e-5 * loss_ref
+    assert np.linalg.norm(g - _flat(grads)) <= 1e-4 * np.linalg.norm(_flat(grads))
+
+
+@pytest.mark.parametrize("mask", [1, 2, 3])
+def test_bordered_cycle_with_learned_levels(setup, mask):
+    """V-cycle with learned smoothing on the levels of `mask` (1: fine, 2:
+    level 1 only, 3: both) against the oracle's bordered cycle with the
+    device's step weights; FGMRES(40) to 1e-10 with the same iteration count,
+    and the solution checked with the oracle's bordered operator."""
+    wl, H, m, f = setup["wl"], setup["H"], setup["m"], setup["f"]
+    m.set_smoother(mask)
+    try:
+        ops = vcycle.Fp64Ops(H)
+        ops.learned = {j: m.export("omega", j).reshape(H.levels[j].N, -1) for j in (0, 1) if (mask >> j) & 1}
+        M = vcycle.make_preconditioner(ops, H.problem)
+        z = m.vcycle(torch.tensor(f, device="cuda")).cpu().numpy()
+        zr = M(f)
+        assert np.max(np.abs(z - zr)) <= 1e-10 * np.abs(zr).max()
+        A = vcycle.make_operator(H)
+        _, info_ref = krylov.fgmres(A, M, f, tol=1e-10, maxit=300)
+        u, inf = m.solve(torch.tensor(f, device="cuda"), rtol=1e-10, maxit=300)
+        print(f"[gpu-learned-bordered] mask {mask}: FGMRES {inf['iters']} (oracle {info_ref.iters})", flush=True)
+        assert inf["status"] == 0 and inf["iters"] == info_ref.iters
+        assert np.linalg.norm(f - A(u.cpu().numpy())) <= 1.01e-10 * np.linalg.norm(f)
+    finally:
+        m.set_smoother(False)
+
+
+def test_bordered_w_cycle_second_visit_holds_the_multiplier(setup):
+    """W cycle: the second visit of level 1 pre-smooths from its current
+    iterate with its multiplier held fixed (the border term in a pre-smoothing
+    sweep); same step weights on a second handle, against the oracle."""
+    wl, H = setup["wl"], setup["H"]
+    params = dict(wl.params, cycle="W")
+    mw = mgm.Mgm(wl.xyz, wl.normals, params, device=0)
+    try:
+        starts1 = torch.tensor(setup["starts"][1], device="cuda")
+        mw.train_smoother(starts1, steps=0, s=2, iters_per_start=2, seed=11, init=True, activate=0, level=1)
+        mw.smoother_params(_flat(setup["p"][1]), level=1)
+        mw.set_smoother(2)
+        ops = vcycle.Fp64Ops(H)
+        ops.learned = {1: mw.export("omega", 1).reshape(H.levels[1].N, -1)}
+        M = vcycle.make_preconditioner(ops, H.problem, cycle="W")
+        f = setup["f"]
+        z = mw.vcycle(torch.tensor(f, device="cuda")).cpu().numpy()
+        zr = M(f)
+        assert np.max(np.abs(z - zr)) <= 1e-10 * np.abs(zr).max()
+    finally:
+        mw.close()
+
+
+def test_bordered_activation_rule(setup):
+    """Training on the bordered system (Adam steps on the device) lowers the
+    loss, and the activation rule compares the measured factors of the
+    bordered stationary iteration."""
+    m = setup["m"]
+    res = m.train_smoother(setup["d_starts"], steps=30, lr=1e-3, s=3, iters_per_start=2, seed=9, init=True,
+                           activate=1)
+    print(f"[gpu-learned-bordered] loss {res['loss_first']:.4f} -> {res['loss_last']:.4f}; factors GS "
+          f"{res['rate_gs']:.3f}, learned {res['rate_learned']:.3f}", flush=True)
+    assert res["loss_last"] < res["loss_first"]
+    assert 0 < res["rate_gs"] < 1 and res["rate_learned"] > 0
+    assert res["active"] == (res["rate_learned"] < res["rate_gs"])
+    m.set_smoother(False)
