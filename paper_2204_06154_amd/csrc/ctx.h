@@ -126,6 +126,8 @@ namespace mgm {
 struct LearnedLevel {
   bool active = false;
   int s = 0, nin = 0, T = 0, adam_t = 0, steps_cap = 0;
+  int snap_cap = 0;   // snapshots (and c_t) that snap / c hold
+  size_t z_cap = 0;   // floats that z holds (snapshots x steps x rows)
   double lam = 0.0;
   std::vector<double> wcheb;
   double* wcheb_d = nullptr;

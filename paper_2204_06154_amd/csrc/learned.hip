@@ -70,11 +70,18 @@ void ensure_learned_buffers(mgm_ctx* c, int j, int s, int T) {
     c->e_tmp64 = track(c, dalloc<double>(c->lv[0].n + 1));
     c->e_tmp32 = track(c, dalloc<float>(c->lv[0].n + 1));
   }
-  if (T > L.T) {
-    L.snap = track(c, dalloc<float>(size_t(T) * n));
-    L.z = track(c, dalloc<float>(size_t(T) * s * n));
-    L.c = track(c, dalloc<double>(T));
-    L.T = T;
+  // snapshots this call makes (T) or keeps from an earlier call (L.T), and the
+  // adjoint's step inputs z for each of them and each of the s steps (s may
+  // differ from the call that made the snapshots)
+  const int tn = std::max(T, L.T);
+  if (tn > L.snap_cap) {
+    L.snap = track(c, dalloc<float>(size_t(tn) * n));
+    L.c = track(c, dalloc<double>(tn));
+    L.snap_cap = tn;
+  }
+  if (size_t(tn) * s * n > L.z_cap) {
+    L.z = track(c, dalloc<float>(size_t(tn) * s * n));
+    L.z_cap = size_t(tn) * s * n;
   }
 }
 
@@ -208,6 +215,7 @@ void train_step(mgm_ctx* c, int j, bool update, double* loss_slot, float lr, hip
   DevLevel& d = c->lv[j];
   LearnedLevel& L = c->ls[j];
   const int n = d.n, s = L.s, nin = L.nin, T = L.T;
+  if (T > L.snap_cap || size_t(T) * s * n > L.z_cap) throw Error(MGM_E_ARG, "learned smoother: training buffers too small");
   const int np = mlp_param_count(nin, s);
   const size_t lds = size_t(np) * sizeof(float);
   hipLaunchKernelGGL(k_mlp_forward, dim3(nblk(n)), dim3(kBlock), lds, st, n, nin, s, L.X, L.params, L.O,

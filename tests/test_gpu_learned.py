@@ -171,3 +171,23 @@ def test_coarse_level_smoother_matches_oracle(setup):
         m.set_smoother(0)
     with pytest.raises(mgm.MgmError):
         m.set_smoother(4)   # level 2 has no trained smoother
+
+
+def test_retraining_with_more_steps_per_sweep(setup):
+    """Snapshots made with s = 2 are kept when the level is retrained with
+    s = 5 and no new starts, so the adjoint's per-step buffers must grow with
+    s: loss and gradient against the oracle on the same snapshots."""
+    wl, H, m, info, L, X, S, d_starts = setup
+    m.train_smoother(d_starts, steps=0, s=2, iters_per_start=2, seed=9, init=True, activate=0)
+    res = m.train_smoother(None, steps=0, s=5, seed=9, init=True, activate=0)
+    w = learned.cheb_omegas(res["lam"], 5)
+    p = learned.init_params(X.shape[1], 5, seed=9)
+    rng = np.random.default_rng(12)
+    p[4] = 0.2 * rng.standard_normal(p[4].shape)
+    m.smoother_params(_flat(p))
+    loss, g = m.smoother_grad()
+    loss_ref, grads = learned.total_loss_and_grads(p, X, L, S, w)
+    assert abs(loss - loss_ref) <= 1e-5 * loss_ref
+    assert np.linalg.norm(g - _flat(grads)) <= 1e-4 * np.linalg.norm(_flat(grads))
+    res = m.train_smoother(None, steps=5, lr=1e-3, s=5, init=False, activate=0)
+    assert res["loss_last"] < res["loss_first"]

@@ -120,6 +120,8 @@ def test_bordered_w_cycle_second_visit_holds_the_multiplier(setup):
     params = dict(wl.params, cycle="W")
     mw = mgm.Mgm(wl.xyz, wl.normals, params, device=0)
     try:
+        with pytest.raises(mgm.MgmError, match="no snapshots"):  # a fresh level has none to train on
+            mw.train_smoother(None, steps=3, s=2, level=1)
         starts1 = torch.tensor(setup["starts"][1], device="cuda")
         mw.train_smoother(starts1, steps=0, s=2, iters_per_start=2, seed=11, init=True, activate=0, level=1)
         mw.smoother_params(_flat(setup["p"][1]), level=1)
