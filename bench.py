@@ -14,6 +14,12 @@ V-cycles (FP32; FP16 values with FP32 row scales) are timed in turn; `value`
 is the solve time with the FP32 V-cycle (FP64 Krylov), the FP64 solve time
 and the ratio are reported beside it.
 
+learned_smoothers: the same FP32 solve with learned per-node Chebyshev
+smoothers (an extension; the paper smooths with Gauss-Seidel): each smoothed
+level trains its own network on the GPU, keeps it when its measured
+convergence factor beats Gauss-Seidel's, and the solve is timed again (not
+`value`, which stays the paper's method).
+
 roofline: the dominant kernel is the patch-blocked Gauss-Seidel launch
 (k_gs_patch, FP32 here: about 70% of the V-cycle's device time). Every
 smoother launch of one V-cycle (all smoothed levels, pre- and post-sweeps) is
@@ -50,7 +56,7 @@ HBM_PEAK_GBS = 8000.0
 # `bench.py --workload traffic` (summary and commands in
 # profiles/gs_patch_torus160k_traffic.md): bytes per launch, valid only for
 # the kernel source it was measured on (SHA-256 over lane_ops.h + gs_patch.h).
-GS_TRAFFIC = {"source_sha256": "3b9def0c998ff9e09a5ca3a668b8293e548cd3cc9747ea6b2773183f06ca592e", "bytes_per_launch": 23420857,
+GS_TRAFFIC = {"source_sha256": "8e1570851bb1354ba1acf1cb3ef3725f2704e0006f95b807967bb25bb11e4b09", "bytes_per_launch": 23408328,
               "summary": "profiles/gs_patch_torus160k_traffic.md"}
 
 
@@ -187,6 +193,42 @@ def bench_learned(args):
         f"coarse rates {[(l['rate_gs'], l['rate_learned']) for l in levels]}")
     print(json.dumps(out), flush=True)
     m.close()
+
+
+def bench_torus_learned(args, m, f, u, sizes, prec, gs):
+    """The torus solve with learned per-node Chebyshev smoothers: every
+    smoothed level trains its own network on the GPU (4 random starts x 2
+    MGM iterations of snapshots on its bordered sub-hierarchy, Adam) with s
+    Richardson steps per sweep, each holding the multiplier fixed; a level
+    keeps it when its measured convergence factor beats Gauss-Seidel's."""
+    import torch
+    m.set_precision(prec)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2204)
+    levels, mask = [], 0
+    t0 = time.perf_counter()
+    for j in range(len(sizes) - 1):
+        sj = torch.randn((4, sizes[j]), generator=gen, device="cuda", dtype=torch.float64)
+        tj = m.train_smoother(sj, steps=args.learned_steps, lr=1e-3, s=args.learned_s, iters_per_start=2,
+                              seed=5 + j, init=True, activate=1, level=j)
+        levels.append({"level": j, "rate_gs": round(tj["rate_gs"], 4), "rate_learned": round(tj["rate_learned"], 4),
+                       "loss_first": round(tj["loss_first"], 5), "loss_last": round(tj["loss_last"], 5),
+                       "active": tj["active"]})
+        if tj["active"]:
+            mask |= 1 << j
+    train_s = time.perf_counter() - t0
+    m.set_smoother(mask)
+    ms, info = timed_solves(m, f, u, "fgmres", args.steps, args.warmup, restart=40, maxit=400, rtol=1e-10)
+    vc_ms, _ = m.time_kernel("vcycle", 0, reps=20)
+    m.set_smoother(False)
+    out = {"precision": prec, "s": args.learned_s, "adam_steps": args.learned_steps, "training_s": round(train_s, 2),
+           "level_mask": mask, "levels": levels, "ms": round(ms, 3), "iters": info["iters"],
+           "rel_res_true": float(f"{info['rel_res_true']:.4g}"), "vcycle_us": round(vc_ms * 1e3, 1),
+           "speedup_vs_gs": round(gs["ms"] / ms, 3)}
+    log(f"learned smoothers (mask {mask:#x}, s={args.learned_s}, trained in {train_s:.1f} s): {ms:.2f} ms/solve, "
+        f"{info['iters']} iters, V-cycle {vc_ms * 1e3:.0f} us; factors "
+        f"{[(l['rate_gs'], l['rate_learned']) for l in levels]}")
+    return out
 
 
 def bench_sphere1m(args):
@@ -530,6 +572,9 @@ def main():
                                                  "setup", "geodesic", "table2"],
                     default="torus")
     ap.add_argument("--train-steps", type=int, default=200)
+    ap.add_argument("--learned-steps", type=int, default=200,
+                    help="Adam steps per level of the torus run's learned smoothers (0: skip that part)")
+    ap.add_argument("--learned-s", type=int, default=2, help="Richardson steps per sweep of the torus run's learned smoothers")
     ap.add_argument("--vcycle-precision", default="fp32", help="V-cycle precision of the learned and sbdf2 workloads")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -619,6 +664,8 @@ def main():
         f"-> {gs_gbs:.0f} GB/s; fine level alone {gs0_ms * 1e3:.2f} us, {gs0_bytes / 1e6:.2f} MB -> {gs0_gbs:.0f} GB/s")
     log(f"SpMV (fp64, fine level): {sp_ms * 1e3:.2f} us, {sp_bytes / 1e6:.1f} MB -> {sp_gbs:.0f} GB/s")
 
+    learned = bench_torus_learned(args, m, f, u, sizes, main_prec, results[main_prec]) if args.learned_steps > 0 else None
+
     # batched per-node weight solves (500,000 star-surface stencils, n=50, r^3 + degree 3: 60x60 systems)
     bw = None
     if args.weights_n > 0:
@@ -688,6 +735,7 @@ def main():
                      "algorithmic_bytes_per_launch": round(gs_bytes), "us_per_launch": round(gs_ms * 1e3, 3),
                      "fine_level": {"us_per_launch": round(gs0_ms * 1e3, 3), "bytes_per_launch": round(gs0_bytes),
                                     "GBps": round(gs0_gbs, 1)}},
+        "learned_smoothers": learned,
         "batched_weights": bw,
         "cpu_baseline": cpu,
     }

@@ -247,50 +247,79 @@ __global__ __launch_bounds__(kBlock) void k_mlp_backward(int n, int nin, int s, 
   }
 }
 
-// C_partial[blk] = sum over the block's node chunk of A[n]^T B[n]
-// (A: N x ka, B: N x kb, row-major FP32, ka, kb <= kAtbMaxK; C: ka x kb).
-// blockIdx.x picks the node chunk, blockIdx.y a group of kAtbPer * kBlock
-// entries of C. Tiles of kAtbTile nodes of A and B are staged in LDS
-// (coalesced loads); each thread owns a fixed set of C entries and sums over
-// the nodes in order, so the result is deterministic.
-constexpr int kAtbChunk = 2048;
+// C_partial[blk] = sum over the block's chunk of kAtbChunk nodes of
+// A[i]^T B[i] (A: N x ka, B: N x kb, row-major FP32; C: ka x kb, row-major),
+// a dense contraction over the nodes, on the FP32 matrix cores: C is cut into
+// 16 x 16 tiles, wave w owns the tile rows w, w + kAtbWaves, ... and all NBJ
+// tile columns (kb <= 16 NBJ), and each v_mfma_f32_16x16x4f32 takes four
+// nodes as its K dimension (lane 16k + i supplies A[node k][16 bi + i] and
+// B[node k][16 bj + i]; accumulator register v of lane 16g + c holds
+// C[16 bi + 4g + v][16 bj + c]). Tiles of kAtbTile nodes of A and B are staged
+// in LDS with coalesced loads, zero past the chunk's end and outside C. The
+// summation order is fixed, so the result is deterministic.
+typedef float atb_f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kAtbChunk = 512;
 constexpr int kAtbTile = 32;
-constexpr int kAtbMaxK = 200;
-constexpr int kAtbPer = 24;  // C entries per thread
-__global__ __launch_bounds__(kBlock) void k_atb_partial(int n, int ka, int kb, const float* __restrict__ A,
-                                                        const float* __restrict__ B, float* __restrict__ partial) {
+constexpr int kAtbMaxK = 200;  // columns of A at most
+constexpr int kAtbWaves = 4;
+constexpr int kAtbRowsPerWave = ((kAtbMaxK + 15) / 16 + kAtbWaves - 1) / kAtbWaves;
+template <int NBJ>
+__global__ __launch_bounds__(64 * kAtbWaves) void k_atb_partial(int n, int ka, int kb, const float* __restrict__ A,
+                                                               const float* __restrict__ B, float* __restrict__ partial) {
   __shared__ float sa[kAtbTile * kAtbMaxK];
-  __shared__ float sb[kAtbTile * kAtbMaxK];
-  const int n0 = blockIdx.x * kAtbChunk;
+  __shared__ float sb[kAtbTile * 16 * NBJ];
+  const int wave = int(threadIdx.x) / 64, lane = int(threadIdx.x) % 64;
+  const int ki = lane / 16, li = lane % 16;
+  const int n0 = int(blockIdx.x) * kAtbChunk;
   const int n1 = min(n, n0 + kAtbChunk);
-  const int nc = ka * kb;
-  constexpr int kPer = kAtbPer;
-  const int e0 = int(blockIdx.y) * kPer * kBlock + int(threadIdx.x);
-  float acc[kPer];
+  const int nbi = (ka + 15) / 16;
+  atb_f32x4 acc[kAtbRowsPerWave][NBJ];
 #pragma unroll
-  for (int r = 0; r < kPer; ++r) acc[r] = 0.0f;
+  for (int r = 0; r < kAtbRowsPerWave; ++r)
+#pragma unroll
+    for (int bj = 0; bj < NBJ; ++bj) acc[r][bj] = atb_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int t0 = n0; t0 < n1; t0 += kAtbTile) {
     const int nt = min(kAtbTile, n1 - t0);
-    for (int e = threadIdx.x; e < nt * ka; e += kBlock) sa[e] = A[size_t(t0) * ka + e];
-    for (int e = threadIdx.x; e < nt * kb; e += kBlock) sb[e] = B[size_t(t0) * kb + e];
+    for (int e = int(threadIdx.x); e < kAtbTile * ka; e += int(blockDim.x))
+      sa[e] = e < nt * ka ? A[size_t(t0) * ka + e] : 0.0f;
+    for (int e = int(threadIdx.x); e < kAtbTile * kb; e += int(blockDim.x))
+      sb[e] = e < nt * kb ? B[size_t(t0) * kb + e] : 0.0f;
     __syncthreads();
+#pragma unroll 2
+    for (int k0 = 0; k0 < kAtbTile; k0 += 4) {
+      const int node = k0 + ki;
+      float bop[NBJ];
 #pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-      const int e = e0 + r * kBlock;
-      if (e < nc) {
-        const int a = e / kb, b = e % kb;
-        float s = acc[r];
-        for (int i = 0; i < nt; ++i) s += sa[i * ka + a] * sb[i * kb + b];
-        acc[r] = s;
+      for (int bj = 0; bj < NBJ; ++bj) {
+        const int col = bj * 16 + li;
+        bop[bj] = col < kb ? sb[node * kb + col] : 0.0f;
+      }
+#pragma unroll
+      for (int r = 0; r < kAtbRowsPerWave; ++r) {
+        const int bi = wave + kAtbWaves * r;
+        if (bi < nbi) {  // the same for every lane of the wave
+          const int row = bi * 16 + li;
+          const float aop = row < ka ? sa[node * ka + row] : 0.0f;
+#pragma unroll
+          for (int bj = 0; bj < NBJ; ++bj)
+            acc[r][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop[bj], acc[r][bj], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
   }
-  float* out = partial + size_t(blockIdx.x) * nc;
+  float* out = partial + size_t(blockIdx.x) * ka * kb;
 #pragma unroll
-  for (int r = 0; r < kPer; ++r) {
-    const int e = e0 + r * kBlock;
-    if (e < nc) out[e] = acc[r];
+  for (int r = 0; r < kAtbRowsPerWave; ++r) {
+    const int bi = wave + kAtbWaves * r;
+    if (bi >= nbi) continue;
+#pragma unroll
+    for (int bj = 0; bj < NBJ; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = bi * 16 + 4 * ki + v, jj = bj * 16 + li;
+        if (i < ka && jj < kb) out[size_t(i) * kb + jj] = acc[r][bj][v];
+      }
   }
 }
 

@@ -202,10 +202,10 @@ void fdot(mgm_ctx* c, int n, const float* x, const float* y, double* out, hipStr
 }
 
 void atb(mgm_ctx* c, LearnedLevel& L, int n, int ka, int kb, const float* A, const float* B, float* out, hipStream_t st) {
-  if (ka > kAtbMaxK || kb > kAtbMaxK) throw Error(MGM_E_ARG, "learned smoother: layer too wide");
+  if (ka > kAtbMaxK || kb > 64) throw Error(MGM_E_ARG, "learned smoother: layer too wide");
   const int nb = (n + kAtbChunk - 1) / kAtbChunk;
-  const int ng = (ka * kb + kAtbPer * kBlock - 1) / (kAtbPer * kBlock);
-  hipLaunchKernelGGL(k_atb_partial, dim3(nb, ng), dim3(kBlock), 0, st, n, ka, kb, A, B, L.atb);
+  if (kb <= 16) hipLaunchKernelGGL((k_atb_partial<1>), dim3(nb), dim3(64 * kAtbWaves), 0, st, n, ka, kb, A, B, L.atb);
+  else hipLaunchKernelGGL((k_atb_partial<4>), dim3(nb), dim3(64 * kAtbWaves), 0, st, n, ka, kb, A, B, L.atb);
   hipLaunchKernelGGL(k_reduce_cols, dim3(nblk(ka * kb)), dim3(kBlock), 0, st, nb, ka * kb, L.atb, out);
 }
 
