@@ -220,7 +220,6 @@ def bench_torus_learned(args, m, f, u, sizes, prec, gs):
     m.set_smoother(mask)
     ms, info = timed_solves(m, f, u, "fgmres", args.steps, args.warmup, restart=40, maxit=400, rtol=1e-10)
     vc_ms, _ = m.time_kernel("vcycle", 0, reps=20)
-    m.set_smoother(False)
     out = {"precision": prec, "s": args.learned_s, "adam_steps": args.learned_steps, "training_s": round(train_s, 2),
            "level_mask": mask, "levels": levels, "ms": round(ms, 3), "iters": info["iters"],
            "rel_res_true": float(f"{info['rel_res_true']:.4g}"), "vcycle_us": round(vc_ms * 1e3, 1),
@@ -228,6 +227,31 @@ def bench_torus_learned(args, m, f, u, sizes, prec, gs):
     log(f"learned smoothers (mask {mask:#x}, s={args.learned_s}, trained in {train_s:.1f} s): {ms:.2f} ms/solve, "
         f"{info['iters']} iters, V-cycle {vc_ms * 1e3:.0f} us; factors "
         f"{[(l['rate_gs'], l['rate_learned']) for l in levels]}")
+    if mask:
+        # the Richardson launches of one V-cycle (k_rowop_patch in Richardson
+        # mode on patch-blocked levels), timed back to back like the GS roofline
+        lr_ms, lr_bytes = m.time_kernel("learned", -1, reps=20)
+        lr_gbs = lr_bytes / (lr_ms * 1e-3) / 1e9
+        out["smoother_roofline"] = {"bound": "hbm", "kernel": f"learned Richardson steps {prec}, mean over one V-cycle",
+                                    "achieved": round(lr_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": round(lr_gbs / HBM_PEAK_GBS, 4), "us_per_launch": round(lr_ms * 1e3, 3),
+                                    "algorithmic_bytes_per_launch": round(lr_bytes)}
+        log(f"learned smoother launches: {lr_ms * 1e3:.2f} us, {lr_bytes / 1e6:.2f} MB -> {lr_gbs:.0f} GB/s")
+        # the same smoothers in the other V-cycle precisions
+        out["solves"] = {prec: {"ms": out["ms"], "iters": out["iters"], "vcycle_us": out["vcycle_us"]}}
+        for p2 in args.precisions.split(","):
+            if p2 == prec:
+                continue
+            m.set_precision(p2)
+            ms2, info2 = timed_solves(m, f, u, "fgmres", args.steps, args.warmup, restart=40, maxit=400, rtol=1e-10)
+            vc2, _ = m.time_kernel("vcycle", 0, reps=20)
+            out["solves"][p2] = {"ms": round(ms2, 3), "iters": info2["iters"],
+                                 "rel_res_true": float(f"{info2['rel_res_true']:.4g}"), "vcycle_us": round(vc2 * 1e3, 1)}
+            log(f"learned smoothers {p2}: {ms2:.2f} ms/solve, {info2['iters']} iters, V-cycle {vc2 * 1e3:.0f} us")
+        if "fp64" in out["solves"] and prec != "fp64":
+            out["speedup_mixed_vs_fp64"] = round(out["solves"]["fp64"]["ms"] / out["ms"], 3)
+        m.set_precision(prec)
+    m.set_smoother(False)
     return out
 
 

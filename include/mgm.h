@@ -294,8 +294,15 @@ mgm_status mgm_set_smoother(mgm_handle h, int32_t level_mask);
  *                    events; *ms and *bytes are per launch.
  *   MGM_TK_RESIDUAL: residual r - L_j e of level `level`, current precision.
  *   MGM_TK_VCYCLE:   one whole V-cycle (Alg. 3) in the current precision;
- *                    bytes = sum over its kernels. */
-enum { MGM_TK_SPMV = 0, MGM_TK_GS = 1, MGM_TK_RESIDUAL = 2, MGM_TK_VCYCLE = 3 };
+ *                    bytes = sum over its kernels.
+ *   MGM_TK_LEARNED:  every launch of the learned smoother in one V-cycle (the
+ *                    levels where it is active, pre- and post-sweeps as the
+ *                    cycle issues them) queued back to back between one pair
+ *                    of events, `level` ignored; *ms and *bytes per launch (a
+ *                    Richardson step: operator, x, f, output, D^-1 and the
+ *                    step weights once each; bordered: b). MGM_E_ARG when no
+ *                    level uses it. */
+enum { MGM_TK_SPMV = 0, MGM_TK_GS = 1, MGM_TK_RESIDUAL = 2, MGM_TK_VCYCLE = 3, MGM_TK_LEARNED = 4 };
 mgm_status mgm_time_kernel(mgm_handle h, int32_t which, int32_t level, int32_t reps,
                            void *stream, double *ms, double *bytes);
 

@@ -22,6 +22,7 @@
 #include <memory>
 #include <numeric>
 #include <string>
+#include <utility>
 
 #include "ctx.h"
 #include "kernels_learned.h"
@@ -629,11 +630,17 @@ static void learned_sweep(mgm_ctx* c, int j, hipStream_t st, bool border, const 
   S* a = e;
   S* b = tmp;
   if (zero_start) {
-    // from e = 0 the first step is e = omega_1 D^-1 f: no operator pass, written in place
-    hipLaunchKernelGGL((k_scale_start<S>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, om, P::dinv(d), P::f(d), e);
+    // from e = 0 the first step is omega_1 D^-1 f: no operator pass, and it
+    // reads no iterate, so it goes to whichever buffer makes the last of the
+    // s steps land in e
+    S* first = (L.s % 2 == 1) ? e : tmp;
+    hipLaunchKernelGGL((k_scale_start<S>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, om, P::dinv(d), P::f(d), first);
+    a = first;
+    b = first == e ? tmp : e;
     q = 1;
   }
-  // the remaining steps ping-pong; with an odd count the result lands in tmp and is copied back
+  // the remaining steps ping-pong; from a non-zero start with an odd count the
+  // result lands in tmp and is copied back
   for (; q < L.s; ++q) {
     step(q, a, b);
     std::swap(a, b);
@@ -1254,6 +1261,28 @@ static double gs_sweep_bytes(const mgm_ctx* c, int j, int prec, bool border) {
   return b;
 }
 
+// one Richardson step of the learned smoother on level j: the operator
+// (values + indices), x, f, the output, D^-1 and the step weights once each
+// (bordered: b)
+static double richardson_bytes(const mgm_ctx* c, int j, int prec, bool border) {
+  const DevLevel& d = c->lv[j];
+  double b = double(d.nnz) * (bval(prec) + 4.0) + 5.0 * bvec(prec) * d.n;
+  if (d.W == 0) b += 4.0 * (d.n + 1);
+  if (prec == MGM_FP16) b += 4.0 * d.n;
+  if (border) b += bvec(prec) * d.n;
+  return b;
+}
+
+// one learned sweep: (launches, bytes); from zero the first step reads
+// omega, D^-1 and f and writes e (no operator pass); from a non-zero start an
+// odd step count ends with a copy back into e
+static std::pair<int, double> learned_sweep_cost(const mgm_ctx* c, int j, int prec, bool border, bool zero_start) {
+  const int s = c->ls[j].s;
+  const double vec = bvec(prec) * c->lv[j].n;
+  if (zero_start) return {s, 4.0 * vec + (s - 1) * richardson_bytes(c, j, prec, false)};
+  return {s + (s % 2), s * richardson_bytes(c, j, prec, border) + (s % 2) * 2.0 * vec};
+}
+
 static double residual_bytes(const mgm_ctx* c, int j, int prec) {
   const DevLevel& d = c->lv[j];
   double b = double(d.nnz) * (bval(prec) + 4.0) + 3.0 * bvec(prec) * d.n;
@@ -1322,7 +1351,9 @@ static void time_kernel_impl(mgm_ctx* c, int which, int level, int reps, hipStre
   build_precision(c, prec);
   ensure_ws(c, 1);
   const bool all_gs = which == MGM_TK_GS && level == -1;
-  if (which != MGM_TK_SPMV && which != MGM_TK_VCYCLE && !all_gs && (level < 0 || level + 1 >= int(c->lv.size())))
+  if (which < MGM_TK_SPMV || which > MGM_TK_LEARNED) throw Error(MGM_E_ARG, "unknown kernel");
+  if (which != MGM_TK_SPMV && which != MGM_TK_VCYCLE && which != MGM_TK_LEARNED && !all_gs &&
+      (level < 0 || level + 1 >= int(c->lv.size())))
     throw Error(MGM_E_ARG, "level out of range");
   if (reps < 1) throw Error(MGM_E_ARG, "reps must be >= 1");
   hipEvent_t e0, e1;
@@ -1380,6 +1411,45 @@ static void time_kernel_impl(mgm_ctx* c, int which, int level, int reps, hipStre
             if (prec == MGM_FP64) gs_sweep<double, double, false>(c, j, c->p.post_smoother == MGM_GS_BWD, bord, c->mu, st);
             else if (prec == MGM_FP32) gs_sweep<float, float, false>(c, j, c->p.post_smoother == MGM_GS_BWD, bord, c->mu, st);
             else gs_sweep<_Float16, float, true>(c, j, c->p.post_smoother == MGM_GS_BWD, bord, c->mu, st);
+          }
+        }
+      };
+      timed(sweeps, b);
+      count += launches - 1;  // timed() counted the batch once
+    } else if (which == MGM_TK_LEARNED) {
+      // the learned smoother's launches of one V-cycle on every level where it
+      // is active, in the cycle's order, as one timed batch
+      const bool bord = c->p.problem == MGM_POISSON;
+      const int p = int(c->lv.size());
+      int64_t launches = 0;
+      double b = 0.0;
+      for (int j = 0; j + 1 < p; ++j) {
+        if (!learned_on(c, j)) continue;
+        for (int s = 0; s < c->p.nu1; ++s) {
+          const auto cost = learned_sweep_cost(c, j, prec, false, s == 0);
+          launches += cost.first;
+          b += cost.second;
+        }
+        for (int s = 0; s < c->p.nu2; ++s) {
+          const auto cost = learned_sweep_cost(c, j, prec, bord, false);
+          launches += cost.first;
+          b += cost.second;
+        }
+      }
+      if (launches == 0) throw Error(MGM_E_ARG, "no level uses the learned smoother");
+      auto sweeps = [&] {
+        for (int j = 0; j + 1 < p; ++j) {
+          if (!learned_on(c, j)) continue;
+          const double* mu = c->mu + j;
+          for (int s = 0; s < c->p.nu1; ++s) {
+            if (prec == MGM_FP64) learned_sweep<double, double, false>(c, j, st, false, mu, s == 0);
+            else if (prec == MGM_FP32) learned_sweep<float, float, false>(c, j, st, false, mu, s == 0);
+            else learned_sweep<_Float16, float, true>(c, j, st, false, mu, s == 0);
+          }
+          for (int s = 0; s < c->p.nu2; ++s) {
+            if (prec == MGM_FP64) learned_sweep<double, double, false>(c, j, st, bord, mu);
+            else if (prec == MGM_FP32) learned_sweep<float, float, false>(c, j, st, bord, mu);
+            else learned_sweep<_Float16, float, true>(c, j, st, bord, mu);
           }
         }
       };

@@ -76,7 +76,7 @@ EXPORTED = ["mgm_default_params", "mgm_setup", "mgm_set_precision", "mgm_vcycle"
             "mgm_smoother_params", "mgm_smoother_grad", "mgm_set_smoother", "mgm_export", "mgm_destroy",
             "mgm_status_str", "mgm_last_error", "mgm_surface_ops_setup", "mgm_surface_gradient",
             "mgm_surface_divergence", "mgm_check", "mgm_set_flow_wait"]
-TK = dict(spmv=0, gs=1, residual=2, vcycle=3)
+TK = dict(spmv=0, gs=1, residual=2, vcycle=3, learned=4)
 
 
 def load():

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import hierarchy, krylov, learned, vcycle
+from oracle import hierarchy, krylov, learned, precision, vcycle
 from paper_2204_06154_amd import mgm
 
 torch = pytest.importorskip("torch")
@@ -96,6 +96,26 @@ def test_vcycle_with_learned_smoother(setup):
         assert inf["status"] == 0 and inf["iters"] == info_ref.iters
         assert np.linalg.norm(wl.f - A(u.cpu().numpy())) <= 1.01e-10 * np.linalg.norm(wl.f)
     finally:
+        m.set_smoother(False)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_reduced_precision_cycle_with_learned_smoother(setup, prec):
+    """The reduced-precision V-cycle with the learned fine-level smoother
+    against the oracle's emulation of that precision with the same step
+    weights (1e-5, as for the Gauss-Seidel cycle)."""
+    wl, H, m, info, L, X, S, _ = setup
+    om = m.export("omega").reshape(-1, 3)
+    m.set_smoother(True)
+    m.set_precision(prec)
+    try:
+        ops = precision.ops_for(H, prec)
+        ops.learned = om.astype(np.float32)
+        z = m.vcycle(torch.tensor(wl.f, device="cuda")).cpu().numpy()
+        ze = vcycle.make_preconditioner(ops, H.problem)(wl.f)
+        assert np.linalg.norm(z - ze) / np.linalg.norm(ze) < 1e-5
+    finally:
+        m.set_precision("fp64")
         m.set_smoother(False)
 
 

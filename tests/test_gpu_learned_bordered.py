@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import hierarchy, krylov, learned, vcycle
+from oracle import hierarchy, krylov, learned, precision, vcycle
 from paper_2204_06154_amd import mgm
 
 torch = pytest.importorskip("torch")
@@ -109,6 +109,40 @@ def test_bordered_cycle_with_learned_levels(setup, mask):
         assert inf["status"] == 0 and inf["iters"] == info_ref.iters
         assert np.linalg.norm(f - A(u.cpu().numpy())) <= 1.01e-10 * np.linalg.norm(f)
     finally:
+        m.set_smoother(False)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_bordered_reduced_precision_cycle_with_learned_levels(setup, prec):
+    """The reduced-precision V-cycle (FP32; FP16 values with FP32 row scales)
+    with learned smoothing on both smoothed levels against the oracle's
+    emulation of that precision with the same step weights (1e-5, as for the
+    Gauss-Seidel cycle); FGMRES then reaches 1e-10 (true FP64 residual)
+    within one iteration of the FP64 oracle's count."""
+    wl, H, m, f = setup["wl"], setup["H"], setup["m"], setup["f"]
+    om = {j: m.export("omega", j).reshape(H.levels[j].N, -1) for j in (0, 1)}
+    m.set_smoother(3)
+    m.set_precision(prec)
+    try:
+        ops = precision.ops_for(H, prec)
+        ops.learned = {j: w.astype(np.float32) for j, w in om.items()}
+        Me = vcycle.make_preconditioner(ops, H.problem)
+        z = m.vcycle(torch.tensor(f, device="cuda")).cpu().numpy()
+        ze = Me(f)
+        assert np.linalg.norm(z - ze) / np.linalg.norm(ze) < 1e-5
+        ops64 = vcycle.Fp64Ops(H)
+        ops64.learned = om
+        M64 = vcycle.make_preconditioner(ops64, H.problem)
+        err64 = np.linalg.norm(z - M64(f)) / np.linalg.norm(M64(f))
+        print(f"[gpu-learned-bordered] {prec} learned V-cycle error vs FP64 oracle: {err64:.2e}", flush=True)
+        assert err64 < (1e-5 if prec == "fp32" else 5e-3)
+        A = vcycle.make_operator(H)
+        _, info_ref = krylov.fgmres(A, M64, f, tol=1e-10, maxit=300)
+        u, inf = m.solve(torch.tensor(f, device="cuda"), rtol=1e-10, maxit=300)
+        assert inf["status"] == 0 and abs(inf["iters"] - info_ref.iters) <= 1, (inf["iters"], info_ref.iters)
+        assert np.linalg.norm(f - A(u.cpu().numpy())) <= 1.01e-10 * np.linalg.norm(f)
+    finally:
+        m.set_precision("fp64")
         m.set_smoother(False)
 
 
