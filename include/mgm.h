@@ -98,7 +98,8 @@ typedef struct {
                              coordinate bisection, patch graph coloured by
                              recursive largest first, in-patch graphs by DSATUR,
                              one workgroup per patch; levels
-                             with rows longer than 96 entries stay plain */
+                             with rows longer than gs_max_width entries stay
+                             plain */
   int32_t cycle;          /* MGM_CYCLE_V | MGM_CYCLE_W | MGM_CYCLE_F */
   int32_t device_setup;   /* 1: kNN searches (k <= 128) and the Galerkin sparse
                              products on the device; results identical to the
@@ -110,12 +111,16 @@ typedef struct {
                              0: one launch per patch colour). A wait is
                              bounded; if one gives up, the next mgm_solve,
                              mgm_level_op or mgm_check returns MGM_E_SYNC */
+  int32_t gs_max_width;   /* part of the smoother ordering: a level is
+                             patch-blocked (gs_block > 0) only if none of its
+                             rows has more than this many entries; 1..96 (the
+                             widest row the patch kernels hold), default 96 */
 } mgm_params;
 
 /* Paper defaults (Table 1): RBF-FD, k = l = 3, n = 20, forward GS, nu = 1,
  * m = 3, factor 4, N_min = 250, screened with mu = 1; FP64 V-cycle, graphs
  * on, device weights and device setup on, gs_block = 256, V-cycle,
- * one-launch sweeps (gs_flow = 1). */
+ * one-launch sweeps (gs_flow = 1), gs_max_width = 96. */
 void mgm_default_params(mgm_params *p);
 
 /* Preprocessing phase (Alg. 2): kNN stencils (Sec. 2), tangent-plane weights

@@ -227,9 +227,10 @@ def max_row_length(pat: sp.csr_matrix) -> int:
     return int(np.diff(pat.indptr).max())
 
 
-def smoother_colouring(pat: sp.csr_matrix, xyz: np.ndarray, block: int, max_width: int = 96):
+def smoother_colouring(pat: sp.csr_matrix, xyz: np.ndarray, block: int, max_width: int):
     """Colouring used by the smoother of one level: patch-blocked when
-    block > 0 and every row has at most max_width entries, else plain."""
+    block > 0 and every row has at most max_width entries (a parameter of the
+    ordering, `gs_max_width`), else plain."""
     if block > 0 and max_row_length(pat) <= max_width:
         comp, patch, pcol, lcol = patch_colouring(pat, xyz, block)
         # relabel the composite colours densely (empty combinations dropped)

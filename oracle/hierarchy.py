@@ -58,7 +58,7 @@ class Hierarchy:
 
 DEFAULTS = dict(disc="rbffd", phs_order=1, poly_degree=2, stencil_size=30, gfd_alpha=4.0,
                 problem="screened", mu=1.0, interp_size=3, coarsen_factor=4, n_min=250,
-                n_coarse_max=0, gs_block=256)
+                n_coarse_max=0, gs_block=256, gs_max_width=96)
 
 
 def fine_operator(xyz, normals, params):
@@ -97,7 +97,7 @@ def build(xyz: np.ndarray, normals: np.ndarray, params: dict) -> Hierarchy:
             nxt.b = galerkin.coarse_border(lv.b, P)
         levels.append(nxt)
     for lv in levels[:-1]:
-        lv.colour, lv.patches = colouring.smoother_colouring(lv.pat, lv.xyz, p["gs_block"])
+        lv.colour, lv.patches = colouring.smoother_colouring(lv.pat, lv.xyz, p["gs_block"], p["gs_max_width"])
         lv.rows_by_colour = [np.nonzero(lv.colour == c)[0] for c in range(lv.ncolours)]
     Lp = levels[-1].L.toarray()
     if p["problem"] == "poisson":

@@ -1544,6 +1544,7 @@ void mgm_default_params(mgm_params* p) {
   p->device_weights = 1;
   p->device_setup = 1;
   p->gs_block = 256;
+  p->gs_max_width = kMaxPatchWidth;
   p->cycle = MGM_CYCLE_V;
   p->gs_flow = 1;
 }

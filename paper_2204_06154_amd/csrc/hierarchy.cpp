@@ -37,6 +37,7 @@ void validate_params(const mgm_params& p, int64_t n) {
   if (p.nu1 < 0 || p.nu2 < 0 || p.nu1 > 8 || p.nu2 > 8) bad("nu1/nu2");
   if (p.precision < MGM_FP64 || p.precision > MGM_FP16) bad("precision");
   if (p.gs_block < 0 || p.gs_block > 256) bad("gs_block must be 0..256");
+  if (p.gs_max_width < 1 || p.gs_max_width > kMaxPatchWidth) bad("gs_max_width must be 1..96");
   if (p.cycle < MGM_CYCLE_V || p.cycle > MGM_CYCLE_F) bad("cycle");
 }
 
@@ -469,7 +470,7 @@ static int32_t rcb_patches(const double* xyz, int32_t n, int block, std::vector<
 }
 
 // Smoother colouring of one level: patch-blocked (block > 0 and every row at
-// most kMaxPatchWidth entries) or plain multicolour.
+// most max_width entries) or plain multicolour.
 void dsatur_patches_host(const std::vector<int32_t>& lptr, const std::vector<int32_t>& ladj,
                          const std::vector<int32_t>& pstart, std::vector<int32_t>& lc, std::vector<int32_t>& pnlc) {
   const int32_t np = int32_t(pstart.size()) - 1;
@@ -480,12 +481,12 @@ void dsatur_patches_host(const std::vector<int32_t>& lptr, const std::vector<int
   }, 2);
 }
 
-void smoother_colouring(HostLevel& l, int block, const DsaturFn& dsatur) {
+void smoother_colouring(HostLevel& l, int block, int max_width, const DsaturFn& dsatur) {
   int32_t maxw = 0;
   for (int32_t i = 0; i < l.n; ++i) maxw = std::max(maxw, l.L.ptr[i + 1] - l.L.ptr[i]);
   std::vector<int32_t> ptr, adj;
   symmetric_adjacency(l.L, ptr, adj);
-  l.patched = block > 0 && maxw <= kMaxPatchWidth;
+  l.patched = block > 0 && maxw <= max_width;
   if (!l.patched) {
     l.colour = jp_colour(ptr, adj, &l.ncolours);
     return;
@@ -635,7 +636,7 @@ void build_hierarchy(const double* xyz, const double* nrm, int64_t n, const mgm_
       if (d == 0.0 && j + 1 < H.lv.size())
         throw Error(MGM_E_ZERO_DIAG, "zero diagonal on level " + std::to_string(j) + " row " + std::to_string(i));
     }
-    if (j + 1 < H.lv.size()) smoother_colouring(l, p.gs_block, be.dsatur);
+    if (j + 1 < H.lv.size()) smoother_colouring(l, p.gs_block, p.gs_max_width, be.dsatur);
   }
   // dense inverse of the coarsest (bordered) operator
   HostLevel& cl = H.lv.back();

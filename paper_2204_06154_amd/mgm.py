@@ -39,7 +39,7 @@ class Params(ctypes.Structure):
                 ("nu2", ctypes.c_int32), ("pre_smoother", ctypes.c_int32), ("post_smoother", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("device_weights", ctypes.c_int32),
                 ("gs_block", ctypes.c_int32), ("cycle", ctypes.c_int32), ("device_setup", ctypes.c_int32),
-                ("gs_flow", ctypes.c_int32)]
+                ("gs_flow", ctypes.c_int32), ("gs_max_width", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):

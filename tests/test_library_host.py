@@ -37,11 +37,14 @@ def test_params_struct_layout_matches_defaults():
     assert (p.interp_size, p.coarsen_factor, p.n_min, p.nu1, p.nu2) == (3, 4, 250, 1, 1)
     assert p.gfd_alpha == 4.0 and p.mu == 1.0 and p.use_graph == 1
     assert p.device_weights == 1 and p.device_setup == 1 and p.cycle == 0 and p.gs_flow == 1
+    assert p.gs_max_width == 96
 
 
 CASES = [
     ("sphere", lambda: synth.sphere_workload(3000), {"n_coarse_max": 150}),
     ("torus", lambda: synth.torus_workload(6000), {"n_min": 300}),
+    # widest rows 50 / 44 / 41 entries: the fine level stays plain, level 1 is patch-blocked
+    ("torus_w45", lambda: synth.torus_workload(6000), {"n_min": 300, "gs_max_width": 45}),
     ("gfd", lambda: synth.big_sphere_workload(9001), {"n_min": 200}),
     ("ragged", lambda: synth.sphere_workload(2053), {"n_coarse_max": 100}),
     ("shifted", lambda: synth.harmonics_workload(3000), {}),
