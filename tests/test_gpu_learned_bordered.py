@@ -184,3 +184,42 @@ def test_bordered_activation_rule(setup):
     assert 0 < res["rate_gs"] < 1 and res["rate_learned"] > 0
     assert res["active"] == (res["rate_learned"] < res["rate_gs"])
     m.set_smoother(False)
+
+
+def _oracle_rate(H, j, e0, k=6, learned=None):
+    """(|A_j x_k| / |A_j x_0|)^(1/k) of the stationary bordered iteration
+    x <- x + M_j(-A_j x) from x_0 = (e0, 0), M_j the cycle of the
+    sub-hierarchy from level j."""
+    ops = vcycle.Fp64Ops(H)
+    ops.learned = learned
+    L, b = H.levels[j].L, H.levels[j].b
+
+    def A(x):
+        return np.concatenate([L @ x[:-1] + b * x[-1], [b @ x[:-1]]])
+
+    x = np.concatenate([e0, [0.0]])
+    r0 = np.linalg.norm(A(x))
+    for _ in range(k):
+        ax = A(x)
+        z, dmu = vcycle.vcycle(ops, -ax[:-1], -ax[-1], level=j)
+        x = x + np.concatenate([z, [dmu]])
+    return (np.linalg.norm(A(x)) / r0) ** (1.0 / k)
+
+
+def test_bordered_coarse_level_factors_follow_oracle(setup):
+    """The measured factors behind the activation rule on level 1 (the
+    bordered operator of the level and its sub-cycle, Gauss-Seidel and the
+    untrained Chebyshev smoother) against the oracle's stationary iteration."""
+    H, m = setup["H"], setup["m"]
+    starts1 = setup["starts"][1]
+    res = m.train_smoother(torch.tensor(starts1, device="cuda"), steps=0, s=2, iters_per_start=2, seed=11, init=True,
+                           activate=1, level=1)
+    om1 = m.export("omega", 1).reshape(H.levels[1].N, -1)
+    gs = _oracle_rate(H, 1, starts1[0])
+    lr = _oracle_rate(H, 1, starts1[0], learned={1: om1})
+    print(f"[gpu-learned-bordered] level 1 factors: GS {res['rate_gs']:.6f} (oracle {gs:.6f}), "
+          f"Chebyshev {res['rate_learned']:.6f} (oracle {lr:.6f})", flush=True)
+    assert abs(res["rate_gs"] - gs) <= 1e-8 * gs
+    assert abs(res["rate_learned"] - lr) <= 1e-8 * lr
+    assert res["active"] == (res["rate_learned"] < res["rate_gs"])
+    m.set_smoother(False)
