@@ -329,7 +329,9 @@ mgm_status mgm_stencils(const double *h_xyz, int64_t n, int32_t k, int32_t *h_id
  * columns whose updates run on the FP64 matrix cores (MFMA); the others
  * one column at a time on the vector units. Synchronises the
  * stream once to report MGM_E_STENCIL_SINGULAR (some system had a pivot below
- * 1e-13 of its largest entry; the other rows are still written). */
+ * 1e-13 of its largest entry; the other rows are still written). An empty
+ * batch (n_systems = 0) checks the sizes and writes nothing; d_stencils and
+ * d_weights may then be null. */
 mgm_status mgm_batched_weights(const double *d_xyz, const double *d_normals, int64_t n_points,
                                const int32_t *d_stencils, int64_t n_systems, int32_t stencil_size,
                                int32_t phs_order, int32_t poly_degree, double *d_weights,

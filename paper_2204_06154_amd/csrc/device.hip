@@ -1736,8 +1736,9 @@ mgm_status mgm_stencils(const double* h_xyz, int64_t n, int32_t k, int32_t* h_id
 mgm_status mgm_batched_weights(const double* d_xyz, const double* d_normals, int64_t n_points, const int32_t* d_stencils,
                                int64_t n_systems, int32_t stencil_size, int32_t phs_order, int32_t poly_degree,
                                double* d_weights, void* stream) {
-  if (!d_xyz || !d_normals || !d_stencils || !d_weights || n_points < 1 || n_systems < 0 || stencil_size < 1 ||
-      stencil_size > n_points) {
+  // an empty batch may pass null stencils and weights (it still checks the sizes)
+  if (!d_xyz || !d_normals || (n_systems > 0 && (!d_stencils || !d_weights)) || n_points < 1 || n_systems < 0 ||
+      stencil_size < 1 || stencil_size > n_points) {
     g_last_error = "bad arguments";
     return MGM_E_ARG;
   }

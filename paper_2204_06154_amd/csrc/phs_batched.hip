@@ -541,8 +541,9 @@ extern "C" mgm_status mgm_batched_weights_noalloc(const double* d_xyz, const dou
                                                   int32_t phs_order, int32_t poly_degree, double* d_weights,
                                                   void* stream) {
   using namespace mgm;
-  if (!d_xyz || !d_normals || !d_stencils || !d_weights || n_points < 1 || n_systems < 0 || stencil_size < 1 ||
-      stencil_size > n_points) {
+  // an empty batch may pass null stencils and weights (it still checks the sizes)
+  if (!d_xyz || !d_normals || (n_systems > 0 && (!d_stencils || !d_weights)) || n_points < 1 || n_systems < 0 ||
+      stencil_size < 1 || stencil_size > n_points) {
     g_last_error = "bad arguments";
     return MGM_E_ARG;
   }

@@ -223,3 +223,19 @@ def test_bordered_coarse_level_factors_follow_oracle(setup):
     assert abs(res["rate_learned"] - lr) <= 1e-8 * lr
     assert res["active"] == (res["rate_learned"] < res["rate_gs"])
     m.set_smoother(False)
+
+
+def test_learned_launch_timer(setup):
+    """mgm_time_kernel(MGM_TK_LEARNED): a positive time and the algorithmic
+    bytes per launch while some level uses the learned smoother; an argument
+    error when none does."""
+    m = setup["m"]
+    m.set_smoother(3)
+    try:
+        ms, nbytes = m.time_kernel("learned", -1, reps=2)
+        assert ms > 0.0 and nbytes > 0.0
+    finally:
+        m.set_smoother(False)
+    with pytest.raises(mgm.MgmError) as ei:
+        m.time_kernel("learned", -1, reps=1)
+    assert ei.value.status == -1

@@ -102,3 +102,21 @@ def test_setup_with_device_weights_matches_host_weights():
         assert np.array_equal(a.export("colours", j), b.export("colours", j))
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("noalloc", [False, True])
+def test_empty_batch_and_size_checks(noalloc):
+    """An empty batch returns at once (null stencil and weight pointers
+    allowed) but still checks its sizes; a system above 64 unknowns is an
+    argument error."""
+    wl = synth.sphere_workload(500)
+    d_x = torch.tensor(wl.xyz, device="cuda")
+    d_n = torch.tensor(wl.normals, device="cuda")
+    d_s = torch.empty((0, 30), dtype=torch.int32, device="cuda")
+    w = mgm.batched_weights(d_x, d_n, d_s, 1, 2, noalloc=noalloc,
+                            d_weights=torch.empty((0, 30), dtype=torch.float64, device="cuda"))
+    assert tuple(w.shape) == (0, 30)
+    with pytest.raises(mgm.MgmError) as ei:   # 60 + 28 unknowns (degree 6) > 64
+        mgm.batched_weights(d_x, d_n, torch.empty((0, 60), dtype=torch.int32, device="cuda"), 1, 6, noalloc=noalloc,
+                            d_weights=torch.empty((0, 60), dtype=torch.float64, device="cuda"))
+    assert ei.value.status == -1
