@@ -198,20 +198,25 @@ def bench_learned(args):
 def bench_torus_learned(args, m, f, u, sizes, prec, gs):
     """The torus solve with learned per-node Chebyshev smoothers: every
     smoothed level trains its own network on the GPU (4 random starts x 2
-    MGM iterations of snapshots on its bordered sub-hierarchy, Adam) with s
-    Richardson steps per sweep, each holding the multiplier fixed; a level
-    keeps it when its measured convergence factor beats Gauss-Seidel's."""
+    MGM iterations of snapshots on its bordered sub-hierarchy, Adam) with its
+    own number of Richardson steps per sweep (default 2 on every level),
+    each step holding the multiplier fixed; a level keeps it when its
+    measured convergence factor beats Gauss-Seidel's (one step per sweep
+    loses that comparison on the coarse levels here, although forcing it on
+    would shorten the solve)."""
     import torch
     m.set_precision(prec)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(2204)
+    s_by_level = [int(x) for x in str(args.learned_s).split(",")]
     levels, mask = [], 0
     t0 = time.perf_counter()
     for j in range(len(sizes) - 1):
         sj = torch.randn((4, sizes[j]), generator=gen, device="cuda", dtype=torch.float64)
-        tj = m.train_smoother(sj, steps=args.learned_steps, lr=1e-3, s=args.learned_s, iters_per_start=2,
+        s_j = s_by_level[min(j, len(s_by_level) - 1)]
+        tj = m.train_smoother(sj, steps=args.learned_steps, lr=args.learned_lr, s=s_j, iters_per_start=2,
                               seed=5 + j, init=True, activate=1, level=j)
-        levels.append({"level": j, "rate_gs": round(tj["rate_gs"], 4), "rate_learned": round(tj["rate_learned"], 4),
+        levels.append({"level": j, "s": s_j, "rate_gs": round(tj["rate_gs"], 4), "rate_learned": round(tj["rate_learned"], 4),
                        "loss_first": round(tj["loss_first"], 5), "loss_last": round(tj["loss_last"], 5),
                        "active": tj["active"]})
         if tj["active"]:
@@ -220,11 +225,12 @@ def bench_torus_learned(args, m, f, u, sizes, prec, gs):
     m.set_smoother(mask)
     ms, info = timed_solves(m, f, u, "fgmres", args.steps, args.warmup, restart=40, maxit=400, rtol=1e-10)
     vc_ms, _ = m.time_kernel("vcycle", 0, reps=20)
-    out = {"precision": prec, "s": args.learned_s, "adam_steps": args.learned_steps, "training_s": round(train_s, 2),
+    out = {"precision": prec, "s_by_level": [l["s"] for l in levels], "adam_steps": args.learned_steps,
+           "lr": args.learned_lr, "training_s": round(train_s, 2),
            "level_mask": mask, "levels": levels, "ms": round(ms, 3), "iters": info["iters"],
            "rel_res_true": float(f"{info['rel_res_true']:.4g}"), "vcycle_us": round(vc_ms * 1e3, 1),
            "speedup_vs_gs": round(gs["ms"] / ms, 3)}
-    log(f"learned smoothers (mask {mask:#x}, s={args.learned_s}, trained in {train_s:.1f} s): {ms:.2f} ms/solve, "
+    log(f"learned smoothers (mask {mask:#x}, s={[l['s'] for l in levels]}, trained in {train_s:.1f} s): {ms:.2f} ms/solve, "
         f"{info['iters']} iters, V-cycle {vc_ms * 1e3:.0f} us; factors "
         f"{[(l['rate_gs'], l['rate_learned']) for l in levels]}")
     if mask:
@@ -596,9 +602,12 @@ def main():
                                                  "setup", "geodesic", "table2"],
                     default="torus")
     ap.add_argument("--train-steps", type=int, default=200)
-    ap.add_argument("--learned-steps", type=int, default=200,
+    ap.add_argument("--learned-steps", type=int, default=400,
                     help="Adam steps per level of the torus run's learned smoothers (0: skip that part)")
-    ap.add_argument("--learned-s", type=int, default=2, help="Richardson steps per sweep of the torus run's learned smoothers")
+    ap.add_argument("--learned-lr", type=float, default=3e-3, help="Adam learning rate of the torus run's learned smoothers")
+    ap.add_argument("--learned-s", default="2",
+                    help="Richardson steps per sweep of the torus run's learned smoothers, by level (the last value "
+                         "holds for the remaining levels)")
     ap.add_argument("--vcycle-precision", default="fp32", help="V-cycle precision of the learned and sbdf2 workloads")
     args = ap.parse_args()
     if args.gpus != 1:

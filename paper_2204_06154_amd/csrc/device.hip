@@ -584,26 +584,34 @@ static void residual_restrict(mgm_ctx* c, int j, hipStream_t st, bool with_mu = 
 // e_j += P_j e_{j+1}; bordered: mu_j = mu_{j+1}, or mu_j += mu_{j+1} when the
 // level continues from an earlier iterate (accumulate).
 template <typename V, typename S, bool SC>
-static void interp_add(mgm_ctx* c, int j, hipStream_t st, bool accumulate = false) {
+static void interp_add(mgm_ctx* c, int j, hipStream_t st, bool accumulate = false, S* out = nullptr) {
   using P = Prec<V, S, SC>;
   DevLevel& d = c->lv[j];
   DevLevel& nx = c->lv[j + 1];
   const bool bord = c->p.problem == MGM_POISSON;
   hipLaunchKernelGGL((k_interp_add<S, S>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, d.m, d.pcol, P::pw(d), P::e(nx), P::e(d),
-                     bord ? c->mu + j + 1 : nullptr, bord ? c->mu + j : nullptr, accumulate ? 1 : 0);
+                     bord ? c->mu + j + 1 : nullptr, bord ? c->mu + j : nullptr, accumulate ? 1 : 0, out);
+}
+
+// scratch vector of the learned smoother's ping-pong (sized for the fine level)
+template <typename S>
+static S* learned_tmp(mgm_ctx* c) {
+  return reinterpret_cast<S*>(sizeof(S) == 8 ? static_cast<void*>(c->e_tmp64) : static_cast<void*>(c->e_tmp32));
 }
 
 // Learned smoother of level j: s Richardson steps with per-node step weights
 // (ping-pong between e and a scratch vector, the result left in e). With
 // border (bordered system) the multiplier is held fixed at *lam, as in the
-// Gauss-Seidel sweep.
+// Gauss-Seidel sweep. from_tmp: the iterate to smooth is in the scratch
+// vector (the interpolation wrote it there), not in e.
 template <typename V, typename S, bool SC>
-static void learned_sweep(mgm_ctx* c, int j, hipStream_t st, bool border, const double* lam, bool zero_start = false) {
+static void learned_sweep(mgm_ctx* c, int j, hipStream_t st, bool border, const double* lam, bool zero_start = false,
+                          bool from_tmp = false) {
   using P = Prec<V, S, SC>;
   DevLevel& d = c->lv[j];
   const LearnedLevel& L = c->ls[j];
   S* e = P::e(d);
-  S* tmp = reinterpret_cast<S*>(sizeof(S) == 8 ? static_cast<void*>(c->e_tmp64) : static_cast<void*>(c->e_tmp32));
+  S* tmp = learned_tmp<S>(c);
   const S* om = reinterpret_cast<const S*>(sizeof(S) == 8 ? static_cast<const void*>(L.om64)
                                                            : static_cast<const void*>(L.om32));
   const unsigned g = nblk(int64_t(d.n) * d.G);
@@ -627,8 +635,8 @@ static void learned_sweep(mgm_ctx* c, int j, hipStream_t st, bool border, const 
     }
   };
   int q = 0;
-  S* a = e;
-  S* b = tmp;
+  S* a = from_tmp ? tmp : e;
+  S* b = from_tmp ? e : tmp;
   if (zero_start) {
     // from e = 0 the first step is omega_1 D^-1 f: no operator pass, and it
     // reads no iterate, so it goes to whichever buffer makes the last of the
@@ -639,8 +647,8 @@ static void learned_sweep(mgm_ctx* c, int j, hipStream_t st, bool border, const 
     b = first == e ? tmp : e;
     q = 1;
   }
-  // the remaining steps ping-pong; from a non-zero start with an odd count the
-  // result lands in tmp and is copied back
+  // the remaining steps ping-pong; if they end in tmp (a start in e with an
+  // odd count, or in tmp with an even one) the result is copied back
   for (; q < L.s; ++q) {
     step(q, a, b);
     std::swap(a, b);
@@ -680,12 +688,17 @@ static void cycle_enqueue(mgm_ctx* c, int j, int kind, bool zero_start, hipStrea
   const int first = kind;
   cycle_enqueue<V, S, SC>(c, j + 1, first, true, st);
   if (kind != MGM_CYCLE_V) cycle_enqueue<V, S, SC>(c, j + 1, kind == MGM_CYCLE_W ? MGM_CYCLE_W : MGM_CYCLE_V, false, st);
-  interp_add<V, S, SC>(c, j, st, !zero_start);
+  // With an odd number of learned steps per sweep, the interpolation writes
+  // e + P e_c into the scratch vector, so that the first post-smoothing sweep
+  // ends in e without a copy.
+  const bool interp_to_tmp = learned && c->p.nu2 > 0 && c->ls[j].s % 2 == 1;
+  S* after = interp_to_tmp ? learned_tmp<S>(c) : P::e(d);
+  interp_add<V, S, SC>(c, j, st, !zero_start, interp_to_tmp ? after : nullptr);
   if (j == c->capture_level && c->capture)
-    hipLaunchKernelGGL((k_gather<S, double>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, (const int32_t*)nullptr, P::e(d),
+    hipLaunchKernelGGL((k_gather<S, double>), dim3(nblk(d.n)), dim3(kBlock), 0, st, d.n, (const int32_t*)nullptr, after,
                        c->capture, (double*)nullptr);
   for (int s = 0; s < c->p.nu2; ++s) {
-    if (learned) learned_sweep<V, S, SC>(c, j, st, bord, mu);
+    if (learned) learned_sweep<V, S, SC>(c, j, st, bord, mu, false, interp_to_tmp && s == 0);
     else gs_sweep<V, S, SC>(c, j, c->p.post_smoother == MGM_GS_BWD, bord, mu, st);
   }
 }
@@ -1273,14 +1286,17 @@ static double richardson_bytes(const mgm_ctx* c, int j, int prec, bool border) {
   return b;
 }
 
-// one learned sweep: (launches, bytes); from zero the first step reads
-// omega, D^-1 and f and writes e (no operator pass); from a non-zero start an
-// odd step count ends with a copy back into e
-static std::pair<int, double> learned_sweep_cost(const mgm_ctx* c, int j, int prec, bool border, bool zero_start) {
+// one learned sweep: (launches, algorithmic bytes); from zero the first step
+// reads omega, D^-1 and f and writes e (no operator pass); from a non-zero
+// start in e an odd step count ends with a copy back into e (a start in the
+// scratch vector, as after the interpolation, needs none), a launch whose
+// bytes are not algorithmic
+static std::pair<int, double> learned_sweep_cost(const mgm_ctx* c, int j, int prec, bool border, bool zero_start,
+                                                 bool from_tmp = false) {
   const int s = c->ls[j].s;
-  const double vec = bvec(prec) * c->lv[j].n;
-  if (zero_start) return {s, 4.0 * vec + (s - 1) * richardson_bytes(c, j, prec, false)};
-  return {s + (s % 2), s * richardson_bytes(c, j, prec, border) + (s % 2) * 2.0 * vec};
+  if (zero_start) return {s, 4.0 * bvec(prec) * c->lv[j].n + (s - 1) * richardson_bytes(c, j, prec, false)};
+  const int copy = (s % 2 == 1) != from_tmp ? 1 : 0;
+  return {s + copy, s * richardson_bytes(c, j, prec, border)};
 }
 
 static double residual_bytes(const mgm_ctx* c, int j, int prec) {
@@ -1302,13 +1318,9 @@ static double visit_bytes(const mgm_ctx* c, int prec, int j, int kind, bool zero
   double tot = 0.0;
   if (zero_start && !((d.patched || learned) && c->p.nu1 > 0)) tot += bvec(prec) * d.n;  // zero fill
   if (learned) {
-    const double step = double(d.nnz) * (bval(prec) + 4.0) + double(d.n) * (5.0 * bvec(prec));
-    int steps = (c->p.nu1 + c->p.nu2) * c->ls[j].s;
-    if (c->p.nu1 > 0 && zero_start) {  // the first step from zero reads omega, dinv, f and writes e
-      --steps;
-      tot += 4.0 * bvec(prec) * d.n;
-    }
-    tot += steps * step;
+    for (int s = 0; s < c->p.nu1; ++s)
+      tot += learned_sweep_cost(c, j, prec, bord && !zero_start, zero_start && s == 0).second;
+    tot += c->p.nu2 * learned_sweep_cost(c, j, prec, bord, false).second;
   } else {
     tot += c->p.nu1 * gs_sweep_bytes(c, j, prec, bord && !zero_start) + c->p.nu2 * gs_sweep_bytes(c, j, prec, bord);
   }
@@ -1431,7 +1443,7 @@ static void time_kernel_impl(mgm_ctx* c, int which, int level, int reps, hipStre
           b += cost.second;
         }
         for (int s = 0; s < c->p.nu2; ++s) {
-          const auto cost = learned_sweep_cost(c, j, prec, bord, false);
+          const auto cost = learned_sweep_cost(c, j, prec, bord, false, s == 0 && c->ls[j].s % 2 == 1);
           launches += cost.first;
           b += cost.second;
         }
@@ -1447,9 +1459,10 @@ static void time_kernel_impl(mgm_ctx* c, int which, int level, int reps, hipStre
             else learned_sweep<_Float16, float, true>(c, j, st, false, mu, s == 0);
           }
           for (int s = 0; s < c->p.nu2; ++s) {
-            if (prec == MGM_FP64) learned_sweep<double, double, false>(c, j, st, bord, mu);
-            else if (prec == MGM_FP32) learned_sweep<float, float, false>(c, j, st, bord, mu);
-            else learned_sweep<_Float16, float, true>(c, j, st, bord, mu);
+            const bool from_tmp = s == 0 && c->ls[j].s % 2 == 1;  // as after the cycle's interpolation
+            if (prec == MGM_FP64) learned_sweep<double, double, false>(c, j, st, bord, mu, false, from_tmp);
+            else if (prec == MGM_FP32) learned_sweep<float, float, false>(c, j, st, bord, mu, false, from_tmp);
+            else learned_sweep<_Float16, float, true>(c, j, st, bord, mu, false, from_tmp);
           }
         }
       };

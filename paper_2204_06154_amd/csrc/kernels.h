@@ -166,13 +166,16 @@ template <typename V, typename S>
 __global__ __launch_bounds__(kBlock) void k_interp_add(int n, int m, const int32_t* __restrict__ pcol,
                                                        const V* __restrict__ pval, const S* __restrict__ ec,
                                                        S* __restrict__ e, const double* __restrict__ mu_in = nullptr,
-                                                       double* __restrict__ mu_out = nullptr, int accumulate = 0) {
+                                                       double* __restrict__ mu_out = nullptr, int accumulate = 0,
+                                                       S* __restrict__ out = nullptr) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (mu_out && i == 0) *mu_out = (accumulate ? *mu_out : 0.0) + *mu_in;
   if (i >= n) return;
   S acc = S(0);
   for (int t = 0; t < m; ++t) acc += S(pval[i * m + t]) * ec[pcol[i * m + t]];
-  e[i] += acc;
+  const S v = e[i] + acc;
+  if (out) out[i] = v;  // out of place (e left as it was)
+  else e[i] = v;
 }
 
 // Coarsest solve by the dense FP64 inverse: x = Ainv [rc; rho]; one
