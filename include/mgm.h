@@ -261,8 +261,8 @@ typedef struct {
  *   i.e. of MGM_EX_COARSE_IDX of the level above);
  *   h_loss_hist: nullable host array of steps+1 losses (entry k: before the
  *   (k+1)-th Adam step; the last: after training).
- * Errors: MGM_E_ARG (bad options, layer too wide: the MLP's parameters above
- * 64 KiB, i.e. a stencil above 59 points with s = 8, above 61 with s = 3).
+ * Errors: MGM_E_ARG (bad options, layer too wide: 3n + 1 inputs above 200,
+ * i.e. a stencil above 66 points).
  * Synchronises the stream. */
 mgm_status mgm_train_smoother(mgm_handle h, const mgm_train_opts *opts, const double *d_starts,
                               mgm_train_info *info, double *h_loss_hist, void *stream);

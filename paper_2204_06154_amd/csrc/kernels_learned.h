@@ -148,55 +148,108 @@ __global__ __launch_bounds__(kBlock) void k_fdot_partial(int n, const float* __r
   if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
-// MLP forward for every node: o = W3 relu(W2 relu(W1 x + b1) + b2) + b3 and,
-// for training, the augmented activations [h; 1] (N x 65 each).
-__global__ __launch_bounds__(kBlock) void k_mlp_forward(int n, int nin, int s, const float* __restrict__ X,
-                                                        const float* __restrict__ params, float* __restrict__ O,
-                                                        float* __restrict__ H1, float* __restrict__ H2) {
-  extern __shared__ float wsh[];
-  const int np = mlp_param_count(nin, s);
-  for (int k = threadIdx.x; k < np; k += kBlock) wsh[k] = params[k];
-  __syncthreads();
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const float* W1 = wsh;
-  const float* W2 = W1 + (nin + 1) * kHid;
-  const float* W3 = W2 + (kHid + 1) * kHid;
-  const float* x = X + size_t(i) * (nin + 1);
-  float h1[kHid];
-#pragma unroll
-  for (int o = 0; o < kHid; ++o) h1[o] = W1[nin * kHid + o];
-  for (int k = 0; k < nin; ++k) {
-    const float xk = x[k];
-#pragma unroll
-    for (int o = 0; o < kHid; ++o) h1[o] += xk * W1[k * kHid + o];
+// The MLP's per-node products on the FP32 matrix cores: each wavefront takes
+// 16 nodes and runs every layer as v_mfma_f32_16x16x4f32 tiles (16 nodes x
+// 16 outputs, four inputs per step; lane 16k + i supplies input k of node i
+// and weight row k for output i; accumulator register v of lane 16g + c is
+// node 4g + v, output c). The weights are read through the caches (the same
+// few tens of KB for every wavefront); each layer's output goes through a
+// 16 x 65 LDS tile ([h; 1], the 1 multiplying the next layer's bias row) to
+// become the next layer's input, and from there, row by row, to the
+// activation arrays the gradient needs.
+typedef float mlp_f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kMlpWaves = 4;
+constexpr int kMlpNodes = 16 * kMlpWaves;  // nodes per workgroup
+constexpr int kActStride = kHid + 1;        // [h; 1]
+
+__device__ __forceinline__ void mlp_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// rows of a wavefront's 16 x 65 tile to H (N x 65, row-major), nodes < n
+__device__ __forceinline__ void mlp_store_tile(const float* tile, float* __restrict__ H, int node0, int n, int lane) {
+  for (int r = 0; r < 16 && node0 + r < n; ++r) {
+    float* hr = H + size_t(node0 + r) * kActStride;
+    hr[lane] = tile[r * kActStride + lane];
+    if (lane == 0) hr[kHid] = 1.0f;
   }
+}
+
+// relu(acc) of four 16 x 16 output tiles into the wavefront's tile, with the
+// ones column
+__device__ __forceinline__ void mlp_relu_to_tile(const mlp_f32x4 (&acc)[4], float* tile, int ki, int li, int lane) {
 #pragma unroll
-  for (int o = 0; o < kHid; ++o) h1[o] = fmaxf(h1[o], 0.0f);
-  float h2[kHid];
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
-  for (int o = 0; o < kHid; ++o) h2[o] = W2[kHid * kHid + o];
+    for (int v = 0; v < 4; ++v) tile[(4 * ki + v) * kActStride + 16 * t + li] = fmaxf(acc[t][v], 0.0f);
+  if (lane < 16) tile[lane * kActStride + kHid] = 1.0f;
+}
+
+// MLP forward for every node: o = W3 relu(W2 relu(W1 x + b1) + b2) + b3
+// (the bias rows multiply the trailing 1 of x and of each [h; 1]) and, for
+// training (H1 non-null), the augmented activations [h; 1] (N x 65 each).
+// Weights: W1 (nin+1) x 64, W2 65 x 64, W3 65 x s, row-major, consecutive.
+__global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_forward(int n, int nin, int s, const float* __restrict__ X,
+                                                               const float* __restrict__ params, float* __restrict__ O,
+                                                               float* __restrict__ H1, float* __restrict__ H2) {
+  __shared__ float act[kMlpWaves][16 * kActStride];
+  const int wave = int(threadIdx.x) / 64, lane = int(threadIdx.x) % 64;
+  const int ki = lane / 16, li = lane % 16;
+  const int node0 = (int(blockIdx.x) * kMlpWaves + wave) * 16;
+  if (node0 >= n) return;  // no workgroup barrier follows
+  const int ka = nin + 1;
+  const float* W1 = params;
+  const float* W2 = W1 + size_t(ka) * kHid;
+  const float* W3 = W2 + size_t(kActStride) * kHid;
+  float* tile = act[wave];
+  const bool arow = node0 + li < n;
+  const float* xr = X + size_t(arow ? node0 + li : node0) * ka;
+  mlp_f32x4 acc[4];
 #pragma unroll
-  for (int k = 0; k < kHid; ++k) {
+  for (int t = 0; t < 4; ++t) acc[t] = mlp_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < ka; k0 += 4) {
+    const int k = k0 + ki;
+    const bool kin = k < ka;
+    const float a = (arow && kin) ? xr[k] : 0.0f;
 #pragma unroll
-    for (int o = 0; o < kHid; ++o) h2[o] += h1[k] * W2[k * kHid + o];
-  }
-#pragma unroll
-  for (int o = 0; o < kHid; ++o) h2[o] = fmaxf(h2[o], 0.0f);
-  for (int q = 0; q < s; ++q) {
-    float acc = W3[kHid * s + q];
-#pragma unroll
-    for (int k = 0; k < kHid; ++k) acc += h2[k] * W3[k * s + q];
-    O[size_t(i) * s + q] = acc;
-  }
-  if (H1) {
-#pragma unroll
-    for (int o = 0; o < kHid; ++o) {
-      H1[size_t(i) * (kHid + 1) + o] = h1[o];
-      H2[size_t(i) * (kHid + 1) + o] = h2[o];
+    for (int t = 0; t < 4; ++t) {
+      const float b = kin ? W1[size_t(k) * kHid + 16 * t + li] : 0.0f;
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
     }
-    H1[size_t(i) * (kHid + 1) + kHid] = 1.0f;
-    H2[size_t(i) * (kHid + 1) + kHid] = 1.0f;
+  }
+  mlp_relu_to_tile(acc, tile, ki, li, lane);
+  mlp_wave_sync();
+  if (H1) mlp_store_tile(tile, H1, node0, n, lane);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = mlp_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < kActStride; k0 += 4) {
+    const int k = k0 + ki;
+    const bool kin = k < kActStride;
+    const float a = kin ? tile[li * kActStride + k] : 0.0f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const float b = kin ? W2[size_t(k) * kHid + 16 * t + li] : 0.0f;
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+    }
+  }
+  mlp_wave_sync();  // every read of the layer-1 tile precedes its overwrite
+  mlp_relu_to_tile(acc, tile, ki, li, lane);
+  mlp_wave_sync();
+  if (H2) mlp_store_tile(tile, H2, node0, n, lane);
+  mlp_f32x4 o = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < kActStride; k0 += 4) {
+    const int k = k0 + ki;
+    const bool kin = k < kActStride;
+    const float a = kin ? tile[li * kActStride + k] : 0.0f;
+    const float b = (kin && li < s) ? W3[size_t(k) * s + li] : 0.0f;
+    o = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, o, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int node = node0 + 4 * ki + v;
+    if (node < n && li < s) O[size_t(node) * s + li] = o[v];
   }
 }
 
@@ -210,41 +263,82 @@ __global__ __launch_bounds__(kBlock) void k_omega(int n, int s, const float* __r
 }
 
 // MLP backward per node: dO = domega * wcheb * 0.5 (1 - tanh^2 o);
-// dH2 = relu'(h2) (W3 dO); dH1 = relu'(h1) (W2 dH2).
-__global__ __launch_bounds__(kBlock) void k_mlp_backward(int n, int nin, int s, const float* __restrict__ params,
-                                                         const float* __restrict__ O, const float* __restrict__ domega,
-                                                         const double* __restrict__ wcheb, const float* __restrict__ H1,
-                                                         const float* __restrict__ H2, float* __restrict__ dO,
-                                                         float* __restrict__ dH1, float* __restrict__ dH2) {
-  extern __shared__ float wsh[];
-  const int np = mlp_param_count(nin, s);
-  for (int k = threadIdx.x; k < np; k += kBlock) wsh[k] = params[k];
-  __syncthreads();
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const float* W2 = wsh + (nin + 1) * kHid;
-  const float* W3 = W2 + (kHid + 1) * kHid;
-  float dq[8];
-  for (int q = 0; q < s; ++q) {
-    const float th = tanhf(O[size_t(i) * s + q]);
-    dq[q] = domega[size_t(q) * n + i] * float(wcheb[q]) * 0.5f * (1.0f - th * th);
-    dO[size_t(i) * s + q] = dq[q];
+// dH2 = relu'(h2) (W3 dO); dH1 = relu'(h1) (W2 dH2) (the bias rows of W3 and
+// W2 take no part). Same tiling as the forward pass: dO, then dH2, pass
+// through the wavefront's LDS tile to become the next product's input.
+__global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_backward(int n, int nin, int s, const float* __restrict__ params,
+                                                                const float* __restrict__ O, const float* __restrict__ domega,
+                                                                const double* __restrict__ wcheb, const float* __restrict__ H1,
+                                                                const float* __restrict__ H2, float* __restrict__ dO,
+                                                                float* __restrict__ dH1, float* __restrict__ dH2) {
+  __shared__ float act[kMlpWaves][16 * kActStride];
+  const int wave = int(threadIdx.x) / 64, lane = int(threadIdx.x) % 64;
+  const int ki = lane / 16, li = lane % 16;
+  const int node0 = (int(blockIdx.x) * kMlpWaves + wave) * 16;
+  if (node0 >= n) return;  // no workgroup barrier follows
+  const float* W2 = params + size_t(nin + 1) * kHid;
+  const float* W3 = W2 + size_t(kActStride) * kHid;
+  float* tile = act[wave];
+  // dO of the wavefront's 16 nodes (zero past n) into the tile
+  for (int idx = lane; idx < 16 * s; idx += 64) {
+    const int r = idx / s, q = idx % s;
+    const int node = node0 + r;
+    float d = 0.0f;
+    if (node < n) {
+      const float th = tanhf(O[size_t(node) * s + q]);
+      d = domega[size_t(q) * n + node] * float(wcheb[q]) * 0.5f * (1.0f - th * th);
+      dO[size_t(node) * s + q] = d;
+    }
+    tile[r * kActStride + q] = d;
   }
-  float g2[kHid];
+  mlp_wave_sync();
+  // dH2 = relu'(h2) (dO W3^T): inputs q < s, weights W3[j][q]
+  mlp_f32x4 acc[4];
 #pragma unroll
-  for (int k = 0; k < kHid; ++k) {
-    float acc = 0.0f;
-    for (int q = 0; q < s; ++q) acc += W3[k * s + q] * dq[q];
-    g2[k] = H2[size_t(i) * (kHid + 1) + k] > 0.0f ? acc : 0.0f;
-    dH2[size_t(i) * kHid + k] = g2[k];
-  }
-#pragma unroll 4
-  for (int k = 0; k < kHid; ++k) {
-    float acc = 0.0f;
+  for (int t = 0; t < 4; ++t) acc[t] = mlp_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < s; k0 += 4) {
+    const int q = k0 + ki;
+    const bool kin = q < s;
+    const float a = kin ? tile[li * kActStride + q] : 0.0f;
 #pragma unroll
-    for (int o = 0; o < kHid; ++o) acc += W2[k * kHid + o] * g2[o];
-    dH1[size_t(i) * kHid + k] = H1[size_t(i) * (kHid + 1) + k] > 0.0f ? acc : 0.0f;
+    for (int t = 0; t < 4; ++t) {
+      const float b = kin ? W3[size_t(16 * t + li) * s + q] : 0.0f;
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+    }
   }
+  mlp_wave_sync();  // every read of dO precedes the overwrite
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int node = node0 + 4 * ki + v, j = 16 * t + li;
+      float g = 0.0f;
+      if (node < n) {
+        g = H2[size_t(node) * kActStride + j] > 0.0f ? acc[t][v] : 0.0f;
+        dH2[size_t(node) * kHid + j] = g;
+      }
+      tile[(4 * ki + v) * kActStride + j] = g;
+    }
+  mlp_wave_sync();
+  // dH1 = relu'(h1) (dH2 W2^T): inputs o < 64, weights W2[k][o]
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = mlp_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < kHid; k0 += 4) {
+    const int o = k0 + ki;
+    const float a = tile[li * kActStride + o];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const float b = W2[size_t(16 * t + li) * kHid + o];
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int node = node0 + 4 * ki + v, k = 16 * t + li;
+      if (node < n) dH1[size_t(node) * kHid + k] = H1[size_t(node) * kActStride + k] > 0.0f ? acc[t][v] : 0.0f;
+    }
 }
 
 // C_partial[blk] = sum over the block's chunk of kAtbChunk nodes of

@@ -217,8 +217,8 @@ void train_step(mgm_ctx* c, int j, bool update, double* loss_slot, float lr, hip
   const int n = d.n, s = L.s, nin = L.nin, T = L.T;
   if (T > L.snap_cap || size_t(T) * s * n > L.z_cap) throw Error(MGM_E_ARG, "learned smoother: training buffers too small");
   const int np = mlp_param_count(nin, s);
-  const size_t lds = size_t(np) * sizeof(float);
-  hipLaunchKernelGGL(k_mlp_forward, dim3(nblk(n)), dim3(kBlock), lds, st, n, nin, s, L.X, L.params, L.O,
+  const unsigned mlp_blocks = unsigned((n + kMlpNodes - 1) / kMlpNodes);
+  hipLaunchKernelGGL(k_mlp_forward, dim3(mlp_blocks), dim3(64 * kMlpWaves), 0, st, n, nin, s, L.X, L.params, L.O,
                      L.H1, L.H2);
   hipLaunchKernelGGL((k_omega<float>), dim3(nblk(n)), dim3(kBlock), 0, st, n, s, L.O, L.wcheb_d, L.omt);
   hipLaunchKernelGGL((k_fill<float>), dim3(nblk(int64_t(n) * s)), dim3(kBlock), 0, st, n * s, L.domega, 0.0f);
@@ -262,8 +262,8 @@ void train_step(mgm_ctx* c, int j, bool update, double* loss_slot, float lr, hip
       }
     }
   }
-  hipLaunchKernelGGL(k_mlp_backward, dim3(nblk(n)), dim3(kBlock), lds, st, n, nin, s, L.params, L.O, L.domega,
-                     L.wcheb_d, L.H1, L.H2, L.dO, L.dH1, L.dH2);
+  hipLaunchKernelGGL(k_mlp_backward, dim3(mlp_blocks), dim3(64 * kMlpWaves), 0, st, n, nin, s, L.params, L.O,
+                     L.domega, L.wcheb_d, L.H1, L.H2, L.dO, L.dH1, L.dH2);
   atb(c, L, n, nin + 1, kHid, L.X, L.dH1, L.grad, st);
   atb(c, L, n, kHid + 1, kHid, L.H1, L.dH2, L.grad + (nin + 1) * kHid, st);
   atb(c, L, n, kHid + 1, s, L.H2, L.dO, L.grad + (nin + 1) * kHid + (kHid + 1) * kHid, st);
@@ -281,9 +281,8 @@ void compute_omega(mgm_ctx* c, int j, hipStream_t st) {
   DevLevel& d = c->lv[j];
   LearnedLevel& L = c->ls[j];
   const int n = d.n, s = L.s, nin = L.nin;
-  const size_t lds = size_t(mlp_param_count(nin, s)) * sizeof(float);
-  hipLaunchKernelGGL(k_mlp_forward, dim3(nblk(n)), dim3(kBlock), lds, st, n, nin, s, L.X, L.params, L.O,
-                     (float*)nullptr, (float*)nullptr);
+  hipLaunchKernelGGL(k_mlp_forward, dim3(unsigned((n + kMlpNodes - 1) / kMlpNodes)), dim3(64 * kMlpWaves), 0, st, n,
+                     nin, s, L.X, L.params, L.O, (float*)nullptr, (float*)nullptr);
   hipLaunchKernelGGL((k_omega<double>), dim3(nblk(n)), dim3(kBlock), 0, st, n, s, L.O, L.wcheb_d, L.om64);
   hipLaunchKernelGGL((k_omega<float>), dim3(nblk(n)), dim3(kBlock), 0, st, n, s, L.O, L.wcheb_d, L.om32);
 }
@@ -408,10 +407,8 @@ mgm_status mgm_train_smoother(mgm_handle h, const mgm_train_opts* o, const doubl
       build_features(h, j, perm);
       build_transpose(h, j);
     }
-    // the MLP kernels stage every parameter in LDS (64 KiB per workgroup) and
-    // the gradient products take at most kAtbMaxK columns a side
-    if (size_t(mlp_param_count(L.nin, o->s)) * sizeof(float) > 65536 || L.nin + 1 > kAtbMaxK)
-      throw Error(MGM_E_ARG, "learned smoother: layer too wide (MLP parameters above 64 KiB of LDS)");
+    // the gradient products take at most kAtbMaxK rows of the first layer
+    if (L.nin + 1 > kAtbMaxK) throw Error(MGM_E_ARG, "learned smoother: layer too wide (stencils above 66 points)");
     const bool was_active = L.active;
     const bool fresh = !L.params || L.s != o->s;
     const int T = o->n_starts * o->iters_per_start;
