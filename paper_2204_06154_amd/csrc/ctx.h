@@ -141,6 +141,7 @@ struct LearnedLevel {
   float* tval = nullptr;
   double *c = nullptr, *loss = nullptr, *scal = nullptr;
   float* atb = nullptr;
+  double* atb2 = nullptr;  // group sums of the partials
 };
 
 }  // namespace mgm

@@ -372,13 +372,40 @@ __global__ __launch_bounds__(64 * kAtbWaves) void k_atb_partial(int n, int ka, i
   for (int r = 0; r < kAtbRowsPerWave; ++r)
 #pragma unroll
     for (int bj = 0; bj < NBJ; ++bj) acc[r][bj] = atb_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int t0 = n0; t0 < n1; t0 += kAtbTile) {
+  // The next tile's loads are issued into registers before the current
+  // tile's products, so that their latency overlaps the matrix-core work;
+  // rows past the chunk's end load as zeros.
+  constexpr int kThreads = 64 * kAtbWaves;
+  constexpr int kPerA = (kAtbTile * kAtbMaxK + kThreads - 1) / kThreads;
+  constexpr int kPerB = (kAtbTile * 16 * NBJ + kThreads - 1) / kThreads;
+  float ra[kPerA], rb[kPerB];
+  auto fetch = [&](int t0) {
     const int nt = min(kAtbTile, n1 - t0);
-    for (int e = int(threadIdx.x); e < kAtbTile * ka; e += int(blockDim.x))
-      sa[e] = e < nt * ka ? A[size_t(t0) * ka + e] : 0.0f;
-    for (int e = int(threadIdx.x); e < kAtbTile * kb; e += int(blockDim.x))
-      sb[e] = e < nt * kb ? B[size_t(t0) * kb + e] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < kPerA; ++i) {
+      const int e = int(threadIdx.x) + i * kThreads;
+      ra[i] = e < nt * ka ? A[size_t(t0) * ka + e] : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < kPerB; ++i) {
+      const int e = int(threadIdx.x) + i * kThreads;
+      rb[i] = e < nt * kb ? B[size_t(t0) * kb + e] : 0.0f;
+    }
+  };
+  if (n0 < n1) fetch(n0);
+  for (int t0 = n0; t0 < n1; t0 += kAtbTile) {
+#pragma unroll
+    for (int i = 0; i < kPerA; ++i) {
+      const int e = int(threadIdx.x) + i * kThreads;
+      if (e < kAtbTile * ka) sa[e] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < kPerB; ++i) {
+      const int e = int(threadIdx.x) + i * kThreads;
+      if (e < kAtbTile * kb) sb[e] = rb[i];
+    }
     __syncthreads();
+    if (t0 + kAtbTile < n1) fetch(t0 + kAtbTile);
 #pragma unroll 2
     for (int k0 = 0; k0 < kAtbTile; k0 += 4) {
       const int node = k0 + ki;
@@ -417,13 +444,26 @@ __global__ __launch_bounds__(64 * kAtbWaves) void k_atb_partial(int n, int ka, i
   }
 }
 
-// out[e] = sum_blk partial[blk][e] in block order (FP64 accumulation)
-__global__ __launch_bounds__(kBlock) void k_reduce_cols(int nblocks, int nc, const float* __restrict__ partial,
+// Sum of the per-block partials, deterministic in two stages (FP64):
+// stage 1, per entry e and group y of kColGroup consecutive blocks,
+// part2[y][e] = sum over the group's blocks in order; stage 2, out[e] = the
+// sum of part2[.][e] over the groups in order.
+constexpr int kColGroup = 16;
+__global__ __launch_bounds__(kBlock) void k_reduce_cols_group(int nblocks, int nc, const float* __restrict__ partial,
+                                                              double* __restrict__ part2) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= nc) return;
+  const int b0 = int(blockIdx.y) * kColGroup, b1 = min(nblocks, b0 + kColGroup);
+  double acc = 0.0;
+  for (int b = b0; b < b1; ++b) acc += double(partial[size_t(b) * nc + e]);
+  part2[size_t(blockIdx.y) * nc + e] = acc;
+}
+__global__ __launch_bounds__(kBlock) void k_reduce_cols(int ngroups, int nc, const double* __restrict__ part2,
                                                         float* __restrict__ out) {
   const int e = blockIdx.x * kBlock + threadIdx.x;
   if (e >= nc) return;
   double acc = 0.0;
-  for (int b = 0; b < nblocks; ++b) acc += double(partial[size_t(b) * nc + e]);
+  for (int y = 0; y < ngroups; ++y) acc += part2[size_t(y) * nc + e];
   out[e] = float(acc);
 }
 

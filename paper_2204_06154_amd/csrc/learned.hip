@@ -65,6 +65,7 @@ void ensure_learned_buffers(mgm_ctx* c, int j, int s, int T) {
     // partials of the widest product: the first layer's (nin + 1) x 64 or the
     // second's 65 x 64 (the last layer's 65 x s is smaller)
     L.atb = track(c, dalloc<float>(size_t(nb) * std::max(nin + 1, kHid + 1) * kHid));
+    L.atb2 = track(c, dalloc<double>(size_t((nb + kColGroup - 1) / kColGroup) * std::max(nin + 1, kHid + 1) * kHid));
   }
   if (!c->e_tmp64) {  // shared by all levels: sized for the fine level
     c->e_tmp64 = track(c, dalloc<double>(c->lv[0].n + 1));
@@ -206,7 +207,9 @@ void atb(mgm_ctx* c, LearnedLevel& L, int n, int ka, int kb, const float* A, con
   const int nb = (n + kAtbChunk - 1) / kAtbChunk;
   if (kb <= 16) hipLaunchKernelGGL((k_atb_partial<1>), dim3(nb), dim3(64 * kAtbWaves), 0, st, n, ka, kb, A, B, L.atb);
   else hipLaunchKernelGGL((k_atb_partial<4>), dim3(nb), dim3(64 * kAtbWaves), 0, st, n, ka, kb, A, B, L.atb);
-  hipLaunchKernelGGL(k_reduce_cols, dim3(nblk(ka * kb)), dim3(kBlock), 0, st, nb, ka * kb, L.atb, out);
+  const int ng = (nb + kColGroup - 1) / kColGroup;
+  hipLaunchKernelGGL(k_reduce_cols_group, dim3(nblk(ka * kb), ng), dim3(kBlock), 0, st, nb, ka * kb, L.atb, L.atb2);
+  hipLaunchKernelGGL(k_reduce_cols, dim3(nblk(ka * kb)), dim3(kBlock), 0, st, ng, ka * kb, L.atb2, out);
 }
 
 // one loss/gradient evaluation (and an Adam step when `update`); the loss of

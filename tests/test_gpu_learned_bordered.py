@@ -239,3 +239,36 @@ def test_learned_launch_timer(setup):
     with pytest.raises(mgm.MgmError) as ei:
         m.time_kernel("learned", -1, reps=1)
     assert ei.value.status == -1
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_learned_graph_replays_match_eager(setup, prec):
+    """The V-cycle with learned smoothers on both levels (s = 3 on the fine
+    level: the odd count that routes the interpolation through the scratch
+    vector; s = 2 on level 1), replayed three times as a captured HIP graph
+    with eager work between the replays, against a handle that runs it
+    eagerly with the same step weights: bit for bit, every replay."""
+    wl, H, m, f = setup["wl"], setup["H"], setup["m"], setup["f"]
+    p = dict(wl.params, use_graph=0)
+    me = mgm.Mgm(wl.xyz, wl.normals, p, device=0)
+    try:
+        for hnd in (m, me):
+            hnd.train_smoother(setup["d_starts"], steps=0, s=3, iters_per_start=2, seed=9, init=True, activate=0)
+            hnd.smoother_params(_flat(setup["p"][0]))
+            hnd.train_smoother(torch.tensor(setup["starts"][1], device="cuda"), steps=0, s=2, iters_per_start=2,
+                               seed=11, init=True, activate=0, level=1)
+            hnd.smoother_params(_flat(setup["p"][1]), level=1)
+            hnd.set_smoother(3)
+            hnd.set_precision(prec)
+        r = torch.tensor(f, device="cuda")
+        zs = []
+        for _ in range(3):
+            zs.append(m.vcycle(r).cpu().numpy())
+            m.apply(r).cpu()  # eager work between graph replays
+        ze = me.vcycle(r).cpu().numpy()
+        for k, z in enumerate(zs):
+            assert np.array_equal(z, ze), k
+    finally:
+        m.set_precision("fp64")
+        m.set_smoother(False)
+        me.close()
