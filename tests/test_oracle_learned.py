@@ -314,3 +314,24 @@ def test_bordered_omega_gradient_matches_finite_differences(torus_small):
         om[i, q] -= h
         fd = (learned.loss_and_grad_omega(L, op, S)[0] - learned.loss_and_grad_omega(L, om, S)[0]) / (2 * h)
         assert abs(fd - g[i, q]) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(g).max())
+
+
+def test_mlp_forward_reduces_to_affine_maps():
+    """Where no ReLU is active the network is one affine map,
+    x -> x (W1 W2 W3) + (b1 W2 W3 + b2 W3 + b3) (the weight product formed
+    first); where the first layer is switched off by its bias, the output
+    is relu(b2) W3 + b3 whatever the input."""
+    rng = np.random.default_rng(90)
+    n_in, s = 12, 3
+    W1, W2, W3 = rng.random((n_in, 64)), rng.random((64, 64)), rng.standard_normal((64, s))
+    b1, b2, b3 = rng.random(64), rng.random(64), rng.standard_normal(s)
+    X = rng.random((7, n_in))
+    o, _ = learned.mlp_forward([W1, b1, W2, b2, W3, b3], X)
+    Wp = W1 @ (W2 @ W3)
+    bp = (b1 @ W2) @ W3 + b2 @ W3 + b3
+    assert np.allclose(o, X @ Wp + bp, rtol=1e-12, atol=1e-12 * np.abs(o).max())
+    b1_off = -1.0 - X.max() * np.abs(W1).sum(axis=0)          # every first-layer unit negative
+    b2_mixed = rng.standard_normal(64)
+    o2, _ = learned.mlp_forward([W1, b1_off, W2, b2_mixed, W3, b3], X)
+    ref = np.maximum(b2_mixed, 0.0) @ W3 + b3
+    assert np.allclose(o2, np.broadcast_to(ref, o2.shape), rtol=0, atol=1e-12)
