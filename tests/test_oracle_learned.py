@@ -335,3 +335,14 @@ def test_mlp_forward_reduces_to_affine_maps():
     o2, _ = learned.mlp_forward([W1, b1_off, W2, b2_mixed, W3, b3], X)
     ref = np.maximum(b2_mixed, 0.0) @ W3 + b3
     assert np.allclose(o2, np.broadcast_to(ref, o2.shape), rtol=0, atol=1e-12)
+
+
+def test_step_weights_stay_within_half_of_chebyshev():
+    """omega = omega_q (1 + tanh(o) / 2): the Chebyshev weight at o = 0, its
+    limits 1.5 and 0.5 times it for o -> +-inf, 1.25 times it at
+    o = artanh(1/2)."""
+    w = learned.cheb_omegas(2.0, 3)
+    o = np.array([[0.0, 60.0, -60.0], [math.atanh(0.5), 0.0, 0.0]])
+    om = learned.omegas_from_output(o, w)
+    assert np.allclose(om[0], w * np.array([1.0, 1.5, 0.5]), rtol=1e-15)
+    assert np.allclose(om[1], w * np.array([1.25, 1.0, 1.0]), rtol=1e-15)
