@@ -83,3 +83,51 @@ def test_fullsize_fp32_solve(torus):
     assert info["status"] == 0
     assert abs(info["iters"] - info_ref.iters) <= 1, (info["iters"], info_ref.iters)
     assert np.linalg.norm(f - A(u)) <= 1.01e-10 * np.linalg.norm(f)
+
+
+def test_fullsize_learned_smoothers(torus):
+    """The bench's learned configuration at full size: every smoothed level
+    trains its network on the GPU (bordered, s = 2, 400 Adam steps at 3e-3)
+    and keeps it if its factor beats Gauss-Seidel's. With the exported step
+    weights, the FP64 cycle matches the oracle's to 1e-10 and the FP32 cycle
+    the oracle's FP32 emulation to 1e-5; the FP32 FGMRES solve reaches a true
+    relative residual of 1e-10 within one iteration of the oracle's FP64
+    count with the same smoothers."""
+    wl, H, m = torus
+    f = np.concatenate([wl.f, [0.0]])
+    sizes = [lv.N for lv in H.levels]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2204)
+    mask = 0
+    for j in range(len(sizes) - 1):
+        sj = torch.randn((4, sizes[j]), generator=gen, device="cuda", dtype=torch.float64)
+        t = m.train_smoother(sj, steps=400, lr=3e-3, s=2, iters_per_start=2, seed=5 + j, init=True, activate=1,
+                             level=j)
+        print(f"[fullsize] level {j}: factor GS {t['rate_gs']:.4f}, learned {t['rate_learned']:.4f}", flush=True)
+        mask |= (1 << j) if t["active"] else 0
+    assert mask != 0
+    m.set_smoother(mask)
+    try:
+        om = {j: m.export("omega", j).reshape(sizes[j], -1) for j in range(len(sizes) - 1) if (mask >> j) & 1}
+        ops = vcycle.Fp64Ops(H)
+        ops.learned = om
+        M = vcycle.make_preconditioner(ops, H.problem)
+        m.set_precision("fp64")
+        z64 = _host(m.vcycle(_dev(f)))
+        ref64 = M(f)
+        assert np.max(np.abs(z64 - ref64)) <= 1e-10 * np.max(np.abs(ref64))
+        ops32 = precision.ops_for(H, "fp32")
+        ops32.learned = {j: w.astype(np.float32) for j, w in om.items()}
+        m.set_precision("fp32")
+        z32 = _host(m.vcycle(_dev(f)))
+        ref32 = vcycle.make_preconditioner(ops32, H.problem)(f)
+        assert np.linalg.norm(z32 - ref32) <= 1e-5 * np.linalg.norm(ref32)
+        A = vcycle.make_operator(H)
+        _, info_ref = krylov.fgmres(A, M, f, tol=1e-10, restart=40, maxit=400)
+        u, info = m.solve(_dev(f), krylov="fgmres", restart=40, maxit=400, rtol=1e-10)
+        print(f"[fullsize] learned mask {mask:#x}: FGMRES {info['iters']} (oracle {info_ref.iters})", flush=True)
+        assert info["status"] == 0 and abs(info["iters"] - info_ref.iters) <= 1, (info["iters"], info_ref.iters)
+        assert np.linalg.norm(f - A(_host(u))) <= 1.01e-10 * np.linalg.norm(f)
+    finally:
+        m.set_precision("fp64")
+        m.set_smoother(False)
