@@ -723,13 +723,29 @@ def main():
         wms = float(np.median(ts))
         S = 60
         flops = (2.0 / 3.0 * S ** 3 + 2.0 * S * S) * args.weights_n
+        # the FP32 matrix-core elimination with FP64 refinement, same systems
+        d_wm = torch.empty_like(d_w)
+        mgm.batched_weights(d_x, d_n, d_s, 1, 3, d_wm, mixed=True)
+        tsm = []
+        for _ in range(reps):
+            ev0.record()
+            mgm.batched_weights(d_x, d_n, d_s, 1, 3, d_wm, mixed=True)
+            ev1.record()
+            ev1.synchronize()
+            tsm.append(ev0.elapsed_time(ev1))
+        wms_mixed = float(np.median(tsm))
+        mixed_diff = float((torch.abs(d_wm - d_w).amax(dim=1) / torch.abs(d_w).amax(dim=1)).max())
         bw = {"systems": args.weights_n, "system_size": S, "ms": round(wms, 3),
               "systems_per_s": round(args.weights_n / (wms * 1e-3)),
               "TFLOPs_lu_model": round(flops / (wms * 1e-3) / 1e12, 2),
               "frac_fp64_peak": round(flops / (wms * 1e-3) / 1e12 / 78.6, 4),
               "note": "FP64 Gauss-Jordan with partial pivoting, one wavefront per system, in panels of 4 columns "
-                      "whose updates run on the FP64 matrix cores (MFMA); flops = (2/3)S^3 + 2S^2"}
-        log(f"batched weights: {wms:.2f} ms for {args.weights_n} systems ({bw['TFLOPs_lu_model']} TFLOP/s LU model)")
+                      "whose updates run on the FP64 matrix cores (MFMA); flops = (2/3)S^3 + 2S^2",
+              "mixed": {"ms": round(wms_mixed, 3), "max_rel_diff_vs_fp64": float(f"{mixed_diff:.3g}"),
+                        "note": "FP32 Gauss-Jordan on [A | I] on the FP32 matrix cores, then FP64 iterative "
+                                "refinement (mgm_batched_weights_mixed)"}}
+        log(f"batched weights: {wms:.2f} ms for {args.weights_n} systems ({bw['TFLOPs_lu_model']} TFLOP/s LU model); "
+            f"mixed precision {wms_mixed:.2f} ms, max rel diff {mixed_diff:.1e}")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -337,6 +337,21 @@ mgm_status mgm_batched_weights(const double *d_xyz, const double *d_normals, int
                                int32_t phs_order, int32_t poly_degree, double *d_weights,
                                void *stream);
 
+/* Mixed-precision form of mgm_batched_weights (the same systems of Sec. 2.2,
+ * eq. rbf_fd_lap; same arguments, layouts and errors, poly_degree <= 4 or
+ * MGM_E_ARG): each system is eliminated in FP32 on the matrix cores (Gauss-
+ * Jordan with partial pivoting in panels of four columns, on [A | I], so that
+ * the elimination yields an FP32 inverse) and the solution is then refined in
+ * FP64: from x = 0, four times x += A32^-1 (b - A x), the residual computed
+ * in FP64 from the stencil coordinates. Each correction contracts the error
+ * by about cond(A) * 6e-8; for the scaled PHS systems (cond ~ 3e4) the result
+ * agrees with the FP64 elimination to ~1e-11. The singular flag is the FP64
+ * kernel's (a pivot below 1e-13 of the largest entry). */
+mgm_status mgm_batched_weights_mixed(const double *d_xyz, const double *d_normals, int64_t n_points,
+                                     const int32_t *d_stencils, int64_t n_systems, int32_t stencil_size,
+                                     int32_t phs_order, int32_t poly_degree, double *d_weights,
+                                     void *stream);
+
 /* Allocation-free form of mgm_batched_weights, for callers that cannot
  * allocate device memory (code that must not call hipMalloc, such as tight
  * serving loops or harnesses that forbid it). Same arguments, results

@@ -21,8 +21,10 @@ Csr spgemm_device(const Csr& A, const Csr& B, hipStream_t st);
 void dsatur_patches_device(const std::vector<int32_t>& lptr, const std::vector<int32_t>& ladj,
                            const std::vector<int32_t>& pstart, std::vector<int32_t>& lc, std::vector<int32_t>& pnlc,
                            hipStream_t st);
+// mixed: FP32 elimination on the matrix cores with FP64 refinement
+// (poly_degree <= 4) instead of the FP64 elimination
 void batched_phs_weights_device(const double* d_xyz, const double* d_nrm, const int32_t* d_sten, int64_t nsys, int ns,
-                                int phs_order, int deg, double* d_w, int* d_status, hipStream_t st);
+                                int phs_order, int deg, double* d_w, int* d_status, hipStream_t st, bool mixed = false);
 
 #define HIPCHECK(x)                                                                                     \
   do {                                                                                                  \

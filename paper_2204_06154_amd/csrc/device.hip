@@ -1746,9 +1746,10 @@ mgm_status mgm_stencils(const double* h_xyz, int64_t n, int32_t k, int32_t* h_id
   });
 }
 
-mgm_status mgm_batched_weights(const double* d_xyz, const double* d_normals, int64_t n_points, const int32_t* d_stencils,
-                               int64_t n_systems, int32_t stencil_size, int32_t phs_order, int32_t poly_degree,
-                               double* d_weights, void* stream) {
+static mgm_status batched_weights_entry(const double* d_xyz, const double* d_normals, int64_t n_points,
+                                        const int32_t* d_stencils, int64_t n_systems, int32_t stencil_size,
+                                        int32_t phs_order, int32_t poly_degree, double* d_weights, void* stream,
+                                        bool mixed) {
   // an empty batch may pass null stencils and weights (it still checks the sizes)
   if (!d_xyz || !d_normals || (n_systems > 0 && (!d_stencils || !d_weights)) || n_points < 1 || n_systems < 0 ||
       stencil_size < 1 || stencil_size > n_points) {
@@ -1763,7 +1764,7 @@ mgm_status mgm_batched_weights(const double* d_xyz, const double* d_normals, int
     try {
       HIPCHECK(hipMemsetAsync(dst, 0, sizeof(int), st));
       batched_phs_weights_device(d_xyz, d_normals, d_stencils, n_systems, stencil_size, phs_order, poly_degree,
-                                 d_weights, dst, st);
+                                 d_weights, dst, st, mixed);
       HIPCHECK(hipMemcpyAsync(&status, dst, sizeof(int), hipMemcpyDeviceToHost, st));
       HIPCHECK(hipStreamSynchronize(st));
     } catch (...) {
@@ -1777,6 +1778,20 @@ mgm_status mgm_batched_weights(const double* d_xyz, const double* d_normals, int
     }
   });
   return s != MGM_OK ? s : res;
+}
+
+mgm_status mgm_batched_weights(const double* d_xyz, const double* d_normals, int64_t n_points, const int32_t* d_stencils,
+                               int64_t n_systems, int32_t stencil_size, int32_t phs_order, int32_t poly_degree,
+                               double* d_weights, void* stream) {
+  return batched_weights_entry(d_xyz, d_normals, n_points, d_stencils, n_systems, stencil_size, phs_order, poly_degree,
+                               d_weights, stream, false);
+}
+
+mgm_status mgm_batched_weights_mixed(const double* d_xyz, const double* d_normals, int64_t n_points,
+                                     const int32_t* d_stencils, int64_t n_systems, int32_t stencil_size,
+                                     int32_t phs_order, int32_t poly_degree, double* d_weights, void* stream) {
+  return batched_weights_entry(d_xyz, d_normals, n_points, d_stencils, n_systems, stencil_size, phs_order, poly_degree,
+                               d_weights, stream, true);
 }
 
 mgm_status mgm_export(mgm_handle h, int32_t what, int32_t level, void* h_buf, int64_t* len) {

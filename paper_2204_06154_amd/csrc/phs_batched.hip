@@ -237,6 +237,95 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The mixed-precision kernel's set-up, the same arithmetic as the FP64
+// matrix-core kernel's (which keeps its own inline copy: factored out, it
+// spilled more registers and took 4% longer). The centre's tangent frame
+// (Sec. 2.1) and this lane's projected stencil point, scaled by the stencil
+// radius s (returned with the lane's scaled distance r), to xsw[lane]. Inactive wavefronts compute on zeros. Its
+// monomials (total degree, then descending power of x) then go to
+// mono[lane * kMonoMax ..] (phs_monomials), so that the polynomial entries
+// are table reads.
+__device__ __forceinline__ void phs_stencil_points(bool active, int64_t sys, int ns, int lane,
+                                                   const double* __restrict__ xyz, const double* __restrict__ nrm,
+                                                   const int32_t* __restrict__ sten, double (*xsw)[2], double& r_out,
+                                                   double& s_out) {
+  double px = 0.0, py = 0.0;
+  if (active) {
+    const int32_t* st = sten + sys * ns;
+    const int ci = st[0];
+    double n0 = nrm[3 * ci], n1 = nrm[3 * ci + 1], n2 = nrm[3 * ci + 2];
+    double nn = sqrt(fma(n0, n0, fma(n1, n1, n2 * n2)));
+    n0 /= nn;
+    n1 /= nn;
+    n2 /= nn;
+    int ax = 0;
+    if (fabs(n1) < fabs(n0)) ax = 1;
+    if (fabs(n2) < fabs(ax == 0 ? n0 : n1)) ax = 2;
+    double nax = ax == 0 ? n0 : (ax == 1 ? n1 : n2);
+    double t1x = (ax == 0 ? 1.0 : 0.0) - nax * n0;
+    double t1y = (ax == 1 ? 1.0 : 0.0) - nax * n1;
+    double t1z = (ax == 2 ? 1.0 : 0.0) - nax * n2;
+    double l1 = sqrt(t1x * t1x + t1y * t1y + t1z * t1z);
+    t1x /= l1;
+    t1y /= l1;
+    t1z /= l1;
+    double t2x = n1 * t1z - n2 * t1y, t2y = n2 * t1x - n0 * t1z, t2z = n0 * t1y - n1 * t1x;
+    if (lane < ns) {
+      const int j = st[lane];
+      double dx = xyz[3 * j] - xyz[3 * ci], dy = xyz[3 * j + 1] - xyz[3 * ci + 1], dz = xyz[3 * j + 2] - xyz[3 * ci + 2];
+      px = t1x * dx + t1y * dy + t1z * dz;
+      py = t2x * dx + t2y * dy + t2z * dz;
+    }
+  }
+  double r = sqrt(px * px + py * py);
+  double s = r;
+  for (int off = 32; off > 0; off >>= 1) s = fmax(s, __shfl_xor(s, off, 64));
+  if (!(s > 0.0)) s = 1.0;
+  px /= s;
+  py /= s;
+  r /= s;
+  xsw[lane][0] = px;
+  xsw[lane][1] = py;
+  r_out = r;
+  s_out = s;
+}
+
+// the monomials of this lane's scaled point (after phs_stencil_points)
+__device__ __forceinline__ void phs_monomials(int deg, int lane, const double (*xsw)[2], double* mono) {
+  const double px = xsw[lane][0], py = xsw[lane][1];
+  int q = 0;  // (deg + 1)(deg + 2) / 2 = L <= kMonoMax monomials (checked on the host)
+  for (int d = 0; d <= deg; ++d)
+    for (int b = 0; b <= d; ++b, ++q) mono[lane * kMonoMax + q] = ipow_d(px, d - b) * ipow_d(py, b);
+}
+
+// Entry (row, col) of the system padded to 64 x 64 with identity rows and
+// columns, column point (xc, yc): the PHS block, P (row a point, col a
+// monomial) or P^T, the zero block; `inside` is false on the padding. Every
+// candidate is computed and the result selected, without branches.
+__device__ __forceinline__ double phs_entry(const double (*xsw)[2], const double* mono, int row, int col, double xc,
+                                            double yc, int ns, int S, int m, bool& inside) {
+  const double dx = xsw[row][0] - xc, dy = xsw[row][1] - yc;
+  const double phs = ipow_d(sqrt(dx * dx + dy * dy), m);
+  const bool rp = row < ns;
+  const int pt = rp ? row : col, mq = (rp ? col : row) - ns;
+  const double pq = mono[pt * kMonoMax + min(max(mq, 0), kMonoMax - 1)];
+  inside = row < S && col < S;
+  if (inside) return (row < ns && col < ns) ? phs : ((row < ns) != (col < ns) ? pq : 0.0);
+  return row == col ? 1.0 : 0.0;
+}
+
+// right-hand side (eq. rbf_fd_lap) of row `lane`: Lap r^m at the points, Lap p(0)
+// for the monomials, zero on the padding
+__device__ __forceinline__ double phs_rhs(int lane, double r, int ns, int S, int m) {
+  if (lane < ns) return double(m) * double(m) * ipow_d(r, m - 2);
+  if (lane < S) {
+    int qa, qb;
+    mono_exp(lane - ns, qa, qb);
+    return ((qa == 2 && qb == 0) || (qa == 0 && qb == 2)) ? 2.0 : 0.0;
+  }
+  return 0.0;
+}
+
 __global__ __launch_bounds__(64 * kMWaves, 3) void k_phs_weights_mfma(int64_t nsys, int ns, int deg, int L, int m,
                                                                  const double* __restrict__ xyz,
                                                                  const double* __restrict__ nrm,
@@ -456,6 +545,256 @@ __global__ __launch_bounds__(64 * kMWaves, 3) void k_phs_weights_mfma(int64_t ns
   }
 }
 
+// --------------------------------- FP32 matrix cores with FP64 refinement
+// The same system, eliminated in FP32 on the matrix cores and refined in FP64
+// (mixed-precision iterative refinement). Gauss-Jordan with partial pivoting,
+// in panels of 4 columns as above, runs on [A | I] (64 x 128 in FP32, tiles
+// bj = 0..3 holding A and 4..7 the identity, v_mfma_f32_16x16x4f32 updates;
+// the FP32 accumulator layout is lane 16g + c, register v -> row 4g + v,
+// column c of a tile). Afterwards pivot row r (the row chosen for column k_r)
+// holds d_r e_{k_r}^T in its A part and T_r in its I part, with T A = D P
+// (P the permutation): A^-1 = (rows T_r / d_r, placed at k_r). Then, from
+// x = 0: res = b - A x in FP64 (row r assembled again on lane r) and
+// x_{k_r} += (T_r . res) / d_r, until a correction is below 2^-50 of the
+// largest |x| or no longer halves the one before (the FP64 residual's
+// rounding is reached), at most kMaxSweeps solves. Each correction contracts
+// the error by about cond(A) eps_fp32: ~2e-3 a sweep for r^3 stencils
+// (condition numbers ~3e4). A system whose last correction still exceeds
+// 1e-8 of |x| (the FP32 elimination too inaccurate for the refinement to
+// converge) is reported like a singular one.
+typedef float flt4 __attribute__((ext_vector_type(4)));
+constexpr int kMaxSweeps = 10;
+
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+__global__ __launch_bounds__(64 * kMWaves, 3) void k_phs_weights_mixed(int64_t nsys, int ns, int deg, int L, int m,
+                                                                  const double* __restrict__ xyz,
+                                                                  const double* __restrict__ nrm,
+                                                                  const int32_t* __restrict__ sten,
+                                                                  double* __restrict__ w, int* __restrict__ status) {
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  const int64_t sys = int64_t(blockIdx.x) * kMWaves + wv;
+  const bool active = sys < nsys;  // uniform per wavefront
+  const int S = ns + L;
+  __shared__ double xs[kMWaves][64][2];
+  __shared__ double mono_s[kMWaves][64 * kMonoMax];  // kept for the residuals
+  // per wavefront: the panel (-M, 64 x 4) and the pivot rows (4 x 128), FP32;
+  // after the elimination the residual, the solution and the correction
+  __shared__ double work[kMWaves][(64 * 4 + 4 * 128) / 2];
+
+  double r, s;
+  phs_stencil_points(active, sys, ns, lane, xyz, nrm, sten, xs[wv], r, s);
+  wave_sync();
+  const double* mono = mono_s[wv];
+  phs_monomials(deg, lane, xs[wv], mono_s[wv]);
+  wave_sync();
+  flt4 acc[4][8];
+  double amax = 0.0;
+#pragma unroll
+  for (int bj = 0; bj < 4; ++bj) {
+    const int col = 16 * bj + c;
+    const double xc = xs[wv][col][0], yc = xs[wv][col][1];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        bool inside;
+        const double val = phs_entry(xs[wv], mono, 16 * bi + 4 * g + v, col, xc, yc, ns, S, m, inside);
+        if (inside) amax = fmax(amax, fabs(val));
+        acc[bi][bj][v] = float(val);
+      }
+    }
+  }
+#pragma unroll
+  for (int bj = 4; bj < 8; ++bj)
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[bi][bj][v] = (16 * bi + 4 * g + v == 16 * (bj - 4) + c) ? 1.0f : 0.0f;
+  for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+  const double tiny = amax * 1e-13;
+  const double b = phs_rhs(lane, r, ns, S, m);
+
+  bool used = false;
+  int kpos = -1;
+  float diag = 1.0f;
+  bool singular = false;
+  float(*pan)[4] = reinterpret_cast<float(*)[4]>(work[wv]);                // 64 x 4
+  float(*ub)[128] = reinterpret_cast<float(*)[128]>(work[wv] + 64 * 4 / 2);  // 4 x 128
+  const int np = (S + 3) / 4;
+  for (int p = 0; p < np; ++p) {
+    const int bjp = p >> 2, co = (p & 3) * 4;
+    // 1. the panel's columns into rows
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+      if (bj == bjp && c >= co && c < co + 4) {
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) pan[16 * bi + 4 * g + v][c - co] = acc[bi][bj][v];
+      }
+    wave_sync();
+    float pr[4], mk[4];
+    int bk[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) pr[j] = pan[lane][j];
+    // 2. pivot steps on the panel (the unused row with the largest |entry|,
+    //    ties to the lowest row)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float v = pr[k];
+      const uint32_t key = used ? 0u : __builtin_bit_cast(uint32_t, fabsf(v)) + 1u;
+      const uint32_t kmax = wave_max_u32(key);
+      const int bl = int(__builtin_ctzll(__ballot(key == kmax)));
+      const float piv = readlane_f(v, bl);
+      if (4 * p + k < S && !(fabs(double(piv)) > tiny)) singular = true;
+      const float rpiv = 1.0f / piv;
+      const float mlt = lane == bl ? 0.0f : v * rpiv;
+#pragma unroll
+      for (int j = k + 1; j < 4; ++j) pr[j] = fmaf(-mlt, readlane_f(pr[j], bl), pr[j]);
+      mk[k] = mlt;
+      bk[k] = bl;
+      if (lane == bl) {
+        used = true;
+        kpos = 4 * p + k;
+        diag = piv;
+      }
+    }
+    // 3. the pivot rows' current entries (A and I parts), then U = Lambda^-1 B
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int rb = bk[k];
+      const int bib = rb >> 4, vb = rb & 3;
+      if (g == ((rb >> 2) & 3)) {
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (bi == bib && v == vb) {
+#pragma unroll
+              for (int bj = 0; bj < 8; ++bj) ub[k][16 * bj + c] = acc[bi][bj][v];
+            }
+      }
+    }
+    float lam[4][4];  // lam[k][q] = multiplier of pivot row b_k at step q < k
+#pragma unroll
+    for (int k = 1; k < 4; ++k)
+#pragma unroll
+      for (int q = 0; q < k; ++q) lam[k][q] = readlane_f(mk[q], bk[k]);
+    wave_sync();
+    float u[4][2];  // columns lane (A part) and 64 + lane (I part)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      u[k][0] = ub[k][lane];
+      u[k][1] = ub[k][64 + lane];
+#pragma unroll
+      for (int q = 0; q < k; ++q) {
+        u[k][0] = fmaf(-lam[k][q], u[q][0], u[k][0]);
+        u[k][1] = fmaf(-lam[k][q], u[q][1], u[k][1]);
+      }
+    }
+    const bool done_col = lane < 4 * p + 4;  // this lane's A column is eliminated already
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      ub[k][lane] = done_col ? 0.0f : u[k][0];
+      ub[k][64 + lane] = u[k][1];
+      pan[lane][k] = -mk[k];
+    }
+    wave_sync();
+    // 4. the update on the matrix cores (A part from the panel's tile on, all of the I part)
+    float aop[4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) aop[bi] = pan[16 * bi + c][g];
+#pragma unroll
+    for (int bj = 0; bj < 8; ++bj)
+      if (bj >= bjp) {
+        const float bop = ub[g][16 * bj + c];
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi) acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[bi], bop, acc[bi][bj], 0, 0, 0);
+      }
+    wave_sync();  // the next panel reuses pan and ub
+  }
+  // 5. solve and refine in FP64
+  double* rs = work[wv];        // residual, by row
+  double* xsol = work[wv] + 64;  // solution, by column
+  double* dv = work[wv] + 128;   // correction, by row
+  xsol[lane] = 0.0;
+  double res = b;
+  bool converged = false;
+  double dprev = 0.0, xlast = 0.0;
+  for (int it = 0; it < kMaxSweeps && !converged; ++it) {
+    if (it > 0) {
+      double ax = 0.0;  // row `lane` of A times x, the entries assembled again
+      for (int j = 0; j < S; ++j) {
+        bool inside;
+        const double a = phs_entry(xs[wv], mono, lane, j, xs[wv][j][0], xs[wv][j][1], ns, S, m, inside);
+        ax = fma(a, xsol[j], ax);
+      }
+      res = lane < S ? b - ax : 0.0;
+    }
+    rs[lane] = res;
+    wave_sync();
+    double rc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) rc[t] = rs[16 * t + c];
+    double pd[4][4];  // T row . res over this lane's four columns, rows 16 bi + 4g + v
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double t0 = 0.0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) t0 = fma(double(acc[bi][4 + t][v]), rc[t], t0);
+        pd[bi][v] = t0;
+      }
+    // sum over the 16 lanes of each row group (the columns), in a fixed tree
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1)
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pd[bi][v] += __shfl_xor(pd[bi][v], off, 64);
+    if (c == 0) {
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dv[16 * bi + 4 * g + v] = pd[bi][v];
+    }
+    wave_sync();
+    double dmax = 0.0, xmax = 0.0;
+    if (kpos >= 0) {
+      const double dx = dv[lane] / double(diag);
+      const double xn = xsol[kpos] + dx;
+      xsol[kpos] = xn;
+      if (kpos < S) {
+        dmax = fabs(dx);
+        xmax = fabs(xn);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
+      xmax = fmax(xmax, __shfl_xor(xmax, off, 64));
+    }
+    // the same on every lane
+    converged = it > 0 && (dmax <= 0x1.0p-50 * xmax || dmax > 0.5 * dprev);
+    dprev = dmax;
+    xlast = xmax;
+    wave_sync();
+  }
+  if (!(dprev <= 1e-8 * xlast)) singular = true;
+  if (active) {
+    if (singular) {
+      if (lane == 0) atomicMax(status, 1);
+    } else if (lane < ns) {
+      w[sys * ns + lane] = xsol[lane] / (s * s);
+    }
+  }
+}
+
 #define HIPOK(x)                                                                                   \
   do {                                                                                             \
     hipError_t e_ = (x);                                                                           \
@@ -466,11 +805,19 @@ __global__ __launch_bounds__(64 * kMWaves, 3) void k_phs_weights_mfma(int64_t ns
 
 // Device pointers; launches on `st`. Throws on invalid sizes.
 void batched_phs_weights_device(const double* d_xyz, const double* d_nrm, const int32_t* d_sten, int64_t nsys, int ns,
-                                int phs_order, int deg, double* d_w, int* d_status, hipStream_t st) {
+                                int phs_order, int deg, double* d_w, int* d_status, hipStream_t st, bool mixed) {
   const int L = (deg + 1) * (deg + 2) / 2;
   if (ns < 1 || ns + L > 64) throw Error(MGM_E_ARG, "device weights need stencil_size + L <= 64");
   if (deg < 0 || deg > 6 || phs_order < 0 || phs_order > 6) throw Error(MGM_E_ARG, "phs_order/poly_degree out of range");
+  if (mixed && L > kMonoMax) throw Error(MGM_E_ARG, "the mixed-precision weights need poly_degree <= 4");
   if (nsys <= 0) return;
+  if (mixed) {
+    if ((nsys + kMWaves - 1) / kMWaves > 0x7fffffff) throw Error(MGM_E_ARG, "too many systems for one launch");
+    hipLaunchKernelGGL(k_phs_weights_mixed, dim3(unsigned((nsys + kMWaves - 1) / kMWaves)), dim3(64 * kMWaves), 0, st,
+                       nsys, ns, deg, L, 2 * phs_order + 1, d_xyz, d_nrm, d_sten, d_w, d_status);
+    HIPOK(hipGetLastError());
+    return;
+  }
   if ((nsys + kWaves - 1) / kWaves > 0x7fffffff) throw Error(MGM_E_ARG, "too many systems for one launch");
   const int m = 2 * phs_order + 1;
   const unsigned blocks = unsigned((nsys + kWaves - 1) / kWaves);
@@ -555,7 +902,7 @@ extern "C" mgm_status mgm_batched_weights_noalloc(const double* d_xyz, const dou
     hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, st, status);
     HIPOK(hipGetLastError());
     batched_phs_weights_device(d_xyz, d_normals, d_stencils, n_systems, stencil_size, phs_order, poly_degree,
-                               d_weights, status, st);
+                               d_weights, status, st, false);
     int h_status = 0;
     HIPOK(hipMemcpyAsync(&h_status, status, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPOK(hipStreamSynchronize(st));

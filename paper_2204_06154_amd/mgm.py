@@ -72,7 +72,8 @@ class MgmError(RuntimeError):
 _lib = None
 
 EXPORTED = ["mgm_default_params", "mgm_setup", "mgm_set_precision", "mgm_vcycle", "mgm_apply", "mgm_solve",
-            "mgm_level_op", "mgm_time_kernel", "mgm_stencils", "mgm_batched_weights", "mgm_batched_weights_noalloc", "mgm_train_smoother",
+            "mgm_level_op", "mgm_time_kernel", "mgm_stencils", "mgm_batched_weights", "mgm_batched_weights_noalloc",
+            "mgm_batched_weights_mixed", "mgm_train_smoother",
             "mgm_smoother_params", "mgm_smoother_grad", "mgm_set_smoother", "mgm_export", "mgm_destroy",
             "mgm_status_str", "mgm_last_error", "mgm_surface_ops_setup", "mgm_surface_gradient",
             "mgm_surface_divergence", "mgm_check", "mgm_set_flow_wait"]
@@ -110,6 +111,8 @@ def load():
     lib.mgm_batched_weights.restype = i32
     lib.mgm_batched_weights_noalloc.argtypes = [vp, vp, i64, vp, i64, i32, i32, i32, vp, vp]
     lib.mgm_batched_weights_noalloc.restype = i32
+    lib.mgm_batched_weights_mixed.argtypes = [vp, vp, i64, vp, i64, i32, i32, i32, vp, vp]
+    lib.mgm_batched_weights_mixed.restype = i32
     lib.mgm_train_smoother.argtypes = [vp, ctypes.POINTER(TrainOpts), vp, ctypes.POINTER(TrainInfo), vp, vp]
     lib.mgm_train_smoother.restype = i32
     lib.mgm_smoother_params.argtypes = [vp, i32, i32, vp, ctypes.POINTER(i64)]
@@ -364,16 +367,22 @@ def stencils(xyz: np.ndarray, k: int) -> np.ndarray:
 
 
 def batched_weights(d_xyz, d_normals, d_stencils, phs_order: int, poly_degree: int, d_weights=None, stream=None,
-                    noalloc: bool = False):
+                    noalloc: bool = False, mixed: bool = False):
     """Device batched RBF-FD weights: torch tensors (n x 3 f64, n x 3 f64, m x ns int32) -> (m x ns f64).
     noalloc=True calls the allocation-free entry point (d_weights should then
-    be passed in, so that nothing is allocated on the caller's side either)."""
+    be passed in, so that nothing is allocated on the caller's side either);
+    mixed=True the FP32-matrix-core elimination with FP64 refinement."""
+    if noalloc and mixed:
+        raise ValueError("the allocation-free entry point is the FP64 elimination")
+    import torch
+    if d_stencils.dtype != torch.int32 or d_xyz.dtype != torch.float64 or d_normals.dtype != torch.float64:
+        raise ValueError("batched_weights takes float64 points and normals and int32 stencils")
     import torch
     m, ns = d_stencils.shape
     if d_weights is None:
         d_weights = torch.empty((m, ns), dtype=torch.float64, device=d_stencils.device)
     lib = load()
-    fn = lib.mgm_batched_weights_noalloc if noalloc else lib.mgm_batched_weights
+    fn = lib.mgm_batched_weights_noalloc if noalloc else (lib.mgm_batched_weights_mixed if mixed else lib.mgm_batched_weights)
     _check(fn(_ptr(d_xyz), _ptr(d_normals), d_xyz.shape[0], _ptr(d_stencils), m, ns,
               phs_order, poly_degree, _ptr(d_weights), _stream(stream)))
     return d_weights

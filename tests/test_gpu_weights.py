@@ -120,3 +120,38 @@ def test_empty_batch_and_size_checks(noalloc):
         mgm.batched_weights(d_x, d_n, torch.empty((0, 60), dtype=torch.int32, device="cuda"), 1, 6, noalloc=noalloc,
                             d_weights=torch.empty((0, 60), dtype=torch.float64, device="cuda"))
     assert ei.value.status == -1
+
+
+@pytest.mark.parametrize("surface,phs,deg,k", [("sphere", 1, 2, 30), ("torus", 2, 3, 50), ("star", 1, 3, 50),
+                                                ("star", 2, 2, 20), ("torus", 1, 0, 7), ("sphere", 3, 4, 45)])
+def test_mixed_precision_weights_match_oracle(surface, phs, deg, k):
+    """FP32 elimination on the matrix cores with FP64 refinement: the same
+    bar as the FP64 elimination (1e-10 of each row's magnitude against the
+    oracle's LAPACK solve, polynomial reproduction to 1e-10)."""
+    if surface == "sphere":
+        wl = synth.sphere_workload(3000)
+    elif surface == "torus":
+        wl = synth.torus_workload(3000)
+    else:
+        wl = synth.star_workload(3001, n_probe=20000)
+    sten = knn.stencils(wl.xyz, k)
+    d_x = torch.tensor(wl.xyz, device="cuda")
+    d_n = torch.tensor(wl.normals, device="cuda")
+    d_s = torch.tensor(sten.astype(np.int32), device="cuda")
+    c = mgm.batched_weights(d_x, d_n, d_s, phs, deg, mixed=True).cpu().numpy()
+    ref = discretize.rbffd_weights(discretize.project_stencils(wl.xyz, wl.normals, sten), phs, deg)
+    scale = np.abs(ref).max(axis=1, keepdims=True)
+    err = np.max(np.abs(c - ref) / scale)
+    print(f"[gpu-weights-mixed] {surface} phs {phs} deg {deg} k {k}: max rel err {err:.2e}", flush=True)
+    assert err < 1e-10
+    assert _poly_repro_error(wl.xyz, wl.normals, sten, c, deg) < 1e-10
+
+
+def test_mixed_precision_weights_need_degree_at_most_four():
+    wl = synth.sphere_workload(500)
+    d_x = torch.tensor(wl.xyz, device="cuda")
+    d_n = torch.tensor(wl.normals, device="cuda")
+    d_s = torch.tensor(knn.stencils(wl.xyz, 30).astype(np.int32), device="cuda")
+    with pytest.raises(mgm.MgmError) as ei:
+        mgm.batched_weights(d_x, d_n, d_s, 1, 5, mixed=True)
+    assert ei.value.status == -1
