@@ -56,7 +56,7 @@ HBM_PEAK_GBS = 8000.0
 # `bench.py --workload traffic` (summary and commands in
 # profiles/gs_patch_torus160k_traffic.md): bytes per launch, valid only for
 # the kernel source it was measured on (SHA-256 over lane_ops.h + gs_patch.h).
-GS_TRAFFIC = {"source_sha256": "8e1570851bb1354ba1acf1cb3ef3725f2704e0006f95b807967bb25bb11e4b09", "bytes_per_launch": 23408328,
+GS_TRAFFIC = {"source_sha256": "0dbb99cff6bf57f47f7c99c3f11636a3336091b5e69b4491e4003c66c482c534", "bytes_per_launch": 23684806,
               "summary": "profiles/gs_patch_torus160k_traffic.md"}
 
 

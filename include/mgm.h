@@ -108,7 +108,12 @@ typedef struct {
                              launch in which a patch starts once the coupled
                              patches before it in the sweep order are done
                              (the same GS order and bit-identical results as
-                             0: one launch per patch colour). A wait is
+                             0: one launch per patch colour); each patch
+                             loads the distinct rows outside it that its
+                             entries reference once, into LDS (levels whose
+                             patches reference at most 1024 such rows; the
+                             others load per entry). 2: one launch per sweep
+                             with loads per entry on every level. A wait is
                              bounded; if one gives up, the next mgm_solve,
                              mgm_level_op or mgm_check returns MGM_E_SYNC */
   int32_t gs_max_width;   /* part of the smoother ordering: a level is

@@ -117,6 +117,10 @@ struct DevLevel {
   int32_t *fl_nbptr = nullptr, *fl_nb = nullptr, *fl_crow = nullptr;
   unsigned long long* fl_ticket = nullptr;
   unsigned* fl_flag = nullptr;
+  // staged halo of the one-launch sweeps (see kMaxHalo): columns in staged
+  // form, per-slot lists of distinct out-of-patch rows
+  bool halo_ok = false;
+  int32_t *pcolh = nullptr, *fl_hstart = nullptr, *fl_hrows = nullptr;
 };
 
 }  // namespace mgm

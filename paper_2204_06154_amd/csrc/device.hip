@@ -271,6 +271,40 @@ static void upload(mgm_ctx* c) {
         HIPCHECK(hipMemset(d.fl_ticket, 0, sizeof(unsigned long long)));
         HIPCHECK(hipMemset(d.fl_flag, 0, sizeof(unsigned) * nsl));
       }
+      {
+        // staged halo: per slot, the distinct out-of-patch rows its entries
+        // reference (ascending), and the columns rewritten to the in-patch
+        // row or kPatch + the place in that list
+        const int nsl = int(ps.size()) - 1;
+        std::vector<int32_t> hstart(nsl + 1, 0), hrows, pch(pci.size());
+        std::vector<int32_t> rows;
+        int hmax = 0;
+        const size_t slot_len = size_t(d.pw) * kPatchG * block;
+        for (int sl = 0; sl < nsl; ++sl) {
+          rows.clear();
+          const size_t e0 = size_t(sl) * slot_len;
+          for (size_t e = e0; e < e0 + slot_len; ++e)
+            if (pci[e] < ps[sl] || pci[e] >= ps[sl + 1]) rows.push_back(pci[e]);
+          std::sort(rows.begin(), rows.end());
+          rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+          for (size_t e = e0; e < e0 + slot_len; ++e) {
+            const int32_t cc = pci[e];
+            pch[e] = (cc >= ps[sl] && cc < ps[sl + 1])
+                         ? cc - ps[sl]
+                         : kPatch + int32_t(std::lower_bound(rows.begin(), rows.end(), cc) - rows.begin());
+          }
+          hmax = std::max(hmax, int(rows.size()));
+          hrows.insert(hrows.end(), rows.begin(), rows.end());
+          hstart[sl + 1] = int32_t(hrows.size());
+        }
+        d.halo_ok = hmax <= kMaxHalo;
+        if (d.halo_ok) {
+          if (hrows.empty()) hrows.push_back(0);
+          d.pcolh = track(c, dupload(pch));
+          d.fl_hstart = track(c, dupload(hstart));
+          d.fl_hrows = track(c, dupload(hrows));
+        }
+      }
       d.pstart = track(c, dupload(ps));
       d.pncl = track(c, dupload(pn));
       d.lcol = track(c, dupload(lc));
@@ -460,16 +494,18 @@ static void gs_patch_launch(mgm_ctx* c, int j, int pc, bool reverse, bool border
   const int ns = flow ? d.pstart_host_slots : d.pc_start[pc + 1] - s0;
   if (ns <= 0) return;
   GsFlow fl{};
-  if (flow) fl = GsFlow{d.fl_ticket, d.fl_flag, d.fl_nbptr, d.fl_nb, d.fl_crow, c->flow_err, ns, c->flow_wait_ticks};
-#define GS_PATCH(WM, BD, FL)                                                                                 \
-  hipLaunchKernelGGL((k_gs_patch<V, S, WM / kPatchG, SC, BD, FL>), dim3(ns), dim3(kPatch * kPatchG), 0, st, s0, \
-                     reverse ? 1 : 0, zero_guess ? 1 : 0, d.pw, d.pblock, d.pstart, \
-                     d.pncl, d.lcol, P::pval(d), d.pcolidx, d.s16, P::dinv(d), P::f(d), P::e(d),  \
-                     P::b(d), lam, fl)
-#define GS_PATCH_W(WM, FL) \
-  if (border) GS_PATCH(WM, true, FL); else GS_PATCH(WM, false, FL);
+  const bool staged = flow && d.halo_ok && c->p.gs_flow == 1;
+  if (flow)
+    fl = GsFlow{d.fl_ticket, d.fl_flag, d.fl_nbptr, d.fl_nb, d.fl_crow, c->flow_err, ns, c->flow_wait_ticks,
+                d.fl_hstart, d.fl_hrows};
+#define GS_PATCH(WM, BD, FL, HL)                                                                             \
+  hipLaunchKernelGGL((k_gs_patch<V, S, WM / kPatchG, SC, BD, FL, HL>), dim3(ns), dim3(kPatch * kPatchG), 0, st, \
+                     s0, reverse ? 1 : 0, zero_guess ? 1 : 0, d.pw, d.pblock, d.pstart, d.pncl, d.lcol,       \
+                     P::pval(d), HL ? d.pcolh : d.pcolidx, d.s16, P::dinv(d), P::f(d), P::e(d), P::b(d), lam, fl)
+#define GS_PATCH_W(WM, FL, HL) \
+  if (border) GS_PATCH(WM, true, FL, HL); else GS_PATCH(WM, false, FL, HL);
 #define GS_PATCH_F(WM) \
-  if (flow) { GS_PATCH_W(WM, true) } else { GS_PATCH_W(WM, false) }
+  if (staged) { GS_PATCH_W(WM, true, true) } else if (flow) { GS_PATCH_W(WM, true, false) } else { GS_PATCH_W(WM, false, false) }
   switch (d.wmax) {
     case 24: GS_PATCH_F(24) break;
     case 32: GS_PATCH_F(32) break;

@@ -64,16 +64,30 @@ struct GsFlow {
   int* err;                      // set when a wait gave up
   int nslot;
   unsigned long long wait_ticks;  // bound of each wait (real-time counter ticks)
+  const int32_t* hstart;         // staged halo: slot s reads rows hrows[hstart[s] .. hstart[s+1])
+  const int32_t* hrows;
 };
 
-template <typename V, typename S, int WL, bool SCALED, bool BORDER, bool FLOW = false>
+// Staged halo (HALO, one-launch sweeps): the distinct rows outside a patch
+// that its entries reference (a few hundred, against a few thousand entries)
+// are listed per slot in ascending order; the workgroup loads each of them
+// once into LDS after the wait, with consecutive lanes on consecutive rows,
+// and the lanes gather their out-of-patch values from there. The column array
+// then holds the in-patch row (below kPatch) or kPatch + the row's place in
+// the slot's list. Same values, same sums: results are those of the direct
+// loads.
+constexpr int kMaxHalo = kPatch * kPatchG;  // staged rows per slot (one per thread)
+
+template <typename V, typename S, int WL, bool SCALED, bool BORDER, bool FLOW = false, bool HALO = false>
 __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
     int slot0, int reverse, int zero_guess, int nw, int block, const int32_t* __restrict__ pstart,
     const int32_t* __restrict__ pncl, const int32_t* __restrict__ lcol,
     const V* __restrict__ pval, const int32_t* __restrict__ pcol, const float* __restrict__ scale,
     const S* __restrict__ dinv, const S* __restrict__ f, S* u, const S* __restrict__ b,
     const double* __restrict__ lam, GsFlow fl) {
+  static_assert(!HALO || FLOW, "staged halo: one-launch sweeps");
   __shared__ S ul[kPatch];
+  __shared__ S hv[HALO ? kMaxHalo : 1];
   __shared__ unsigned s_ticket[2];
   int slot = slot0 + blockIdx.x;
   unsigned sweep = 0;
@@ -109,6 +123,14 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
   const int r0 = pstart[slot];
   const int nr = pstart[slot + 1] - r0;
   const int ncl = pncl[slot];
+  int hrow = 0;
+  bool hact = false;
+  if (HALO) {
+    // this thread's staged row (the list is known before the wait)
+    const int h0 = fl.hstart[slot];
+    hact = int(threadIdx.x) < fl.hstart[slot + 1] - h0;
+    if (hact) hrow = fl.hrows[h0 + int(threadIdx.x)];
+  }
   // rows [upd_lo, upd_hi) hold current values (all rows unless zero_guess)
   int upd_lo = 0, upd_hi = INT_MAX;
   if (zero_guess) {
@@ -153,11 +175,28 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
     }
     __syncthreads();
   }
+  if (HALO) {
+    if (hact) {
+      S v = S(0);
+      if (hrow >= upd_lo && hrow < upd_hi) v = __hip_atomic_load(u + hrow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      hv[threadIdx.x] = v;
+    }
+    __syncthreads();
+  }
   if (act) {
     S halo = S(0);
 #pragma unroll
     for (int i = 0; i < WL; ++i) {
       const bool live = i < nw;
+      if (HALO) {
+        // cc: in-patch row, or kPatch + place in the staged list
+        const bool in = live && cc[i] < kPatch;
+        const S hval = hv[(live && !in) ? cc[i] - kPatch : 0];
+        halo += iv[i] * ((live && !in) ? hval : S(0));
+        ic[i] = in ? cc[i] : t;
+        iv[i] = in ? iv[i] : S(0);
+        continue;
+      }
       const bool in = live && unsigned(cc[i] - r0) < unsigned(nr);
       const bool cur = cc[i] >= upd_lo && cc[i] < upd_hi;
       S uv = S(0);

@@ -38,6 +38,7 @@ void validate_params(const mgm_params& p, int64_t n) {
   if (p.precision < MGM_FP64 || p.precision > MGM_FP16) bad("precision");
   if (p.gs_block < 0 || p.gs_block > 256) bad("gs_block must be 0..256");
   if (p.gs_max_width < 1 || p.gs_max_width > kMaxPatchWidth) bad("gs_max_width must be 1..96");
+  if (p.gs_flow < 0 || p.gs_flow > 2) bad("gs_flow must be 0, 1 or 2");
   if (p.cycle < MGM_CYCLE_V || p.cycle > MGM_CYCLE_F) bad("cycle");
 }
 

@@ -19,11 +19,12 @@ pytestmark = pytest.mark.gpu
 E_SYNC = -10
 
 
+@pytest.mark.parametrize("flow", [1, 2])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_give_up_is_reported_and_the_next_solves_are_clean(prec):
+def test_give_up_is_reported_and_the_next_solves_are_clean(prec, flow):
     wl = synth.torus_workload(20000)
-    p = dict(wl.params, precision=prec)
-    print(f"[gpu-flow-sync] torus N=20000 {prec}", flush=True)
+    p = dict(wl.params, precision=prec, gs_flow=flow)
+    print(f"[gpu-flow-sync] torus N=20000 {prec} gs_flow={flow}", flush=True)
     m = mgm.Mgm(wl.xyz, wl.normals, p, device=0)
     ref = mgm.Mgm(wl.xyz, wl.normals, p, device=0)
     f = torch.tensor(np.concatenate([wl.f, [0.0]]), device="cuda")

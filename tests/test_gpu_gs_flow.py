@@ -1,5 +1,6 @@
-"""One-launch patch-blocked sweeps (gs_flow = 1) against one launch per patch
-colour (gs_flow = 0).
+"""One-launch patch-blocked sweeps (gs_flow = 1, halo rows staged in LDS;
+gs_flow = 2, halo values loaded per entry) against one launch per patch colour
+(gs_flow = 0).
 
 Both run the same arithmetic in the same Gauss-Seidel order (patch colour,
 patch, local colour); only the synchronisation between patches differs, so
@@ -34,9 +35,11 @@ def pair(request):
     print(f"[gpu-gs-flow] setting up {request.param}", flush=True)
     m0 = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, gs_flow=0), device=0)
     m1 = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, gs_flow=1), device=0)
-    yield request.param, wl, m0, m1
+    m2 = mgm.Mgm(wl.xyz, wl.normals, dict(wl.params, gs_flow=2), device=0)
+    yield request.param, wl, m0, (m1, m2)
     m0.close()
     m1.close()
+    m2.close()
 
 
 def _rhs(wl, m):
@@ -46,49 +49,54 @@ def _rhs(wl, m):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
 def test_cycles_identical(pair, prec):
-    name, wl, m0, m1 = pair
-    m0.set_precision(prec)
-    m1.set_precision(prec)
+    name, wl, m0, ms = pair
+    for m in (m0,) + ms:
+        m.set_precision(prec)
     f = _rhs(wl, m0)
     rng = np.random.default_rng(5)
     for k in range(6):
         r = f if k == 0 else torch.tensor(rng.standard_normal(m0.vec_len), device="cuda")
         z0 = m0.vcycle(r)
-        z1 = m1.vcycle(r)
+        zs = [m.vcycle(r) for m in ms]
         torch.cuda.synchronize()
-        assert torch.equal(z0, z1), (name, prec, k)
+        for mode, z in zip((1, 2), zs):
+            assert torch.equal(z0, z), (name, prec, k, mode)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_solves_identical(pair, prec):
-    name, wl, m0, m1 = pair
-    m0.set_precision(prec)
-    m1.set_precision(prec)
+    name, wl, m0, ms = pair
+    for m in (m0,) + ms:
+        m.set_precision(prec)
     f = _rhs(wl, m0)
     u0, i0 = m0.solve(f, rtol=1e-10, maxit=200, history=True)
-    u1, i1 = m1.solve(f, rtol=1e-10, maxit=200, history=True)
-    assert i0["status"] == 0 and i1["status"] == 0
-    assert i0["iters"] == i1["iters"]
-    assert np.array_equal(i0["history"], i1["history"])
-    assert torch.equal(u0, u1)
+    assert i0["status"] == 0
+    for m in ms:
+        u1, i1 = m.solve(f, rtol=1e-10, maxit=200, history=True)
+        assert i1["status"] == 0
+        assert i0["iters"] == i1["iters"]
+        assert np.array_equal(i0["history"], i1["history"])
+        assert torch.equal(u0, u1)
 
 
-def test_single_sweeps_identical(pair):
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_single_sweeps_identical(pair, prec):
     """One smoothing sweep of every smoothed level, forward and backward, from
     the same start vector and right-hand side."""
-    name, wl, m0, m1 = pair
-    m0.set_precision("fp64")
-    m1.set_precision("fp64")
+    name, wl, m0, ms = pair
+    for m in (m0,) + ms:
+        m.set_precision(prec)
     sizes = [int(s) for s in m0.export("level_sizes")]
     rng = np.random.default_rng(7)
     for j, n in enumerate(sizes[:-1]):
         x = rng.standard_normal(n)
         b = rng.standard_normal(n)
         for reverse in (False, True):
-            y0 = torch.tensor(x, device="cuda")
-            y1 = torch.tensor(x, device="cuda")
             bt = torch.tensor(b, device="cuda")
+            y0 = torch.tensor(x, device="cuda")
             m0.level_op(mgm.OP_SMOOTH, j, y0, b=bt, scalar=0.3, reverse=reverse)
-            m1.level_op(mgm.OP_SMOOTH, j, y1, b=bt, scalar=0.3, reverse=reverse)
-            torch.cuda.synchronize()
-            assert torch.equal(y0, y1), (name, j, reverse)
+            for mode, m in zip((1, 2), ms):
+                y1 = torch.tensor(x, device="cuda")
+                m.level_op(mgm.OP_SMOOTH, j, y1, b=bt, scalar=0.3, reverse=reverse)
+                torch.cuda.synchronize()
+                assert torch.equal(y0, y1), (name, prec, j, reverse, mode)

@@ -126,7 +126,7 @@ def test_host_only_handle_rejects_device_calls():
 
 @pytest.mark.parametrize("mutate,status", [
     ("dup", -5), ("nan", -9), ("mu0", -1), ("muinf", -1), ("tiny", -1), ("onelevel", -1), ("badstencil", -1),
-    ("collinear", -4),
+    ("collinear", -4), ("gsflow3", -1),
 ])
 def test_failure_injection(mutate, status):
     wl = synth.sphere_workload(800)
@@ -147,6 +147,8 @@ def test_failure_injection(mutate, status):
         p.pop("n_coarse_max")
         p["n_min"] = 250
         x, nrm = x[:600], nrm[:600]
+    elif mutate == "gsflow3":
+        p["gs_flow"] = 3
     elif mutate == "badstencil":
         p["stencil_size"] = 3   # fewer than the 6 degree-2 monomials
     elif mutate == "collinear":
