@@ -71,8 +71,9 @@ struct GsFlow {
 // Staged halo (HALO, one-launch sweeps): the distinct rows outside a patch
 // that its entries reference (a few hundred, against a few thousand entries)
 // are listed per slot in ascending order; the workgroup loads each of them
-// once into LDS after the wait, with consecutive lanes on consecutive rows,
-// and the lanes gather their out-of-patch values from there. The column array
+// once into LDS, with consecutive lanes on consecutive rows (rows of slots
+// later in the sweep before the wait, the others after it), and the lanes
+// gather their out-of-patch values from there. The column array
 // then holds the in-patch row (below kPatch) or kPatch + the row's place in
 // the slot's list. Same values, same sums: results are those of the direct
 // loads.
@@ -144,6 +145,15 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
   }
   const bool act = t < nr;
   const int row = r0 + t;
+  // staged rows of slots after this one in the sweep keep their old values
+  // until this patch is done (those slots wait for it): load them before the wait
+  S hval = S(0);
+  bool hlate = false;
+  if (HALO && hact) {
+    hlate = reverse ? hrow < r0 : hrow > r0;
+    if (hlate && hrow >= upd_lo && hrow < upd_hi)
+      hval = __hip_atomic_load(u + hrow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   int ic[WL];
   S rhs = S(0), di = S(0), sc = S(1), uown = S(0);
   int myc = -1;
@@ -177,9 +187,9 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
   }
   if (HALO) {
     if (hact) {
-      S v = S(0);
-      if (hrow >= upd_lo && hrow < upd_hi) v = __hip_atomic_load(u + hrow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      hv[threadIdx.x] = v;
+      if (!hlate && hrow >= upd_lo && hrow < upd_hi)
+        hval = __hip_atomic_load(u + hrow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      hv[threadIdx.x] = hval;
     }
     __syncthreads();
   }
