@@ -424,14 +424,20 @@ mgm_status mgm_surface_divergence(mgm_handle h, const double *d_v, double *d_out
  *                             the order of MGM_EX_L_VALS; built on first use.
  *                             Smoothed levels of a device handle only
  *   MGM_EX_ROW_SCALE     F64  the FP32 row scales s_i of that operator
- *                             (L_ij ~ s_i h_ij), natural order */
+ *                             (L_ij ~ s_i h_ij), natural order
+ *   MGM_EX_HALO_ROWS     I32  the staged halo of the one-launch sweeps of
+ *                             level j: for each patch in ascending patch id,
+ *                             its count, then the distinct rows outside it
+ *                             that its rows' entries reference (natural
+ *                             numbering, ascending); empty when the level
+ *                             loads its halo per entry. Device handles only */
 enum {
   MGM_EX_LEVEL_SIZES = 0, MGM_EX_STENCILS = 1, MGM_EX_WEIGHTS = 2,
   MGM_EX_COARSE_IDX = 3, MGM_EX_INTERP_IDX = 4, MGM_EX_INTERP_W = 5,
   MGM_EX_COLOURS = 6, MGM_EX_L_ROWPTR = 7, MGM_EX_L_COLS = 8,
   MGM_EX_L_VALS = 9, MGM_EX_BORDER = 10, MGM_EX_NCOLOURS = 11, MGM_EX_PATCH = 12,
   MGM_EX_OMEGA = 13, MGM_EX_GRAD_STENCILS = 14, MGM_EX_GRAD_WEIGHTS = 15,
-  MGM_EX_L16_VALS = 16, MGM_EX_ROW_SCALE = 17
+  MGM_EX_L16_VALS = 16, MGM_EX_ROW_SCALE = 17, MGM_EX_HALO_ROWS = 18
 };
 mgm_status mgm_export(mgm_handle h, int32_t what, int32_t level, void *h_buf,
                       int64_t *len);

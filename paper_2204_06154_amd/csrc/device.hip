@@ -1922,6 +1922,37 @@ mgm_status mgm_export(mgm_handle h, int32_t what, int32_t level, void* h_buf, in
         isint = false;
         break;
       }
+      case MGM_EX_HALO_ROWS: {
+        // the staged halo lists of the one-launch sweeps, moved from the
+        // device's slot order and permuted numbering to patch ids and the
+        // natural numbering
+        need_level(p - 2);
+        need_device(h);
+        HIPCHECK(hipSetDevice(h->device));
+        const DevLevel& d = h->lv[level];
+        if (!d.patched || !d.halo_ok) break;
+        const int n = d.n, nsl = d.pstart_host_slots;
+        std::vector<int32_t> perm(n), ps(nsl + 1), hs(nsl + 1);
+        if (d.perm) HIPCHECK(hipMemcpy(perm.data(), d.perm, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+        else std::iota(perm.begin(), perm.end(), 0);
+        HIPCHECK(hipMemcpy(ps.data(), d.pstart, (nsl + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(hs.data(), d.fl_hstart, (nsl + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+        std::vector<int32_t> hr(std::max(hs[nsl], 1));
+        HIPCHECK(hipMemcpy(hr.data(), d.fl_hrows, hr.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        const std::vector<int32_t>& patch = H.lv[level].patch;
+        std::vector<std::vector<int32_t>> lists(size_t(H.lv[level].npatch));
+        for (int sl = 0; sl < nsl; ++sl) {
+          if (ps[sl + 1] <= ps[sl]) continue;
+          auto& l = lists[size_t(patch[perm[ps[sl]]])];
+          for (int k = hs[sl]; k < hs[sl + 1]; ++k) l.push_back(perm[hr[k]]);
+          std::sort(l.begin(), l.end());
+        }
+        for (const auto& l : lists) {
+          vi.push_back(int32_t(l.size()));
+          vi.insert(vi.end(), l.begin(), l.end());
+        }
+        break;
+      }
       default: throw Error(MGM_E_ARG, "unknown export item");
     }
     int64_t cnt = isint ? int64_t(vi.size()) : int64_t(vd.size());

@@ -24,7 +24,7 @@ OP_SMOOTH, OP_SPMV, OP_RESTRICT_RESIDUAL, OP_INTERP_ADD = 0, 1, 2, 3
 EX = dict(level_sizes=0, stencils=1, weights=2, coarse_idx=3, interp_idx=4, interp_w=5, colours=6,
           l_rowptr=7, l_cols=8, l_vals=9, border=10, ncolours=11, patch=12, omega=13, grad_stencils=14,
           grad_weights=15,
-          l16_vals=16, row_scale=17)
+          l16_vals=16, row_scale=17, halo_rows=18)
 EX_FLOAT = {"weights", "interp_w", "l_vals", "border", "omega", "grad_weights", "l16_vals", "row_scale"}
 
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16}

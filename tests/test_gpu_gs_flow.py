@@ -100,3 +100,35 @@ def test_single_sweeps_identical(pair, prec):
                 m.level_op(mgm.OP_SMOOTH, j, y1, b=bt, scalar=0.3, reverse=reverse)
                 torch.cuda.synchronize()
                 assert torch.equal(y0, y1), (name, prec, j, reverse, mode)
+
+
+def test_staged_halo_lists(pair):
+    """The staged halo lists the device builds (exported in the natural
+    numbering) are, for each patch, the distinct columns outside the patch
+    that its rows' entries reference: recomputed here from the exported
+    operator pattern and patch assignment. Every patch-blocked level of these
+    workloads is staged, so the sweeps above ran the staged path."""
+    name, wl, m0, ms = pair
+    m1 = ms[0]
+    sizes = [int(s) for s in m1.export("level_sizes")]
+    staged = 0
+    for j, n in enumerate(sizes[:-1]):
+        patch = np.asarray(m1.export("patch", j))
+        if patch.size == 0:
+            continue
+        ptr = np.asarray(m1.export("l_rowptr", j))
+        cols = np.asarray(m1.export("l_cols", j))
+        rows = np.repeat(np.arange(n), np.diff(ptr))
+        out = patch[rows] != patch[cols]
+        keys = np.unique(patch[rows[out]].astype(np.int64) * n + cols[out])
+        kp, kc = keys // n, keys % n
+        want = []
+        for p in range(int(patch.max()) + 1):
+            sel = kc[kp == p]
+            want.append(len(sel))
+            want.extend(sel.tolist())
+        got = np.asarray(m1.export("halo_rows", j))
+        assert got.size > 0, (name, j)
+        assert np.array_equal(got, np.asarray(want)), (name, j)
+        staged += 1
+    assert staged > 0
