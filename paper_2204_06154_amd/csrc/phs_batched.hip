@@ -65,6 +65,20 @@ __device__ __forceinline__ double ipow_d(double x, int e) {
   return r;
 }
 
+// x^e with the exponent fixed at compile time when EC > 0 (the same products
+// in the same order as ipow_d, so the same bits), else e
+template <int EC>
+__device__ __forceinline__ double ipow_c(double x, int e) {
+  if constexpr (EC > 0) {
+    double r = 1.0;
+#pragma unroll
+    for (int t = 0; t < EC; ++t) r *= x;
+    return r;
+  } else {
+    return ipow_d(x, e);
+  }
+}
+
 // exponents (a, b) of monomial q: by total degree, then descending a
 __device__ __forceinline__ void mono_exp(int q, int& a, int& b) {
   int d = 0;
@@ -302,10 +316,11 @@ __device__ __forceinline__ void phs_monomials(int deg, int lane, const double (*
 // columns, column point (xc, yc): the PHS block, P (row a point, col a
 // monomial) or P^T, the zero block; `inside` is false on the padding. Every
 // candidate is computed and the result selected, without branches.
+template <int MC>
 __device__ __forceinline__ double phs_entry(const double (*xsw)[2], const double* mono, int row, int col, double xc,
                                             double yc, int ns, int S, int m, bool& inside) {
   const double dx = xsw[row][0] - xc, dy = xsw[row][1] - yc;
-  const double phs = ipow_d(sqrt(dx * dx + dy * dy), m);
+  const double phs = ipow_c<MC>(sqrt(dx * dx + dy * dy), m);
   const bool rp = row < ns;
   const int pt = rp ? row : col, mq = (rp ? col : row) - ns;
   const double pq = mono[pt * kMonoMax + min(max(mq, 0), kMonoMax - 1)];
@@ -316,8 +331,9 @@ __device__ __forceinline__ double phs_entry(const double (*xsw)[2], const double
 
 // right-hand side (eq. rbf_fd_lap) of row `lane`: Lap r^m at the points, Lap p(0)
 // for the monomials, zero on the padding
+template <int MC>
 __device__ __forceinline__ double phs_rhs(int lane, double r, int ns, int S, int m) {
-  if (lane < ns) return double(m) * double(m) * ipow_d(r, m - 2);
+  if (lane < ns) return double(m) * double(m) * ipow_c<(MC > 2 ? MC - 2 : 0)>(r, m - 2);
   if (lane < S) {
     int qa, qb;
     mono_exp(lane - ns, qa, qb);
@@ -326,6 +342,7 @@ __device__ __forceinline__ double phs_rhs(int lane, double r, int ns, int S, int
   return 0.0;
 }
 
+template <int MC>  // PHS exponent m fixed at compile time (MC > 0) or read from m
 __global__ __launch_bounds__(64 * kMWaves, 3) void k_phs_weights_mfma(int64_t nsys, int ns, int deg, int L, int m,
                                                                  const double* __restrict__ xyz,
                                                                  const double* __restrict__ nrm,
@@ -404,7 +421,7 @@ __global__ __launch_bounds__(64 * kMWaves, 3) void k_phs_weights_mfma(int64_t ns
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * bi + 4 * v + g;
         const double dx = xs[wv][row][0] - xc, dy = xs[wv][row][1] - yc;
-        const double phs = ipow_d(sqrt(dx * dx + dy * dy), m);
+        const double phs = ipow_c<MC>(sqrt(dx * dx + dy * dy), m);
         // P (row a point, col a monomial) or P^T (row a monomial, col a point)
         const bool rp = row < ns;
         const int pt = rp ? row : col, mq = (rp ? col : row) - ns;
@@ -426,7 +443,7 @@ __global__ __launch_bounds__(64 * kMWaves, 3) void k_phs_weights_mfma(int64_t ns
   // right-hand side (eq. rbf_fd_lap), row `lane`
   double rhs = 0.0;
   if (lane < ns) {
-    rhs = double(m) * double(m) * ipow_d(r, m - 2);
+    rhs = double(m) * double(m) * ipow_c<(MC > 2 ? MC - 2 : 0)>(r, m - 2);
   } else if (lane < S) {
     int qa, qb;
     mono_exp(lane - ns, qa, qb);
@@ -569,6 +586,7 @@ __device__ __forceinline__ float readlane_f(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
+template <int MC>  // PHS exponent m fixed at compile time (MC > 0) or read from m
 __global__ __launch_bounds__(64 * kMWaves, 3) void k_phs_weights_mixed(int64_t nsys, int ns, int deg, int L, int m,
                                                                   const double* __restrict__ xyz,
                                                                   const double* __restrict__ nrm,
@@ -603,7 +621,7 @@ __global__ __launch_bounds__(64 * kMWaves, 3) void k_phs_weights_mixed(int64_t n
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         bool inside;
-        const double val = phs_entry(xs[wv], mono, 16 * bi + 4 * g + v, col, xc, yc, ns, S, m, inside);
+        const double val = phs_entry<MC>(xs[wv], mono, 16 * bi + 4 * g + v, col, xc, yc, ns, S, m, inside);
         if (inside) amax = fmax(amax, fabs(val));
         acc[bi][bj][v] = float(val);
       }
@@ -617,7 +635,7 @@ __global__ __launch_bounds__(64 * kMWaves, 3) void k_phs_weights_mixed(int64_t n
       for (int v = 0; v < 4; ++v) acc[bi][bj][v] = (16 * bi + 4 * g + v == 16 * (bj - 4) + c) ? 1.0f : 0.0f;
   for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
   const double tiny = amax * 1e-13;
-  const double b = phs_rhs(lane, r, ns, S, m);
+  const double b = phs_rhs<MC>(lane, r, ns, S, m);
 
   bool used = false;
   int kpos = -1;
@@ -731,7 +749,7 @@ __global__ __launch_bounds__(64 * kMWaves, 3) void k_phs_weights_mixed(int64_t n
       double ax = 0.0;  // row `lane` of A times x, the entries assembled again
       for (int j = 0; j < S; ++j) {
         bool inside;
-        const double a = phs_entry(xs[wv], mono, lane, j, xs[wv][j][0], xs[wv][j][1], ns, S, m, inside);
+        const double a = phs_entry<MC>(xs[wv], mono, lane, j, xs[wv][j][0], xs[wv][j][1], ns, S, m, inside);
         ax = fma(a, xsol[j], ax);
       }
       res = lane < S ? b - ax : 0.0;
@@ -813,8 +831,17 @@ void batched_phs_weights_device(const double* d_xyz, const double* d_nrm, const 
   if (nsys <= 0) return;
   if (mixed) {
     if ((nsys + kMWaves - 1) / kMWaves > 0x7fffffff) throw Error(MGM_E_ARG, "too many systems for one launch");
-    hipLaunchKernelGGL(k_phs_weights_mixed, dim3(unsigned((nsys + kMWaves - 1) / kMWaves)), dim3(64 * kMWaves), 0, st,
-                       nsys, ns, deg, L, 2 * phs_order + 1, d_xyz, d_nrm, d_sten, d_w, d_status);
+    const dim3 grid(unsigned((nsys + kMWaves - 1) / kMWaves)), block(64 * kMWaves);
+    const int mm = 2 * phs_order + 1;
+#define PHS_MIXED(MC) \
+  hipLaunchKernelGGL(k_phs_weights_mixed<MC>, grid, block, 0, st, nsys, ns, deg, L, mm, d_xyz, d_nrm, d_sten, d_w, d_status)
+    switch (mm) {
+      case 3: PHS_MIXED(3); break;
+      case 5: PHS_MIXED(5); break;
+      case 7: PHS_MIXED(7); break;
+      default: PHS_MIXED(0); break;
+    }
+#undef PHS_MIXED
     HIPOK(hipGetLastError());
     return;
   }
@@ -826,8 +853,16 @@ void batched_phs_weights_device(const double* d_xyz, const double* d_nrm, const 
   if (S > 32 && L <= kMonoMax) {
     // larger systems: blocked elimination with the update on the matrix cores
     const unsigned mblocks = unsigned((nsys + kMWaves - 1) / kMWaves);
-    hipLaunchKernelGGL(k_phs_weights_mfma, dim3(mblocks), dim3(64 * kMWaves), 0, st, nsys, ns, deg, L, m, d_xyz, d_nrm,
-                       d_sten, d_w, d_status);
+#define PHS_MFMA(MC)                                                                                            \
+  hipLaunchKernelGGL(k_phs_weights_mfma<MC>, dim3(mblocks), dim3(64 * kMWaves), 0, st, nsys, ns, deg, L, m, d_xyz, \
+                     d_nrm, d_sten, d_w, d_status)
+    switch (m) {
+      case 3: PHS_MFMA(3); break;
+      case 5: PHS_MFMA(5); break;
+      case 7: PHS_MFMA(7); break;
+      default: PHS_MFMA(0); break;
+    }
+#undef PHS_MFMA
   } else if (S <= 32)
     hipLaunchKernelGGL(k_phs_weights<32>, dim3(blocks), dim3(64 * kWaves), 0, st, nsys, ns, L, m, d_xyz, d_nrm, d_sten,
                        d_w, d_status);
