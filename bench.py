@@ -555,6 +555,62 @@ def bench_table2(args):
                       "rows": rows}), flush=True)
 
 
+def bench_weights(n_sys: int):
+    """Batched per-node weight solves: n_sys star-surface stencils (n = 50, r^3 + degree 3: 60x60 systems), the
+    FP64 matrix-core kernel and the mixed-precision one, each the median of 5 timed calls."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2204_06154_amd import mgm
+
+    t0 = time.perf_counter()
+    wl4 = synth.star_workload(n_sys)
+    sten = mgm.stencils(wl4.xyz, 50)
+    log(f"star surface N={n_sys} + stencils in {time.perf_counter() - t0:.1f} s")
+    d_x = torch.tensor(wl4.xyz, device="cuda")
+    d_n = torch.tensor(wl4.normals, device="cuda")
+    d_s = torch.tensor(sten, device="cuda")
+    d_w = torch.empty((n_sys, 50), dtype=torch.float64, device="cuda")
+    mgm.batched_weights(d_x, d_n, d_s, 1, 3, d_w)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    ts = []
+    for _ in range(reps):
+        ev0.record()
+        mgm.batched_weights(d_x, d_n, d_s, 1, 3, d_w)
+        ev1.record()
+        ev1.synchronize()
+        ts.append(ev0.elapsed_time(ev1))
+    wms = float(np.median(ts))
+    S = 60
+    flops = (2.0 / 3.0 * S ** 3 + 2.0 * S * S) * n_sys
+    # the FP32 matrix-core elimination with FP64 refinement, same systems
+    d_wm = torch.empty_like(d_w)
+    mgm.batched_weights(d_x, d_n, d_s, 1, 3, d_wm, mixed=True)
+    tsm = []
+    for _ in range(reps):
+        ev0.record()
+        mgm.batched_weights(d_x, d_n, d_s, 1, 3, d_wm, mixed=True)
+        ev1.record()
+        ev1.synchronize()
+        tsm.append(ev0.elapsed_time(ev1))
+    wms_mixed = float(np.median(tsm))
+    mixed_diff = float((torch.abs(d_wm - d_w).amax(dim=1) / torch.abs(d_w).amax(dim=1)).max())
+    bw = {"systems": n_sys, "system_size": S, "ms": round(wms, 3),
+          "systems_per_s": round(n_sys / (wms * 1e-3)),
+          "TFLOPs_lu_model": round(flops / (wms * 1e-3) / 1e12, 2),
+          "frac_fp64_peak": round(flops / (wms * 1e-3) / 1e12 / 78.6, 4),
+          "note": "FP64 Gauss-Jordan with partial pivoting, one wavefront per system, in panels of 4 columns "
+                  "whose updates run on the FP64 matrix cores (MFMA); flops = (2/3)S^3 + 2S^2",
+          "mixed": {"ms": round(wms_mixed, 3), "max_rel_diff_vs_fp64": float(f"{mixed_diff:.3g}"),
+                    "note": "FP32 Gauss-Jordan on [A | I] on the FP32 matrix cores, then FP64 iterative "
+                            "refinement (mgm_batched_weights_mixed)"}}
+    log(f"batched weights: {wms:.2f} ms for {n_sys} systems ({bw['TFLOPs_lu_model']} TFLOP/s LU model); "
+        f"mixed precision {wms_mixed:.2f} ms, max rel diff {mixed_diff:.1e}")
+    return bw
+
+
 def bench_traffic(args):
     """Launch set for the HBM-traffic counters: FP32 patch-GS launches of the
     torus workload as the roofline times them (every smoother launch of a
@@ -599,7 +655,7 @@ def main():
                          "0: one launch per patch colour")
     ap.add_argument("--cycle", choices=["V", "W", "F"], default="V", help="multigrid cycle of the torus workload")
     ap.add_argument("--workload", choices=["torus", "learned", "sphere1m", "traffic", "sbdf2", "harmonics",
-                                                 "setup", "geodesic", "table2"],
+                                                 "setup", "geodesic", "table2", "weights"],
                     default="torus")
     ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--learned-steps", type=int, default=400,
@@ -628,6 +684,12 @@ def main():
         return bench_learned(args)
     if args.workload == "traffic":
         return bench_traffic(args)
+    if args.workload == "weights":
+        n_sys = args.weights_n if args.weights_n > 0 else 500_000
+        bw = bench_weights(n_sys)
+        print(json.dumps(dict(workload=f"batched PHS weight solves, star surface, {n_sys} stencils n=50, "
+                                       "r^3 + degree 3 (60x60 systems)", **bw)), flush=True)
+        return
     if args.workload == "sbdf2":
         if args.n == 160_000:
             args.n = 300_000
@@ -700,52 +762,7 @@ def main():
     learned = bench_torus_learned(args, m, f, u, sizes, main_prec, results[main_prec]) if args.learned_steps > 0 else None
 
     # batched per-node weight solves (500,000 star-surface stencils, n=50, r^3 + degree 3: 60x60 systems)
-    bw = None
-    if args.weights_n > 0:
-        t0 = time.perf_counter()
-        wl4 = synth.star_workload(args.weights_n)
-        sten = mgm.stencils(wl4.xyz, 50)
-        log(f"star surface N={args.weights_n} + stencils in {time.perf_counter() - t0:.1f} s")
-        d_x = torch.tensor(wl4.xyz, device="cuda")
-        d_n = torch.tensor(wl4.normals, device="cuda")
-        d_s = torch.tensor(sten, device="cuda")
-        d_w = torch.empty((args.weights_n, 50), dtype=torch.float64, device="cuda")
-        mgm.batched_weights(d_x, d_n, d_s, 1, 3, d_w)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 5
-        ts = []
-        for _ in range(reps):
-            ev0.record()
-            mgm.batched_weights(d_x, d_n, d_s, 1, 3, d_w)
-            ev1.record()
-            ev1.synchronize()
-            ts.append(ev0.elapsed_time(ev1))
-        wms = float(np.median(ts))
-        S = 60
-        flops = (2.0 / 3.0 * S ** 3 + 2.0 * S * S) * args.weights_n
-        # the FP32 matrix-core elimination with FP64 refinement, same systems
-        d_wm = torch.empty_like(d_w)
-        mgm.batched_weights(d_x, d_n, d_s, 1, 3, d_wm, mixed=True)
-        tsm = []
-        for _ in range(reps):
-            ev0.record()
-            mgm.batched_weights(d_x, d_n, d_s, 1, 3, d_wm, mixed=True)
-            ev1.record()
-            ev1.synchronize()
-            tsm.append(ev0.elapsed_time(ev1))
-        wms_mixed = float(np.median(tsm))
-        mixed_diff = float((torch.abs(d_wm - d_w).amax(dim=1) / torch.abs(d_w).amax(dim=1)).max())
-        bw = {"systems": args.weights_n, "system_size": S, "ms": round(wms, 3),
-              "systems_per_s": round(args.weights_n / (wms * 1e-3)),
-              "TFLOPs_lu_model": round(flops / (wms * 1e-3) / 1e12, 2),
-              "frac_fp64_peak": round(flops / (wms * 1e-3) / 1e12 / 78.6, 4),
-              "note": "FP64 Gauss-Jordan with partial pivoting, one wavefront per system, in panels of 4 columns "
-                      "whose updates run on the FP64 matrix cores (MFMA); flops = (2/3)S^3 + 2S^2",
-              "mixed": {"ms": round(wms_mixed, 3), "max_rel_diff_vs_fp64": float(f"{mixed_diff:.3g}"),
-                        "note": "FP32 Gauss-Jordan on [A | I] on the FP32 matrix cores, then FP64 iterative "
-                                "refinement (mgm_batched_weights_mixed)"}}
-        log(f"batched weights: {wms:.2f} ms for {args.weights_n} systems ({bw['TFLOPs_lu_model']} TFLOP/s LU model); "
-            f"mixed precision {wms_mixed:.2f} ms, max rel diff {mixed_diff:.1e}")
+    bw = bench_weights(args.weights_n) if args.weights_n > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
