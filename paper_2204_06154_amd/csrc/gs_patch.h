@@ -73,10 +73,9 @@ struct GsFlow {
 // are listed per slot in ascending order; the workgroup loads each of them
 // once into LDS, with consecutive lanes on consecutive rows (rows of slots
 // later in the sweep before the wait, the others after it), and the lanes
-// gather their out-of-patch values from there. The column array
-// then holds the in-patch row (below kPatch) or kPatch + the row's place in
-// the slot's list. Same values, same sums: results are those of the direct
-// loads.
+// gather their out-of-patch values from there. The column array then holds
+// the in-patch row (below kPatch) or kPatch + the row's place in the slot's
+// list. Same values, same sums: results are those of the direct loads.
 constexpr int kMaxHalo = kPatch * kPatchG;  // staged rows per slot (one per thread)
 
 template <typename V, typename S, int WL, bool SCALED, bool BORDER, bool FLOW = false, bool HALO = false>
@@ -201,8 +200,8 @@ __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
       if (HALO) {
         // cc: in-patch row, or kPatch + place in the staged list
         const bool in = live && cc[i] < kPatch;
-        const S hval = hv[(live && !in) ? cc[i] - kPatch : 0];
-        halo += iv[i] * ((live && !in) ? hval : S(0));
+        const S hx = hv[(live && !in) ? cc[i] - kPatch : 0];
+        halo += iv[i] * ((live && !in) ? hx : S(0));
         ic[i] = in ? cc[i] : t;
         iv[i] = in ? iv[i] : S(0);
         continue;
