@@ -74,7 +74,9 @@ enum { MGM_FGMRES = 0, MGM_BICGSTAB = 1, MGM_STATIONARY = 2 };
 
 typedef struct {
   int32_t disc;           /* MGM_RBFFD | MGM_GFD */
-  int32_t phs_order;      /* k of the PHS kernel r^(2k+1) (RBF-FD only), 0..8 */
+  int32_t phs_order;      /* k of the PHS kernel r^(2k+1) (RBF-FD only), 1..8
+                             (its Laplacian at the stencil centre is finite
+                             only for k >= 1) */
   int32_t poly_degree;    /* l, degree of the bivariate polynomials, 0..8 */
   int32_t stencil_size;   /* n, stencil size, centre included, > L = (l+1)(l+2)/2 */
   double  gfd_alpha;      /* alpha of the GFD Gaussian weight (Sec. 2.3) */
@@ -329,6 +331,7 @@ mgm_status mgm_stencils(const double *h_xyz, int64_t n, int32_t k, int32_t *h_id
  * saddle system in the tangent plane of the centre and write the stencil_size
  * weights of row i to d_weights (device FP64, n_systems x stencil_size).
  * One wavefront per system, FP64 Gauss-Jordan with partial pivoting; needs
+ * phs_order 1..6, poly_degree 0..6 and
  * stencil_size + (poly_degree+1)(poly_degree+2)/2 <= 64. Systems of more
  * than 32 unknowns with poly_degree <= 4 are eliminated in panels of four
  * columns whose updates run on the FP64 matrix cores (MFMA); the others

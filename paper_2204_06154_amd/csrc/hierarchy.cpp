@@ -24,7 +24,8 @@ void validate_params(const mgm_params& p, int64_t n) {
   if (n < 16 || n > (int64_t(1) << 30)) bad("number of points out of range");
   if (p.disc != MGM_RBFFD && p.disc != MGM_GFD) bad("disc");
   if (p.poly_degree < 0 || p.poly_degree > 8) bad("poly_degree must be 0..8");
-  if (p.disc == MGM_RBFFD && (p.phs_order < 0 || p.phs_order > 8)) bad("phs_order must be 0..8");
+  // the Laplacian of r^(2k+1) is (2k+1)^2 r^(2k-1): finite at the stencil centre only for k >= 1
+  if (p.disc == MGM_RBFFD && (p.phs_order < 1 || p.phs_order > 8)) bad("phs_order must be 1..8");
   int L = (p.poly_degree + 1) * (p.poly_degree + 2) / 2;
   if (p.stencil_size < L || p.stencil_size > 128 || p.stencil_size > n) bad("stencil_size");
   if (p.disc == MGM_GFD && !(p.gfd_alpha > 0)) bad("gfd_alpha must be > 0");

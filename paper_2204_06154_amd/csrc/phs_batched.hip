@@ -826,7 +826,8 @@ void batched_phs_weights_device(const double* d_xyz, const double* d_nrm, const 
                                 int phs_order, int deg, double* d_w, int* d_status, hipStream_t st, bool mixed) {
   const int L = (deg + 1) * (deg + 2) / 2;
   if (ns < 1 || ns + L > 64) throw Error(MGM_E_ARG, "device weights need stencil_size + L <= 64");
-  if (deg < 0 || deg > 6 || phs_order < 0 || phs_order > 6) throw Error(MGM_E_ARG, "phs_order/poly_degree out of range");
+  if (deg < 0 || deg > 6 || phs_order < 1 || phs_order > 6)
+    throw Error(MGM_E_ARG, "phs_order must be 1..6 and poly_degree 0..6");
   if (mixed && L > kMonoMax) throw Error(MGM_E_ARG, "the mixed-precision weights need poly_degree <= 4");
   if (nsys <= 0) return;
   if (mixed) {

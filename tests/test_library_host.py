@@ -126,7 +126,7 @@ def test_host_only_handle_rejects_device_calls():
 
 @pytest.mark.parametrize("mutate,status", [
     ("dup", -5), ("nan", -9), ("mu0", -1), ("muinf", -1), ("tiny", -1), ("onelevel", -1), ("badstencil", -1),
-    ("collinear", -4), ("gsflow3", -1),
+    ("collinear", -4), ("gsflow3", -1), ("phs0", -1),
 ])
 def test_failure_injection(mutate, status):
     wl = synth.sphere_workload(800)
@@ -149,6 +149,8 @@ def test_failure_injection(mutate, status):
         x, nrm = x[:600], nrm[:600]
     elif mutate == "gsflow3":
         p["gs_flow"] = 3
+    elif mutate == "phs0":
+        p["phs_order"] = 0  # r^1: its Laplacian is infinite at the stencil centre
     elif mutate == "badstencil":
         p["stencil_size"] = 3   # fewer than the 6 degree-2 monomials
     elif mutate == "collinear":
