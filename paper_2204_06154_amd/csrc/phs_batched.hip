@@ -498,20 +498,25 @@ __global__ __launch_bounds__(64 * kMWaves, 3) void k_phs_weights_mfma(int64_t ns
         diag = piv;
       }
     }
-    // 3. pivot rows B (current entries) into LDS, then U = Lambda^-1 B
+    // 3. pivot rows B (current entries) into LDS, then U = Lambda^-1 B. The
+    // pivot row's register (bi, v) is uniform: one switch (a short tree of
+    // scalar branches) instead of a test per register
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int rb = bk[k];
-      const int bib = rb >> 4, vb = (rb >> 2) & 3;
       if (g == (rb & 3)) {
-#pragma unroll
-        for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            if (bi == bib && v == vb) {
-#pragma unroll
-              for (int bj = 0; bj < 4; ++bj) ub[k][16 * bj + c] = acc[bi][bj][v];
-            }
+#define PIVOT_ROW(BI, V)                                                          \
+  case 4 * BI + V:                                                                \
+    _Pragma("unroll") for (int bj = 0; bj < 4; ++bj) ub[k][16 * bj + c] = acc[BI][bj][V]; \
+    break;
+        switch (rb >> 2) {
+          PIVOT_ROW(0, 0) PIVOT_ROW(0, 1) PIVOT_ROW(0, 2) PIVOT_ROW(0, 3)
+          PIVOT_ROW(1, 0) PIVOT_ROW(1, 1) PIVOT_ROW(1, 2) PIVOT_ROW(1, 3)
+          PIVOT_ROW(2, 0) PIVOT_ROW(2, 1) PIVOT_ROW(2, 2) PIVOT_ROW(2, 3)
+          PIVOT_ROW(3, 0) PIVOT_ROW(3, 1) PIVOT_ROW(3, 2) PIVOT_ROW(3, 3)
+          default: break;
+        }
+#undef PIVOT_ROW
       }
     }
     double lam[4][4];  // lam[k][q] = multiplier of pivot row b_k at step q < k
@@ -686,16 +691,20 @@ __global__ __launch_bounds__(64 * kMWaves, 3) void k_phs_weights_mixed(int64_t n
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int rb = bk[k];
-      const int bib = rb >> 4, vb = rb & 3;
       if (g == ((rb >> 2) & 3)) {
-#pragma unroll
-        for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            if (bi == bib && v == vb) {
-#pragma unroll
-              for (int bj = 0; bj < 8; ++bj) ub[k][16 * bj + c] = acc[bi][bj][v];
-            }
+        // the pivot row's register (bi, v) is uniform: one switch
+#define PIVOT_ROW32(BI, V)                                                        \
+  case 4 * BI + V:                                                                \
+    _Pragma("unroll") for (int bj = 0; bj < 8; ++bj) ub[k][16 * bj + c] = acc[BI][bj][V]; \
+    break;
+        switch (((rb >> 4) << 2) | (rb & 3)) {
+          PIVOT_ROW32(0, 0) PIVOT_ROW32(0, 1) PIVOT_ROW32(0, 2) PIVOT_ROW32(0, 3)
+          PIVOT_ROW32(1, 0) PIVOT_ROW32(1, 1) PIVOT_ROW32(1, 2) PIVOT_ROW32(1, 3)
+          PIVOT_ROW32(2, 0) PIVOT_ROW32(2, 1) PIVOT_ROW32(2, 2) PIVOT_ROW32(2, 3)
+          PIVOT_ROW32(3, 0) PIVOT_ROW32(3, 1) PIVOT_ROW32(3, 2) PIVOT_ROW32(3, 3)
+          default: break;
+        }
+#undef PIVOT_ROW32
       }
     }
     float lam[4][4];  // lam[k][q] = multiplier of pivot row b_k at step q < k
