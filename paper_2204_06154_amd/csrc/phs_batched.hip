@@ -79,6 +79,28 @@ __device__ __forceinline__ double ipow_c(double x, int e) {
   }
 }
 
+// Square root of a scaled squared distance x: zero, or at least 2^-767 (the
+// points lie in the unit disc, and two distinct FP64 points there are at
+// least ~1e-16 apart), so no range scaling is needed. Goldschmidt's iteration
+// from the hardware reciprocal square root y ~ 1/sqrt(x): g = x y and
+// h = y / 2 converge to sqrt(x) and 1/(2 sqrt(x)); one coupled step, then two
+// corrections g += (x - g^2) h. These are the steps of the correctly rounded
+// sqrt() of this target without its scaling of inputs below 2^-767, so in
+// this range the bits are sqrt()'s. x = 0 gives 0 (the iteration would give
+// NaN).
+__device__ __forceinline__ double sqrt_dist(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = y * 0.5;
+  const double r = fma(-h, g, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  g = fma(d, h, g);
+  return x == 0.0 ? 0.0 : g;
+}
+
 // exponents (a, b) of monomial q: by total degree, then descending a
 __device__ __forceinline__ void mono_exp(int q, int& a, int& b) {
   int d = 0;
@@ -320,13 +342,13 @@ template <int MC>
 __device__ __forceinline__ double phs_entry(const double (*xsw)[2], const double* mono, int row, int col, double xc,
                                             double yc, int ns, int S, int m, bool& inside) {
   const double dx = xsw[row][0] - xc, dy = xsw[row][1] - yc;
-  const double phs = ipow_c<MC>(sqrt(dx * dx + dy * dy), m);
+  const double phs = ipow_c<MC>(sqrt_dist(dx * dx + dy * dy), m);
   const bool rp = row < ns;
   const int pt = rp ? row : col, mq = (rp ? col : row) - ns;
   const double pq = mono[pt * kMonoMax + min(max(mq, 0), kMonoMax - 1)];
   inside = row < S && col < S;
-  if (inside) return (row < ns && col < ns) ? phs : ((row < ns) != (col < ns) ? pq : 0.0);
-  return row == col ? 1.0 : 0.0;
+  const double vin = (row < ns && col < ns) ? phs : ((row < ns) != (col < ns) ? pq : 0.0);
+  return inside ? vin : (row == col ? 1.0 : 0.0);
 }
 
 // right-hand side (eq. rbf_fd_lap) of row `lane`: Lap r^m at the points, Lap p(0)
@@ -421,7 +443,7 @@ __global__ __launch_bounds__(64 * kMWaves, 3) void k_phs_weights_mfma(int64_t ns
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * bi + 4 * v + g;
         const double dx = xs[wv][row][0] - xc, dy = xs[wv][row][1] - yc;
-        const double phs = ipow_c<MC>(sqrt(dx * dx + dy * dy), m);
+        const double phs = ipow_c<MC>(sqrt_dist(dx * dx + dy * dy), m);
         // P (row a point, col a monomial) or P^T (row a monomial, col a point)
         const bool rp = row < ns;
         const int pt = rp ? row : col, mq = (rp ? col : row) - ns;
