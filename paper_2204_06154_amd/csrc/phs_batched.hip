@@ -364,12 +364,17 @@ __device__ __forceinline__ double phs_rhs(int lane, double r, int ns, int S, int
   return 0.0;
 }
 
-template <int MC>  // PHS exponent m fixed at compile time (MC > 0) or read from m
-__global__ __launch_bounds__(64 * kMWaves, 3) void k_phs_weights_mfma(int64_t nsys, int ns, int deg, int L, int m,
-                                                                 const double* __restrict__ xyz,
+// PHS exponent m fixed at compile time (MC > 0) or read from m; likewise the
+// stencil size (NSC > 0) and the polynomial degree (DEGC >= 0)
+template <int MC, int NSC = 0, int DEGC = -1>
+__global__ __launch_bounds__(64 * kMWaves, 3) void k_phs_weights_mfma(int64_t nsys, int ns_rt, int deg_rt, int L_rt,
+                                                                 int m, const double* __restrict__ xyz,
                                                                  const double* __restrict__ nrm,
                                                                  const int32_t* __restrict__ sten,
                                                                  double* __restrict__ w, int* __restrict__ status) {
+  const int ns = NSC > 0 ? NSC : ns_rt;
+  const int deg = DEGC >= 0 ? DEGC : deg_rt;
+  const int L = DEGC >= 0 ? (DEGC + 1) * (DEGC + 2) / 2 : L_rt;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int g = lane >> 4, c = lane & 15;
@@ -613,12 +618,16 @@ __device__ __forceinline__ float readlane_f(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-template <int MC>  // PHS exponent m fixed at compile time (MC > 0) or read from m
-__global__ __launch_bounds__(64 * kMWaves, 3) void k_phs_weights_mixed(int64_t nsys, int ns, int deg, int L, int m,
-                                                                  const double* __restrict__ xyz,
+// compile-time PHS exponent, stencil size and degree as in k_phs_weights_mfma
+template <int MC, int NSC = 0, int DEGC = -1>
+__global__ __launch_bounds__(64 * kMWaves, 3) void k_phs_weights_mixed(int64_t nsys, int ns_rt, int deg_rt, int L_rt,
+                                                                  int m, const double* __restrict__ xyz,
                                                                   const double* __restrict__ nrm,
                                                                   const int32_t* __restrict__ sten,
                                                                   double* __restrict__ w, int* __restrict__ status) {
+  const int ns = NSC > 0 ? NSC : ns_rt;
+  const int deg = DEGC >= 0 ? DEGC : deg_rt;
+  const int L = DEGC >= 0 ? (DEGC + 1) * (DEGC + 2) / 2 : L_rt;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int g = lane >> 4, c = lane & 15;
@@ -865,15 +874,20 @@ void batched_phs_weights_device(const double* d_xyz, const double* d_nrm, const 
     if ((nsys + kMWaves - 1) / kMWaves > 0x7fffffff) throw Error(MGM_E_ARG, "too many systems for one launch");
     const dim3 grid(unsigned((nsys + kMWaves - 1) / kMWaves)), block(64 * kMWaves);
     const int mm = 2 * phs_order + 1;
+    const bool n50d3 = ns == 50 && deg == 3;
+#define PHS_MIXED_K(...)                                                                                          \
+  hipLaunchKernelGGL((k_phs_weights_mixed<__VA_ARGS__>), grid, block, 0, st, nsys, ns, deg, L, mm, d_xyz, d_nrm, \
+                     d_sten, d_w, d_status)
 #define PHS_MIXED(MC) \
-  hipLaunchKernelGGL(k_phs_weights_mixed<MC>, grid, block, 0, st, nsys, ns, deg, L, mm, d_xyz, d_nrm, d_sten, d_w, d_status)
+  if (n50d3) PHS_MIXED_K(MC, 50, 3); else PHS_MIXED_K(MC);
     switch (mm) {
-      case 3: PHS_MIXED(3); break;
-      case 5: PHS_MIXED(5); break;
-      case 7: PHS_MIXED(7); break;
-      default: PHS_MIXED(0); break;
+      case 3: PHS_MIXED(3) break;
+      case 5: PHS_MIXED(5) break;
+      case 7: PHS_MIXED(7) break;
+      default: PHS_MIXED_K(0); break;
     }
 #undef PHS_MIXED
+#undef PHS_MIXED_K
     HIPOK(hipGetLastError());
     return;
   }
@@ -885,16 +899,21 @@ void batched_phs_weights_device(const double* d_xyz, const double* d_nrm, const 
   if (S > 32 && L <= kMonoMax) {
     // larger systems: blocked elimination with the update on the matrix cores
     const unsigned mblocks = unsigned((nsys + kMWaves - 1) / kMWaves);
-#define PHS_MFMA(MC)                                                                                            \
-  hipLaunchKernelGGL(k_phs_weights_mfma<MC>, dim3(mblocks), dim3(64 * kMWaves), 0, st, nsys, ns, deg, L, m, d_xyz, \
-                     d_nrm, d_sten, d_w, d_status)
+    // the common 50-point, degree-3 stencils also with their sizes fixed
+    const bool n50d3 = ns == 50 && deg == 3;
+#define PHS_MFMA_K(...)                                                                                         \
+  hipLaunchKernelGGL((k_phs_weights_mfma<__VA_ARGS__>), dim3(mblocks), dim3(64 * kMWaves), 0, st, nsys, ns, deg, L, m, \
+                     d_xyz, d_nrm, d_sten, d_w, d_status)
+#define PHS_MFMA(MC) \
+  if (n50d3) PHS_MFMA_K(MC, 50, 3); else PHS_MFMA_K(MC);
     switch (m) {
-      case 3: PHS_MFMA(3); break;
-      case 5: PHS_MFMA(5); break;
-      case 7: PHS_MFMA(7); break;
-      default: PHS_MFMA(0); break;
+      case 3: PHS_MFMA(3) break;
+      case 5: PHS_MFMA(5) break;
+      case 7: PHS_MFMA(7) break;
+      default: PHS_MFMA_K(0); break;
     }
 #undef PHS_MFMA
+#undef PHS_MFMA_K
   } else if (S <= 32)
     hipLaunchKernelGGL(k_phs_weights<32>, dim3(blocks), dim3(64 * kWaves), 0, st, nsys, ns, L, m, d_xyz, d_nrm, d_sten,
                        d_w, d_status);
