@@ -56,7 +56,7 @@ HBM_PEAK_GBS = 8000.0
 # `bench.py --workload traffic` (summary and commands in
 # profiles/gs_patch_torus160k_traffic.md): bytes per launch, valid only for
 # the kernel source it was measured on (SHA-256 over lane_ops.h + gs_patch.h).
-GS_TRAFFIC = {"source_sha256": "2a44d530cab7a83c141bca0694d21b87dbe06005ffb16496e0e2ede5708d4d6d", "bytes_per_launch": 23664403,
+GS_TRAFFIC = {"source_sha256": "2a44d530cab7a83c141bca0694d21b87dbe06005ffb16496e0e2ede5708d4d6d", "bytes_per_launch": 23472672,
               "summary": "profiles/gs_patch_torus160k_traffic.md"}
 
 
