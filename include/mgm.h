@@ -113,9 +113,11 @@ typedef struct {
                              0: one launch per patch colour); each patch
                              loads the distinct rows outside it that its
                              entries reference once, into LDS (levels whose
-                             patches reference at most 1024 such rows; the
-                             others load per entry). 2: one launch per sweep
-                             with loads per entry on every level. A wait is
+                             patches reference at most 1024 such rows, and
+                             with 32-bit vectors only levels of at most 512
+                             patches; the others load per entry). 2: one
+                             launch per sweep with loads per entry on every
+                             level. A wait is
                              bounded; if one gives up, the next mgm_solve,
                              mgm_level_op or mgm_check returns MGM_E_SYNC */
   int32_t gs_max_width;   /* part of the smoother ordering: a level is
