@@ -277,24 +277,28 @@ static void upload(mgm_ctx* c) {
         // row or kPatch + the place in that list
         const int nsl = int(ps.size()) - 1;
         std::vector<int32_t> hstart(nsl + 1, 0), hrows, pch(pci.size());
-        std::vector<int32_t> rows;
-        int hmax = 0;
+        std::vector<std::vector<int32_t>> lists(nsl);
         const size_t slot_len = size_t(d.pw) * kPatchG * block;
-        for (int sl = 0; sl < nsl; ++sl) {
-          rows.clear();
-          const size_t e0 = size_t(sl) * slot_len;
-          for (size_t e = e0; e < e0 + slot_len; ++e)
-            if (pci[e] < ps[sl] || pci[e] >= ps[sl + 1]) rows.push_back(pci[e]);
-          std::sort(rows.begin(), rows.end());
-          rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
-          for (size_t e = e0; e < e0 + slot_len; ++e) {
-            const int32_t cc = pci[e];
-            pch[e] = (cc >= ps[sl] && cc < ps[sl + 1])
-                         ? cc - ps[sl]
-                         : kPatch + int32_t(std::lower_bound(rows.begin(), rows.end(), cc) - rows.begin());
+        parallel_for(nsl, [&](int64_t b, int64_t e1) {  // slots are independent
+          for (int64_t sl = b; sl < e1; ++sl) {
+            auto& rows = lists[size_t(sl)];
+            const size_t e0 = size_t(sl) * slot_len;
+            for (size_t e = e0; e < e0 + slot_len; ++e)
+              if (pci[e] < ps[sl] || pci[e] >= ps[sl + 1]) rows.push_back(pci[e]);
+            std::sort(rows.begin(), rows.end());
+            rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+            for (size_t e = e0; e < e0 + slot_len; ++e) {
+              const int32_t cc = pci[e];
+              pch[e] = (cc >= ps[sl] && cc < ps[sl + 1])
+                           ? cc - ps[sl]
+                           : kPatch + int32_t(std::lower_bound(rows.begin(), rows.end(), cc) - rows.begin());
+            }
           }
-          hmax = std::max(hmax, int(rows.size()));
-          hrows.insert(hrows.end(), rows.begin(), rows.end());
+        }, 8);
+        int hmax = 0;
+        for (int sl = 0; sl < nsl; ++sl) {
+          hmax = std::max(hmax, int(lists[sl].size()));
+          hrows.insert(hrows.end(), lists[sl].begin(), lists[sl].end());
           hstart[sl + 1] = int32_t(hrows.size());
         }
         d.halo_ok = hmax <= kMaxHalo;
