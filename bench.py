@@ -55,7 +55,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of the dominant kernel from two rocprofv3 --pmc passes over
 # `bench.py --workload traffic` (summary and commands in
 # profiles/gs_patch_torus160k_traffic.md): bytes per launch, valid only for
-# the kernel source it was measured on (SHA-256 over lane_ops.h + gs_patch.h).
+# the kernel source it was measured on (SHA-256 over lane_ops.h + gs_patch.h,
+# which also fixes which levels stage their halo).
 GS_TRAFFIC = {"source_sha256": "2a44d530cab7a83c141bca0694d21b87dbe06005ffb16496e0e2ede5708d4d6d", "bytes_per_launch": 23472672,
               "summary": "profiles/gs_patch_torus160k_traffic.md"}
 

@@ -486,8 +486,6 @@ struct Prec<_Float16, float, true> {
     default: { constexpr int GG = 16; __VA_ARGS__; } break; \
   }
 
-constexpr int kStageMaxSlots = 512;
-
 // One patch colour (pc >= 0, one workgroup per patch of that colour) or, with
 // pc < 0, the whole sweep in one dataflow launch (one workgroup per patch).
 template <typename V, typename S, bool SC>
@@ -500,10 +498,8 @@ static void gs_patch_launch(mgm_ctx* c, int j, int pc, bool reverse, bool border
   const int ns = flow ? d.pstart_host_slots : d.pc_start[pc + 1] - s0;
   if (ns <= 0) return;
   GsFlow fl{};
-  // staged halo: FP64 vectors on every level; 32-bit vectors on levels of at
-  // most kStageMaxSlots patches (measured: on the larger ones, whose
-  // workgroups outnumber what the chip holds at once, loads per entry are
-  // faster for 4-byte values)
+  // staged halo: FP64 vectors on every level, 32-bit ones on levels of at
+  // most kStageMaxSlots patches
   const bool staged = flow && d.halo_ok && c->p.gs_flow == 1 &&
                       (sizeof(S) == 8 || d.pstart_host_slots <= kStageMaxSlots);
   if (flow)

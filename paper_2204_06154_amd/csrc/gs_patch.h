@@ -77,6 +77,11 @@ struct GsFlow {
 // the in-patch row (below kPatch) or kPatch + the row's place in the slot's
 // list. Same values, same sums: results are those of the direct loads.
 constexpr int kMaxHalo = kPatch * kPatchG;  // staged rows per slot (one per thread)
+// With 32-bit vectors a level stages its halo only if it has at most this many
+// patch slots: on larger levels, whose workgroups outnumber what the chip
+// holds at once, the per-entry loads measured faster for 4-byte values (FP64
+// vectors stage on every level).
+constexpr int kStageMaxSlots = 512;
 
 template <typename V, typename S, int WL, bool SCALED, bool BORDER, bool FLOW = false, bool HALO = false>
 __global__ __launch_bounds__(kPatch * kPatchG) void k_gs_patch(
