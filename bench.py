@@ -57,7 +57,7 @@ HBM_PEAK_GBS = 8000.0
 # profiles/gs_patch_torus160k_traffic.md): bytes per launch, valid only for
 # the kernel source it was measured on (SHA-256 over lane_ops.h + gs_patch.h,
 # which also fixes which levels stage their halo).
-GS_TRAFFIC = {"source_sha256": "2a44d530cab7a83c141bca0694d21b87dbe06005ffb16496e0e2ede5708d4d6d", "bytes_per_launch": 23472672,
+GS_TRAFFIC = {"source_sha256": "0681a9d6c2c43480c901c3f88aa869920316267d93121901513d4dae4a6e7307", "bytes_per_launch": 23478655,
               "summary": "profiles/gs_patch_torus160k_traffic.md"}
 
 
